@@ -1,0 +1,152 @@
+/*
+ * ht_rise.h - C ABI of the MI355X (gfx950) batch hierarchical Tucker library.
+ *
+ * The library computes, on one AMD GPU, the batch hierarchical Tucker (batch-HT)
+ * representation of a stream of d-way tensors (Aksoy & Gorodetsky, "Incremental
+ * Hierarchical Tucker Decomposition", arXiv 2412.16544):
+ *
+ *   - ht_init_batch   : BHT-l2r on the first batch (Sec. 3.1, Algorithm 1);
+ *   - ht_rise_update  : HT-RISE on every later batch (Sec. 3.2, Algorithm 2);
+ *   - ht_project      : Step 1 of HT-RISE alone - the latent code of a batch in
+ *                       the current cores (Sec. 3.2, Step 1; Problem 1's encoder);
+ *   - ht_reconstruct  : root-to-leaves contraction (Eq. htucker_reconstruction),
+ *                       the decoder of Problem 1;
+ *   - ht_query_ranks  : the HT rank vector R (Sec. 2.3) and accumulated count.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Tensors.  A batch Y is a DEVICE pointer to N samples stored C-order as
+ *   [N][n_1]...[n_d]: each sample is contiguous, the batch index is slowest.  This
+ *   is the paper's Y in R^{n_1 x ... x n_d x N} (Sec. 1) with the batch mode moved
+ *   first, which the paper allows (Sec. 3.1 footnote on the batch position).
+ *   Element type is cfg->in_dtype (float32 or float64).
+ * Dimension tree.  Balanced binary tree, depth ceil(log2 d), the first half of a
+ *   node's modes (ceil(q/2) of them) going to its first successor (Sec. 2.3).
+ *   Nodes are numbered layer by layer from the root, left to right; the HT rank
+ *   vector R = [r_{1,1}, r_{1,2}, r_{2,1}, ...] (Sec. 2.3) lists the 2d-2 non-root
+ *   nodes in that order.
+ * Cores.  A leaf core is n_i x r; a transfer core is the (r_a r_b) x r matrix whose
+ *   row index is i_a * r_b + i_b (the C-order fold to r_a x r_b x r of Eq.
+ *   ht_tucker_core_reshape); the root core is r_{1,1} x r_{1,2} x N_acc (Sec. 3.1).
+ * Streams.  hip_stream is a hipStream_t (NULL = the legacy default stream).  All
+ *   device work of a call is enqueued on it.  The calls below synchronise that
+ *   stream before returning (they need the rank decisions on the host to size
+ *   the next launches), so on return every output is ready.
+ * Memory.  The caller owns every buffer it passes (Y, ws, out, latent).  All
+ *   device state of a handle lives in the caller's workspace ws; the library
+ *   never allocates device memory.  The handle itself is a small host object.
+ *   One handle is used by one host thread at a time.
+ * Errors.  Every entry point returns an ht_status.  Argument errors are detected
+ *   before any work is enqueued and leave the handle unchanged.  A device-side
+ *   failure inside an update (rank capacity exceeded, a non-finite norm) rolls
+ *   the handle back to its state before the call.  ht_last_error() returns a
+ *   human-readable message for the calling thread's last failure.
+ */
+#ifndef HT_RISE_H
+#define HT_RISE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ht_state* ht_handle;
+
+typedef enum {
+  HT_OK = 0,
+  HT_EINVAL = 1,    /* invalid argument (null pointer, size out of range, ...)    */
+  HT_ESHAPE = 2,    /* batch size above cfg->max_batch, or accumulation full      */
+  HT_ENOMEM = 3,    /* workspace smaller than ht_workspace_bytes() reported       */
+  HT_ERANKCAP = 4,  /* a rank decision exceeded cfg->rank_cap (handle rolled back) */
+  HT_EDEVICE = 5,   /* no usable gfx950 device, or a HIP runtime error            */
+  HT_ENUMERIC = 6   /* NaN or Inf met in a norm (handle rolled back)              */
+} ht_status;
+
+/* Precision of the contractions and Gram products.  Eigen solves, rank
+ * decisions and re-orthogonalisation are FP64 in every form. */
+typedef enum { HT_FP64 = 0, HT_FP32 = 1, HT_BF16X3 = 2 } ht_precision;
+
+/* Element type of Y and of reconstructions. */
+typedef enum { HT_F32 = 0, HT_F64 = 1 } ht_dtype;
+
+typedef struct {
+  int32_t d;              /* modes per sample, d >= 2                                    */
+  const int64_t* n;       /* n[0..d-1] >= 1 mode sizes (copied at init)                  */
+  double eps_rel;         /* relative tolerance, 0 < eps_rel < 1 (Alg. 1 and 2 input)    */
+  int32_t rank_cap;       /* capacity: maximum rank of any node, >= 1                    */
+  int64_t max_batch;      /* capacity: largest N of any single call, >= 1                */
+  int64_t n_cap;          /* capacity: largest accumulated sample count N_acc, >= 1      */
+  int32_t prec;           /* ht_precision                                                */
+  int32_t in_dtype;       /* ht_dtype of Y                                               */
+  uint64_t flags;         /* reserved, must be 0                                         */
+} ht_config;
+
+typedef struct {
+  int32_t skipped;        /* 1 when the batch was represented well enough (Alg. 2 skip) */
+  int32_t rank_growth;    /* sum over nodes of the ranks added by this call              */
+  double norm_y;          /* ||Y||_F                                                     */
+  double eps_proj;        /* sqrt(max(0, ||Y||^2 - ||C_1||^2)) before the update          */
+  double eps_des;         /* eps_rel * ||Y||_F                                            */
+  float device_ms;        /* device time of the call, from HIP events on hip_stream       */
+} ht_update_info;
+
+/* Bytes of device workspace a handle with this configuration needs.  Host only.
+ * Returns HT_EINVAL for an invalid configuration. */
+ht_status ht_workspace_bytes(const ht_config* cfg, size_t* bytes);
+
+/* BHT-l2r (Sec. 3.1, Algorithm 1) on the first batch Y (N samples).
+ * Creates *out, whose device state lives in ws (ws_bytes >= ht_workspace_bytes,
+ * 256-byte aligned).  eps_nw = eps_rel ||Y|| / sqrt(2d-2); every node keeps the
+ * minimal rank r >= 1 whose discarded energy is <= eps_nw^2.  ||Y|| = 0 is
+ * HT_EINVAL.  info may be NULL. */
+ht_status ht_init_batch(const ht_config* cfg, void* ws, size_t ws_bytes, const void* Y, int64_t N,
+                        void* hip_stream, ht_handle* out, ht_update_info* info);
+
+/* HT-RISE (Sec. 3.2, Algorithm 2) with batch Y of N samples: project (Step 1),
+ * skip when sqrt(||Y||^2 - ||C_1||^2) <= eps_rel ||Y|| (Eq. relative_error_threshold),
+ * else per layer from the leaves: residual (Eq. compute_residual), truncated
+ * eigen-decomposition of its Gram (Eq. svd_on_residual), expansion of the bases
+ * (Eq. concatenating_orthonormal_vectors), zero padding of the parents
+ * (Eq. incremental_zero_padding1), projection onto the updated cores; finally the
+ * root grows by the N new latent slices (Eq. incremental_root_concatenate).
+ * info may be NULL. */
+ht_status ht_rise_update(ht_handle h, const void* Y, int64_t N, void* hip_stream, ht_update_info* info);
+
+/* Latent codes of a batch in the current cores, without changing the handle:
+ * latent is a device buffer of N * r_{1,1} * r_{1,2} float64, C-order [N][r11][r12]. */
+ht_status ht_project(ht_handle h, const void* Y, int64_t N, void* latent, void* hip_stream);
+
+/* Reconstruction of accumulated samples [first, first+count) into the device
+ * buffer out (count * prod(n) elements of type dtype, C-order [count][n_1]...[n_d]). */
+ht_status ht_reconstruct(ht_handle h, int64_t first, int64_t count, void* out, int32_t dtype,
+                         void* hip_stream);
+
+/* Copies the rank vector R (2d-2 entries, order as above) into ranks[0..cap-1],
+ * the entry count into *n_ranks and N_acc into *n_accum (each pointer may be NULL).
+ * Host memory; synchronises the handle's last stream.  cap < 2d-2 is HT_EINVAL
+ * unless ranks is NULL. */
+ht_status ht_query_ranks(ht_handle h, int32_t* ranks, int32_t cap, int32_t* n_ranks, int64_t* n_accum);
+
+/* Test and inspection export of the whole representation as float64 into host
+ * memory: for each non-root node in rank-vector order its core matrix
+ * (rows x r, column-major), then the root as C-order [N_acc][r11][r12].
+ * *needed receives the byte count; host_buf may be NULL to query it.  A buffer
+ * shorter than *needed is HT_ENOMEM.  Synchronises. */
+ht_status ht_export_cores(ht_handle h, double* host_buf, size_t bytes, size_t* needed);
+
+/* Releases the host handle (the workspace stays the caller's).  NULL is a no-op. */
+void ht_destroy(ht_handle h);
+
+/* Static description of a status code. */
+const char* ht_status_str(ht_status s);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* ht_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HT_RISE_H */
