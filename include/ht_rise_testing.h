@@ -1,0 +1,60 @@
+/*
+ * ht_rise_testing.h - kernel-level entry points of the batch hierarchical Tucker
+ * library, for verification against independent references.  Each wraps one
+ * device step of the path on caller-owned device buffers; none allocates.
+ *
+ * Unfolding views: a C-order tensor viewed as (P, m, S), element (p, a, s) at
+ * (p * m + a) * S + s; its mode unfolding is the m x (P*S) matrix with column
+ * (p, s) (Sec. 2.1 "matricization").  dtype arguments are ht_dtype values.
+ * All matrices are float64; U matrices are column-major (m x R).  Calls are
+ * enqueued on hip_stream and return without synchronising.  Invalid sizes or
+ * NULL pointers return HT_EINVAL before anything is enqueued.
+ */
+#ifndef HT_RISE_TESTING_H
+#define HT_RISE_TESTING_H
+
+#include "ht_rise.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* sum of squares of n elements into out[0] (float64); scratch >= 1024 doubles */
+ht_status ht_test_sumsq(const void* x, int32_t dtype, int64_t n, double* out, double* scratch, void* hip_stream);
+
+/* Gram of the mode unfolding: G (m x m row-major) = X_(k) X_(k)^T (the matrix
+ * whose eigen-decomposition gives the SVD of Eq. ht_leaf_svd).  scratch must hold
+ * ht_test_gram_scratch_doubles(P, m, S) doubles. */
+size_t ht_test_gram_scratch_doubles(int64_t P, int64_t m, int64_t S);
+ht_status ht_test_gram(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, double* G, double* scratch,
+                       void* hip_stream);
+
+/* Mode contraction with U^T (Eq. multi_index_contraction): Z[p, r, s] = sum_a U[a, r] X[p, a, s], 1 <= R <= 64. */
+ht_status ht_test_ttm_contract(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
+                               int32_t R, double* Z, void* hip_stream);
+
+/* Mode expansion: out[p, a, s] = sum_t U[a, t] Z[p, t, s], or M[p, a, s] minus that when M
+ * is not NULL (the residual of Eq. compute_residual).  1 <= R <= 64. */
+ht_status ht_test_ttm_expand(const double* Z, int64_t P, int32_t R, int64_t S, const double* U, int64_t m,
+                             const void* M, int32_t m_dtype, void* out, int32_t out_dtype, void* hip_stream);
+
+/* Eigen-decomposition of the symmetric k x k G (row-major) and the truncation rule:
+ * evals (k, descending), the minimal rank r in [rmin, rmax] whose discarded energy
+ * (sum of clipped eigenvalues from the smallest up) is <= thr, written to rank[0],
+ * that energy to tail[0], and the r leading sign-normalised eigenvectors to vecs
+ * (k x r column-major).  scratch holds ht_test_eig_scratch_doubles(k, rmax). */
+size_t ht_test_eig_scratch_doubles(int32_t k, int32_t rmax);
+ht_status ht_test_eig(const double* G, int32_t k, int32_t rmin, int32_t rmax, double thr, double* evals,
+                      double* vecs, int32_t* rank, double* tail, double* scratch, void* hip_stream);
+
+/* Basis expansion (Eq. concatenating_orthonormal_vectors): V (alpha x rR) is made
+ * orthogonal to U_old (alpha x r_old) twice, orthonormalised by CholeskyQR twice,
+ * sign-normalised, and [U_old, V] is written to core (alpha x (r_old + rR)). */
+ht_status ht_test_orth_expand(const double* U_old, int64_t alpha, int32_t r_old, double* V, int32_t rR, double* core,
+                              void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HT_RISE_TESTING_H */

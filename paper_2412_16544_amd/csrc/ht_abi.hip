@@ -1,0 +1,841 @@
+// Host driver and C ABI of the batch hierarchical Tucker library.
+//
+// A handle keeps the dimension tree, the host mirror of the HT ranks and the
+// device pointers into the caller's workspace.  BHT-l2r (Alg. 1) and HT-RISE
+// (Alg. 2) are driven layer by layer from the leaves; every arithmetic step runs
+// in the device kernels of ht_kernels.hip / ht_eig.hip.  The host reads back the
+// norms (skip test) and the rank decisions of each layer, because they size the
+// launches of the next step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ht_internal.h"
+#include "ht_rise.h"
+
+using ht::Elem;
+using ht::ModeView;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ht_status fail(ht_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HT_HIP(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(HT_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+// --------------------------------------------------------------------------
+// Dimension tree: balanced, first half of a node's modes to its first successor
+// (Sec. 2.3); nodes numbered layer by layer, left to right.
+// --------------------------------------------------------------------------
+struct TNode {
+  int layer = 0, lo = 0, hi = 0, parent = -1, child[2] = {-1, -1}, child_pos = -1;
+  bool leaf() const { return child[0] < 0; }
+};
+
+struct Tree {
+  int d = 0, depth = 0;
+  std::vector<TNode> nodes;
+
+  void build(int d_) {
+    d = d_;
+    struct Raw {
+      int layer, lo, hi, parent, pos;
+    };
+    std::vector<Raw> raw;
+    struct Rec {
+      static void go(std::vector<Raw>& raw, int lo, int hi, int layer, int parent, int pos) {
+        const int me = (int)raw.size();
+        raw.push_back({layer, lo, hi, parent, pos});
+        if (hi - lo > 1) {
+          const int mid = lo + (hi - lo + 1) / 2;
+          go(raw, lo, mid, layer + 1, me, 0);
+          go(raw, mid, hi, layer + 1, me, 1);
+        }
+      }
+    };
+    Rec::go(raw, 0, d, 0, -1, -1);
+    std::vector<int> order(raw.size());
+    for (size_t i = 0; i < raw.size(); ++i) order[i] = (int)i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+      return raw[a].layer != raw[b].layer ? raw[a].layer < raw[b].layer : raw[a].lo < raw[b].lo;
+    });
+    std::vector<int> newid(raw.size());
+    for (size_t i = 0; i < order.size(); ++i) newid[order[i]] = (int)i;
+    nodes.assign(raw.size(), TNode());
+    depth = 0;
+    for (size_t i = 0; i < order.size(); ++i) {
+      const Raw& r = raw[order[i]];
+      TNode& t = nodes[i];
+      t.layer = r.layer;
+      t.lo = r.lo;
+      t.hi = r.hi;
+      t.parent = r.parent >= 0 ? newid[r.parent] : -1;
+      t.child_pos = r.pos;
+      depth = std::max(depth, r.layer);
+    }
+    for (size_t i = 0; i < nodes.size(); ++i) {
+      const int p = nodes[i].parent;
+      if (p >= 0) nodes[p].child[nodes[i].child_pos] = (int)i;
+    }
+  }
+
+  // modes of the level tensor entering layer ell, in mode order
+  std::vector<int> frontier(int ell) const {
+    std::vector<int> f;
+    for (size_t i = 0; i < nodes.size(); ++i)
+      if (nodes[i].layer == ell || (nodes[i].leaf() && nodes[i].layer < ell)) f.push_back((int)i);
+    std::sort(f.begin(), f.end(), [&](int a, int b) { return nodes[a].lo < nodes[b].lo; });
+    return f;
+  }
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// ============================================================================
+// handle
+// ============================================================================
+struct ht_state {
+  // configuration
+  int d = 0;
+  std::vector<int64_t> n;
+  double eps = 0.0;
+  int rank_cap = 0;
+  int64_t max_batch = 0, n_cap = 0;
+  Elem in_t = Elem::F32;
+  Tree tree;
+  // per-node capacities: rows of the basis matrix (alpha) and rank bound
+  std::vector<int64_t> alpha_cap;
+  std::vector<int> rc;
+  // live state
+  std::vector<int> rank;
+  int64_t n_acc = 0;
+  // workspace carve (device pointers)
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<double*> core, gram, vecs, evals, eigsc;
+  double* core_backup = nullptr;
+  size_t core_backup_elems = 0;
+  double* root = nullptr;
+  double* bufA = nullptr;
+  double* bufB = nullptr;
+  double* resid = nullptr;
+  double* bufZ = nullptr;
+  double* gpart = nullptr;
+  double* scal = nullptr;
+  double* sspart = nullptr;
+  double* orthsc = nullptr;
+  double* padtmp = nullptr;
+  double* tails = nullptr;
+  int* ranks_dev = nullptr;
+  // host staging for small read-backs
+  std::vector<double> h_scal;
+  hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+struct Layout {
+  size_t total = 0;
+  // offsets (bytes)
+  std::vector<size_t> core, gram, vecs, evals, eigsc;
+  size_t core_backup = 0, core_backup_elems = 0, root = 0, bufA = 0, bufB = 0, buf_elems = 0, resid = 0, bufZ = 0,
+         resid_elems = 0, gpart = 0, scal = 0, sspart = 0, orthsc = 0, padtmp = 0, tails = 0, ranks_dev = 0;
+};
+
+size_t take(Layout& L, size_t bytes) {
+  const size_t off = L.total;
+  L.total += align256(bytes);
+  return off;
+}
+
+// Capacities and the level-tensor chain sizes for a configuration.
+void capacities(const Tree& tree, const std::vector<int64_t>& n, int rank_cap, std::vector<int64_t>& alpha_cap,
+                std::vector<int>& rc) {
+  const int nn = (int)tree.nodes.size();
+  alpha_cap.assign(nn, 0);
+  rc.assign(nn, 0);
+  for (int ell = tree.depth; ell >= 0; --ell) {
+    for (int i = 0; i < nn; ++i) {
+      const TNode& t = tree.nodes[i];
+      if (t.layer != ell) continue;
+      if (t.leaf())
+        alpha_cap[i] = n[t.lo];
+      else
+        alpha_cap[i] = (int64_t)rc[t.child[0]] * rc[t.child[1]];
+      rc[i] = (int)std::min<int64_t>(rank_cap, alpha_cap[i]);
+    }
+  }
+}
+
+// Largest intermediate of the projection chains at capacity (elements, FP64),
+// and the largest level tensor entering any layer (for the residual buffer).
+void chain_sizes(const Tree& tree, const std::vector<int64_t>& n, const std::vector<int64_t>& alpha_cap,
+                 const std::vector<int>& rc, int64_t N, size_t& max_inter, size_t& max_level) {
+  max_inter = 1;
+  max_level = 1;
+  for (int ell = tree.depth; ell >= 1; --ell) {
+    const std::vector<int> f = tree.frontier(ell);
+    std::vector<int64_t> sz(f.size());
+    for (size_t k = 0; k < f.size(); ++k) {
+      const TNode& t = tree.nodes[f[k]];
+      sz[k] = t.leaf() ? n[t.lo] : alpha_cap[f[k]];
+    }
+    auto total = [&]() {
+      size_t p = (size_t)N;
+      for (int64_t s : sz) p *= (size_t)s;
+      return p;
+    };
+    max_level = std::max(max_level, total());
+    for (size_t k = 0; k < f.size(); ++k) {
+      if (tree.nodes[f[k]].layer != ell) continue;
+      sz[k] = rc[f[k]];
+      max_inter = std::max(max_inter, total());
+    }
+  }
+}
+
+bool valid_config(const ht_config* c, std::string& why) {
+  if (c == nullptr) return why = "cfg is NULL", false;
+  if (c->d < 2 || c->d > 64) return why = "d must lie in [2, 64]", false;
+  if (c->n == nullptr) return why = "cfg->n is NULL", false;
+  for (int i = 0; i < c->d; ++i)
+    if (c->n[i] < 1 || c->n[i] > (int64_t)1 << 31) return why = "mode sizes must lie in [1, 2^31]", false;
+  if (!(c->eps_rel > 0.0 && c->eps_rel < 1.0)) return why = "eps_rel must lie in (0, 1)", false;
+  if (c->rank_cap < 1 || c->rank_cap > 64) return why = "rank_cap must lie in [1, 64]", false;
+  if (c->max_batch < 1) return why = "max_batch must be >= 1", false;
+  if (c->n_cap < 1) return why = "n_cap must be >= 1", false;
+  if (c->prec != HT_FP64) return why = "only HT_FP64 is available", false;
+  if (c->in_dtype != HT_F32 && c->in_dtype != HT_F64) return why = "in_dtype must be HT_F32 or HT_F64", false;
+  if (c->flags != 0) return why = "flags must be 0", false;
+  return true;
+}
+
+Layout make_layout(const ht_config* c, const Tree& tree, std::vector<int64_t>& alpha_cap, std::vector<int>& rc) {
+  std::vector<int64_t> n(c->n, c->n + c->d);
+  capacities(tree, n, c->rank_cap, alpha_cap, rc);
+  const int nn = (int)tree.nodes.size();
+  Layout L;
+  L.core.assign(nn, 0);
+  L.gram.assign(nn, 0);
+  L.vecs.assign(nn, 0);
+  L.evals.assign(nn, 0);
+  L.eigsc.assign(nn, 0);
+  size_t max_core = 1, gpart = 1;
+  for (int i = 1; i < nn; ++i) {
+    const size_t a = (size_t)alpha_cap[i], r = (size_t)rc[i];
+    L.core[i] = take(L, a * r * sizeof(double));
+    L.core_backup_elems += a * r;
+    max_core = std::max(max_core, a * r);
+    L.gram[i] = take(L, a * a * sizeof(double));
+    L.vecs[i] = take(L, a * r * sizeof(double));
+    L.evals[i] = take(L, a * sizeof(double));
+    L.eigsc[i] = take(L, ht::eig_scratch_doubles((int)a, (int)r) * sizeof(double));
+    // Gram partial scratch bound: at most max(512, npairs) * min(128, a)^2 doubles
+    const size_t nb = (a + 127) / 128, npairs = nb * (nb + 1) / 2, side = std::min<size_t>(128, a);
+    gpart = std::max(gpart, std::max<size_t>(512, npairs) * side * side);
+  }
+  L.core_backup = take(L, L.core_backup_elems * sizeof(double));
+  L.root = take(L, (size_t)c->n_cap * c->rank_cap * c->rank_cap * sizeof(double));
+  size_t max_inter = 1, max_level = 1;
+  chain_sizes(tree, n, alpha_cap, rc, c->max_batch, max_inter, max_level);
+  L.buf_elems = max_inter;
+  L.bufA = take(L, max_inter * sizeof(double));
+  L.bufB = take(L, max_inter * sizeof(double));
+  L.resid_elems = max_level;
+  L.resid = take(L, max_level * sizeof(double));
+  L.bufZ = take(L, max_level * sizeof(double));
+  L.gpart = take(L, gpart * sizeof(double));
+  L.scal = take(L, 64 * sizeof(double));
+  L.sspart = take(L, ht::kSumsqBlocks * sizeof(double));
+  L.orthsc = take(L, ht::orth_scratch_doubles(64) * sizeof(double));
+  L.padtmp = take(L, max_core * sizeof(double));
+  L.tails = take(L, (size_t)nn * sizeof(double));
+  L.ranks_dev = take(L, (size_t)nn * sizeof(int));
+  return L;
+}
+
+int64_t prod(const std::vector<int64_t>& v, size_t lo, size_t hi) {
+  int64_t p = 1;
+  for (size_t i = lo; i < hi; ++i) p *= v[i];
+  return p;
+}
+
+// A level tensor: data pointer, element type, batch size and mode sizes (C order).
+struct Level {
+  const void* ptr;
+  Elem t;
+  int64_t N;
+  std::vector<int64_t> modes;
+  size_t elems() const { return (size_t)N * (size_t)prod(modes, 0, modes.size()); }
+};
+
+ModeView view_of(const Level& L, size_t k) {
+  ModeView v;
+  v.P = L.N * prod(L.modes, 0, k);
+  v.m = L.modes[k];
+  v.S = prod(L.modes, k + 1, L.modes.size());
+  return v;
+}
+
+int alpha_now(const ht_state* h, int node) {
+  const TNode& t = h->tree.nodes[node];
+  if (t.leaf()) return (int)h->n[t.lo];
+  return h->rank[t.child[0]] * h->rank[t.child[1]];
+}
+
+// Sizes of frontier(ell) before layer ell is processed.
+std::vector<int64_t> frontier_sizes(const ht_state* h, int ell) {
+  const std::vector<int> f = h->tree.frontier(ell);
+  std::vector<int64_t> s(f.size());
+  for (size_t k = 0; k < f.size(); ++k) s[k] = alpha_now(h, f[k]);
+  return s;
+}
+
+double* other(const ht_state* h, const void* p) { return p == h->bufA ? h->bufB : h->bufA; }
+
+// Contract every node of layer ell (left to right) with U^T, then merge siblings.
+Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s) {
+  const std::vector<int> f = h->tree.frontier(ell);
+  Level cur = in;
+  for (size_t k = 0; k < f.size(); ++k) {
+    const int node = f[k];
+    if (h->tree.nodes[node].layer != ell) continue;
+    double* dst = other(h, cur.ptr);
+    ht::ttm_contract(cur.ptr, cur.t, view_of(cur, k), h->core[node], h->rank[node], dst, s);
+    cur.ptr = dst;
+    cur.t = Elem::F64;
+    cur.modes[k] = h->rank[node];
+  }
+  // merge to the frontier of layer ell - 1 (a reshape: adjacent siblings fuse)
+  Level out = cur;
+  if (ell >= 1) out.modes = frontier_sizes(h, ell - 1 >= 1 ? ell - 1 : 1);
+  if (ell == 1) {
+    const TNode& root = h->tree.nodes[0];
+    out.modes = {h->rank[root.child[0]], h->rank[root.child[1]]};
+  }
+  return out;
+}
+
+Level project_all(const ht_state* h, const void* Y, int64_t N, hipStream_t s) {
+  Level cur{Y, h->in_t, N, h->n};
+  for (int ell = h->tree.depth; ell >= 1; --ell) cur = project_layer(h, ell, cur, s);
+  return cur;
+}
+
+ht_status sync_read(ht_state* h, hipStream_t s, const double* dev, size_t count, double* host) {
+  HT_HIP(hipMemcpyAsync(host, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
+  HT_HIP(hipStreamSynchronize(s));
+  (void)h;
+  return HT_OK;
+}
+
+ht_status check_device() {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(HT_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return fail(HT_EDEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(HT_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  return HT_OK;
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  explicit Timer(hipStream_t s_) : s(s_) {
+    if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) (void)hipEventRecord(a, s);
+  }
+  float stop() {
+    float ms = 0.f;
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      (void)hipEventSynchronize(b);
+      (void)hipEventElapsedTime(&ms, a, b);
+    }
+    return ms;
+  }
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+void backup_cores(ht_state* h, hipStream_t s) {
+  size_t off = 0;
+  for (size_t i = 1; i < h->tree.nodes.size(); ++i) {
+    const size_t n = (size_t)h->alpha_cap[i] * h->rc[i];
+    ht::copy_f64(h->core[i], h->core_backup + off, (int64_t)n, s);
+    off += n;
+  }
+}
+
+void restore_cores(ht_state* h, hipStream_t s) {
+  size_t off = 0;
+  for (size_t i = 1; i < h->tree.nodes.size(); ++i) {
+    const size_t n = (size_t)h->alpha_cap[i] * h->rc[i];
+    ht::copy_f64(h->core_backup + off, h->core[i], (int64_t)n, s);
+    off += n;
+  }
+}
+
+// One layer of rank decisions: Gram (of the data, or of the explicit residual
+// R = M - U_old U_old^T M), eigen-decomposition, truncation, expansion.
+// rmin = 1 / r_old = 0 for BHT-l2r; rmin = 0 for HT-RISE.
+ht_status decide_layer(ht_state* h, int ell, const Level& cur, double thr, bool initial, hipStream_t s,
+                       int* growth) {
+  const std::vector<int> f = h->tree.frontier(ell);
+  std::vector<ht::EigJob> jobs;
+  std::vector<int> job_node, job_rold;
+  for (size_t k = 0; k < f.size(); ++k) {
+    const int node = f[k];
+    if (h->tree.nodes[node].layer != ell) continue;
+    const ModeView v = view_of(cur, k);
+    const int alpha = (int)v.m;
+    const int r_old = initial ? 0 : h->rank[node];
+    if (alpha - r_old <= 0) continue;  // the basis already spans the whole mode
+    // at the rank cap the decision still runs (rmax = 0) to detect a needed growth
+    const int room = std::max(0, std::min(alpha, h->rank_cap) - r_old);
+    const void* gsrc = cur.ptr;
+    Elem gt = cur.t;
+    if (r_old > 0) {
+      double* z = h->bufZ;  // U_old^T M: as large as the level tensor when alpha == r_old
+      ht::ttm_contract(cur.ptr, cur.t, v, h->core[node], r_old, z, s);
+      ht::ttm_expand(z, v.P, r_old, v.S, h->core[node], v.m, cur.ptr, cur.t, h->resid, Elem::F64, s);
+      gsrc = h->resid;
+      gt = Elem::F64;
+    }
+    ht::gram(gsrc, gt, v, h->gpart, h->gram[node], s);
+    ht::EigJob j;
+    j.G = h->gram[node];
+    j.scratch = h->eigsc[node];
+    j.evals = h->evals[node];
+    j.vecs = h->vecs[node];
+    j.rank = h->ranks_dev + node;
+    j.tail = h->tails + node;
+    j.thr = thr;
+    j.k = alpha;
+    j.rmin = initial ? 1 : 0;
+    j.rmax = room;
+    j.pad = 0;
+    jobs.push_back(j);
+    job_node.push_back(node);
+    job_rold.push_back(r_old);
+  }
+  for (size_t b = 0; b < jobs.size(); b += ht::kMaxEigJobs)
+    ht::eig_trunc(jobs.data() + b, (int)std::min<size_t>(ht::kMaxEigJobs, jobs.size() - b), s);
+  HT_HIP(hipGetLastError());
+  // read back the decisions of this layer
+  const int nn = (int)h->tree.nodes.size();
+  std::vector<int> rk(nn, 0);
+  std::vector<double> tl(nn, 0.0);
+  HT_HIP(hipMemcpyAsync(rk.data(), h->ranks_dev, nn * sizeof(int), hipMemcpyDeviceToHost, s));
+  HT_HIP(hipMemcpyAsync(tl.data(), h->tails, nn * sizeof(double), hipMemcpyDeviceToHost, s));
+  HT_HIP(hipStreamSynchronize(s));
+  for (size_t q = 0; q < jobs.size(); ++q) {
+    const int node = job_node[q];
+    const int r = rk[node];
+    const int alpha = jobs[q].k;
+    const int room = jobs[q].rmax;
+    if (r == room && tl[node] > thr && job_rold[q] + room < alpha)
+      return fail(HT_ERANKCAP, "rank of node " + std::to_string(node) + " would exceed rank_cap " +
+                                   std::to_string(h->rank_cap));
+    if (!std::isfinite(tl[node])) return fail(HT_ENUMERIC, "non-finite eigenvalues at node " + std::to_string(node));
+  }
+  // expansion: [U_old, U_R] with U_R re-orthogonalised, then parents padded
+  std::vector<int> old_rank = h->rank;
+  for (size_t q = 0; q < jobs.size(); ++q) {
+    const int node = job_node[q];
+    const int r = rk[node];
+    if (r == 0) continue;
+    ht::orth_expand(h->core[node], jobs[q].k, job_rold[q], h->vecs[node], r, h->core[node], h->orthsc, s);
+    h->rank[node] = job_rold[q] + r;
+    *growth += initial ? 0 : r;
+  }
+  // padWithZeros on every parent whose successors grew (the root's capacity layout pads itself)
+  for (size_t q = 0; q < jobs.size(); ++q) {
+    const int node = job_node[q];
+    const int par = h->tree.nodes[node].parent;
+    if (par <= 0 || initial) continue;
+    if (h->tree.nodes[node].child_pos != 0 &&
+        std::find(job_node.begin(), job_node.end(), h->tree.nodes[par].child[0]) != job_node.end())
+      continue;  // parent handled once, at its first successor
+    const int a = h->tree.nodes[par].child[0], b = h->tree.nodes[par].child[1];
+    const int ra = old_rank[a], rb = old_rank[b], ra2 = h->rank[a], rb2 = h->rank[b];
+    if (ra == ra2 && rb == rb2) continue;
+    const int rp = h->rank[par];
+    ht::pad_core(h->core[par], ra, rb, rp, h->padtmp, ra2, rb2, s);
+    ht::copy_f64(h->padtmp, h->core[par], (int64_t)ra2 * rb2 * rp, s);
+  }
+  HT_HIP(hipGetLastError());
+  return HT_OK;
+}
+
+ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state** out) {
+  std::string why;
+  if (!valid_config(cfg, why)) return fail(HT_EINVAL, why);
+  if (ws == nullptr) return fail(HT_EINVAL, "ws is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(HT_EINVAL, "ws must be 256-byte aligned");
+  ht_state* h = new (std::nothrow) ht_state();
+  if (h == nullptr) return fail(HT_ENOMEM, "host allocation failed");
+  h->d = cfg->d;
+  h->n.assign(cfg->n, cfg->n + cfg->d);
+  h->eps = cfg->eps_rel;
+  h->rank_cap = cfg->rank_cap;
+  h->max_batch = cfg->max_batch;
+  h->n_cap = cfg->n_cap;
+  h->in_t = cfg->in_dtype == HT_F32 ? Elem::F32 : Elem::F64;
+  h->tree.build(cfg->d);
+  Layout L = make_layout(cfg, h->tree, h->alpha_cap, h->rc);
+  if (ws_bytes < L.total) {
+    delete h;
+    return fail(HT_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes, " + std::to_string(L.total) +
+                               " needed");
+  }
+  char* base = static_cast<char*>(ws);
+  h->ws = base;
+  h->ws_bytes = ws_bytes;
+  const int nn = (int)h->tree.nodes.size();
+  h->core.assign(nn, nullptr);
+  h->gram.assign(nn, nullptr);
+  h->vecs.assign(nn, nullptr);
+  h->evals.assign(nn, nullptr);
+  h->eigsc.assign(nn, nullptr);
+  for (int i = 1; i < nn; ++i) {
+    h->core[i] = reinterpret_cast<double*>(base + L.core[i]);
+    h->gram[i] = reinterpret_cast<double*>(base + L.gram[i]);
+    h->vecs[i] = reinterpret_cast<double*>(base + L.vecs[i]);
+    h->evals[i] = reinterpret_cast<double*>(base + L.evals[i]);
+    h->eigsc[i] = reinterpret_cast<double*>(base + L.eigsc[i]);
+  }
+  h->core_backup = reinterpret_cast<double*>(base + L.core_backup);
+  h->core_backup_elems = L.core_backup_elems;
+  h->root = reinterpret_cast<double*>(base + L.root);
+  h->bufA = reinterpret_cast<double*>(base + L.bufA);
+  h->bufB = reinterpret_cast<double*>(base + L.bufB);
+  h->resid = reinterpret_cast<double*>(base + L.resid);
+  h->bufZ = reinterpret_cast<double*>(base + L.bufZ);
+  h->gpart = reinterpret_cast<double*>(base + L.gpart);
+  h->scal = reinterpret_cast<double*>(base + L.scal);
+  h->sspart = reinterpret_cast<double*>(base + L.sspart);
+  h->orthsc = reinterpret_cast<double*>(base + L.orthsc);
+  h->padtmp = reinterpret_cast<double*>(base + L.padtmp);
+  h->tails = reinterpret_cast<double*>(base + L.tails);
+  h->ranks_dev = reinterpret_cast<int*>(base + L.ranks_dev);
+  h->rank.assign(nn, 0);
+  h->h_scal.assign(8, 0.0);
+  *out = h;
+  return HT_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* ht_status_str(ht_status s) {
+  switch (s) {
+    case HT_OK: return "ok";
+    case HT_EINVAL: return "invalid argument";
+    case HT_ESHAPE: return "batch or accumulation exceeds the configured capacity";
+    case HT_ENOMEM: return "workspace too small";
+    case HT_ERANKCAP: return "rank capacity exceeded";
+    case HT_EDEVICE: return "device or HIP runtime error";
+    case HT_ENUMERIC: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+const char* ht_last_error(void) { return g_last_error.c_str(); }
+
+ht_status ht_workspace_bytes(const ht_config* cfg, size_t* bytes) {
+  std::string why;
+  if (bytes == nullptr) return fail(HT_EINVAL, "bytes is NULL");
+  if (!valid_config(cfg, why)) return fail(HT_EINVAL, why);
+  Tree t;
+  t.build(cfg->d);
+  std::vector<int64_t> ac;
+  std::vector<int> rc;
+  *bytes = make_layout(cfg, t, ac, rc).total;
+  return HT_OK;
+}
+
+ht_status ht_init_batch(const ht_config* cfg, void* ws, size_t ws_bytes, const void* Y, int64_t N, void* hip_stream,
+                        ht_handle* out, ht_update_info* info) {
+  g_last_error.clear();
+  if (out == nullptr) return fail(HT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (Y == nullptr) return fail(HT_EINVAL, "Y is NULL");
+  std::string why;
+  if (!valid_config(cfg, why)) return fail(HT_EINVAL, why);
+  if (N < 1) return fail(HT_EINVAL, "N must be >= 1");
+  if (N > cfg->max_batch) return fail(HT_ESHAPE, "N exceeds max_batch");
+  if (N > cfg->n_cap) return fail(HT_ESHAPE, "N exceeds n_cap");
+  ht_status st = check_device();
+  if (st != HT_OK) return st;
+  ht_state* h = nullptr;
+  st = setup_handle(cfg, ws, ws_bytes, &h);
+  if (st != HT_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  h->last_stream = s;
+  Timer timer(s);
+  const int64_t E = N * prod(h->n, 0, h->n.size());
+  ht::sumsq(Y, h->in_t, E, h->sspart, h->scal, s);
+  st = sync_read(h, s, h->scal, 1, h->h_scal.data());
+  if (st != HT_OK) {
+    delete h;
+    return st;
+  }
+  const double ny2 = h->h_scal[0];
+  if (!std::isfinite(ny2)) {
+    delete h;
+    return fail(HT_ENUMERIC, "||Y|| is not finite");
+  }
+  if (ny2 == 0.0) {
+    delete h;
+    return fail(HT_EINVAL, "the initial batch is all zeros");
+  }
+  const double ny = std::sqrt(ny2);
+  const double eps_nw = h->eps * ny / std::sqrt(2.0 * h->d - 2.0);
+  Level cur{Y, h->in_t, N, h->n};
+  int growth = 0;
+  for (int ell = h->tree.depth; ell >= 1; --ell) {
+    st = decide_layer(h, ell, cur, eps_nw * eps_nw, true, s, &growth);
+    if (st != HT_OK) {
+      delete h;
+      return st;
+    }
+    cur = project_layer(h, ell, cur, s);
+  }
+  const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
+  ht::sumsq(cur.ptr, Elem::F64, (int64_t)cur.elems(), h->sspart, h->scal + 1, s);
+  ht::root_append(static_cast<const double*>(cur.ptr), N, r11, r12, h->root, 0, h->rank_cap, s);
+  if (hipGetLastError() != hipSuccess) {
+    delete h;
+    return fail(HT_EDEVICE, "kernel launch failed");
+  }
+  st = sync_read(h, s, h->scal + 1, 1, h->h_scal.data() + 1);
+  if (st != HT_OK) {
+    delete h;
+    return st;
+  }
+  h->n_acc = N;
+  if (info) {
+    info->skipped = 0;
+    info->rank_growth = 0;
+    for (size_t i = 1; i < h->rank.size(); ++i) info->rank_growth += h->rank[i];
+    info->norm_y = ny;
+    info->eps_des = h->eps * ny;
+    info->eps_proj = std::sqrt(std::max(0.0, ny2 - h->h_scal[1]));
+    info->device_ms = timer.stop();
+  }
+  *out = h;
+  return HT_OK;
+}
+
+ht_status ht_rise_update(ht_handle h, const void* Y, int64_t N, void* hip_stream, ht_update_info* info) {
+  g_last_error.clear();
+  if (h == nullptr) return fail(HT_EINVAL, "handle is NULL");
+  if (Y == nullptr) return fail(HT_EINVAL, "Y is NULL");
+  if (N < 1) return fail(HT_EINVAL, "N must be >= 1");
+  if (N > h->max_batch) return fail(HT_ESHAPE, "N exceeds max_batch");
+  if (h->n_acc + N > h->n_cap) return fail(HT_ESHAPE, "accumulation would exceed n_cap");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  h->last_stream = s;
+  Timer timer(s);
+  const int64_t E = N * prod(h->n, 0, h->n.size());
+  // Step 1: norms and projection onto the existing cores
+  ht::sumsq(Y, h->in_t, E, h->sspart, h->scal, s);
+  Level c1 = project_all(h, Y, N, s);
+  ht::sumsq(c1.ptr, Elem::F64, (int64_t)c1.elems(), h->sspart, h->scal + 1, s);
+  ht_status st = sync_read(h, s, h->scal, 2, h->h_scal.data());
+  if (st != HT_OK) return st;
+  const double ny2 = h->h_scal[0], c2 = h->h_scal[1];
+  if (!std::isfinite(ny2) || !std::isfinite(c2)) return fail(HT_ENUMERIC, "non-finite norm");
+  const double ny = std::sqrt(ny2);
+  const double eps_des = h->eps * ny;
+  const double eps_proj = std::sqrt(std::max(0.0, ny2 - c2));
+  const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
+  int growth = 0;
+  if (eps_proj <= eps_des) {
+    ht::root_append(static_cast<const double*>(c1.ptr), N, r11, r12, h->root, h->n_acc, h->rank_cap, s);
+    HT_HIP(hipGetLastError());
+  } else {
+    const std::vector<int> saved = h->rank;
+    backup_cores(h, s);
+    const double eps_nw = eps_des / std::sqrt(2.0 * h->d - 2.0);
+    Level cur{Y, h->in_t, N, h->n};
+    for (int ell = h->tree.depth; ell >= 1; --ell) {
+      st = decide_layer(h, ell, cur, eps_nw * eps_nw, false, s, &growth);
+      if (st != HT_OK) {
+        restore_cores(h, s);
+        h->rank = saved;
+        (void)hipStreamSynchronize(s);
+        return st;
+      }
+      cur = project_layer(h, ell, cur, s);
+    }
+    const int q11 = h->rank[h->tree.nodes[0].child[0]], q12 = h->rank[h->tree.nodes[0].child[1]];
+    ht::root_append(static_cast<const double*>(cur.ptr), N, q11, q12, h->root, h->n_acc, h->rank_cap, s);
+    HT_HIP(hipGetLastError());
+  }
+  h->n_acc += N;
+  const float ms = timer.stop();
+  HT_HIP(hipGetLastError());
+  if (info) {
+    info->skipped = eps_proj <= eps_des ? 1 : 0;
+    info->rank_growth = growth;
+    info->norm_y = ny;
+    info->eps_des = eps_des;
+    info->eps_proj = eps_proj;
+    info->device_ms = ms;
+  }
+  return HT_OK;
+}
+
+ht_status ht_project(ht_handle h, const void* Y, int64_t N, void* latent, void* hip_stream) {
+  g_last_error.clear();
+  if (h == nullptr || Y == nullptr || latent == nullptr) return fail(HT_EINVAL, "NULL argument");
+  if (N < 1) return fail(HT_EINVAL, "N must be >= 1");
+  if (N > h->max_batch) return fail(HT_ESHAPE, "N exceeds max_batch");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  h->last_stream = s;
+  Level c1 = project_all(h, Y, N, s);
+  ht::copy_f64(static_cast<const double*>(c1.ptr), static_cast<double*>(latent), (int64_t)c1.elems(), s);
+  HT_HIP(hipGetLastError());
+  HT_HIP(hipStreamSynchronize(s));
+  return HT_OK;
+}
+
+ht_status ht_reconstruct(ht_handle h, int64_t first, int64_t count, void* out, int32_t dtype, void* hip_stream) {
+  g_last_error.clear();
+  if (h == nullptr || out == nullptr) return fail(HT_EINVAL, "NULL argument");
+  if (dtype != HT_F32 && dtype != HT_F64) return fail(HT_EINVAL, "dtype must be HT_F32 or HT_F64");
+  if (first < 0 || count < 0 || first + count > h->n_acc) return fail(HT_EINVAL, "sample range out of bounds");
+  if (count == 0) return HT_OK;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  h->last_stream = s;
+  const Elem ot = dtype == HT_F32 ? Elem::F32 : Elem::F64;
+  const size_t esz = dtype == HT_F32 ? 4 : 8;
+  const int64_t per = prod(h->n, 0, h->n.size());
+  const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
+  for (int64_t c0 = 0; c0 < count; c0 += h->max_batch) {
+    const int64_t cn = std::min<int64_t>(h->max_batch, count - c0);
+    ht::root_extract(h->root, first + c0, cn, r11, r12, h->rank_cap, h->bufA, s);
+    Level cur{h->bufA, Elem::F64, cn, {r11, r12}};
+    char* dst_final = static_cast<char*>(out) + (size_t)c0 * per * esz;
+    for (int ell = 1; ell <= h->tree.depth; ++ell) {
+      const std::vector<int> f = h->tree.frontier(ell);
+      // split merged modes: sizes of frontier(ell) after its layer is processed
+      std::vector<int64_t> sz(f.size());
+      for (size_t k = 0; k < f.size(); ++k) {
+        const TNode& t = h->tree.nodes[f[k]];
+        sz[k] = (t.layer == ell) ? h->rank[f[k]] : h->n[t.lo];
+      }
+      cur.modes = sz;
+      // expand right to left (the reverse of the projection order)
+      int last_k = -1;
+      for (size_t k = 0; k < f.size(); ++k)
+        if (h->tree.nodes[f[k]].layer == ell) last_k = (int)k;
+      for (int k = (int)f.size() - 1; k >= 0; --k) {
+        const int node = f[k];
+        if (h->tree.nodes[node].layer != ell) continue;
+        int64_t first_k = -1;
+        for (size_t q = 0; q < f.size(); ++q)
+          if (h->tree.nodes[f[q]].layer == ell) {
+            first_k = (int64_t)q;
+            break;
+          }
+        const int64_t alpha = alpha_now(h, node);
+        const ModeView v = view_of(cur, (size_t)k);
+        const bool final_step = (ell == h->tree.depth) && (k == first_k);
+        void* dst = final_step ? static_cast<void*>(dst_final) : static_cast<void*>(other(h, cur.ptr));
+        ht::ttm_expand(static_cast<const double*>(cur.ptr), v.P, h->rank[node], v.S, h->core[node], alpha, nullptr,
+                       Elem::F64, dst, final_step ? ot : Elem::F64, s);
+        cur.ptr = dst;
+        cur.modes[k] = alpha;
+      }
+      (void)last_k;
+      if (ell < h->tree.depth) {
+        // alpha of a transfer node splits into its successors' ranks: frontier(ell+1) sizes
+        std::vector<int> f2 = h->tree.frontier(ell + 1);
+        std::vector<int64_t> s2(f2.size());
+        for (size_t k = 0; k < f2.size(); ++k) {
+          const TNode& t = h->tree.nodes[f2[k]];
+          s2[k] = (t.layer == ell + 1) ? h->rank[f2[k]] : h->n[t.lo];
+        }
+        cur.modes = s2;
+      }
+    }
+    if (h->tree.depth == 0) return fail(HT_EINVAL, "degenerate tree");
+  }
+  HT_HIP(hipGetLastError());
+  HT_HIP(hipStreamSynchronize(s));
+  return HT_OK;
+}
+
+ht_status ht_query_ranks(ht_handle h, int32_t* ranks, int32_t cap, int32_t* n_ranks, int64_t* n_accum) {
+  g_last_error.clear();
+  if (h == nullptr) return fail(HT_EINVAL, "handle is NULL");
+  const int nr = (int)h->tree.nodes.size() - 1;
+  if (ranks != nullptr && cap < nr) return fail(HT_EINVAL, "cap smaller than 2d-2");
+  const hipError_t e = hipStreamSynchronize(h->last_stream);
+  if (e != hipSuccess) return fail(HT_EDEVICE, hipGetErrorString(e));
+  if (ranks != nullptr)
+    for (int i = 0; i < nr; ++i) ranks[i] = h->rank[i + 1];
+  if (n_ranks) *n_ranks = nr;
+  if (n_accum) *n_accum = h->n_acc;
+  return HT_OK;
+}
+
+ht_status ht_export_cores(ht_handle h, double* host_buf, size_t bytes, size_t* needed) {
+  g_last_error.clear();
+  if (h == nullptr) return fail(HT_EINVAL, "handle is NULL");
+  const int nn = (int)h->tree.nodes.size();
+  const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
+  size_t total = 0;
+  for (int i = 1; i < nn; ++i) total += (size_t)alpha_now(h, i) * h->rank[i];
+  total += (size_t)h->n_acc * r11 * r12;
+  if (needed) *needed = total * sizeof(double);
+  if (host_buf == nullptr) return HT_OK;
+  if (bytes < total * sizeof(double)) return fail(HT_ENOMEM, "export buffer too small");
+  hipStream_t s = h->last_stream;
+  HT_HIP(hipStreamSynchronize(s));
+  size_t off = 0;
+  for (int i = 1; i < nn; ++i) {
+    const size_t n = (size_t)alpha_now(h, i) * h->rank[i];
+    HT_HIP(hipMemcpy(host_buf + off, h->core[i], n * sizeof(double), hipMemcpyDeviceToHost));
+    off += n;
+  }
+  for (int64_t c0 = 0; c0 < h->n_acc; c0 += h->max_batch) {
+    const int64_t cn = std::min<int64_t>(h->max_batch, h->n_acc - c0);
+    ht::root_extract(h->root, c0, cn, r11, r12, h->rank_cap, h->bufA, s);
+    HT_HIP(hipStreamSynchronize(s));
+    HT_HIP(hipMemcpy(host_buf + off, h->bufA, (size_t)cn * r11 * r12 * sizeof(double), hipMemcpyDeviceToHost));
+    off += (size_t)cn * r11 * r12;
+  }
+  return HT_OK;
+}
+
+void ht_destroy(ht_handle h) { delete h; }
+
+}  // extern "C"

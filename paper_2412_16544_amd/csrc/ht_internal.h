@@ -1,0 +1,85 @@
+// Internal interface between the host driver (ht_abi.hip) and the device
+// kernels (ht_kernels.hip, ht_eig.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ht {
+
+// A mode-k view of a C-order level tensor [N][m_1]...[m_q]: P = N * prod_{i<k} m_i,
+// m = m_k, S = prod_{i>k} m_i.  Element (p, a, s) sits at (p * m + a) * S + s.  The
+// mode-k unfolding is the m x (P*S) matrix whose column c is (p, s) = divmod(c, S).
+struct ModeView {
+  int64_t P;
+  int64_t m;
+  int64_t S;
+};
+
+enum class Elem : int { F32 = 0, F64 = 1 };
+
+// ---- reductions -------------------------------------------------------------
+// Sum of squares of n elements into *out (FP64), deterministic two-level reduction.
+// partials must hold kSumsqBlocks doubles.
+constexpr int kSumsqBlocks = 1024;
+void sumsq(const void* x, Elem t, int64_t n, double* partials, double* out, hipStream_t s);
+
+// ---- Gram of a mode unfolding (FP64 MFMA) -----------------------------------
+// G (m x m, row-major, both triangles) = X_(k) X_(k)^T.  part is scratch of
+// gram_partial_doubles(view) doubles.
+size_t gram_partial_doubles(const ModeView& v);
+void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hipStream_t s);
+
+// ---- tensor-times-matrix ------------------------------------------------------
+// Z[p, r, s] = sum_a U[a, r] X[p, a, s]: mode contraction with U^T (U m x R, column-major).
+void ttm_contract(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z,
+                  hipStream_t s);
+// out[p, a, s] = sum_t U[a, t] Z[p, t, s] (mode expansion, U m x R column-major), or with
+// M given: out = M - that (the explicit residual of a projection).  out is FP64 unless
+// out_t says F32.
+void ttm_expand(const double* Z, int64_t P, int R, int64_t S, const double* U, int64_t m,
+                const void* M, Elem mt, void* out, Elem out_t, hipStream_t s);
+
+// ---- symmetric eigen-decomposition and truncation (FP64) -----------------------
+struct EigJob {
+  const double* G;     // k x k symmetric, row-major
+  double* scratch;     // eig_scratch_doubles(k, rmax) doubles
+  double* evals;       // out: k eigenvalues, descending
+  double* vecs;        // out: k x r eigenvectors (column-major, sign-normalised)
+  int* rank;           // out: chosen rank r
+  double* tail;        // out: discarded energy sum_{i>=r} max(lambda_i, 0)
+  double thr;          // eps_nw^2
+  int k;
+  int rmin;
+  int rmax;
+  int pad;
+};
+constexpr int kMaxEigJobs = 8;
+size_t eig_scratch_doubles(int k, int rmax);
+// Runs up to kMaxEigJobs independent problems in one launch (one workgroup each).
+void eig_trunc(const EigJob* jobs, int count, hipStream_t s);
+
+// ---- basis expansion (FP64) -----------------------------------------------------
+// Orthogonalises the rR columns of V (alpha x rR) against U_old (alpha x r_old) twice
+// (classical Gram-Schmidt), orthonormalises them by CholeskyQR twice, normalises signs
+// and writes [U_old, V] into core (alpha x (r_old + rR)).  core may alias U_old.
+void orth_expand(const double* U_old, int64_t alpha, int r_old, double* V, int rR, double* core,
+                 double* scratch, hipStream_t s);
+size_t orth_scratch_doubles(int rR);
+
+// ---- layout helpers ---------------------------------------------------------------
+// Zero-padding of a transfer core when a successor grows (padWithZeros): src is
+// (ra*rb) x rp column-major with row i_a*rb + i_b, dst is (ra2*rb2) x rp.
+void pad_core(const double* src, int ra, int rb, int rp, double* dst, int ra2, int rb2, hipStream_t s);
+// root[(n_acc + n) * rcap * rcap + i * rcap + j] = C1[n][i][j] for n < N, i < r11, j < r12.
+void root_append(const double* C1, int64_t N, int r11, int r12, double* root, int64_t n_acc, int rcap,
+                 hipStream_t s);
+// latent[n][i][j] = root[(first + n)][i][j] (packed r11 x r12), zero for i >= r11 etc.
+void root_extract(const double* root, int64_t first, int64_t count, int r11, int r12, int rcap,
+                  double* latent, hipStream_t s);
+void copy_f64(const double* src, double* dst, int64_t n, hipStream_t s);
+void fill_f64(double* dst, double v, int64_t n, hipStream_t s);
+
+}  // namespace ht

@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+entry point, sizes workspaces and rejects invalid arguments before touching a
+device.  No compute call is made here."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2412_16544_amd import htrise as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built_library():
+    if not os.path.exists(H.LIB_PATH):
+        from paper_2412_16544_amd import build
+        build.build()
+    return H.lib()
+
+
+def declared_functions():
+    names = []
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if hdr.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", hdr)).read()
+            names += re.findall(r"^\s*(?:ht_status|void|const char\s*\*)\s*(ht_\w+)\s*\(", text, re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert "ht_init_batch" in names and "ht_rise_update" in names and "ht_reconstruct" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", H.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(H.lib(), n)
+
+
+def test_status_strings():
+    for st in range(7):
+        assert H.ht_status_str(st)
+    assert "rank" in H.ht_status_str(H.HT_ERANKCAP)
+
+
+def _ws(**kw):
+    args = dict(n=(16, 16, 16, 16), eps=1e-4, rank_cap=32, max_batch=8, n_cap=64)
+    args.update(kw)
+    cfg, keep = H.make_config(args["n"], args["eps"], args["rank_cap"], args["max_batch"], args["n_cap"],
+                              args.get("prec", H.HT_FP64), args.get("in_dtype", H.HT_F32), args.get("flags", 0))
+    return H.ht_workspace_bytes(cfg)
+
+
+def test_workspace_sizing_is_monotone():
+    a = _ws()
+    assert a > 0
+    assert _ws(max_batch=16) > a
+    assert _ws(n_cap=1024) > a
+    assert _ws(rank_cap=8) < a
+
+
+@pytest.mark.parametrize("kw", [dict(n=(16,)), dict(eps=0.0), dict(eps=1.0), dict(n=(16, 0, 3)),
+                                dict(rank_cap=0), dict(rank_cap=65), dict(max_batch=0), dict(n_cap=0),
+                                dict(prec=7), dict(in_dtype=5), dict(flags=1)])
+def test_invalid_configs_rejected(kw):
+    with pytest.raises(H.HTError) as e:
+        _ws(**kw)
+    assert e.value.status == H.HT_EINVAL
+    assert H.lib().ht_last_error().decode()
+
+
+def test_null_arguments_rejected_before_device_work():
+    L = H.lib()
+    cfg, keep = H.make_config((4, 4), 1e-3, 4, 2, 4)
+    h = ctypes.c_void_p(0)
+    info = H.ht_update_info()
+    # NULL batch
+    assert L.ht_init_batch(ctypes.byref(cfg), None, 0, None, 2, None, ctypes.byref(h), ctypes.byref(info)) == H.HT_EINVAL
+    # NULL out handle
+    assert L.ht_init_batch(ctypes.byref(cfg), None, 0, 1, 2, None, None, ctypes.byref(info)) == H.HT_EINVAL
+    # N out of range
+    assert L.ht_init_batch(ctypes.byref(cfg), None, 0, 1, 0, None, ctypes.byref(h), None) == H.HT_EINVAL
+    assert L.ht_init_batch(ctypes.byref(cfg), None, 0, 1, 3, None, ctypes.byref(h), None) == H.HT_ESHAPE
+    # calls on a NULL handle
+    assert L.ht_rise_update(None, 1, 1, None, None) == H.HT_EINVAL
+    assert L.ht_reconstruct(None, 0, 1, 1, H.HT_F64, None) == H.HT_EINVAL
+    assert L.ht_project(None, 1, 1, 1, None) == H.HT_EINVAL
+    assert L.ht_query_ranks(None, None, 0, None, None) == H.HT_EINVAL
+    assert L.ht_export_cores(None, None, 0, None) == H.HT_EINVAL
+    L.ht_destroy(None)
+
+
+def test_binding_refuses_missing_library(monkeypatch):
+    monkeypatch.setattr(H, "_lib", None)
+    monkeypatch.setattr(H, "LIB_PATH", "/nonexistent/libhtrise.so")
+    with pytest.raises(RuntimeError):
+        H.lib()

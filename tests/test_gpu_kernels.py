@@ -1,0 +1,146 @@
+"""Kernel-level parity of the HIP library with NumPy FP64, through the C ABI test entry points."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2412_16544_amd import htrise as H  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def unfold_np(x, P, m, S):
+    return x.reshape(P, m, S).transpose(1, 0, 2).reshape(m, P * S)
+
+
+@pytest.mark.parametrize("n,dtype", [(1, np.float32), (1000, np.float64), (1 << 20, np.float32), (3_000_001, np.float64)])
+def test_sumsq(n, dtype):
+    x = rng(1).standard_normal(n).astype(dtype)
+    got = H.ht_test_sumsq(torch.from_numpy(x).cuda()).item()
+    ref = float(np.sum(x.astype(np.float64) ** 2))
+    assert got == pytest.approx(ref, rel=1e-13)
+
+
+GRAM_SHAPES = [(1, 1, 1), (3, 96, 1000), (5, 3, 7), (100, 16, 1), (2, 200, 33), (1, 130, 40), (7, 17, 5),
+               (4, 256, 3), (9, 40, 64), (1, 300, 2)]
+
+
+@pytest.mark.parametrize("P,m,S", GRAM_SHAPES)
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_gram(P, m, S, dtype):
+    x = rng(P * 1000 + m + S).standard_normal(P * m * S).astype(dtype)
+    G = H.ht_test_gram(torch.from_numpy(x).cuda(), P, m, S).cpu().numpy()
+    M = unfold_np(x.astype(np.float64), P, m, S)
+    ref = M @ M.T
+    assert np.max(np.abs(G - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("P,m,S,R", [(3, 96, 1000, 12), (5, 3, 7, 3), (100, 16, 1, 5), (2, 200, 33, 64),
+                                     (1, 130, 40, 17), (7, 17, 5, 1), (4, 64, 300, 16), (50, 9, 1, 9)])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_ttm_contract(P, m, S, R, dtype):
+    g = rng(P + m + S + R)
+    x = g.standard_normal(P * m * S).astype(dtype)
+    U = g.standard_normal((m, R))
+    Z = H.ht_test_ttm_contract(torch.from_numpy(x).cuda(), P, m, S, torch.from_numpy(U).cuda()).cpu().numpy()
+    ref = np.einsum("ar,pas->prs", U, x.astype(np.float64).reshape(P, m, S))
+    assert np.max(np.abs(Z - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("P,R,S,m", [(3, 12, 1000, 96), (5, 3, 7, 3), (100, 5, 1, 16), (2, 64, 33, 200),
+                                     (1, 17, 40, 130), (7, 1, 5, 17)])
+@pytest.mark.parametrize("with_m", [False, True])
+def test_ttm_expand(P, R, S, m, with_m):
+    g = rng(P + m + S + R + 7)
+    Z = g.standard_normal((P, R, S))
+    U = g.standard_normal((m, R))
+    M = g.standard_normal((P, m, S)).astype(np.float32) if with_m else None
+    out = H.ht_test_ttm_expand(torch.from_numpy(Z).cuda(), torch.from_numpy(U).cuda(),
+                               None if M is None else torch.from_numpy(M).cuda()).cpu().numpy()
+    ref = np.einsum("ar,prs->pas", U, Z)
+    if with_m:
+        ref = M.astype(np.float64) - ref
+    assert np.max(np.abs(out - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_ttm_expand_float32_output():
+    g = rng(3)
+    Z = g.standard_normal((4, 6, 50))
+    U = g.standard_normal((20, 6))
+    out = H.ht_test_ttm_expand(torch.from_numpy(Z).cuda(), torch.from_numpy(U).cuda(), out_dtype=torch.float32)
+    ref = np.einsum("ar,prs->pas", U, Z).astype(np.float32)
+    np.testing.assert_array_equal(out.cpu().numpy(), ref)
+
+
+def psd_with_spectrum(k, lam, seed):
+    q = np.linalg.qr(rng(seed).standard_normal((k, k)))[0]
+    return (q * lam[None, :]) @ q.T, q
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 16, 40, 96, 132, 133, 200, 300])
+def test_eig_spectrum_and_vectors(k):
+    lam = np.logspace(0, -12, k) if k > 1 else np.array([2.0])
+    G, q = psd_with_spectrum(k, lam, k)
+    thr = 0.5 * np.sum(lam[k // 2:]) + 0.5 * np.sum(lam[k // 2 + 1:]) if k > 1 else 0.0
+    ev, vecs, r, tail = H.ht_test_eig(torch.from_numpy(G).cuda(), 1, k, thr)
+    ev = ev.cpu().numpy()
+    ref = np.sort(np.linalg.eigvalsh(G))[::-1]
+    assert np.max(np.abs(ev - ref)) <= 1e-13 * ref[0] * max(1, k / 16)
+    # truncation rule against the reference spectrum: tail after k//2 is <= thr < tail after k//2 - 1
+    assert r == (k // 2 + 1 if k > 1 else 1)
+    v = vecs.cpu().numpy()
+    assert np.linalg.norm(v.T @ v - np.eye(r)) < 1e-12
+    resid = G @ v - v * ev[:r][None, :]
+    assert np.max(np.abs(resid)) <= 1e-12 * ref[0]
+    piv = np.argmax(np.abs(v), axis=0)
+    assert np.all(v[piv, np.arange(r)] > 0)
+
+
+@pytest.mark.parametrize("k", [8, 96, 150])
+def test_eig_rank_rule_exact_boundary(k):
+    lam = np.concatenate([np.linspace(10, 1, 5), np.full(k - 5, 1e-6)])
+    G, _ = psd_with_spectrum(k, lam, 5 + k)
+    thr = (k - 5) * 1e-6 * 1.5
+    _, _, r, tail = H.ht_test_eig(torch.from_numpy(G).cuda(), 1, k, thr)
+    assert r == 5
+    assert tail == pytest.approx((k - 5) * 1e-6, rel=1e-6)
+    _, _, r0, _ = H.ht_test_eig(torch.from_numpy(G * 0).cuda() + 0.0, 0, k, 1.0)
+    assert r0 == 0
+
+
+def test_eig_degenerate_cluster_spans_the_eigenspace():
+    k = 60
+    lam = np.concatenate([np.full(4, 3.0), np.full(3, 1.0), np.full(k - 7, 1e-9)])
+    G, q = psd_with_spectrum(k, lam, 17)
+    _, vecs, r, _ = H.ht_test_eig(torch.from_numpy(G).cuda(), 1, k, 1e-6)
+    assert r == 7
+    v = vecs.cpu().numpy()
+    P = v @ v.T
+    Pref = q[:, :7] @ q[:, :7].T
+    assert np.linalg.norm(P - Pref) < 1e-10
+
+
+@pytest.mark.parametrize("alpha,r_old,rR", [(96, 12, 3), (16, 0, 4), (200, 40, 8), (9, 4, 5)])
+def test_orth_expand(alpha, r_old, rR):
+    g = rng(alpha + r_old)
+    U = np.linalg.qr(g.standard_normal((alpha, r_old)))[0] if r_old else None
+    V = g.standard_normal((alpha, rR))
+    if U is not None:
+        V = V - U @ (U.T @ V) + 1e-9 * (U @ g.standard_normal((r_old, rR)))
+    core = H.ht_test_orth_expand(None if U is None else torch.from_numpy(U).cuda(), torch.from_numpy(V).cuda())
+    core = core.cpu().numpy()
+    assert np.linalg.norm(core.T @ core - np.eye(r_old + rR)) < 1e-13
+    if U is not None:
+        np.testing.assert_array_equal(core[:, :r_old], U)
+    new = core[:, r_old:]
+    # same span as V projected off U
+    Vp = V if U is None else V - U @ (U.T @ V)
+    Q = np.linalg.qr(Vp)[0]
+    assert np.linalg.norm(Q @ (Q.T @ new) - new) < 1e-12
+    piv = np.argmax(np.abs(new), axis=0)
+    assert np.all(new[piv, np.arange(rR)] > 0)

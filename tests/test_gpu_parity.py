@@ -1,0 +1,276 @@
+"""GPU (MI355X) parity of the HIP library with the FP64 oracle, through the C ABI.
+
+Every case feeds the same seeded float32 batches to both sides.  The bar:
+identical ranks and skip decisions at every batch; reconstructions within
+RECON_TOL of the oracle's (relative to the norm of the data); the per-batch
+error bound ||Y - Y_hat|| <= eps ||Y|| on the GPU's own reconstruction;
+orthonormal cores; unchanged reconstructions of past batches.
+
+RECON_TOL = 1e-10: both sides compute in FP64; the library takes singular
+vectors from Gram matrices (accuracy ~ u ||G|| / gap), the oracle from SVDs of
+the unfoldings, so kept directions whose eigenvalue sits near the truncation
+threshold (~eps_nw^2 ~ 1e-9 ||Y||^2) may differ by ~1e-7 in angle, weighted by
+their amplitude ~sqrt(1e-9) in the reconstruction: ~1e-11 relative.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import datagen  # noqa: E402
+from oracle import ht_oracle as ho  # noqa: E402
+from paper_2412_16544_amd import htrise as H  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+RECON_TOL = 1e-10
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def dev(y):
+    return torch.from_numpy(np.ascontiguousarray(y)).to("cuda:0")
+
+
+def run_gpu(ys, eps, rank_cap=64, n_cap=None, in_dtype="float32"):
+    N = max(y.shape[0] for y in ys)
+    n_cap = n_cap or sum(y.shape[0] for y in ys)
+    st = H.HTStream(ys[0].shape[1:], eps, rank_cap, N, n_cap, in_dtype)
+    infos, ranks = [], []
+    for y in ys:
+        yy = dev(y if in_dtype == "float32" else y.astype(np.float64))
+        infos.append(st.push(yy))
+        ranks.append(st.ranks()[0])
+    torch.cuda.synchronize()
+    return st, infos, ranks
+
+
+def run_oracle(ys, eps):
+    st = ho.BHT(ys[0].shape[1:], eps)
+    infos = [st.init_batch(ys[0])] + [st.update(y) for y in ys[1:]]
+    return st, infos
+
+
+def split_export(st_gpu, oracle_st):
+    """Cores (rank-vector order) and root from the flat export, shaped by the oracle's tree."""
+    flat = st_gpu.export()
+    ranks, nacc = st_gpu.ranks()
+    tree = oracle_st.tree
+    cores, off = {}, 0
+    for nd, r in zip(tree.non_root, ranks):
+        if nd.is_leaf:
+            rows = st_gpu.n[nd.dim]
+        else:
+            a, b = nd.children
+            rows = ranks[a - 1] * ranks[b - 1]
+        cores[nd.idx] = flat[off:off + rows * r].reshape(r, rows).T
+        off += rows * r
+    r11, r12 = ranks[0], ranks[1]
+    root = flat[off:off + nacc * r11 * r12].reshape(nacc, r11, r12)
+    return cores, root
+
+
+def check_stream(ys, eps, rank_cap=64, in_dtype="float32", cores_tol=1e-8):
+    gst, ginfo, granks = run_gpu(ys, eps, rank_cap, in_dtype=in_dtype)
+    ost, oinfo = run_oracle(ys, eps)
+    assert granks == [i.ranks for i in oinfo], (granks, [i.ranks for i in oinfo])
+    assert [i.skipped for i in ginfo[1:]] == [i.skipped for i in oinfo[1:]]
+    rec_g = gst.reconstruct().cpu().numpy()
+    rec_o = ost.reconstruct()
+    yall = np.concatenate([y.astype(np.float64) for y in ys])
+    ny = np.linalg.norm(yall)
+    assert np.linalg.norm(rec_g - rec_o) <= RECON_TOL * ny
+    off = 0
+    for y in ys:
+        e = np.linalg.norm(rec_g[off:off + y.shape[0]] - y.astype(np.float64))
+        assert e <= eps * np.linalg.norm(y.astype(np.float64))
+        off += y.shape[0]
+    cores, root = split_export(gst, ost)
+    for idx, u in cores.items():
+        assert np.linalg.norm(u.T @ u - np.eye(u.shape[1])) < 1e-12
+        if cores_tol is not None:
+            assert np.linalg.norm(u - ost.core[idx]) <= cores_tol * math.sqrt(u.shape[1]), idx
+    # eps_proj and norms of the skip test
+    for gi, oi in zip(ginfo, oinfo):
+        assert gi.norm_y == pytest.approx(oi.norm_y, rel=1e-12)
+        assert gi.eps_proj == pytest.approx(oi.eps_proj, rel=1e-6, abs=1e-7 * oi.norm_y)
+    return gst, ost
+
+
+# --------------------------------------------------------------------------- #
+# exact-rank streams
+# --------------------------------------------------------------------------- #
+
+
+def test_tiny_stream_parity():
+    ys = datagen.tiny_stream()
+    gst, ost = check_stream(ys, 1e-4)
+    assert gst.ranks() == ([8] * 6, 40)
+
+
+def test_tiny_stream_float64_input():
+    ys = datagen.tiny_stream(3)
+    check_stream([y.astype(np.float64) for y in ys], 1e-4, in_dtype="float64")
+
+
+def test_project_matches_oracle_latent():
+    ys = datagen.tiny_stream()
+    gst, _, _ = run_gpu(ys, 1e-4)
+    ost, _ = run_oracle(ys, 1e-4)
+    for y in ys:
+        lat_g = gst.project(dev(y)).cpu().numpy()
+        lat_o = ost.project(y)
+        assert np.linalg.norm(lat_g - lat_o) <= RECON_TOL * np.linalg.norm(lat_o)
+
+
+def test_past_stream_reconstruction_unchanged():
+    ys = datagen.tiny_stream()
+    N = ys[0].shape[0]
+    st = H.HTStream(ys[0].shape[1:], 1e-4, 64, N, 40)
+    st.push(dev(ys[0]))
+    first = st.reconstruct(0, N).cpu().numpy()
+    for y in ys[1:]:
+        st.push(dev(y))
+        again = st.reconstruct(0, N).cpu().numpy()
+        assert np.linalg.norm(again - first) <= 1e-14 * np.linalg.norm(first)
+
+
+def test_reconstruct_float32_output():
+    ys = datagen.tiny_stream(2)
+    st, _, _ = run_gpu(ys, 1e-4)
+    r64 = st.reconstruct(dtype="float64").cpu().numpy()
+    r32 = st.reconstruct(dtype="float32").cpu().numpy()
+    assert r32.dtype == np.float32
+    np.testing.assert_allclose(r32, r64.astype(np.float32), rtol=0, atol=1e-6 * np.abs(r64).max())
+
+
+@pytest.mark.parametrize("n,rank,N", [((17, 33, 5), 3, 7), ((6, 5, 7, 4, 3), 2, 1), ((40, 24), 5, 3),
+                                      ((9, 8, 7, 6, 5, 4), 2, 4)])
+def test_other_orders_and_ragged_shapes(n, rank, N):
+    spec = datagen.HTModelSpec(n=n, rank=rank, N=N, n_batches=4, seed=77, batch_seed0=7700, nu=1e-7,
+                               grow_at=(2,), grow_by=1, grow_scale=0.1)
+    ys = list(datagen.ht_model_stream(spec))
+    check_stream(ys, 1e-4)
+
+
+def test_single_sample_batches():
+    ys = [y[:1] for y in datagen.tiny_stream()]
+    check_stream(ys, 1e-4, cores_tol=None)
+
+
+def test_duplicate_and_zero_batches_skip():
+    ys = datagen.tiny_stream(1)
+    st = H.HTStream(ys[0].shape[1:], 1e-4, 64, 8, 24)
+    st.push(dev(ys[0]))
+    i1 = st.push(dev(ys[0]))
+    i2 = st.push(dev(np.zeros_like(ys[0])))
+    assert i1.skipped and i2.skipped
+    rec = st.reconstruct().cpu().numpy()
+    np.testing.assert_allclose(rec[8:16], rec[:8], rtol=0, atol=1e-12 * np.abs(rec).max())
+    assert np.all(rec[16:] == 0)
+
+
+def test_d2_closed_form():
+    g = np.random.default_rng(3)
+    s = (1.0, 0.3, 0.05, 4e-5, 1e-6)
+    a = np.linalg.qr(g.standard_normal((7, 5)))[0]
+    b = np.linalg.qr(g.standard_normal((6, 5)))[0]
+    w = np.linalg.qr(g.standard_normal((5, 5)))[0]
+    y = np.einsum("i,ni,xi,yi->nxy", np.asarray(s), w, a, b)
+    st, _, ranks = run_gpu([y.astype(np.float64)], 1e-4, in_dtype="float64")
+    assert ranks == [[3, 3]]
+    err2 = float(np.sum((st.reconstruct().cpu().numpy() - y) ** 2))
+    assert err2 == pytest.approx(4e-5 ** 2 + 1e-6 ** 2, rel=1e-6)
+
+
+# --------------------------------------------------------------------------- #
+# failure handling
+# --------------------------------------------------------------------------- #
+
+
+def test_rank_cap_exceeded_rolls_back():
+    ys = datagen.tiny_stream()
+    st = H.HTStream(ys[0].shape[1:], 1e-4, 6, 8, 40)   # batch 4 needs rank 8
+    for y in ys[:4]:
+        st.push(dev(y))
+    before_r = st.ranks()
+    before_rec = st.reconstruct().cpu().numpy()
+    with pytest.raises(H.HTError) as e:
+        st.push(dev(ys[4]))
+    assert e.value.status == H.HT_ERANKCAP
+    assert st.ranks() == before_r
+    np.testing.assert_array_equal(st.reconstruct().cpu().numpy(), before_rec)
+    info = st.push(dev(ys[1]))           # the handle still works
+    assert info.skipped and st.ranks()[1] == 40
+
+
+def test_capacity_errors():
+    ys = datagen.tiny_stream(1)
+    st = H.HTStream(ys[0].shape[1:], 1e-4, 64, 8, 8)
+    st.push(dev(ys[0]))
+    with pytest.raises(H.HTError) as e:
+        st.push(dev(ys[0]))
+    assert e.value.status == H.HT_ESHAPE
+    with pytest.raises(H.HTError) as e:
+        H.HTStream(ys[0].shape[1:], 1e-4, 64, 4, 8).push(dev(ys[0]))
+    assert e.value.status == H.HT_ESHAPE
+    with pytest.raises(H.HTError) as e:
+        H.HTStream(ys[0].shape[1:], 1e-4, 64, 8, 8).push(dev(np.zeros_like(ys[0])))
+    assert e.value.status == H.HT_EINVAL
+
+
+# --------------------------------------------------------------------------- #
+# drifting fields
+# --------------------------------------------------------------------------- #
+
+
+def test_small_field_stream_parity():
+    """24^3 x 3 grid, N = 8, 8 batches of the drifting field family: every batch vs the oracle."""
+    spec = datagen.FieldSpec(grid=(24, 24, 24), channels=3, terms=6, N=8, n_batches=8, drift=2e-3, seed=9,
+                             batch_seed0=900, nu=0.0, w_lo=0.2, w_hi=0.5)
+    ys = list(datagen.separable_field_stream(spec))
+    check_stream(ys, 1e-4, cores_tol=None)
+
+
+@pytest.fixture(scope="module")
+def field96():
+    spec = datagen.field_96_spec()
+    ys = list(datagen.separable_field_stream(spec))
+    golden = json.load(open(os.path.join(HERE, "golden", "field96_trace.json")))
+    return ys, golden
+
+
+def test_field96_full_size_ranks_and_error_bound(field96):
+    """The 96^3 x 3, N = 32, 20-batch stream at eps = 1e-4: ranks and skips equal the
+    oracle's stored trace, and every batch meets ||Y - Y_hat|| <= eps ||Y||."""
+    ys, golden = field96
+    st = H.HTStream(ys[0].shape[1:], 1e-4, 48, 32, 640)
+    for k, y in enumerate(ys):
+        yd = dev(y)
+        info = st.push(yd)
+        row = golden["batches"][k]
+        assert st.ranks()[0] == row["ranks"], k
+        if k > 0:
+            assert info.skipped == row["skipped"], k
+            assert info.eps_proj / info.norm_y == pytest.approx(row["eps_proj_rel"], rel=1e-5)
+        rec = st.reconstruct(32 * k, 32)
+        err = torch.linalg.vector_norm(rec - yd.double()).item()
+        assert err <= 1e-4 * torch.linalg.vector_norm(yd.double()).item(), k
+
+
+def test_field96_first_batches_elementwise(field96):
+    """Element-wise parity on the full-size batches the oracle finishes quickly (init + 2 updates)."""
+    ys, _ = field96
+    sub = ys[:3]
+    gst, ginfo, granks = run_gpu(sub, 1e-4, rank_cap=48, n_cap=96)
+    ost, oinfo = run_oracle(sub, 1e-4)
+    assert granks == [i.ranks for i in oinfo]
+    g = torch.Generator().manual_seed(0)
+    for k in range(3):
+        rec_g = gst.reconstruct(32 * k, 32).cpu().numpy()
+        rec_o = ost.reconstruct(32 * k, 32)
+        assert np.linalg.norm(rec_g - rec_o) <= RECON_TOL * np.linalg.norm(sub[k].astype(np.float64))
