@@ -12,7 +12,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["ht_kernels.hip", "ht_eig.hip", "ht_abi.hip", "ht_testing.hip"]
+SOURCES = ["ht_kernels.hip", "ht_eig.hip", "ht_abi.hip", "ht_testing.hip", "ht_profile.hip"]
 LIB = os.path.join(HERE, "libhtrise.so")
 ARCH = "gfx950"
 

@@ -389,6 +389,7 @@ void eig_trunc(const EigJob* jobs, int count, hipStream_t s) {
                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
     attr_set = true;
   }
+  ProfScope prof(KKind::Eig, s, 0.0, 0.0);
   eig_trunc_kernel<<<count, ET, lds, s>>>(b);
 }
 

@@ -83,3 +83,21 @@ void copy_f64(const double* src, double* dst, int64_t n, hipStream_t s);
 void fill_f64(double* dst, double v, int64_t n, hipStream_t s);
 
 }  // namespace ht
+
+namespace ht {
+// ---- optional per-kernel timing (include/ht_rise_profile.h) -----------------------
+enum class KKind : int { Sumsq = 0, Gram, TtmContract, TtmExpand, Eig, Orth, Layout, Count };
+extern bool g_prof_on;
+void prof_begin(KKind k, hipStream_t s, double flops, double bytes);
+void prof_end(hipStream_t s);
+struct ProfScope {
+  bool on;
+  hipStream_t s;
+  ProfScope(KKind k, hipStream_t s_, double flops, double bytes) : on(g_prof_on), s(s_) {
+    if (on) prof_begin(k, s, flops, bytes);
+  }
+  ~ProfScope() {
+    if (on) prof_end(s);
+  }
+};
+}  // namespace ht

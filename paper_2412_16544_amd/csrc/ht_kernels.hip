@@ -529,6 +529,7 @@ inline unsigned grid_for(int64_t n, int64_t cap = 4096) {
 // host launchers
 // ============================================================================
 void sumsq(const void* x, Elem t, int64_t n, double* partials, double* out, hipStream_t s) {
+  ProfScope prof(KKind::Sumsq, s, 2.0 * n, (double)n * (t == Elem::F32 ? 4 : 8));
   if (t == Elem::F32)
     sumsq_partial_kernel<float><<<kSumsqBlocks, 256, 0, s>>>(static_cast<const float*>(x), n, partials);
   else
@@ -543,19 +544,27 @@ size_t gram_partial_doubles(const ModeView& v) {
 
 void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hipStream_t s) {
   const GramPlan g = gram_plan(v);
+  // algorithmic work of the symmetric product: m^2 K flops, the m x K unfolding read once
+  const double K = (double)v.P * v.S, md = (double)v.m;
   dim3 grid(g.npairs, g.nsplit);
-  if (t == Elem::F32)
-    gram_partial_kernel<float><<<grid, 256, 0, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, g.nb, g.npairs,
-                                                    g.ktiles, g.kt_per_split, g.blk, part);
-  else
-    gram_partial_kernel<double><<<grid, 256, 0, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, g.nb, g.npairs,
-                                                     g.ktiles, g.kt_per_split, g.blk, part);
+  {
+    ProfScope prof(KKind::Gram, s, md * md * K, md * K * (t == Elem::F32 ? 4 : 8));
+    if (t == Elem::F32)
+      gram_partial_kernel<float><<<grid, 256, 0, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, g.nb, g.npairs,
+                                                      g.ktiles, g.kt_per_split, g.blk, part);
+    else
+      gram_partial_kernel<double><<<grid, 256, 0, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, g.nb,
+                                                       g.npairs, g.ktiles, g.kt_per_split, g.blk, part);
+  }
   const int64_t mm = v.m * v.m;
+  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
   gram_reduce_kernel<<<(unsigned)((mm + 255) / 256), 256, 0, s>>>(part, v.m, g.nb, g.npairs, g.nsplit, g.blk, G);
 }
 
 void ttm_contract(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z, hipStream_t s) {
   const int64_t K = v.P * v.S;
+  ProfScope prof(KKind::TtmContract, s, 2.0 * R * v.m * (double)K,
+                 (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8);
   const unsigned blocks = (unsigned)((K + 255) / 256);
   if (t == Elem::F32)
     ttm_contract_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R, Z);
@@ -566,6 +575,9 @@ void ttm_contract(const void* x, Elem t, const ModeView& v, const double* U, int
 void ttm_expand(const double* Z, int64_t P, int R, int64_t S, const double* U, int64_t m, const void* M, Elem mt,
                 void* out, Elem out_t, hipStream_t s) {
   const int64_t K = P * S;
+  ProfScope prof(KKind::TtmExpand, s, 2.0 * R * m * (double)K,
+                 (double)R * K * 8 + (double)m * K * (out_t == Elem::F32 ? 4 : 8) +
+                     (M ? (double)m * K * (mt == Elem::F32 ? 4 : 8) : 0.0));
   dim3 grid((unsigned)((K + 255) / 256), (unsigned)((m + 63) / 64));
   if (out_t == Elem::F32) {
     ttm_expand_kernel<double, float><<<grid, 256, 0, s>>>(Z, P, R, S, U, m, nullptr, static_cast<float*>(out));
@@ -585,16 +597,19 @@ size_t orth_scratch_doubles(int rR) { return (size_t)64 * 64 + (size_t)rR; }
 void orth_expand(const double* U_old, int64_t alpha, int r_old, double* V, int rR, double* core, double* scratch,
                  hipStream_t s) {
   if (rR <= 0) return;
+  ProfScope prof(KKind::Orth, s, 0.0, 0.0);
   orth_expand_kernel<<<1, 256, 0, s>>>(U_old, alpha, r_old, V, rR, core, scratch);
 }
 
 void pad_core(const double* src, int ra, int rb, int rp, double* dst, int ra2, int rb2, hipStream_t s) {
   const int64_t n = (int64_t)ra2 * rb2 * rp;
+  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
   pad_core_kernel<<<grid_for(n), 256, 0, s>>>(src, ra, rb, rp, dst, ra2, rb2);
 }
 
 void root_append(const double* C1, int64_t N, int r11, int r12, double* root, int64_t n_acc, int rcap, hipStream_t s) {
   const int64_t n = N * rcap * rcap;
+  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
   root_append_kernel<<<grid_for(n), 256, 0, s>>>(C1, N, r11, r12, root, n_acc, rcap);
 }
 

@@ -222,6 +222,12 @@ class HTStream:
         flat = ht_export_cores(self.h)
         return flat
 
+    def reset(self) -> None:
+        """Drops the representation; the workspace is kept for the next init_batch."""
+        if self.h:
+            ht_destroy(self.h)
+            self.h = 0
+
     def close(self) -> None:
         if self.h:
             ht_destroy(self.h)
@@ -329,3 +335,38 @@ def ht_test_orth_expand(U_old, V, stream=None):
     _check(_tlib().ht_test_orth_expand(_ptr(core), alpha, r_old, _ptr(Vcm), rR, _ptr(core), _stream(stream)),
            "ht_test_orth_expand")
     return core.t()
+
+
+# ---- optional per-kernel timing (include/ht_rise_profile.h) --------------------------------------
+class ht_kernel_stats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+def _plib():
+    L = lib()
+    if not getattr(L, "_ht_profile_ready", False):
+        L.ht_profile_enable.argtypes = [ctypes.c_int32]
+        L.ht_profile_enable.restype = ctypes.c_int
+        L.ht_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ht_kernel_stats)]
+        L.ht_profile_read.restype = ctypes.c_int
+        L.ht_profile_kind_count.restype = ctypes.c_int32
+        L.ht_profile_kind_name.argtypes = [ctypes.c_int32]
+        L.ht_profile_kind_name.restype = ctypes.c_char_p
+        L._ht_profile_ready = True
+    return L
+
+
+def ht_profile_enable(on: bool) -> None:
+    _check(_plib().ht_profile_enable(1 if on else 0), "ht_profile_enable")
+
+
+def ht_profile_read_all() -> dict:
+    L = _plib()
+    out = {}
+    for k in range(L.ht_profile_kind_count()):
+        st = ht_kernel_stats()
+        _check(L.ht_profile_read(k, ctypes.byref(st)), "ht_profile_read")
+        out[L.ht_profile_kind_name(k).decode()] = {"launches": int(st.launches), "ms": float(st.ms),
+                                                   "flops": float(st.flops), "bytes": float(st.bytes)}
+    return out
