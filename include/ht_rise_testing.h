@@ -29,6 +29,11 @@ size_t ht_test_gram_scratch_doubles(int64_t P, int64_t m, int64_t S);
 ht_status ht_test_gram(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, double* G, double* scratch,
                        void* hip_stream);
 
+/* Gram of the explicit residual R = X_(k) - U (U^T X_(k)) (Eq. compute_residual) for
+ * m <= 128 and 1 <= R <= 64, U column-major (m x R); the scratch of ht_test_gram. */
+ht_status ht_test_resid_gram(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U, int32_t R,
+                             double* G, double* scratch, void* hip_stream);
+
 /* Mode contraction with U^T (Eq. multi_index_contraction): Z[p, r, s] = sum_a U[a, r] X[p, a, s], 1 <= R <= 64. */
 ht_status ht_test_ttm_contract(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
                                int32_t R, double* Z, void* hip_stream);

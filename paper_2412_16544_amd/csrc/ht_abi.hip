@@ -139,6 +139,7 @@ struct ht_state {
   double* gpart = nullptr;
   double* scal = nullptr;
   double* sspart = nullptr;
+  double* nrmpart = nullptr;
   double* orthsc = nullptr;
   double* padtmp = nullptr;
   double* tails = nullptr;
@@ -155,7 +156,7 @@ struct Layout {
   // offsets (bytes)
   std::vector<size_t> core, gram, vecs, evals, eigsc;
   size_t core_backup = 0, core_backup_elems = 0, root = 0, bufA = 0, bufB = 0, buf_elems = 0, resid = 0, bufZ = 0,
-         resid_elems = 0, gpart = 0, scal = 0, sspart = 0, orthsc = 0, padtmp = 0, tails = 0, ranks_dev = 0;
+         resid_elems = 0, gpart = 0, scal = 0, sspart = 0, nrmpart = 0, orthsc = 0, padtmp = 0, tails = 0, ranks_dev = 0;
 };
 
 size_t take(Layout& L, size_t bytes) {
@@ -246,9 +247,7 @@ Layout make_layout(const ht_config* c, const Tree& tree, std::vector<int64_t>& a
     L.vecs[i] = take(L, a * r * sizeof(double));
     L.evals[i] = take(L, a * sizeof(double));
     L.eigsc[i] = take(L, ht::eig_scratch_doubles((int)a, (int)r) * sizeof(double));
-    // Gram partial scratch bound: at most max(512, npairs) * min(128, a)^2 doubles
-    const size_t nb = (a + 127) / 128, npairs = nb * (nb + 1) / 2, side = std::min<size_t>(128, a);
-    gpart = std::max(gpart, std::max<size_t>(512, npairs) * side * side);
+    gpart = std::max(gpart, ht::gram_partial_bound((int64_t)a));
   }
   L.core_backup = take(L, L.core_backup_elems * sizeof(double));
   L.root = take(L, (size_t)c->n_cap * c->rank_cap * c->rank_cap * sizeof(double));
@@ -263,6 +262,7 @@ Layout make_layout(const ht_config* c, const Tree& tree, std::vector<int64_t>& a
   L.gpart = take(L, gpart * sizeof(double));
   L.scal = take(L, 64 * sizeof(double));
   L.sspart = take(L, ht::kSumsqBlocks * sizeof(double));
+  L.nrmpart = take(L, std::max<size_t>(ht::ttm_norm_partials(), ht::kSumsqBlocks) * sizeof(double));
   L.orthsc = take(L, ht::orth_scratch_doubles(64) * sizeof(double));
   L.padtmp = take(L, max_core * sizeof(double));
   L.tails = take(L, (size_t)nn * sizeof(double));
@@ -310,14 +310,21 @@ std::vector<int64_t> frontier_sizes(const ht_state* h, int ell) {
 double* other(const ht_state* h, const void* p) { return p == h->bufA ? h->bufB : h->bufA; }
 
 // Contract every node of layer ell (left to right) with U^T, then merge siblings.
-Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s) {
+// With norm_out the first contraction also writes the squared norm of the input.
+Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, double* norm_out = nullptr) {
   const std::vector<int> f = h->tree.frontier(ell);
   Level cur = in;
   for (size_t k = 0; k < f.size(); ++k) {
     const int node = f[k];
     if (h->tree.nodes[node].layer != ell) continue;
     double* dst = other(h, cur.ptr);
-    ht::ttm_contract(cur.ptr, cur.t, view_of(cur, k), h->core[node], h->rank[node], dst, s);
+    if (norm_out != nullptr) {
+      ht::ttm_contract_norm(cur.ptr, cur.t, view_of(cur, k), h->core[node], h->rank[node], dst, h->nrmpart,
+                            norm_out, s);
+      norm_out = nullptr;
+    } else {
+      ht::ttm_contract(cur.ptr, cur.t, view_of(cur, k), h->core[node], h->rank[node], dst, s);
+    }
     cur.ptr = dst;
     cur.t = Elem::F64;
     cur.modes[k] = h->rank[node];
@@ -332,9 +339,12 @@ Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s) 
   return out;
 }
 
-Level project_all(const ht_state* h, const void* Y, int64_t N, hipStream_t s) {
+Level project_all(const ht_state* h, const void* Y, int64_t N, hipStream_t s, double* norm_out = nullptr) {
   Level cur{Y, h->in_t, N, h->n};
-  for (int ell = h->tree.depth; ell >= 1; --ell) cur = project_layer(h, ell, cur, s);
+  for (int ell = h->tree.depth; ell >= 1; --ell) {
+    cur = project_layer(h, ell, cur, s, norm_out);
+    norm_out = nullptr;
+  }
   return cur;
 }
 
@@ -413,16 +423,17 @@ ht_status decide_layer(ht_state* h, int ell, const Level& cur, double thr, bool 
     if (alpha - r_old <= 0) continue;  // the basis already spans the whole mode
     // at the rank cap the decision still runs (rmax = 0) to detect a needed growth
     const int room = std::max(0, std::min(alpha, h->rank_cap) - r_old);
-    const void* gsrc = cur.ptr;
-    Elem gt = cur.t;
-    if (r_old > 0) {
+    if (r_old == 0) {
+      ht::gram(cur.ptr, cur.t, v, h->gpart, h->gram[node], s);
+    } else if (v.m <= ht::kResidGramMaxM) {
+      // Gram of R = M - U_old U_old^T M, formed tile by tile in LDS (Eq. compute_residual)
+      ht::resid_gram(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], s);
+    } else {
       double* z = h->bufZ;  // U_old^T M: as large as the level tensor when alpha == r_old
       ht::ttm_contract(cur.ptr, cur.t, v, h->core[node], r_old, z, s);
       ht::ttm_expand(z, v.P, r_old, v.S, h->core[node], v.m, cur.ptr, cur.t, h->resid, Elem::F64, s);
-      gsrc = h->resid;
-      gt = Elem::F64;
+      ht::gram(h->resid, Elem::F64, v, h->gpart, h->gram[node], s);
     }
-    ht::gram(gsrc, gt, v, h->gpart, h->gram[node], s);
     ht::EigJob j;
     j.G = h->gram[node];
     j.scratch = h->eigsc[node];
@@ -535,6 +546,7 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   h->gpart = reinterpret_cast<double*>(base + L.gpart);
   h->scal = reinterpret_cast<double*>(base + L.scal);
   h->sspart = reinterpret_cast<double*>(base + L.sspart);
+  h->nrmpart = reinterpret_cast<double*>(base + L.nrmpart);
   h->orthsc = reinterpret_cast<double*>(base + L.orthsc);
   h->padtmp = reinterpret_cast<double*>(base + L.padtmp);
   h->tails = reinterpret_cast<double*>(base + L.tails);
@@ -663,9 +675,10 @@ ht_status ht_rise_update(ht_handle h, const void* Y, int64_t N, void* hip_stream
   h->last_stream = s;
   Timer timer(s);
   const int64_t E = N * prod(h->n, 0, h->n.size());
-  // Step 1: norms and projection onto the existing cores
-  ht::sumsq(Y, h->in_t, E, h->sspart, h->scal, s);
-  Level c1 = project_all(h, Y, N, s);
+  // Step 1: projection onto the existing cores; the first contraction reads all of Y
+  // and returns ||Y||^2 as well
+  (void)E;
+  Level c1 = project_all(h, Y, N, s, h->scal);
   ht::sumsq(c1.ptr, Elem::F64, (int64_t)c1.elems(), h->sspart, h->scal + 1, s);
   ht_status st = sync_read(h, s, h->scal, 2, h->h_scal.data());
   if (st != HT_OK) return st;

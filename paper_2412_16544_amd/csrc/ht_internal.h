@@ -30,12 +30,23 @@ void sumsq(const void* x, Elem t, int64_t n, double* partials, double* out, hipS
 // G (m x m, row-major, both triangles) = X_(k) X_(k)^T.  part is scratch of
 // gram_partial_doubles(view) doubles.
 size_t gram_partial_doubles(const ModeView& v);
+// upper bound of gram_partial_doubles over every view with m rows
+size_t gram_partial_bound(int64_t m);
 void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hipStream_t s);
+// Gram of the explicit residual R = X_(k) - U (U^T X_(k)) for m <= 128 (U m x R column-major,
+// R <= 64), reading X once; the same partial scratch as gram().
+constexpr int kResidGramMaxM = 128;
+void resid_gram(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,
+                hipStream_t s);
 
 // ---- tensor-times-matrix ------------------------------------------------------
 // Z[p, r, s] = sum_a U[a, r] X[p, a, s]: mode contraction with U^T (U m x R, column-major).
 void ttm_contract(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z,
                   hipStream_t s);
+// The same, also writing ||X||^2 (FP64) to norm_out; norm_part holds ttm_norm_partials() doubles.
+size_t ttm_norm_partials();
+void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z, double* norm_part,
+                       double* norm_out, hipStream_t s);
 // out[p, a, s] = sum_t U[a, t] Z[p, t, s] (mode expansion, U m x R column-major), or with
 // M given: out = M - that (the explicit residual of a projection).  out is FP64 unless
 // out_t says F32.

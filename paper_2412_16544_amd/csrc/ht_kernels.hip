@@ -97,10 +97,32 @@ __device__ __forceinline__ void tile_of(int t, bool diag, int tI, int tJ, int& t
   tj = row + rem;
 }
 
+// Column tiles: when S >= GBK a tile is GBK consecutive columns (rows strided by
+// S, each row segment contiguous), loaded by this helper into registers one tile
+// ahead; when S < GBK it is floor(GBK/S) whole slices p, one contiguous block of
+// memory, scattered straight into LDS by the kernel.
+template <typename T>
+__device__ __forceinline__ void gram_load_tile(const T* __restrict__ X, int64_t m, int64_t S, int64_t K, int64_t kt,
+                                               int tw, int64_t rowI0, int rowsI, int64_t rowJ0, int rowsJ, bool diag,
+                                               double (&ri)[GBK * GB / 256], double (&rj)[GBK * GB / 256]) {
+  constexpr int PER = GBK * GB / 256;
+  // thread owns column kk = tid % GBK of the tile and rows tid / GBK + 8 q
+  const int kk = threadIdx.x % GBK;
+  const int64_t c = kt * tw + kk;
+  const bool cv = c < K;
+  const int64_t base = cv ? col_base(c, m, S) : 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int row = threadIdx.x / GBK + q * (256 / GBK);
+    ri[q] = (cv && row < rowsI) ? ld(X, base + (rowI0 + row) * S) : 0.0;
+    rj[q] = (!diag && cv && row < rowsJ) ? ld(X, base + (rowJ0 + row) * S) : 0.0;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
                                                            int nb, int npairs, int64_t ktiles, int64_t kt_per_split,
-                                                           int64_t blk, double* __restrict__ part) {
+                                                           int64_t blk, int tw, double* __restrict__ part) {
   __shared__ double sI[GBK * GLD];
   __shared__ double sJ[GBK * GLD];
   const int pair = blockIdx.x;
@@ -136,27 +158,46 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
   const int64_t kt1 = min(ktiles, kt0 + kt_per_split);
   const int64_t rowI0 = (int64_t)bi * GB, rowJ0 = (int64_t)bj * GB;
   const double* sB = diag ? sI : sJ;
+  constexpr int PER = GBK * GB / 256;
+  const bool slab = S < GBK;
+  const int ms = (int)(m * S);
 
+  double ri[PER], rj[PER];
+  if (kt0 < kt1 && !slab)
+    gram_load_tile(X, m, S, K, kt0, tw, rowI0, rowsI, rowJ0, rowsJ, diag, ri, rj);
   for (int64_t kt = kt0; kt < kt1; ++kt) {
-    const int64_t c0 = kt * GBK;
-    for (int e = threadIdx.x; e < GBK * GB; e += 256) {
-      int kk, row;
-      if (S == 1) {
-        row = e % GB;
-        kk = e / GB;
-      } else {
-        kk = e % GBK;
-        row = e / GBK;
+    if (slab) {
+      // contiguous region of whole slices, scattered to (column, row) in LDS
+      for (int e = threadIdx.x; e < GBK * GB; e += 256) {
+        sI[(e % GBK) * GLD + e / GBK] = 0.0;
+        if (!diag) sJ[(e % GBK) * GLD + e / GBK] = 0.0;
       }
-      const int64_t c = c0 + kk;
-      double vi = 0.0, vj = 0.0;
-      if (c < K) {
-        const int64_t base = col_base(c, m, S);
-        if (row < rowsI) vi = ld(X, base + (rowI0 + row) * S);
-        if (!diag && row < rowsJ) vj = ld(X, base + (rowJ0 + row) * S);
+      __syncthreads();
+      const int64_t p0 = kt * tw / S;
+      const int64_t np = min<int64_t>(tw / S, P - p0);
+      const int64_t nvalid = np * ms;
+      const T* src = X + p0 * m * S;
+      for (int64_t q = threadIdx.x; q < nvalid; q += 256) {
+        const int pp = (int)(q / ms);
+        const int remq = (int)(q - (int64_t)pp * ms);
+        const int a = remq / (int)S;
+        const int sidx = remq - a * (int)S;
+        const int kk = pp * (int)S + sidx;
+        const double v = ld(src, q);
+        const int64_t li = a - rowI0, lj = a - rowJ0;
+        if (li >= 0 && li < rowsI) sI[kk * GLD + li] = v;
+        if (!diag && lj >= 0 && lj < rowsJ) sJ[kk * GLD + lj] = v;
       }
-      sI[kk * GLD + row] = vi;
-      if (!diag) sJ[kk * GLD + row] = vj;
+    } else {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int kk = threadIdx.x % GBK;
+        const int row = threadIdx.x / GBK + q * (256 / GBK);
+        sI[kk * GLD + row] = ri[q];
+        if (!diag) sJ[kk * GLD + row] = rj[q];
+      }
+      // prefetch the next tile while this one is multiplied
+      if (kt + 1 < kt1) gram_load_tile(X, m, S, K, kt + 1, tw, rowI0, rowsI, rowJ0, rowsJ, diag, ri, rj);
     }
     __syncthreads();
 #pragma unroll
@@ -188,6 +229,279 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
   }
 }
 
+// Gram of a unfolding with few rows (m <= kSmallM) on the vector ALUs: every
+// thread accumulates the m(m+1)/2 products of its columns, the block sums them.
+constexpr int kSmallM = 8;
+constexpr int kSmallBlocks = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(256) void gram_small_kernel(const T* __restrict__ X, int64_t m64, int64_t S, int64_t K,
+                                                         double* __restrict__ part) {
+  const int m = (int)m64;
+  double acc[kSmallM * (kSmallM + 1) / 2];
+#pragma unroll
+  for (int q = 0; q < kSmallM * (kSmallM + 1) / 2; ++q) acc[q] = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < K; c += (int64_t)gridDim.x * 256) {
+    const int64_t base = (S == 1) ? c * m : col_base(c, m, S);
+    double x[kSmallM];
+#pragma unroll
+    for (int a = 0; a < kSmallM; ++a) x[a] = a < m ? ld(X, base + (int64_t)a * S) : 0.0;
+    int q = 0;
+#pragma unroll
+    for (int a = 0; a < kSmallM; ++a)
+#pragma unroll
+      for (int b = 0; b <= a; ++b, ++q) acc[q] = fma(x[a], x[b], acc[q]);
+  }
+  __shared__ double red[4][kSmallM * (kSmallM + 1) / 2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kSmallM * (kSmallM + 1) / 2; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) red[wave][q] = v;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < kSmallM * (kSmallM + 1) / 2; q += 256)
+    part[(int64_t)blockIdx.x * (kSmallM * (kSmallM + 1) / 2) + q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+}
+
+__global__ __launch_bounds__(64) void gram_small_reduce_kernel(const double* __restrict__ part, int m, int nblk,
+                                                               double* __restrict__ G) {
+  const int e = threadIdx.x;
+  if (e >= m * m) return;
+  int a = e / m, b = e % m;
+  if (b > a) {
+    const int t = a;
+    a = b;
+    b = t;
+  }
+  const int q = a * (a + 1) / 2 + b;
+  double acc = 0.0;
+  for (int i = 0; i < nblk; ++i) acc += part[(int64_t)i * (kSmallM * (kSmallM + 1) / 2) + q];
+  G[e] = acc;
+}
+
+// --------------------------------------------------------------------------
+// Single-panel Gram for m <= 128, optionally of the explicit residual.
+// Each workgroup walks its column tiles; a tile (all m rows x 32 columns) is
+// prefetched into registers one step ahead and stored to LDS as sM[column][row].
+// With RESID the tile is first replaced, in LDS, by R = M - U (U^T M) (both
+// products on FP64 MFMA, Z = U^T M staged in LDS), so only the data is read.
+// --------------------------------------------------------------------------
+constexpr int PER_PANEL = GBK * GB / 256;     // prefetched values per thread (16)
+constexpr int ZLD = GBK + 1;
+constexpr int kTtmMaxBlocks = 4096;
+
+template <typename T>
+struct PanelLoader {
+  // S >= GBK: thread owns column kk = tid % GBK, rows tid / GBK + 8 q.
+  // S <  GBK: whole slices, entry q = tid + 256 t of the contiguous slab; its
+  //           destination (column, row) is fixed for every tile.
+  bool slab;
+  int dst[PER_PANEL];
+  __device__ void init(int64_t m, int64_t S, int tw) {
+    slab = S < GBK;
+    const int ms = (int)(m * S);
+#pragma unroll
+    for (int t = 0; t < PER_PANEL; ++t) {
+      if (slab) {
+        const int q = threadIdx.x + 256 * t;
+        const int pp = q / ms, rq = q - pp * ms;
+        const int a = rq / (int)S, sidx = rq - a * (int)S;
+        dst[t] = (q < tw * (int)m) ? (pp * (int)S + sidx) * GLD + a : -1;
+      } else {
+        const int kk = threadIdx.x % GBK, row = threadIdx.x / GBK + t * (256 / GBK);
+        dst[t] = (row < m) ? kk * GLD + row : -1;
+      }
+    }
+  }
+  // raw elements stay in registers; the conversion to FP64 happens at the LDS store,
+  // so the loads of the next tile overlap the products of the current one
+  __device__ void load(const T* __restrict__ X, int64_t P, int64_t m, int64_t S, int64_t K, int64_t kt, int tw,
+                       T (&r)[PER_PANEL]) const {
+    if (slab) {
+      const int64_t p0 = kt * tw / S;
+      const int64_t nvalid = min<int64_t>(tw / S, P - p0) * m * S;
+      const T* src = X + p0 * m * S;
+#pragma unroll
+      for (int t = 0; t < PER_PANEL; ++t) {
+        const int q = threadIdx.x + 256 * t;
+        r[t] = (dst[t] >= 0 && q < nvalid) ? src[q] : T(0);
+      }
+    } else {
+      const int kk = threadIdx.x % GBK;
+      const int64_t c = kt * tw + kk;
+      const bool cv = c < K;
+      const int64_t base = cv ? col_base(c, m, S) : 0;
+#pragma unroll
+      for (int t = 0; t < PER_PANEL; ++t) {
+        const int row = threadIdx.x / GBK + t * (256 / GBK);
+        r[t] = (cv && dst[t] >= 0) ? X[base + (int64_t)row * S] : T(0);
+      }
+    }
+  }
+  __device__ void store(double* sM, const T (&r)[PER_PANEL]) const {
+#pragma unroll
+    for (int t = 0; t < PER_PANEL; ++t)
+      if (dst[t] >= 0) sM[dst[t]] = static_cast<double>(r[t]);
+  }
+};
+
+template <typename T, bool RESID, int MT>
+__global__ __launch_bounds__(256) void gram_panel_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
+                                                         int64_t ktiles, int64_t kt_per_split, int tw,
+                                                         const double* __restrict__ U, int R,
+                                                         double* __restrict__ part) {
+  extern __shared__ double dsm[];
+  double* sM = dsm;                      // [GBK][GLD]
+  const int RP = (R + 15) & ~15;         // rank padded to the MFMA tile
+  const int ULD = RP + 1;
+  double* sU = sM + GBK * GLD;           // [128][ULD]   (RESID)
+  double* sZ = sU + GB * ULD;            // [RP][ZLD]    (RESID)
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+  const int mi = (int)m;
+  const int tI = (mi + 15) >> 4;
+  const int ntiles = tI * (tI + 1) / 2;
+  // MT upper tiles per wave, round-robin; a wave's surplus slots recompute tile (0,0)
+  int offa[MT], offb[MT];
+  bool live[MT];
+#pragma unroll
+  for (int q = 0; q < MT; ++q) {
+    const int t = wave + 4 * q;
+    int a = 0, b = 0;
+    live[q] = t < ntiles;
+    if (live[q]) tile_of(t, true, tI, tI, a, b);
+    offa[q] = a * 16 + (lane & 15);
+    offb[q] = b * 16 + (lane & 15);
+  }
+  d4 acc[MT];
+#pragma unroll
+  for (int q = 0; q < MT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+
+  // zero the panel once: entries never written by a tile stay zero
+  for (int e = threadIdx.x; e < GBK * GLD; e += 256) sM[e] = 0.0;
+  if (RESID) {
+    for (int e = threadIdx.x; e < GB * ULD; e += 256) {
+      const int a = e / ULD, t = e - (e / ULD) * ULD;
+      sU[e] = (a < mi && t < R) ? U[a + (int64_t)t * m] : 0.0;
+    }
+  }
+  PanelLoader<T> L;
+  L.init(m, S, tw);
+  const int64_t K = P * S;
+  const int64_t kt0 = (int64_t)blockIdx.x * kt_per_split;
+  const int64_t kt1 = min(ktiles, kt0 + kt_per_split);
+  T rg[PER_PANEL];
+  if (kt0 < kt1) L.load(X, P, m, S, K, kt0, tw, rg);
+  __syncthreads();
+  const int nzt = (RP >> 4) * 2;  // Z tiles: (RP/16) x (GBK/16)
+  const int nrt = tI * 2;         // R tiles: (m/16) x (GBK/16)
+  for (int64_t kt = kt0; kt < kt1; ++kt) {
+    L.store(sM, rg);
+    if (kt + 1 < kt1) L.load(X, P, m, S, K, kt + 1, tw, rg);
+    __syncthreads();
+    if (RESID) {
+      // Z = U^T M (RP x GBK)
+      for (int zt = wave; zt < nzt; zt += 4) {
+        const int zi = zt >> 1, zc = zt & 1;
+        d4 z = d4{0.0, 0.0, 0.0, 0.0};
+        const double* pa = sU + (lane >> 4) * ULD + zi * 16 + (lane & 15);
+        const double* pb = sM + (zc * 16 + (lane & 15)) * GLD + (lane >> 4);
+        for (int ks = 0; ks < tI * 16; ks += 16) {
+          double a[4], b[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            a[u] = pa[(ks + 4 * u) * ULD];
+            b[u] = pb[ks + 4 * u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) z = mfma16(a[u], b[u], z);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sZ[(zi * 16 + (lane >> 4) + 4 * v) * ZLD + zc * 16 + (lane & 15)] = z[v];
+      }
+      __syncthreads();
+      // M <- M - U Z (m x GBK), in place
+      for (int rt = wave; rt < nrt; rt += 4) {
+        const int ri = rt >> 1, rc = rt & 1;
+        d4 y = d4{0.0, 0.0, 0.0, 0.0};
+        const double* pa = sU + (ri * 16 + (lane & 15)) * ULD + (lane >> 4);
+        const double* pb = sZ + (lane >> 4) * ZLD + rc * 16 + (lane & 15);
+        for (int ks = 0; ks < RP; ks += 16) {
+          double a[4], b[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            a[u] = pa[ks + 4 * u];
+            b[u] = pb[(ks + 4 * u) * ZLD];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) y = mfma16(a[u], b[u], y);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sM[(rc * 16 + (lane & 15)) * GLD + ri * 16 + (lane >> 4) + 4 * v] -= y[v];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int ks = 0; ks < GBK; ks += 4) {
+      const int kr = (ks + (lane >> 4)) * GLD;
+      double a[MT], b[MT];
+#pragma unroll
+      for (int q = 0; q < MT; ++q) {
+        a[q] = sM[kr + offa[q]];
+        b[q] = sM[kr + offb[q]];
+      }
+#pragma unroll
+      for (int q = 0; q < MT; ++q) acc[q] = mfma16(a[q], b[q], acc[q]);
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.x * m * m;
+#pragma unroll
+  for (int q = 0; q < MT; ++q) {
+    if (live[q]) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = (offa[q] - (lane & 15)) + (lane >> 4) + 4 * v;
+        const int j = offb[q];
+        if (i < mi && j < mi) out[i * m + j] = acc[q][v];
+      }
+    }
+  }
+}
+
+// Fixed-order sum of the split partials: 16 groups of 64 lanes split the partial
+// range for 64 consecutive outputs, then add their sums in group order.
+__global__ __launch_bounds__(1024) void gram_reduce2_kernel(const double* __restrict__ part, int64_t m, int nb,
+                                                            int npairs, int nsplit, int64_t blk,
+                                                            double* __restrict__ G) {
+  __shared__ double red[16][64];
+  const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + l;
+  double acc = 0.0;
+  if (e < m * m) {
+    int64_t i = e / m, j = e - (e / m) * m;
+    int bi = (int)(i / GB), bj = (int)(j / GB);
+    int li = (int)(i - (int64_t)bi * GB), lj = (int)(j - (int64_t)bj * GB);
+    if (bi > bj || (bi == bj && (li >> 4) > (lj >> 4))) {
+      int t = bi; bi = bj; bj = t;
+      t = li; li = lj; lj = t;
+    }
+    const int pair = bi * nb - bi * (bi - 1) / 2 + (bj - bi);
+    const int ld_out = (int)min<int64_t>(GB, m);
+    const int64_t off = (int64_t)pair * blk + li * ld_out + lj;
+    for (int sp = g; sp < nsplit; sp += 16) acc += part[(int64_t)sp * npairs * blk + off];
+  }
+  red[g][l] = acc;
+  __syncthreads();
+  if (g == 0 && e < m * m) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += red[q][l];
+    G[e] = s;
+  }
+}
+
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ part, int64_t m, int nb,
                                                           int npairs, int nsplit, int64_t blk,
                                                           double* __restrict__ G) {
@@ -208,7 +522,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
 }
 
 struct GramPlan {
-  int nb, npairs, nsplit;
+  int nb, npairs, nsplit, tw;
   int64_t ktiles, kt_per_split, blk;
 };
 
@@ -217,7 +531,8 @@ GramPlan gram_plan(const ModeView& v) {
   g.nb = (int)((v.m + GB - 1) / GB);
   g.npairs = g.nb * (g.nb + 1) / 2;
   const int64_t K = v.P * v.S;
-  g.ktiles = (K + GBK - 1) / GBK;
+  g.tw = v.S >= GBK ? GBK : (int)(v.S * (GBK / v.S));
+  g.ktiles = (K + g.tw - 1) / g.tw;
   int64_t want = std::max<int64_t>(1, 512 / g.npairs);
   want = std::min<int64_t>(want, std::max<int64_t>(1, g.ktiles));
   g.kt_per_split = (g.ktiles + want - 1) / want;
@@ -235,6 +550,92 @@ GramPlan gram_plan(const ModeView& v) {
 // is staged in LDS in chunks of 64 rows of a; X is read once, straight into
 // the B operand registers.
 // --------------------------------------------------------------------------
+// --------------------------------------------------------------------------
+// TTM contraction for m <= 128: Z[p, r, s] = sum_a U[a, r] X[p, a, s].  Tiles of
+// 32 unfolding columns go through the same prefetching panel loader as the Gram;
+// U^T (R <= 64 rows) sits in LDS; each wave computes 16 x 16 blocks of Z and
+// writes them straight from its accumulators.  With NORM the workgroup also sums
+// the squares of every element it reads (the ||Y||^2 of the skip test).
+// --------------------------------------------------------------------------
+template <typename T, bool NORM>
+__global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
+                                                        int64_t ktiles, int64_t kt_per_split, int tw,
+                                                        const double* __restrict__ U, int R, double* __restrict__ Z,
+                                                        double* __restrict__ norm_part) {
+  extern __shared__ double dsm[];
+  double* sM = dsm;                   // [GBK][GLD]
+  const int RP = (R + 15) & ~15;
+  const int ULD = RP + 1;
+  double* sU = sM + GBK * GLD;        // [128][ULD]
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int mi = (int)m;
+  const int tI = (mi + 15) >> 4;
+  for (int e = threadIdx.x; e < GBK * GLD; e += 256) sM[e] = 0.0;
+  for (int e = threadIdx.x; e < GB * ULD; e += 256) {
+    const int a = e / ULD, t = e - (e / ULD) * ULD;
+    sU[e] = (a < mi && t < R) ? U[a + (int64_t)t * m] : 0.0;
+  }
+  PanelLoader<T> L;
+  L.init(m, S, tw);
+  const int64_t K = P * S;
+  const int64_t kt0 = (int64_t)blockIdx.x * kt_per_split;
+  const int64_t kt1 = min(ktiles, kt0 + kt_per_split);
+  T rg[PER_PANEL];
+  if (kt0 < kt1) L.load(X, P, m, S, K, kt0, tw, rg);
+  double nrm = 0.0;
+  __syncthreads();
+  const int nzt = (RP >> 4) * 2;
+  for (int64_t kt = kt0; kt < kt1; ++kt) {
+    if (NORM) {
+#pragma unroll
+      for (int t = 0; t < PER_PANEL; ++t) {
+        const double v = static_cast<double>(rg[t]);
+        nrm = fma(v, v, nrm);
+      }
+    }
+    L.store(sM, rg);
+    if (kt + 1 < kt1) L.load(X, P, m, S, K, kt + 1, tw, rg);
+    __syncthreads();
+    for (int zt = wave; zt < nzt; zt += 4) {
+      const int zi = zt >> 1, zc = zt & 1;
+      d4 z = d4{0.0, 0.0, 0.0, 0.0};
+      const double* pa = sU + (lane >> 4) * ULD + zi * 16 + (lane & 15);
+      const double* pb = sM + (zc * 16 + (lane & 15)) * GLD + (lane >> 4);
+      for (int ks = 0; ks < tI * 16; ks += 16) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u] = pa[(ks + 4 * u) * ULD];
+          b[u] = pb[ks + 4 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) z = mfma16(a[u], b[u], z);
+      }
+      // column j of the tile is unfolding column kt * tw + zc * 16 + j
+      const int64_t c = kt * tw + zc * 16 + (lane & 15);
+      const bool slab = S < GBK;
+      const bool cv = slab ? (zc * 16 + (lane & 15)) < tw && c < K : c < K;
+      if (cv) {
+        const int64_t p = c / S, sidx = c - (c / S) * S;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = zi * 16 + (lane >> 4) + 4 * v;
+          if (r < R) Z[(p * R + r) * S + sidx] = z[v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (NORM) {
+    __shared__ double red[4];
+    nrm = wave_sum(nrm);
+    if (lane == 0) red[threadIdx.x >> 6] = nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) norm_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
 constexpr int TAC = 64;
 constexpr int TUS = 65;  // LDS row stride (doubles) of the staged U chunk
 
@@ -537,32 +938,164 @@ void sumsq(const void* x, Elem t, int64_t n, double* partials, double* out, hipS
   reduce_kernel<<<1, 256, 0, s>>>(partials, kSumsqBlocks, out);
 }
 
+size_t panel_lds_bytes(bool resid, int R) {
+  const int RP = (R + 15) & ~15;
+  size_t n = (size_t)GBK * GLD;
+  if (resid) n += (size_t)GB * (RP + 1) + (size_t)RP * ZLD;
+  return n * sizeof(double);
+}
+
+template <typename T, bool RESID, int MT>
+void launch_panel_t(const void* x, const ModeView& v, const GramPlan& g, const double* U, int R, double* part,
+                    hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_panel_kernel<T, RESID, MT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    attr = true;
+  }
+  gram_panel_kernel<T, RESID, MT><<<g.nsplit, 256, panel_lds_bytes(RESID, R), s>>>(
+      static_cast<const T*>(x), v.P, v.m, v.S, g.ktiles, g.kt_per_split, g.tw, U, R, part);
+}
+
+template <typename T, bool RESID>
+void launch_panel_mt(const void* x, const ModeView& v, const GramPlan& g, const double* U, int R, double* part,
+                     hipStream_t s) {
+  const int tI = (int)((v.m + 15) / 16);
+  const int mt = (tI * (tI + 1) / 2 + 3) / 4;  // upper 16x16 tiles per wave
+  switch (mt) {
+    case 1: launch_panel_t<T, RESID, 1>(x, v, g, U, R, part, s); break;
+    case 2: launch_panel_t<T, RESID, 2>(x, v, g, U, R, part, s); break;
+    case 3: launch_panel_t<T, RESID, 3>(x, v, g, U, R, part, s); break;
+    case 4: launch_panel_t<T, RESID, 4>(x, v, g, U, R, part, s); break;
+    case 6: launch_panel_t<T, RESID, 6>(x, v, g, U, R, part, s); break;
+    case 7: launch_panel_t<T, RESID, 7>(x, v, g, U, R, part, s); break;
+    default: launch_panel_t<T, RESID, 9>(x, v, g, U, R, part, s); break;
+  }
+}
+
+template <bool RESID>
+void launch_panel(const void* x, Elem t, const ModeView& v, const GramPlan& g, const double* U, int R, double* part,
+                  hipStream_t s) {
+  if (t == Elem::F32)
+    launch_panel_mt<float, RESID>(x, v, g, U, R, part, s);
+  else
+    launch_panel_mt<double, RESID>(x, v, g, U, R, part, s);
+}
+
+void gram_finish(const GramPlan& g, const ModeView& v, const double* part, double* G, hipStream_t s) {
+  const int64_t mm = v.m * v.m;
+  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+  gram_reduce2_kernel<<<(unsigned)((mm + 63) / 64), 1024, 0, s>>>(part, v.m, g.nb, g.npairs, g.nsplit, g.blk, G);
+}
+
+size_t gram_partial_bound(int64_t m) {
+  if (m <= kSmallM) return (size_t)kSmallBlocks * (kSmallM * (kSmallM + 1) / 2);
+  const size_t nb = (size_t)((m + GB - 1) / GB), npairs = nb * (nb + 1) / 2, side = (size_t)std::min<int64_t>(GB, m);
+  return std::max<size_t>(512, npairs) * side * side;
+}
+
 size_t gram_partial_doubles(const ModeView& v) {
+  if (v.m <= kSmallM) return (size_t)kSmallBlocks * (kSmallM * (kSmallM + 1) / 2);
   const GramPlan g = gram_plan(v);
   return (size_t)g.nsplit * g.npairs * g.blk;
 }
 
 void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hipStream_t s) {
-  const GramPlan g = gram_plan(v);
-  // algorithmic work of the symmetric product: m^2 K flops, the m x K unfolding read once
   const double K = (double)v.P * v.S, md = (double)v.m;
-  dim3 grid(g.npairs, g.nsplit);
-  {
+  if (v.m <= kSmallM) {
+    {
+      ProfScope prof(KKind::Gram, s, md * md * K, md * K * (t == Elem::F32 ? 4 : 8));
+      const int64_t Ki = v.P * v.S;
+      if (t == Elem::F32)
+        gram_small_kernel<float><<<kSmallBlocks, 256, 0, s>>>(static_cast<const float*>(x), v.m, v.S, Ki, part);
+      else
+        gram_small_kernel<double><<<kSmallBlocks, 256, 0, s>>>(static_cast<const double*>(x), v.m, v.S, Ki, part);
+    }
+    ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+    gram_small_reduce_kernel<<<1, 64, 0, s>>>(part, (int)v.m, kSmallBlocks, G);
+    return;
+  }
+  const GramPlan g = gram_plan(v);
+  if (v.m <= GB) {
+    ProfScope prof(KKind::Gram, s, md * md * K, md * K * (t == Elem::F32 ? 4 : 8));
+    launch_panel<false>(x, t, v, g, nullptr, 0, part, s);
+  } else {
+    dim3 grid(g.npairs, g.nsplit);
     ProfScope prof(KKind::Gram, s, md * md * K, md * K * (t == Elem::F32 ? 4 : 8));
     if (t == Elem::F32)
       gram_partial_kernel<float><<<grid, 256, 0, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, g.nb, g.npairs,
-                                                      g.ktiles, g.kt_per_split, g.blk, part);
+                                                      g.ktiles, g.kt_per_split, g.blk, g.tw, part);
     else
       gram_partial_kernel<double><<<grid, 256, 0, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, g.nb,
-                                                       g.npairs, g.ktiles, g.kt_per_split, g.blk, part);
+                                                       g.npairs, g.ktiles, g.kt_per_split, g.blk, g.tw, part);
   }
-  const int64_t mm = v.m * v.m;
-  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
-  gram_reduce_kernel<<<(unsigned)((mm + 255) / 256), 256, 0, s>>>(part, v.m, g.nb, g.npairs, g.nsplit, g.blk, G);
+  gram_finish(g, v, part, G, s);
+}
+
+void resid_gram(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,
+                hipStream_t s) {
+  const GramPlan g = gram_plan(v);
+  const double K = (double)v.P * v.S, md = (double)v.m;
+  // residual formation (4 R m flops per column) plus the symmetric product
+  ProfScope prof(KKind::Gram, s, md * md * K + 4.0 * R * md * K, md * K * (t == Elem::F32 ? 4 : 8));
+  launch_panel<true>(x, t, v, g, U, R, part, s);
+  gram_finish(g, v, part, G, s);
 }
 
 void ttm_contract(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z, hipStream_t s) {
+  ttm_contract_norm(x, t, v, U, R, Z, nullptr, nullptr, s);
+}
+
+size_t ttm_norm_partials() { return kTtmMaxBlocks; }
+
+void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z, double* norm_part,
+                       double* norm_out, hipStream_t s) {
   const int64_t K = v.P * v.S;
+  if (v.m <= GB) {
+    // many workgroups: no partial sums to reduce, only the optional norm
+    GramPlan g;
+    g.tw = v.S >= GBK ? GBK : (int)(v.S * (GBK / v.S));
+    g.ktiles = (K + g.tw - 1) / g.tw;
+    const int64_t want = std::min<int64_t>(kTtmMaxBlocks, std::max<int64_t>(1, g.ktiles));
+    g.kt_per_split = (g.ktiles + want - 1) / want;
+    const int blocks = (int)((g.ktiles + g.kt_per_split - 1) / g.kt_per_split);
+    const int RP = (R + 15) & ~15;
+    const size_t lds = ((size_t)GBK * GLD + (size_t)GB * (RP + 1)) * sizeof(double);
+    ProfScope prof(KKind::TtmContract, s, 2.0 * R * v.m * (double)K,
+                   (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8);
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_panel_kernel<float, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_panel_kernel<float, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_panel_kernel<double, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_panel_kernel<double, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+      attr = true;
+    }
+    const bool nrm = norm_part != nullptr;
+    if (t == Elem::F32) {
+      if (nrm)
+        ttm_panel_kernel<float, true><<<blocks, 256, lds, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, g.ktiles,
+                                                               g.kt_per_split, g.tw, U, R, Z, norm_part);
+      else
+        ttm_panel_kernel<float, false><<<blocks, 256, lds, s>>>(static_cast<const float*>(x), v.P, v.m, v.S,
+                                                                g.ktiles, g.kt_per_split, g.tw, U, R, Z, nullptr);
+    } else {
+      if (nrm)
+        ttm_panel_kernel<double, true><<<blocks, 256, lds, s>>>(static_cast<const double*>(x), v.P, v.m, v.S,
+                                                                g.ktiles, g.kt_per_split, g.tw, U, R, Z, norm_part);
+      else
+        ttm_panel_kernel<double, false><<<blocks, 256, lds, s>>>(static_cast<const double*>(x), v.P, v.m, v.S,
+                                                                 g.ktiles, g.kt_per_split, g.tw, U, R, Z, nullptr);
+    }
+    if (nrm) reduce_kernel<<<1, 256, 0, s>>>(norm_part, blocks, norm_out);
+    return;
+  }
+  if (norm_part != nullptr) sumsq(x, t, v.P * v.m * v.S, norm_part, norm_out, s);
   ProfScope prof(KKind::TtmContract, s, 2.0 * R * v.m * (double)K,
                  (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8);
   const unsigned blocks = (unsigned)((K + 255) / 256);

@@ -31,6 +31,15 @@ ht_status ht_test_gram(const void* x, int32_t dtype, int64_t P, int64_t m, int64
   return hipGetLastError() == hipSuccess ? HT_OK : HT_EDEVICE;
 }
 
+ht_status ht_test_resid_gram(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U, int32_t R,
+                             double* G, double* scratch, void* s) {
+  if (!x || !U || !G || !scratch || P < 1 || m < 1 || m > ht::kResidGramMaxM || S < 1 || R < 1 || R > 64 ||
+      !ok_dtype(dtype))
+    return HT_EINVAL;
+  ht::resid_gram(x, elem(dtype), ht::ModeView{P, m, S}, U, R, scratch, G, st(s));
+  return hipGetLastError() == hipSuccess ? HT_OK : HT_EDEVICE;
+}
+
 ht_status ht_test_ttm_contract(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
                                int32_t R, double* Z, void* s) {
   if (!x || !U || !Z || P < 1 || m < 1 || S < 1 || R < 1 || R > 64 || !ok_dtype(dtype)) return HT_EINVAL;

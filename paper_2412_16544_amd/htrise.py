@@ -250,12 +250,13 @@ def _tlib():
         L.ht_test_gram_scratch_doubles.restype = sz
         L.ht_test_gram.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp]
         L.ht_test_ttm_contract.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp]
+        L.ht_test_resid_gram.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, vp]
         L.ht_test_ttm_expand.argtypes = [vp, i64, i32, i64, vp, i64, vp, i32, vp, i32, vp]
         L.ht_test_eig_scratch_doubles.argtypes = [i32, i32]
         L.ht_test_eig_scratch_doubles.restype = sz
         L.ht_test_eig.argtypes = [vp, i32, i32, i32, dbl, vp, vp, vp, vp, vp, vp]
         L.ht_test_orth_expand.argtypes = [vp, i64, i32, vp, i32, vp, vp]
-        for name in ("ht_test_sumsq", "ht_test_gram", "ht_test_ttm_contract", "ht_test_ttm_expand", "ht_test_eig",
+        for name in ("ht_test_sumsq", "ht_test_gram", "ht_test_resid_gram", "ht_test_ttm_contract", "ht_test_ttm_expand", "ht_test_eig",
                      "ht_test_orth_expand"):
             getattr(L, name).restype = ctypes.c_int
         L._ht_testing_ready = True
@@ -281,6 +282,17 @@ def ht_test_gram(x, P: int, m: int, S: int, stream=None):
     sc = torch.empty(max(1, L.ht_test_gram_scratch_doubles(P, m, S)), dtype=torch.float64, device=x.device)
     G = torch.empty((m, m), dtype=torch.float64, device=x.device)
     _check(L.ht_test_gram(_ptr(x), _dt(x), P, m, S, _ptr(G), _ptr(sc), _stream(stream)), "ht_test_gram")
+    return G
+
+
+def ht_test_resid_gram(x, P: int, m: int, S: int, U, stream=None):
+    import torch
+    L = _tlib()
+    sc = torch.empty(max(1, L.ht_test_gram_scratch_doubles(P, m, S)), dtype=torch.float64, device=x.device)
+    G = torch.empty((m, m), dtype=torch.float64, device=x.device)
+    Ucm = U.t().contiguous()
+    _check(L.ht_test_resid_gram(_ptr(x), _dt(x), P, m, S, _ptr(Ucm), U.shape[1], _ptr(G), _ptr(sc),
+                                _stream(stream)), "ht_test_resid_gram")
     return G
 
 

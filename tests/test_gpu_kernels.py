@@ -26,7 +26,7 @@ def test_sumsq(n, dtype):
     assert got == pytest.approx(ref, rel=1e-13)
 
 
-GRAM_SHAPES = [(1, 1, 1), (3, 96, 1000), (5, 3, 7), (100, 16, 1), (2, 200, 33), (1, 130, 40), (7, 17, 5),
+GRAM_SHAPES = [(1, 1, 1), (3, 8, 1), (2, 9, 31), (6, 33, 32), (3, 96, 1000), (5, 3, 7), (100, 16, 1), (2, 200, 33), (1, 130, 40), (7, 17, 5),
                (4, 256, 3), (9, 40, 64), (1, 300, 2)]
 
 
@@ -38,6 +38,20 @@ def test_gram(P, m, S, dtype):
     M = unfold_np(x.astype(np.float64), P, m, S)
     ref = M @ M.T
     assert np.max(np.abs(G - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("P,m,S,R", [(3, 96, 1000, 12), (5, 9, 7, 3), (100, 16, 1, 5), (2, 128, 33, 64), (7, 17, 5, 1),
+                                     (4, 64, 300, 16), (50, 40, 2, 20), (1, 96, 31, 47)])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_resid_gram(P, m, S, R, dtype):
+    g = rng(P * 7 + m + S + R)
+    x = g.standard_normal(P * m * S).astype(dtype)
+    U = np.linalg.qr(g.standard_normal((m, R)))[0]
+    G = H.ht_test_resid_gram(torch.from_numpy(x).cuda(), P, m, S, torch.from_numpy(U).cuda()).cpu().numpy()
+    M = unfold_np(x.astype(np.float64), P, m, S)
+    Rr = M - U @ (U.T @ M)
+    ref = Rr @ Rr.T
+    assert np.max(np.abs(G - ref)) <= 1e-12 * max(1.0, np.max(np.abs(M @ M.T)))
 
 
 @pytest.mark.parametrize("P,m,S,R", [(3, 96, 1000, 12), (5, 3, 7, 3), (100, 16, 1, 5), (2, 200, 33, 64),
