@@ -47,7 +47,9 @@ ht_status ht_test_ttm_expand(const double* Z, int64_t P, int32_t R, int64_t S, c
  * evals (k, descending), the minimal rank r in [rmin, rmax] whose discarded energy
  * (sum of clipped eigenvalues from the smallest up) is <= thr, written to rank[0],
  * that energy to tail[0], and the r leading sign-normalised eigenvectors to vecs
- * (k x r column-major).  scratch holds ht_test_eig_scratch_doubles(k, rmax). */
+ * (k x r column-major).  When rmin = 0 and trace(G) <= thr the rule keeps nothing and the
+ * decomposition is skipped: rank 0, tail = trace(G), evals and vecs untouched.
+ * scratch holds ht_test_eig_scratch_doubles(k, rmax). */
 size_t ht_test_eig_scratch_doubles(int32_t k, int32_t rmax);
 ht_status ht_test_eig(const double* G, int32_t k, int32_t rmin, int32_t rmax, double thr, double* evals,
                       double* vecs, int32_t* rank, double* tail, double* scratch, void* hip_stream);

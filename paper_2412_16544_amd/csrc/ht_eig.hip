@@ -35,11 +35,36 @@ struct EigBatch {
   EigJob j[kMaxEigJobs];
 };
 
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// Cross-lane sums of doubles through DPP (row shifts and row broadcasts of the
+// two 32-bit halves) instead of ds_bpermute-based shuffles.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the 64 lanes, returned to every lane
+__device__ __forceinline__ double dpp_wave_sum(double v) {
+  v += dpp_mov<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_mov<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_mov<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_mov<0x118, 0xf>(v);  // row_shr:8  -> lane 15 of each row holds its row sum
+  v += dpp_mov<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_mov<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3 -> lane 63 holds the total
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over each aligned group of 4 lanes, returned to the 4 lanes
+__device__ __forceinline__ double dpp_quad_sum(double v) {
+  v += dpp_mov<0xB1, 0xf>(v);  // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E, 0xf>(v);  // quad_perm [2,3,0,1]
   return v;
 }
+
+__device__ __forceinline__ double wsum(double v) { return dpp_wave_sum(v); }
 
 __device__ __forceinline__ double bsum(double v, double* red) {
   v = wsum(v);
@@ -104,8 +129,11 @@ __device__ __forceinline__ double start_entry(int j, int i) {
 // pk(a, b)): column j is annihilated below the subdiagonal, the reflector goes to
 // row j of hv.
 __device__ __forceinline__ void house_step(double* P, int k, int j, double* vb, double* pb, double* wb, double* red,
-                                           double* d, double* e, double* tau, double* hv) {
+                                           double* d, double* e, double* tau, double* hv, double* clk) {
   const int tid = threadIdx.x;
+#define HT_STEP_MARK(i) \
+  if (j == 10 && tid == 0) clk[8 + (i)] = (double)wall_clock64();
+  HT_STEP_MARK(0)
   const int r0 = j + 1, n2 = k - r0;
   double loc = 0.0;
   for (int i = 1 + tid; i < n2; i += ET) {
@@ -113,6 +141,7 @@ __device__ __forceinline__ void house_step(double* P, int k, int j, double* vb, 
     loc = fma(x, x, loc);
   }
   const double xn2 = bsum(loc, red);
+  HT_STEP_MARK(1)
   const double alpha = P[pk(r0, j)];
   double beta, tj, scale;
   if (xn2 == 0.0) {
@@ -135,6 +164,7 @@ __device__ __forceinline__ void house_step(double* P, int k, int j, double* vb, 
     tau[j] = tj;
   }
   __syncthreads();
+  HT_STEP_MARK(2)
   if (tj != 0.0) {
     // p = tau A22 v: four lanes per row, each summing every fourth entry, joined by shuffles
     for (int base = 0; base < n2; base += ET / 4) {
@@ -174,16 +204,17 @@ __device__ __forceinline__ void house_step(double* P, int k, int j, double* vb, 
         }
         s += (s1 + s2) + s3;
       }
-      s += __shfl_xor(s, 1);
-      s += __shfl_xor(s, 2);
+      s = dpp_quad_sum(s);
       if (i < n2 && u == 0) pb[i] = tj * s;
     }
     __syncthreads();
+    HT_STEP_MARK(3)
     double loc2 = 0.0;
     for (int i = tid; i < n2; i += ET) loc2 = fma(pb[i], vb[i], loc2);
     const double kk = -0.5 * tj * bsum(loc2, red);
     for (int i = tid; i < n2; i += ET) wb[i] = fma(kk, vb[i], pb[i]);
     __syncthreads();
+    HT_STEP_MARK(4)
     // rank-2 update of the trailing packed triangle; (a, b) advanced incrementally
     const int nq = n2 * (n2 + 1) / 2;
     if (tid < nq) {
@@ -202,6 +233,8 @@ __device__ __forceinline__ void house_step(double* P, int k, int j, double* vb, 
     }
   }
   __syncthreads();
+  HT_STEP_MARK(5)
+#undef HT_STEP_MARK
 }
 
 // Phase 1: packed copy of G's lower triangle into P, Householder steps, then the
@@ -209,7 +242,7 @@ __device__ __forceinline__ void house_step(double* P, int k, int j, double* vb, 
 __device__ __forceinline__ void tridiagonalise(double* P, const double* __restrict__ G, int k, double* vb, double* pb,
                                                double* wb, double* red, double* d, double* e, double* e2,
                                                double* tau, double* hv, double* s_gl, double* s_gu,
-                                               double* s_pivmin, double* s_tnorm) {
+                                               double* s_pivmin, double* s_tnorm, double* clk) {
   const int tid = threadIdx.x;
   const int npk = k * (k + 1) / 2;
   for (int q = tid; q < npk; q += ET) {
@@ -218,7 +251,7 @@ __device__ __forceinline__ void tridiagonalise(double* P, const double* __restri
     P[q] = G[(int64_t)a * k + b];
   }
   __syncthreads();
-  for (int j = 0; j + 2 < k; ++j) house_step(P, k, j, vb, pb, wb, red, d, e, tau, hv);
+  for (int j = 0; j + 2 < k; ++j) house_step(P, k, j, vb, pb, wb, red, d, e, tau, hv, clk);
   if (tid == 0) {
     if (k >= 2) {
       d[k - 2] = P[pk(k - 2, k - 2)];
@@ -423,11 +456,26 @@ __global__ __launch_bounds__(ET) void eig_trunc_kernel(EigBatch batch) {
   const int64_t npk = (int64_t)k * (k + 1) / 2;
   const bool packed_lds = npk <= work_cap;
 
+  // all the energy already within the budget and no rank floor: the rule keeps
+  // nothing (tail(0) = trace <= thr), so the decomposition is not needed
+  if (J.rmin == 0) {
+    double tr = 0.0;
+    for (int i = tid; i < k; i += ET) tr += J.G[(int64_t)i * k + i];
+    tr = bsum(tr, red);
+    if (tr <= J.thr) {
+      if (tid == 0) {
+        *J.rank = 0;
+        *J.tail = tr;
+      }
+      return;
+    }
+  }
+
   // ---- 1. tridiagonalisation
   if (packed_lds)
-    tridiagonalise(work, J.G, k, vb, pb, wb, red, d, e, e2, tau, hv, &s_gl, &s_gu, &s_pivmin, &s_tnorm);
+    tridiagonalise(work, J.G, k, vb, pb, wb, red, d, e, e2, tau, hv, &s_gl, &s_gu, &s_pivmin, &s_tnorm, clk);
   else
-    tridiagonalise(gP, J.G, k, vb, pb, wb, red, d, e, e2, tau, hv, &s_gl, &s_gu, &s_pivmin, &s_tnorm);
+    tridiagonalise(gP, J.G, k, vb, pb, wb, red, d, e, e2, tau, hv, &s_gl, &s_gu, &s_pivmin, &s_tnorm, clk);
 
   HT_EIG_MARK(1)
   // ---- 2. all eigenvalues by multisection: T lanes of one wave share an eigenvalue,

@@ -36,11 +36,36 @@ __device__ __forceinline__ int64_t col_base(int64_t c, int64_t m, int64_t S) {
   return p * m * S + s;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// Cross-lane sums of doubles through DPP (row shifts and row broadcasts of the
+// two 32-bit halves) instead of ds_bpermute-based shuffles.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the 64 lanes, returned to every lane
+__device__ __forceinline__ double dpp_wave_sum(double v) {
+  v += dpp_mov<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_mov<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_mov<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_mov<0x118, 0xf>(v);  // row_shr:8  -> lane 15 of each row holds its row sum
+  v += dpp_mov<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_mov<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3 -> lane 63 holds the total
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over each aligned group of 4 lanes, returned to the 4 lanes
+__device__ __forceinline__ double dpp_quad_sum(double v) {
+  v += dpp_mov<0xB1, 0xf>(v);  // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E, 0xf>(v);  // quad_perm [2,3,0,1]
   return v;
 }
+
+__device__ __forceinline__ double wave_sum(double v) { return dpp_wave_sum(v); }
 
 // --------------------------------------------------------------------------
 // Sum of squares (FP64 accumulation), two fixed-order levels
