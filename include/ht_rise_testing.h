@@ -44,11 +44,13 @@ ht_status ht_test_ttm_expand(const double* Z, int64_t P, int32_t R, int64_t S, c
                              const void* M, int32_t m_dtype, void* out, int32_t out_dtype, void* hip_stream);
 
 /* Eigen-decomposition of the symmetric k x k G (row-major) and the truncation rule:
- * evals (k, descending), the minimal rank r in [rmin, rmax] whose discarded energy
- * (sum of clipped eigenvalues from the smallest up) is <= thr, written to rank[0],
- * that energy to tail[0], and the r leading sign-normalised eigenvectors to vecs
- * (k x r column-major).  When rmin = 0 and trace(G) <= thr the rule keeps nothing and the
- * decomposition is skipped: rank 0, tail = trace(G), evals and vecs untouched.
+ * the minimal rank r in [rmin, rmax] whose discarded energy (the clipped eigenvalues
+ * beyond the r leading ones) is <= thr, written to rank[0], that energy to tail[0],
+ * and the r leading sign-normalised eigenvectors to vecs (k x r column-major).
+ * evals receives the leading eigenvalues in descending order, as many as the rule
+ * needed (at least r); the remaining entries are left untouched.  When rmin = 0 and
+ * trace(G) <= thr the rule keeps nothing and the decomposition is skipped: rank 0,
+ * tail = trace(G), evals and vecs untouched.
  * scratch holds ht_test_eig_scratch_doubles(k, rmax). */
 size_t ht_test_eig_scratch_doubles(int32_t k, int32_t rmax);
 ht_status ht_test_eig(const double* G, int32_t k, int32_t rmin, int32_t rmax, double thr, double* evals,

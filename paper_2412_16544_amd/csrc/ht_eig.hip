@@ -4,10 +4,11 @@
 // taken from the Gram matrix G = M M^T: sigma_i^2 = lambda_i(G) and the left
 // singular vectors are G's eigenvectors.  One workgroup solves one k x k problem:
 //
-//   1. Householder reduction G = Q T Q^T to tridiagonal T.  The lower triangle
-//      is kept packed in LDS when it fits (k <= ~190), else in global memory;
+//   1. Householder reduction G = Q T Q^T to tridiagonal T.  Up to k = 224 the
+//      matrix stays in registers (lower 32 x 32 tiles, one entry per thread per
+//      tile); beyond, its lower triangle is packed in LDS or global memory;
 //   2. every eigenvalue of T by multisection on Sturm counts (several lanes of a
-//      wave per eigenvalue);
+//      wave per eigenvalue; signs of the leading principal minors);
 //   3. the minimal rank r in [rmin, rmax] whose discarded energy, summed from the
 //      smallest eigenvalue up, is <= thr = eps_nw^2 (clipping lambda at 0);
 //   4. the r leading eigenvectors of T by inverse iteration (the partial-pivoting
@@ -26,7 +27,7 @@
 namespace ht {
 namespace {
 
-constexpr int ET = 1024;
+constexpr int ET = 512;
 constexpr int NW = ET / 64;
 constexpr int kLdsDoubles = 19968;  // 156 KiB of dynamic LDS per workgroup
 constexpr int kSmallMax = 1024;     // the 6k work vectors live in LDS up to this k
@@ -66,6 +67,31 @@ __device__ __forceinline__ double dpp_quad_sum(double v) {
 
 __device__ __forceinline__ double wsum(double v) { return dpp_wave_sum(v); }
 
+// DPP move that keeps the lane's own value where the source lane is invalid
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_self(double x) {
+  const int xl = __double2loint(x), xh = __double2hiint(x);
+  const int lo = __builtin_amdgcn_update_dpp(xl, xl, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(xh, xh, CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <bool MAX>
+__device__ __forceinline__ double dpp_wave_minmax(double v) {
+#define HT_MM(a, b) (MAX ? fmax((a), (b)) : fmin((a), (b)))
+  v = HT_MM(v, (dpp_self<0x111, 0xf>(v)));
+  v = HT_MM(v, (dpp_self<0x112, 0xf>(v)));
+  v = HT_MM(v, (dpp_self<0x114, 0xf>(v)));
+  v = HT_MM(v, (dpp_self<0x118, 0xf>(v)));
+  v = HT_MM(v, (dpp_self<0x142, 0xa>(v)));
+  v = HT_MM(v, (dpp_self<0x143, 0xc>(v)));
+#undef HT_MM
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+
 __device__ __forceinline__ double bsum(double v, double* red) {
   v = wsum(v);
   __syncthreads();
@@ -92,26 +118,106 @@ __device__ __forceinline__ int prow(int q) {
   return a;
 }
 
-// 1/q to full double precision: hardware reciprocal refined by two Newton steps
-__device__ __forceinline__ double recip(double q) {
-  double r = __builtin_amdgcn_rcp(q);
-  r = fma(r, fma(-q, r, 1.0), r);
-  r = fma(r, fma(-q, r, 1.0), r);
-  return r;
+// Number of eigenvalues of T below x from the signs of the leading principal
+// minors p_i = det(T_i - x I) = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}: the pivot
+// p_i / p_{i-1} of T - x I is negative exactly when the two signs differ
+// (Sylvester's law of inertia).  dn and e2n are T scaled by a power of two so
+// that |T| <= 1; the pair (p_{i-1}, p_{i-2}) is rescaled by a power of two every
+// four steps, which keeps it in range without touching the signs.  As in the
+// pivot form, a pivot of magnitude below the floor DBL_MIN is replaced by
+// -DBL_MIN (the pair is then re-expressed at a large scale so that it cannot
+// underflow).  The recurrence has one dependent FMA per step, against a division
+// or a refined reciprocal per step in the pivot form.
+__device__ __forceinline__ int sturm_scaled(const double* __restrict__ dn, const double* __restrict__ e2n, int k,
+                                            double x) {
+  double p1 = 1.0, p2 = 0.0;
+  int cnt = 0;
+#define HT_STURM_STEP(dd, ff)                                    \
+  {                                                              \
+    const double fl = DBL_MIN * fabs(p1);                        \
+    double p = fma((dd) - x, p1, -((ff) * p2));                  \
+    if (fabs(p) < fl) {                                          \
+      p1 = copysign(0x1p960, p1);                                \
+      p = -DBL_MIN * p1;                                         \
+    }                                                            \
+    cnt += (__double2hiint(p) ^ __double2hiint(p1)) < 0 ? 1 : 0; \
+    p2 = p1;                                                     \
+    p1 = p;                                                      \
+  }
+  HT_STURM_STEP(dn[0], 0.0)
+  int i = 1;
+  for (; i + 4 <= k; i += 4) {
+    const double d0 = dn[i], d1 = dn[i + 1], d2 = dn[i + 2], d3 = dn[i + 3];
+    const double f0 = e2n[i - 1], f1 = e2n[i], f2 = e2n[i + 1], f3 = e2n[i + 2];
+    HT_STURM_STEP(d0, f0)
+    HT_STURM_STEP(d1, f1)
+    HT_STURM_STEP(d2, f2)
+    HT_STURM_STEP(d3, f3)
+    const int ex = __builtin_amdgcn_frexp_exp(p1);
+    p1 = __builtin_amdgcn_ldexp(p1, -ex);
+    p2 = __builtin_amdgcn_ldexp(p2, -ex);
+  }
+  for (; i < k; ++i) HT_STURM_STEP(dn[i], e2n[i - 1])
+#undef HT_STURM_STEP
+  return cnt;
 }
 
-// number of eigenvalues of T (diag d, squared off-diagonal e2) below x
-__device__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int k, double x,
-                           double pivmin) {
+// The same count without the pivot floor on the dependent chain: each step is
+// one FMA (the e^2 p_{i-2} product and the sign test hang off the chain), the pair
+// is rescaled every eight steps, and the dn / e2n loads run one block ahead.  A
+// pivot below the floor only raises a flag, and the caller then repeats the count
+// with sturm_scaled.
+__device__ __forceinline__ int sturm_fast(const double* __restrict__ dn, const double* __restrict__ e2n, int k,
+                                          double x, bool& tiny) {
+  double p1 = 1.0, p2 = 0.0;
   int cnt = 0;
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  cnt += q < 0.0;
-  for (int i = 1; i < k; ++i) {
-    q = (d[i] - x) - e2[i - 1] * recip(q);
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
+  bool t = false;
+#define HT_FAST_STEP(dd, ff)                                         \
+  {                                                                  \
+    const double fl = DBL_MIN * fabs(p1);                            \
+    const double p = fma((dd) - x, p1, -((ff) * p2));                \
+    t |= !(fabs(p) >= fl) | (p == 0.0);                              \
+    cnt += (__double2hiint(p) ^ __double2hiint(p1)) < 0 ? 1 : 0;     \
+    p2 = p1;                                                         \
+    p1 = p;                                                          \
   }
+  HT_FAST_STEP(dn[0], 0.0)
+  int i = 1;
+  if (i + 8 <= k) {
+    double d[8], f[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      d[q] = dn[i + q];
+      f[q] = e2n[i + q - 1];
+    }
+    for (; i + 16 <= k; i += 8) {
+      double dn8[8], f8[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        dn8[q] = dn[i + 8 + q];
+        f8[q] = e2n[i + 7 + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) HT_FAST_STEP(d[q], f[q])
+      const int ex = __builtin_amdgcn_frexp_exp(p1);
+      p1 = __builtin_amdgcn_ldexp(p1, -ex);
+      p2 = __builtin_amdgcn_ldexp(p2, -ex);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        d[q] = dn8[q];
+        f[q] = f8[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) HT_FAST_STEP(d[q], f[q])
+    i += 8;
+    const int ex = __builtin_amdgcn_frexp_exp(p1);
+    p1 = __builtin_amdgcn_ldexp(p1, -ex);
+    p2 = __builtin_amdgcn_ldexp(p2, -ex);
+  }
+  for (; i < k; ++i) HT_FAST_STEP(dn[i], e2n[i - 1])
+#undef HT_FAST_STEP
+  tiny = t;
   return cnt;
 }
 
@@ -129,11 +235,8 @@ __device__ __forceinline__ double start_entry(int j, int i) {
 // pk(a, b)): column j is annihilated below the subdiagonal, the reflector goes to
 // row j of hv.
 __device__ __forceinline__ void house_step(double* P, int k, int j, double* vb, double* pb, double* wb, double* red,
-                                           double* d, double* e, double* tau, double* hv, double* clk) {
+                                           double* d, double* e, double* tau, double* hv) {
   const int tid = threadIdx.x;
-#define HT_STEP_MARK(i) \
-  if (j == 10 && tid == 0) clk[8 + (i)] = (double)wall_clock64();
-  HT_STEP_MARK(0)
   const int r0 = j + 1, n2 = k - r0;
   double loc = 0.0;
   for (int i = 1 + tid; i < n2; i += ET) {
@@ -141,7 +244,6 @@ __device__ __forceinline__ void house_step(double* P, int k, int j, double* vb, 
     loc = fma(x, x, loc);
   }
   const double xn2 = bsum(loc, red);
-  HT_STEP_MARK(1)
   const double alpha = P[pk(r0, j)];
   double beta, tj, scale;
   if (xn2 == 0.0) {
@@ -164,7 +266,6 @@ __device__ __forceinline__ void house_step(double* P, int k, int j, double* vb, 
     tau[j] = tj;
   }
   __syncthreads();
-  HT_STEP_MARK(2)
   if (tj != 0.0) {
     // p = tau A22 v: four lanes per row, each summing every fourth entry, joined by shuffles
     for (int base = 0; base < n2; base += ET / 4) {
@@ -208,13 +309,11 @@ __device__ __forceinline__ void house_step(double* P, int k, int j, double* vb, 
       if (i < n2 && u == 0) pb[i] = tj * s;
     }
     __syncthreads();
-    HT_STEP_MARK(3)
     double loc2 = 0.0;
     for (int i = tid; i < n2; i += ET) loc2 = fma(pb[i], vb[i], loc2);
     const double kk = -0.5 * tj * bsum(loc2, red);
     for (int i = tid; i < n2; i += ET) wb[i] = fma(kk, vb[i], pb[i]);
     __syncthreads();
-    HT_STEP_MARK(4)
     // rank-2 update of the trailing packed triangle; (a, b) advanced incrementally
     const int nq = n2 * (n2 + 1) / 2;
     if (tid < nq) {
@@ -233,16 +332,13 @@ __device__ __forceinline__ void house_step(double* P, int k, int j, double* vb, 
     }
   }
   __syncthreads();
-  HT_STEP_MARK(5)
-#undef HT_STEP_MARK
 }
 
-// Phase 1: packed copy of G's lower triangle into P, Householder steps, then the
-// tridiagonal (d, e, e2), its Gershgorin interval and the pivot floor.
-__device__ __forceinline__ void tridiagonalise(double* P, const double* __restrict__ G, int k, double* vb, double* pb,
-                                               double* wb, double* red, double* d, double* e, double* e2,
-                                               double* tau, double* hv, double* s_gl, double* s_gu,
-                                               double* s_pivmin, double* s_tnorm, double* clk) {
+// ---- phase 1, packed path (k > 16 kRegRowTiles): lower triangle packed in LDS or
+//      global memory, one Householder step at a time over the whole workgroup
+__device__ __forceinline__ void tridiagonalise_packed(double* P, const double* __restrict__ G, int k, double* vb,
+                                                      double* pb, double* wb, double* red, double* d, double* e,
+                                                      double* tau, double* hv) {
   const int tid = threadIdx.x;
   const int npk = k * (k + 1) / 2;
   for (int q = tid; q < npk; q += ET) {
@@ -251,7 +347,7 @@ __device__ __forceinline__ void tridiagonalise(double* P, const double* __restri
     P[q] = G[(int64_t)a * k + b];
   }
   __syncthreads();
-  for (int j = 0; j + 2 < k; ++j) house_step(P, k, j, vb, pb, wb, red, d, e, tau, hv, clk);
+  for (int j = 0; j + 2 < k; ++j) house_step(P, k, j, vb, pb, wb, red, d, e, tau, hv);
   if (tid == 0) {
     if (k >= 2) {
       d[k - 2] = P[pk(k - 2, k - 2)];
@@ -261,93 +357,458 @@ __device__ __forceinline__ void tridiagonalise(double* P, const double* __restri
     d[k - 1] = P[pk(k - 1, k - 1)];
     e[k - 1] = 0.0;
     tau[k - 1] = 0.0;
-    double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0.0;
-    for (int i = 0; i < k; ++i) {
-      const double off = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < k ? fabs(e[i]) : 0.0);
-      gl = fmin(gl, d[i] - off);
-      gu = fmax(gu, d[i] + off);
-      e2[i] = (i + 1 < k) ? e[i] * e[i] : 0.0;
-      emax2 = fmax(emax2, e2[i]);
-    }
-    const double tn = fmax(fabs(gl), fabs(gu));
-    *s_tnorm = tn;
-    *s_pivmin = DBL_MIN * fmax(1.0, emax2);
-    *s_gl = gl - 2.2e-16 * tn - *s_pivmin;
-    *s_gu = gu + 2.2e-16 * tn + *s_pivmin;
   }
   __syncthreads();
 }
 
-// Phase 4: the r leading eigenvectors of T (ascending eigenvalues lam), mapped
-// back with the reflectors in hv and sign-normalised into vecs (k x r).  Z holds
-// 4 k r doubles; entry (i, j) of a work array at i * r + j.
-__device__ __forceinline__ void eigenvectors(double* Z, int k, int r, const double* lam, const double* d,
-                                             const double* e, double* pb, double* red, const double* tau,
-                                             const double* hv, double* vecs, double tnorm) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // ---- 4a. inverse iteration, one thread per vector; entry (i, j) at i * r + j
-  double* U0 = Z + (size_t)k * r;
-  double* U1 = U0 + (size_t)k * r;
-  double* U2 = U1 + (size_t)k * r;
-  {
-    const double tiny = fmax(2.2e-16 * tnorm, DBL_MIN);
-    for (int j = tid; j < r; j += ET) {
-      const double lm = lam[k - 1 - j];
-      for (int i = 0; i < k; ++i) Z[(size_t)i * r + j] = start_entry(j, i);
-      for (int it = 0; it < 3; ++it) {
-        // forward: factor T - lm I row by row with partial pivoting, apply to the rhs
-        double u0 = d[0] - lm, u1 = (k > 1) ? e[0] : 0.0, u2 = 0.0;
-        double bi = Z[j];
-        for (int i = 0; i + 1 < k; ++i) {
-          const double l0 = e[i], l1 = d[i + 1] - lm, l2 = (i + 2 < k) ? e[i + 1] : 0.0;
-          double bn = Z[(size_t)(i + 1) * r + j];
-          double nu0, nu1;
-          if (fabs(u0) >= fabs(l0)) {
-            if (u0 == 0.0) u0 = tiny;
-            const double mlt = l0 / u0;
-            U0[(size_t)i * r + j] = u0;
-            U1[(size_t)i * r + j] = u1;
-            U2[(size_t)i * r + j] = u2;
-            Z[(size_t)i * r + j] = bi;
-            nu0 = l1 - mlt * u1;
-            nu1 = l2 - mlt * u2;
-            bn = bn - mlt * bi;
-          } else {
-            const double mlt = u0 / l0;
-            U0[(size_t)i * r + j] = l0;
-            U1[(size_t)i * r + j] = l1;
-            U2[(size_t)i * r + j] = l2;
-            Z[(size_t)i * r + j] = bn;
-            nu0 = u1 - mlt * l1;
-            nu1 = u2 - mlt * l2;
-            bn = bi - mlt * bn;
-          }
-          u0 = nu0;
-          u1 = nu1;
-          u2 = 0.0;
-          bi = bn;
-        }
-        if (fabs(u0) < tiny) u0 = (u0 < 0.0) ? -tiny : tiny;
-        // backward substitution, the two previous unknowns kept in registers
-        double x1 = bi / u0, x2 = 0.0, mx = fabs(x1);
-        Z[(size_t)(k - 1) * r + j] = x1;
-        for (int i = k - 2; i >= 0; --i) {
-          double piv = U0[(size_t)i * r + j];
-          if (fabs(piv) < tiny) piv = (piv < 0.0) ? -tiny : tiny;
-          const double x = (Z[(size_t)i * r + j] - U1[(size_t)i * r + j] * x1 - U2[(size_t)i * r + j] * x2) / piv;
-          Z[(size_t)i * r + j] = x;
-          x2 = x1;
-          x1 = x;
-          mx = fmax(mx, fabs(x));
-        }
-        const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
-        for (int i = 0; i < k; ++i) Z[(size_t)i * r + j] *= inv;
+// ---- phase 1, register path (k <= 16 kRegRowTiles) ---------------------------------
+// The symmetric matrix lives in registers: thread (tr, tc) = (tid / 32, tid % 32)
+// holds entry (16 a + tr, 32 b + tc) of every stored tile (a, b), the 16 x 32 tiles
+// that meet the lower triangle (b <= a / 2), so the 32 x 32 diagonal blocks are
+// stored in full.  Step j annihilates column j below the subdiagonal with the
+// reflector H = I - tau v v^T, v = e_{j+1} + s x' (x' the column below row j + 1,
+// s its scale), and costs three workgroup barriers:
+//   A. the owners of columns j and j + 1 publish them in LDS;
+//   B. every thread forms its partial sums of y = A x' (row partials of each
+//      active tile, transposed partials of the strictly lower ones), while wave 0
+//      computes tau and s from the column -- the reflector is not needed yet since
+//      A v = s y + A e_{j+1};
+//   C. p = tau A v and v are assembled in LDS;
+// then every wave forms p^T v redundantly and applies A -= v w^T + w v^T,
+// w = p - (tau / 2)(p^T v) v, to its registers.  LDS loads of a phase are issued
+// before their first use, and tiles outside the active trailing block are skipped.
+constexpr int kRegRowTiles = 14;  // k <= 224
+
+__host__ __device__ constexpr int tile_base(int a) {
+  int s = 0;
+  for (int q = 0; q < a; ++q) s += q / 2 + 1;
+  return s;
+}
+
+// the owners of column c copy its entries of rows >= c into buf
+template <int TA>
+__device__ __forceinline__ void put_column(const double (&A)[tile_base(TA)], int c, int k, int tr, int tc,
+                                           double* buf) {
+  if (tc != (c & 31)) return;
+  const int bc = c >> 5;
+#pragma unroll
+  for (int a = 0; a < TA; ++a) {
+#pragma unroll
+    for (int b = 0; b <= a / 2; ++b) {
+      if (b == bc) {
+        const int i = 16 * a + tr;
+        if (i >= c && i < k) buf[i] = A[tile_base(a) + b];
       }
     }
   }
-  __syncthreads();
+}
 
-  // ---- 4b. orthonormalise the r vectors in order (classical Gram-Schmidt, twice)
+template <int TA>
+__device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k, double* xb, double* cb,
+                                            double* vbuf, double* pbuf, double* rowpart, double* colpart, double* d,
+                                            double* e, double* tau, double* __restrict__ hv, double* s_red) {
+  constexpr int TB = (TA + 1) / 2;
+  constexpr int NT = tile_base(TA);
+  constexpr int RP = 16 * TA + 1;  // row strides of the partials (odd: spreads the LDS banks)
+  constexpr int CP = 32 * TB + 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, tr = tid >> 5, tc = tid & 31;
+  double A[NT];
+#pragma unroll
+  for (int a = 0; a < TA; ++a) {
+#pragma unroll
+    for (int b = 0; b <= a / 2; ++b) {
+      const int i = 16 * a + tr, l = 32 * b + tc;
+      A[tile_base(a) + b] = (i < k && l < k) ? G[(int64_t)i * k + l] : 0.0;
+    }
+  }
+  for (int i = tid; i < 32 * TB; i += ET) {
+    vbuf[i] = 0.0;
+    pbuf[i] = 0.0;
+  }
+  for (int j = 0; j + 2 < k; ++j) {
+    const int r0 = j + 1;
+    const int a0 = r0 >> 4, b0 = r0 >> 5;  // first row / column tiles that meet the trailing block
+    // ---- A
+    put_column<TA>(A, j, k, tr, tc, xb);
+    put_column<TA>(A, r0, k, tr, tc, cb);
+    __syncthreads();
+    // ---- B: partial sums of y = A x', x'_i = xb[i] for r0 < i < k
+    {
+      double xr[TA], xc[TB];
+#pragma unroll
+      for (int a = 0; a < TA; ++a) {
+        const int i = 16 * a + tr;
+        const double x = xb[i];
+        xr[a] = (i > r0 && i < k) ? x : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int l = 32 * b + tc;
+        const double x = xb[l];
+        xc[b] = (l > r0 && l < k) ? x : 0.0;
+      }
+      double colacc[TB];
+#pragma unroll
+      for (int b = 0; b < TB; ++b) colacc[b] = 0.0;
+#pragma unroll
+      for (int a = 0; a < TA; ++a) {
+        if (a >= a0) {
+          double racc = 0.0;
+#pragma unroll
+          for (int b = 0; b <= a / 2; ++b) {
+            if (b >= b0) {
+              racc = fma(A[tile_base(a) + b], xc[b], racc);
+              if (b < a / 2) colacc[b] = fma(A[tile_base(a) + b], xr[a], colacc[b]);
+            }
+          }
+          rowpart[tc * RP + 16 * a + tr] = racc;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < TB; ++b)
+        if (b >= b0) colpart[tr * CP + 32 * b + tc] = colacc[b];
+      if (wave == 0) {
+        double sq = 0.0;
+        double xv[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int i = r0 + 1 + lane + 64 * m;
+          const double x = xb[i < 256 ? i : 255];
+          xv[m] = (i < k) ? x : 0.0;
+        }
+        const double alpha = xb[r0], dj = xb[j];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) sq = fma(xv[m], xv[m], sq);
+        const double xn2 = dpp_wave_sum(sq);
+        double beta, tj, scale;
+        if (xn2 == 0.0) {
+          beta = alpha;
+          tj = 0.0;
+          scale = 0.0;
+        } else {
+          beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+          tj = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
+        }
+        if (lane == 0) {
+          d[j] = dj;
+          e[j] = beta;
+          tau[j] = tj;
+          s_red[0] = tj;
+          s_red[1] = scale;
+        }
+      }
+    }
+    __syncthreads();
+    const double tj = s_red[0], scale = s_red[1];
+    if (tj == 0.0) continue;  // the column is already reduced (uniform)
+    // ---- C: p_i = tau (s y_i + A[i][r0]) and v_i for i >= 32 b0; two threads per entry
+    {
+      const int i = 32 * b0 + (tid >> 1), h = tid & 1;
+      const int ic = i < k ? i : k - 1;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+      for (int m = 0; m < 16; m += 4) {
+        s0 += rowpart[(h + 2 * m) * RP + ic];
+        s1 += rowpart[(h + 2 * m + 2) * RP + ic];
+        s2 += rowpart[(h + 2 * m + 4) * RP + ic];
+        s3 += rowpart[(h + 2 * m + 6) * RP + ic];
+      }
+#pragma unroll
+      for (int m = 0; m < 8; m += 2) {
+        s0 += colpart[(h + 2 * m) * CP + ic];
+        s1 += colpart[(h + 2 * m + 2) * CP + ic];
+      }
+      const double x = xb[ic], c = cb[ic];
+      double y = (s0 + s1) + (s2 + s3);
+      y += dpp_mov<0xB1, 0xf>(y);  // quad_perm [1,0,3,2]: the pair's sum
+      if (h == 0 && i < k) {
+        const double v = (i == r0) ? 1.0 : (i > r0 ? x * scale : 0.0);
+        vbuf[i] = v;
+        pbuf[i] = (i < r0) ? 0.0 : tj * fma(scale, y, c);
+        if (i >= r0) hv[(int64_t)j * k + i] = v;
+      }
+    }
+    __syncthreads();
+    // ---- w = p - (tau / 2)(p^T v) v and A -= v w^T + w v^T on the active tiles
+    {
+      double vr[TA], pr[TA], vc[TB], pc[TB], dv[4], dp[4];
+#pragma unroll
+      for (int a = 0; a < TA; ++a) {
+        vr[a] = vbuf[16 * a + tr];
+        pr[a] = pbuf[16 * a + tr];
+      }
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        vc[b] = vbuf[32 * b + tc];
+        pc[b] = pbuf[32 * b + tc];
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int i = r0 + lane + 64 * m;
+        const int ii = i < 32 * TB ? i : 0;
+        dv[m] = vbuf[ii];
+        dp[m] = (i < 32 * TB) ? pbuf[ii] : 0.0;
+      }
+      double dl = 0.0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) dl = fma(dp[m], dv[m], dl);
+      const double kk = -0.5 * tj * dpp_wave_sum(dl);
+#pragma unroll
+      for (int a = 0; a < TA; ++a) {
+        if (a >= a0) {
+          const double wr = fma(kk, vr[a], pr[a]);
+#pragma unroll
+          for (int b = 0; b <= a / 2; ++b)
+            if (b >= b0) A[tile_base(a) + b] -= fma(vr[a], fma(kk, vc[b], pc[b]), wr * vc[b]);
+        }
+      }
+    }
+  }
+  // the trailing 2 x 2 (or 1 x 1) block
+  __syncthreads();
+  if (k >= 2) put_column<TA>(A, k - 2, k, tr, tc, xb);
+  put_column<TA>(A, k - 1, k, tr, tc, cb);
+  __syncthreads();
+  if (tid == 0) {
+    if (k >= 2) {
+      d[k - 2] = xb[k - 2];
+      e[k - 2] = xb[k - 1];
+      tau[k - 2] = 0.0;
+    }
+    d[k - 1] = cb[k - 1];
+    e[k - 1] = 0.0;
+    tau[k - 1] = 0.0;
+  }
+  __syncthreads();
+}
+
+// ---- end of phase 1 (both paths): squared off-diagonal, Gershgorin interval, |T|
+//      and the power-of-two scaled copy used by the Sturm counts.
+//      sh = {lower bound, upper bound, |T|, scale}
+__device__ __forceinline__ void finish_tridiag(int k, const double* d, const double* e, double* e2, double* dn,
+                                               double* e2n, double* sh) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < 64) {
+    double gl = DBL_MAX, gu = -DBL_MAX, em = 0.0;
+    for (int i = lane; i < k; i += 64) {
+      const double off = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < k ? fabs(e[i]) : 0.0);
+      gl = fmin(gl, d[i] - off);
+      gu = fmax(gu, d[i] + off);
+      const double ee = (i + 1 < k) ? e[i] * e[i] : 0.0;
+      e2[i] = ee;
+      em = fmax(em, ee);
+    }
+    gl = dpp_wave_minmax<false>(gl);
+    gu = dpp_wave_minmax<true>(gu);
+    em = dpp_wave_minmax<true>(em);
+    if (lane == 0) {
+      const double tn = fmax(fabs(gl), fabs(gu));
+      const double pivmin = DBL_MIN * fmax(1.0, em);
+      sh[0] = gl - 2.2e-16 * tn - pivmin;
+      sh[1] = gu + 2.2e-16 * tn + pivmin;
+      sh[2] = tn;
+      sh[3] = tn > 0.0 ? __builtin_amdgcn_ldexp(1.0, -__builtin_amdgcn_frexp_exp(tn)) : 1.0;
+    }
+  }
+  __syncthreads();
+  const double sc = sh[3];
+  for (int i = tid; i < k; i += ET) {
+    dn[i] = d[i] * sc;
+    const double es = (i + 1 < k) ? e[i] * sc : 0.0;
+    e2n[i] = es * es;
+  }
+  __syncthreads();
+}
+
+// ---- phases 2 and 3: the leading eigenvalues and the truncation rule.  The
+//      discarded energy of rank c is trace(T) minus the sum of the c leading
+//      eigenvalues (clipped at 0); eigenvalues are found in descending chunks (8,
+//      then 32 at a time) only until the rule is decided.  Each eigenvalue is
+//      isolated by multisection: 16 lanes of a wave evaluate Sturm counts at 16
+//      interior points of its interval and keep the sub-interval that holds it.
+//      top[m] receives the m-th largest eigenvalue; returns how many were found.
+__device__ __forceinline__ int top_eigen_rank(const double* dn, const double* e2n, const double* d, int k,
+                                              const double* sh, int rmin, int rmax, double thr, double* top,
+                                              int* rank_out, double* tail_out, int* s_rank, double* s_acc) {
+  constexpr int T = 16;
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < 64) {
+    double t = 0.0;
+    for (int i = lane; i < k; i += 64) t += d[i];
+    t = dpp_wave_sum(t);
+    if (lane == 0) {
+      s_acc[0] = t;    // trace(T)
+      s_acc[1] = 0.0;  // sum of the clipped eigenvalues found so far
+    }
+  }
+  __syncthreads();
+  const int kmax = min(k, rmax);
+  const double atol = 2.2e-16 * sh[2], sc = sh[3];
+  const int slot = tid / T, u = tid % T, gbase = lane - (lane % T);
+  int m0 = 0, chunk = 8;
+  for (;;) {
+    const int m = m0 + slot;
+    if (slot < chunk && m < k) {
+      const int idx = k - 1 - m;      // ascending index
+      double lo = sh[0], hi = sh[1];  // invariant: count(lo) <= idx < count(hi)
+      for (int it = 0; it < 160; ++it) {
+        const bool done = hi - lo <= fmax(2.2e-16 * fmax(fabs(lo), fabs(hi)), atol);
+        if (__all(done)) break;
+        const double w = (hi - lo) / (double)(T + 1);
+        const double x = lo + w * (double)(u + 1);
+        bool above = false;
+        if (!done && x < hi && x > lo) {
+          bool tiny;
+          int cnt = sturm_fast(dn, e2n, k, x * sc, tiny);
+          if (tiny) cnt = sturm_scaled(dn, e2n, k, x * sc);
+          above = cnt > idx;
+        } else {
+          above = !done && x >= hi;
+        }
+        const unsigned long long msk = __ballot(above);
+        if (!done) {
+          const unsigned long long gm = (msk >> gbase) & ((1ull << T) - 1);
+          double nlo, nhi;
+          if (gm == 0) {
+            nlo = lo + w * (double)T;
+            nhi = hi;
+          } else {
+            const int us = __builtin_ctzll(gm);
+            nhi = lo + w * (double)(us + 1);
+            nlo = us > 0 ? lo + w * (double)us : lo;
+          }
+          if (nhi > hi) nhi = hi;
+          if (nlo < lo) nlo = lo;
+          lo = nlo;
+          hi = nhi;
+        }
+      }
+      if (u == 0) top[m] = 0.5 * (lo + hi);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double tr = s_acc[0];
+      double S = s_acc[1];
+      const int cend = min(min(kmax, m0 + chunk), k);
+      int r = -1;
+      double tl = 0.0;
+      int c = m0;
+      for (; c <= cend; ++c) {
+        if (c >= rmin && tr - S <= thr) {
+          r = c;
+          tl = tr - S;
+          break;
+        }
+        if (c < cend) S += fmax(top[c], 0.0);
+      }
+      if (r < 0 && cend == kmax) {
+        r = kmax;
+        tl = tr - S;
+      }
+      if (r >= 0) {
+        *rank_out = r;
+        *tail_out = fmax(tl, 0.0);
+      }
+      *s_rank = r;
+      s_acc[1] = S;
+    }
+    __syncthreads();
+    const int found = min(m0 + chunk, k);
+    if (*s_rank >= 0 || found >= k) {
+      if (*s_rank < 0 && tid == 0) *s_rank = kmax;  // not reached: found == k implies cend == kmax
+      __syncthreads();
+      return found;
+    }
+    m0 += chunk;
+    chunk = ET / T;
+  }
+}
+
+// ---- phase 4a: inverse iteration (two sweeps from a fixed pseudo-random start),
+//      one thread per vector, for the r leading eigenvalues (top, descending).  W holds 4 k r doubles: the iterate Z and the
+//      three rows of U of the partial-pivoting LU of T - lambda I; entry (i, j) of
+//      each at i * r + j.
+__device__ __forceinline__ void inverse_iteration(double* W, int k, int r, const double* top, const double* d,
+                                                  const double* e, double tnorm) {
+  const int tid = threadIdx.x;
+  double* Z = W;
+  double* U0 = Z + (size_t)k * r;
+  double* U1 = U0 + (size_t)k * r;
+  double* U2 = U1 + (size_t)k * r;
+  const double tiny = fmax(2.2e-16 * tnorm, DBL_MIN);
+  for (int j = tid; j < r; j += ET) {
+    const double lm = top[j];
+    for (int i = 0; i < k; ++i) Z[(size_t)i * r + j] = start_entry(j, i);
+    for (int it = 0; it < 2; ++it) {
+      // forward: factor T - lm I row by row with partial pivoting, apply to the rhs
+      double u0 = d[0] - lm, u1 = (k > 1) ? e[0] : 0.0, u2 = 0.0;
+      double bi = Z[j];
+      for (int i = 0; i + 1 < k; ++i) {
+        const double l0 = e[i], l1 = d[i + 1] - lm, l2 = (i + 2 < k) ? e[i + 1] : 0.0;
+        double bn = Z[(size_t)(i + 1) * r + j];
+        double nu0, nu1;
+        if (fabs(u0) >= fabs(l0)) {
+          if (u0 == 0.0) u0 = tiny;
+          const double mlt = l0 / u0;
+          U0[(size_t)i * r + j] = u0;
+          U1[(size_t)i * r + j] = u1;
+          U2[(size_t)i * r + j] = u2;
+          Z[(size_t)i * r + j] = bi;
+          nu0 = l1 - mlt * u1;
+          nu1 = l2 - mlt * u2;
+          bn = bn - mlt * bi;
+        } else {
+          const double mlt = u0 / l0;
+          U0[(size_t)i * r + j] = l0;
+          U1[(size_t)i * r + j] = l1;
+          U2[(size_t)i * r + j] = l2;
+          Z[(size_t)i * r + j] = bn;
+          nu0 = u1 - mlt * l1;
+          nu1 = u2 - mlt * l2;
+          bn = bi - mlt * bn;
+        }
+        u0 = nu0;
+        u1 = nu1;
+        u2 = 0.0;
+        bi = bn;
+      }
+      if (fabs(u0) < tiny) u0 = (u0 < 0.0) ? -tiny : tiny;
+      // backward substitution, the two previous unknowns kept in registers and the
+      // next rows' factors loaded one step ahead
+      double x1 = bi / u0, x2 = 0.0, mx = fabs(x1);
+      Z[(size_t)(k - 1) * r + j] = x1;
+      if (k >= 2) {
+        size_t o = (size_t)(k - 2) * r + j;
+        double q0 = U0[o], q1 = U1[o], q2 = U2[o], qz = Z[o];
+        for (int i = k - 2; i >= 0; --i) {
+          const size_t on = (i > 0) ? o - r : o;
+          const double n0 = U0[on], n1 = U1[on], n2 = U2[on], nz = Z[on];
+          double piv = q0;
+          if (fabs(piv) < tiny) piv = (piv < 0.0) ? -tiny : tiny;
+          const double x = (qz - q1 * x1 - q2 * x2) / piv;
+          Z[o] = x;
+          x2 = x1;
+          x1 = x;
+          mx = fmax(mx, fabs(x));
+          q0 = n0;
+          q1 = n1;
+          q2 = n2;
+          qz = nz;
+          o = on;
+        }
+      }
+      const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
+      for (int i = 0; i < k; ++i) Z[(size_t)i * r + j] *= inv;
+    }
+  }
+  __syncthreads();
+}
+
+// ---- phase 4b: orthonormalise the r columns of Z in order (classical
+//      Gram-Schmidt, two passes)
+__device__ __forceinline__ void cgs2_columns(double* Z, int k, int r, double* pb, double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int pass = 0; pass < 2; ++pass) {
     for (int j = 0; j < r; ++j) {
       for (int t = wave; t < j; t += NW) {
@@ -370,9 +831,29 @@ __device__ __forceinline__ void eigenvectors(double* Z, int k, int r, const doub
       __syncthreads();
     }
   }
+}
 
-  // ---- 4c. back-transformation x = Q z: each wave applies every reflector to its
-  //          own vectors, so no block barrier is needed between reflectors
+// sign rule on a wave-held vector: the largest-magnitude entry (lowest index on ties)
+// is made positive; returns the factor
+__device__ __forceinline__ double sign_factor(double best, int bidx, double at_best) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o);
+    const int oi = __shfl_xor(bidx, o);
+    const double ov = __shfl_xor(at_best, o);
+    if (ob > best || (ob == best && oi < bidx)) {
+      best = ob;
+      bidx = oi;
+      at_best = ov;
+    }
+  }
+  return at_best < 0.0 ? -1.0 : 1.0;
+}
+
+// ---- phase 4c, packed path: x = Q z with each wave applying every reflector
+//      (global hv rows) to its own vectors, then the sign rule
+__device__ __forceinline__ void back_transform_wave(double* Z, int k, int r, const double* tau,
+                                                    const double* __restrict__ hv, double* vecs) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int j = wave; j < r; j += NW) {
     for (int jj = k - 3; jj >= 0; --jj) {
       const double tj = tau[jj];
@@ -389,62 +870,216 @@ __device__ __forceinline__ void eigenvectors(double* Z, int k, int r, const doub
   }
   __syncthreads();
   for (int j = wave; j < r; j += NW) {
-    double best = -1.0;
+    double best = -1.0, at = 0.0;
     int bidx = 0;
     for (int i = lane; i < k; i += 64) {
-      const double a = fabs(Z[(size_t)i * r + j]);
-      if (a > best) {
-        best = a;
+      const double z = Z[(size_t)i * r + j];
+      if (fabs(z) > best) {
+        best = fabs(z);
         bidx = i;
+        at = z;
       }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o);
-      const int oi = __shfl_xor(bidx, o);
-      if (ob > best || (ob == best && oi < bidx)) {
-        best = ob;
-        bidx = oi;
-      }
-    }
-    const double sg = Z[(size_t)bidx * r + j] < 0.0 ? -1.0 : 1.0;
+    const double sg = sign_factor(best, bidx, at);
     for (int i = lane; i < k; i += 64) vecs[(size_t)j * k + i] = sg * Z[(size_t)i * r + j];
   }
 }
 
-template <bool SMALL_LDS>
-__global__ __launch_bounds__(ET) void eig_trunc_kernel(EigBatch batch) {
-  const EigJob J = batch.j[blockIdx.x];
-  // phase clocks (wall_clock64 ticks) in the 64 spare doubles at the end of the scratch
-  double* clk = J.scratch + (eig_scratch_doubles_dev(J.k, J.rmax) - 64);
-#define HT_EIG_MARK(i) \
-  if (threadIdx.x == 0) clk[i] = (double)wall_clock64();
-  HT_EIG_MARK(0)
-  extern __shared__ double lds[];
-  __shared__ double red[NW];
-  __shared__ double s_gl, s_gu, s_pivmin, s_tnorm;
-  __shared__ int s_rank;
-  const int k = J.k;
+// ---- phase 4c, register path (k <= 64 ZR, r <= kStagedVectors): the vectors stay in the
+//      registers of their wave (vector wave + NW t); the reflectors are staged
+//      through LDS 32 at a time by the whole workgroup, so each is read from
+//      global memory once.
+constexpr int kStagedVectors = 64;  // vectors kept in registers by the staged back-transformation
+
+template <int ZR>
+__device__ __forceinline__ void back_transform_staged(const double* Z, int k, int r, const double* tau,
+                                                      const double* __restrict__ hv, double* stage, double* vecs) {
+  constexpr int MV = kStagedVectors / NW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nv = (r - wave + NW - 1) / NW;  // vectors of this wave
+  double z[MV][ZR];
+#pragma unroll
+  for (int t = 0; t < MV; ++t) {
+    const int j = wave + NW * t;
+#pragma unroll
+    for (int m = 0; m < ZR; ++m) {
+      const int i = lane + 64 * m;
+      z[t][m] = (j < r && i < k) ? Z[(size_t)i * r + j] : 0.0;
+    }
+  }
+  __syncthreads();  // Z may share the staging area
+  for (int top = k - 3; top >= 0; top -= 32) {
+    const int lo = top >= 31 ? top - 31 : 0;
+    for (int q = wave; q <= top - lo; q += NW) {
+      const int jj = lo + q;
+      for (int i = lane; i < k; i += 64) stage[q * k + i] = (i > jj) ? hv[(int64_t)jj * k + i] : 0.0;
+    }
+    __syncthreads();
+    if (nv > 0) {
+      for (int jj = top; jj >= lo; --jj) {
+        const double tj = tau[jj];
+        if (tj == 0.0) continue;
+        const double* vr = stage + (jj - lo) * k;
+        double v[ZR];
+#pragma unroll
+        for (int m = 0; m < ZR; ++m) {
+          const int i = lane + 64 * m;
+          v[m] = i < k ? vr[i] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < MV; ++t) {
+          if (t < nv) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < ZR; ++m) s = fma(v[m], z[t][m], s);
+            s = dpp_wave_sum(s) * tj;
+#pragma unroll
+            for (int m = 0; m < ZR; ++m) z[t][m] = fma(-s, v[m], z[t][m]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < MV; ++t) {
+    if (t < nv) {
+      const int j = wave + NW * t;
+      double best = -1.0, at = 0.0;
+      int bidx = 0;
+#pragma unroll
+      for (int m = 0; m < ZR; ++m) {
+        const int i = lane + 64 * m;
+        if (i < k && fabs(z[t][m]) > best) {
+          best = fabs(z[t][m]);
+          bidx = i;
+          at = z[t][m];
+        }
+      }
+      const double sg = sign_factor(best, bidx, at);
+#pragma unroll
+      for (int m = 0; m < ZR; ++m) {
+        const int i = lane + 64 * m;
+        if (i < k) vecs[(size_t)j * k + i] = sg * z[t][m];
+      }
+    }
+  }
+}
 
-  // ---- carve scratch (global) and LDS
+// Global scratch of one problem (doubles): packed triangle (packed path), the
+// Householder vectors (row j = reflector j), 6 k small vectors (packed path),
+// tau, ascending eigenvalues, tail sums, the inverse-iteration arrays when they do
+// not fit in LDS, 64 doubles of phase clocks.
+struct EigScratch {
+  double* P;
+  double* hv;
+  double* small;
+  double* tau;
+  double* lam;
+  double* tail;
+  double* gz;
+  double* clk;
+};
+
+__device__ __forceinline__ EigScratch carve(const EigJob& J) {
+  const size_t K = (size_t)J.k;
+  EigScratch c;
   double* sc = J.scratch;
-  double* gP = sc;  // packed lower triangle when it does not fit in LDS
-  sc += (size_t)k * (k + 1) / 2;
-  double* hv = sc;  // Householder vectors, reflector j in row j
-  sc += (size_t)k * k;
-  double* gsmall = sc;
-  sc += (size_t)6 * k;
-  double* tau = sc;
-  sc += k;
-  double* lam = sc;  // ascending eigenvalues
-  sc += k;
-  double* tail = sc;
-  sc += k + 1;
-  double* gz = sc;  // 4 k rmax, used when the inverse-iteration arrays do not fit in LDS
+  c.P = sc;
+  sc += K * (K + 1) / 2;
+  c.hv = sc;
+  sc += K * K;
+  c.small = sc;
+  sc += 6 * K;
+  c.tau = sc;
+  sc += K;
+  c.lam = sc;
+  sc += K;
+  c.tail = sc;
+  sc += K + 1;
+  c.gz = sc;
+  c.clk = J.scratch + (eig_scratch_doubles_dev(J.k, J.rmax) - 64);
+  return c;
+}
 
-  // the storage choice is a compile-time one so that every access keeps a single
-  // address space (LDS accesses through a generic pointer would be flat loads)
-  double* small = SMALL_LDS ? lds : gsmall;
+#define HT_EIG_MARK(i) \
+  if (threadIdx.x == 0) c.clk[i] = (double)wall_clock64();
+
+// LDS of the register path (doubles): d, e, e2, tau, dn, e2n, top, xb, cb, vbuf,
+// pbuf (256 each), then one region shared by the row and column partials (phase
+// 1), the inverse-iteration arrays (4a, 4b) and the reflector staging (4c).
+constexpr int kRegSmall = 11 * 256;
+
+// Phase 1 of the register path, the only part that depends on the tile count: one
+// instantiation per tile count, each a compact loop (the code of all phases
+// together would not fit the instruction cache).
+template <int TA>
+__device__ __noinline__ void phase1_reg(const EigJob& J, double* lds, double* sh) {
+  double* d = lds;
+  double* e = d + 256;
+  double* tau = e + 512;
+  double* xb = lds + 7 * 256;
+  double* cb = xb + 256;
+  double* vbuf = cb + 256;
+  double* pbuf = vbuf + 256;
+  double* region = lds + kRegSmall;
+  const EigScratch c = carve(J);
+  tridiag_reg<TA>(J.G, J.k, xb, cb, vbuf, pbuf, region, region + 32 * (16 * TA + 1), d, e, tau, c.hv, sh + 4);
+}
+
+// Phases 2 - 4 of the register path (k <= 16 kRegRowTiles), after phase1_reg.
+__device__ __forceinline__ void solve_reg_tail(const EigJob& J, double* lds, double* sh, int* s_rank, double* red) {
+  constexpr int ZR = (16 * kRegRowTiles + 63) / 64;
+  const EigScratch c = carve(J);
+  const int k = J.k, tid = threadIdx.x;
+  double* d = lds;
+  double* e = d + 256;
+  double* e2 = e + 256;
+  double* tau = e2 + 256;
+  double* dn = tau + 256;
+  double* e2n = dn + 256;
+  double* top = e2n + 256;
+  double* pbuf = lds + 10 * 256;
+  double* region = lds + kRegSmall;
+  const int64_t region_cap = kLdsDoubles - kRegSmall;
+
+  finish_tridiag(k, d, e, e2, dn, e2n, sh);
+  HT_EIG_MARK(1)
+  const int found = top_eigen_rank(dn, e2n, d, k, sh, J.rmin, J.rmax, J.thr, top, J.rank, J.tail, s_rank, sh + 6);
+  for (int i = tid; i < found; i += ET) J.evals[i] = top[i];
+  const int r = *s_rank;
+  HT_EIG_MARK(2)
+  if (r == 0) return;
+  if ((int64_t)4 * k * r <= region_cap) {
+    inverse_iteration(region, k, r, top, d, e, sh[2]);
+    HT_EIG_MARK(3)
+    cgs2_columns(region, k, r, pbuf, red);
+    HT_EIG_MARK(4)
+    if (r <= kStagedVectors)
+      back_transform_staged<ZR>(region, k, r, tau, c.hv, region, J.vecs);
+    else
+      back_transform_wave(region, k, r, tau, c.hv, J.vecs);
+  } else {
+    inverse_iteration(c.gz, k, r, top, d, e, sh[2]);
+    HT_EIG_MARK(3)
+    cgs2_columns(c.gz, k, r, pbuf, red);
+    HT_EIG_MARK(4)
+    if (r <= kStagedVectors)
+      back_transform_staged<ZR>(c.gz, k, r, tau, c.hv, region, J.vecs);
+    else
+      back_transform_wave(c.gz, k, r, tau, c.hv, J.vecs);
+  }
+  HT_EIG_MARK(6)
+}
+
+// One problem on the packed path.  SMALL_LDS: the 6 k vectors (d, e, e2 and three
+// work vectors) live in LDS (k <= kSmallMax), else in global scratch; the storage
+// choice is a compile-time one so every access keeps a single address space.
+template <bool SMALL_LDS>
+__device__ __forceinline__ void solve_packed(const EigJob& J, double* lds, double* sh, int* s_rank, double* red) {
+  const EigScratch c = carve(J);
+  const int k = J.k, tid = threadIdx.x;
+  double* small = SMALL_LDS ? lds : c.small;
   double* d = small;
   double* e = d + k;
   double* e2 = e + k;
@@ -454,7 +1089,45 @@ __global__ __launch_bounds__(ET) void eig_trunc_kernel(EigBatch batch) {
   double* work = lds + (SMALL_LDS ? 6 * k : 0);
   const int64_t work_cap = kLdsDoubles - (SMALL_LDS ? 6 * k : 0);
   const int64_t npk = (int64_t)k * (k + 1) / 2;
-  const bool packed_lds = npk <= work_cap;
+
+  if (npk <= work_cap)
+    tridiagonalise_packed(work, J.G, k, vb, pb, wb, red, d, e, c.tau, c.hv);
+  else
+    tridiagonalise_packed(c.P, J.G, k, vb, pb, wb, red, d, e, c.tau, c.hv);
+  // vb and wb are free again: they hold the scaled copy for the Sturm counts
+  finish_tridiag(k, d, e, e2, vb, wb, sh);
+  HT_EIG_MARK(1)
+  const int found = top_eigen_rank(vb, wb, d, k, sh, J.rmin, J.rmax, J.thr, c.lam, J.rank, J.tail, s_rank, sh + 6);
+  for (int i = tid; i < found; i += ET) J.evals[i] = c.lam[i];
+  const int r = *s_rank;
+  HT_EIG_MARK(2)
+  if (r == 0) return;
+  if ((int64_t)4 * k * r <= work_cap) {
+    inverse_iteration(work, k, r, c.lam, d, e, sh[2]);
+    HT_EIG_MARK(3)
+    cgs2_columns(work, k, r, pb, red);
+    HT_EIG_MARK(4)
+    back_transform_wave(work, k, r, c.tau, c.hv, J.vecs);
+  } else {
+    inverse_iteration(c.gz, k, r, c.lam, d, e, sh[2]);
+    HT_EIG_MARK(3)
+    cgs2_columns(c.gz, k, r, pb, red);
+    HT_EIG_MARK(4)
+    back_transform_wave(c.gz, k, r, c.tau, c.hv, J.vecs);
+  }
+  HT_EIG_MARK(6)
+}
+
+template <bool SMALL_LDS>
+__global__ __launch_bounds__(ET) void eig_trunc_kernel(EigBatch batch) {
+  const EigJob J = batch.j[blockIdx.x];
+  const EigScratch c = carve(J);
+  HT_EIG_MARK(0)
+  extern __shared__ double lds[];
+  __shared__ double red[NW];
+  __shared__ double sh[8];
+  __shared__ int s_rank;
+  const int k = J.k, tid = threadIdx.x;
 
   // all the energy already within the budget and no rank floor: the rule keeps
   // nothing (tail(0) = trace <= thr), so the decomposition is not needed
@@ -470,93 +1143,32 @@ __global__ __launch_bounds__(ET) void eig_trunc_kernel(EigBatch batch) {
       return;
     }
   }
-
-  // ---- 1. tridiagonalisation
-  if (packed_lds)
-    tridiagonalise(work, J.G, k, vb, pb, wb, red, d, e, e2, tau, hv, &s_gl, &s_gu, &s_pivmin, &s_tnorm, clk);
-  else
-    tridiagonalise(gP, J.G, k, vb, pb, wb, red, d, e, e2, tau, hv, &s_gl, &s_gu, &s_pivmin, &s_tnorm, clk);
-
-  HT_EIG_MARK(1)
-  // ---- 2. all eigenvalues by multisection: T lanes of one wave share an eigenvalue,
-  //         evaluate Sturm counts at T interior points and keep the sub-interval.
-  {
-    const double tn = s_tnorm, pivmin = s_pivmin;
-    const double atol = 2.2e-16 * tn;
-    int T = 1;
-    while (T < 64 && 2 * T * k <= ET) T *= 2;
-    const int groups = ET / T;
-    const int u = tid % T;
-    const int gbase = lane - (lane % T);
-    // a group's lanes share idx, so every group runs a uniform number of rounds
-    for (int idx = tid / T; idx < k; idx += groups) {
-      double lo = s_gl, hi = s_gu;  // invariant: count(lo) <= idx < count(hi)
-      for (int it = 0; it < 160; ++it) {
-        const bool done = hi - lo <= fmax(2.2e-16 * fmax(fabs(lo), fabs(hi)), atol);
-        if (__all(done)) break;
-        const double w = (hi - lo) / (double)(T + 1);
-        const double x = lo + w * (double)(u + 1);
-        bool above = false;
-        if (!done) above = (x >= hi) ? true : (x <= lo) ? false : (sturm_count(d, e2, k, x, pivmin) > idx);
-        const unsigned long long m = __ballot(above);
-        if (!done) {
-          const unsigned long long gm = (m >> gbase) & ((T == 64) ? ~0ull : ((1ull << T) - 1));
-          double nlo, nhi;
-          if (gm == 0) {
-            nlo = lo + w * (double)T;
-            nhi = hi;
-          } else {
-            const int us = __builtin_ctzll(gm);
-            nhi = lo + w * (double)(us + 1);
-            nlo = us > 0 ? lo + w * (double)us : lo;
-          }
-          if (nhi > hi) nhi = hi;
-          if (nlo < lo) nlo = lo;
-          lo = nlo;
-          hi = nhi;
-        }
+  if constexpr (SMALL_LDS) {
+    if (k <= 16 * kRegRowTiles) {
+      switch ((k + 15) >> 4) {
+        case 1: phase1_reg<1>(J, lds, sh); break;
+        case 2: phase1_reg<2>(J, lds, sh); break;
+        case 3: phase1_reg<3>(J, lds, sh); break;
+        case 4: phase1_reg<4>(J, lds, sh); break;
+        case 5: phase1_reg<5>(J, lds, sh); break;
+        case 6: phase1_reg<6>(J, lds, sh); break;
+        case 7: phase1_reg<7>(J, lds, sh); break;
+        case 8: phase1_reg<8>(J, lds, sh); break;
+        case 9: phase1_reg<9>(J, lds, sh); break;
+        case 10: phase1_reg<10>(J, lds, sh); break;
+        case 11: phase1_reg<11>(J, lds, sh); break;
+        case 12: phase1_reg<12>(J, lds, sh); break;
+        case 13: phase1_reg<13>(J, lds, sh); break;
+        case 14: phase1_reg<14>(J, lds, sh); break;
+        default: break;
       }
-      if (u == 0) lam[idx] = 0.5 * (lo + hi);
+      solve_reg_tail(J, lds, sh, &s_rank, red);
+      return;
     }
   }
-  __syncthreads();
-
-  HT_EIG_MARK(2)
-  // ---- 3. truncation rule
-  if (tid == 0) {
-    double acc = 0.0;
-    tail[k] = 0.0;
-    for (int i = 0; i < k; ++i) {
-      const double l = lam[i];
-      acc += l > 0.0 ? l : 0.0;
-      tail[k - 1 - i] = acc;
-    }
-    const int kmax = min(k, J.rmax);
-    int r = kmax;
-    for (int cand = J.rmin; cand <= kmax; ++cand) {
-      if (tail[cand] <= J.thr) {
-        r = cand;
-        break;
-      }
-    }
-    s_rank = r;
-    *J.rank = r;
-    *J.tail = tail[r];
-  }
-  for (int i = tid; i < k; i += ET) J.evals[i] = lam[k - 1 - i];
-  __syncthreads();
-  const int r = s_rank;
-  if (r == 0) return;
-
-  HT_EIG_MARK(3)
-  // ---- 4. eigenvectors, in LDS when the 4 k r work arrays fit
-  if ((int64_t)4 * k * r <= work_cap)
-    eigenvectors(work, k, r, lam, d, e, pb, red, tau, hv, J.vecs, s_tnorm);
-  else
-    eigenvectors(gz, k, r, lam, d, e, pb, red, tau, hv, J.vecs, s_tnorm);
-  HT_EIG_MARK(6)
-#undef HT_EIG_MARK
+  solve_packed<SMALL_LDS>(J, lds, sh, &s_rank, red);
 }
+#undef HT_EIG_MARK
 
 }  // namespace
 

@@ -57,7 +57,7 @@ void ttm_expand(const double* Z, int64_t P, int R, int64_t S, const double* U, i
 struct EigJob {
   const double* G;     // k x k symmetric, row-major
   double* scratch;     // eig_scratch_doubles(k, rmax) doubles
-  double* evals;       // out: k eigenvalues, descending
+  double* evals;       // out: the leading eigenvalues, descending (as many as the rule needed, >= rank)
   double* vecs;        // out: k x r eigenvectors (column-major, sign-normalised)
   int* rank;           // out: chosen rank r
   double* tail;        // out: discarded energy sum_{i>=r} max(lambda_i, 0)

@@ -324,7 +324,7 @@ def ht_test_eig(G, rmin: int, rmax: int, thr: float, stream=None):
     k = G.shape[0]
     L = _tlib()
     sc = torch.empty(L.ht_test_eig_scratch_doubles(k, max(rmax, 1)), dtype=torch.float64, device=G.device)
-    ev = torch.empty(k, dtype=torch.float64, device=G.device)
+    ev = torch.full((k,), float('nan'), dtype=torch.float64, device=G.device)
     vecs = torch.zeros((max(rmax, 1), k), dtype=torch.float64, device=G.device)
     rank = torch.zeros(1, dtype=torch.int32, device=G.device)
     tail = torch.zeros(1, dtype=torch.float64, device=G.device)
