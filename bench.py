@@ -1,23 +1,32 @@
 #!/usr/bin/env python3
-"""HT-RISE ingest throughput on one MI355X.
+"""HT-RISE ingest throughput on one MI355X: mixed precision form vs plain FP64.
 
 Workload: the 96x96x96x3 drifting separable-field stream, N = 32 samples per
 batch, 20 batches, eps = 1e-4, rank capacity 48 (84,934,656 elements per
 batch).  One step compresses the whole stream from scratch: BHT-l2r on batch 0
 and HT-RISE on batches 1..19, every batch already resident in HBM as float32.
-`value` is elements ingested per second over the timed steps.
+Both forms run on the same staged data:
 
-Also reported: the roofline position of the dominant kernel class, measured
-live with the library's HIP-event instrumentation over the timed steps, and the
-FP64 NumPy oracle timed on this host on a bounded sample of the same stream.
+  fp64   every contraction and Gram product on FP64 matrix cores;
+  mixed  HT-RISE contractions and residual Grams on FP32 matrix cores with FP64
+         sums, skip test from explicit residual energies; BHT-l2r, eigen solves,
+         decisions and expansion in FP64.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+`value` is the mixed form's elements ingested per second over the timed steps;
+the plain form's rate and the ratio are reported beside it, together with the
+HT-RISE-only rates (update calls only, as the paper times updates).  Each run is
+checked after timing against the oracle's stored rank / skip trace and the
+per-batch error bound.  Also reported: the roofline position of the mixed form's
+dominant kernel class (HIP-event timing inside the library, on the launch
+stream), and the FP64 NumPy oracle timed on this host on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--form both|mixed|fp64]
+    python bench.py --copy-probe      # a plain 256 MiB device copy (counter calibration)
 """
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -29,8 +38,13 @@ if ROOT not in sys.path:
 METRIC = "HT-RISE ingest elements/s at rel. err ≤1e-4, mixed-prec batched vs FP64 plain"
 EPS = 1e-4
 RANK_CAP = 48
-PEAK_FP64_TFLOPS = 78.6
+BOUND_SLACK = 1e-3
+# MI355X datasheet peaks (dense)
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 PEAK_HBM_GBS = 8000.0
+# profile kind -> arithmetic type of its products
+KIND_TYPE = {"gram": "f64", "ttm_contract": "f64", "ttm_expand": "f64", "sumsq": "f64", "gram_f32": "f32",
+             "ttm_contract_f32": "f32"}
 
 
 def log(*a):
@@ -62,9 +76,26 @@ def traffic_for(kind: str):
     return None if ent is None else ent.get("hbm_bytes_per_launch")
 
 
+def roofline(kind: str, d: dict) -> dict:
+    """Achieved rate of a kernel class against the roofline that bounds it."""
+    ty = KIND_TYPE.get(kind, "f64")
+    peak_f = PEAK_TFLOPS[ty]
+    ai = d["flops"] / d["bytes"] if d["bytes"] > 0 else float("inf")
+    sec = d["ms"] * 1e-3
+    if ai > peak_f * 1e12 / (PEAK_HBM_GBS * 1e9):
+        ach = d["flops"] / sec / 1e12
+        r = {"bound": "mfma", "achieved": ach, "peak": peak_f, "unit": "TFLOP/s", "frac": ach / peak_f}
+    else:
+        ach = d["bytes"] / sec / 1e9
+        r = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS}
+    r.update({"kernel": kind, "dtype": ty, "launches": d["launches"], "avg_launch_ms": d["ms"] / d["launches"],
+              "flops_per_launch": d["flops"] / d["launches"], "bytes_per_launch": d["bytes"] / d["launches"],
+              "traffic": traffic_for(kind)})
+    return r
+
+
 def cpu_baseline(spec, n_sample: int):
     """The oracle as it stands, on the first n_sample batches of the same stream (host cores)."""
-    import numpy as np
     import datagen
     from oracle import ht_oracle as ho
     try:
@@ -86,23 +117,94 @@ def cpu_baseline(spec, n_sample: int):
             "ranks_after_sample": st.ranks}
 
 
+def copy_probe():
+    """A plain device copy of 256 MiB: the reference for the HBM byte counters."""
+    import torch
+    n = 1 << 25  # doubles
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}), flush=True)
+
+
+def run_form(form, spec, ys, golden, steps, warmup):
+    import torch
+    from paper_2412_16544_amd import htrise as H
+    nb = spec.n_batches
+    prec = H.HT_FP32 if form == "mixed" else H.HT_FP64
+    st = H.HTStream(spec.n, EPS, RANK_CAP, spec.N, spec.N * nb, "float32", prec=prec)
+
+    def one_pass():
+        st.reset()
+        return [st.push(y) for y in ys]
+
+    for w in range(warmup):
+        one_pass()
+        log("%s: warmup %d done" % (form, w))
+    torch.cuda.synchronize()
+    H.ht_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos = one_pass()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = H.ht_profile_read_all()
+    H.ht_profile_enable(False)
+    log("%s: timed %d steps in %.3f s" % (form, steps, elapsed))
+
+    # correctness of the last timed pass, outside the timed region
+    ranks, nacc = st.ranks()
+    ok = ranks == golden["batches"][-1]["ranks"] and nacc == spec.N * nb
+    ok = ok and all(i.skipped == g["skipped"] for i, g in zip(infos[1:], golden["batches"][1:]))
+    worst = 0.0
+    for k in (0, 1, nb // 2, nb - 1):
+        rec = st.reconstruct(spec.N * k, spec.N)
+        yk = ys[k].double()
+        worst = max(worst, (torch.linalg.vector_norm(rec - yk) / torch.linalg.vector_norm(yk)).item())
+    ok = ok and worst <= EPS * (1 + BOUND_SLACK)
+    log("%s: ranks/skips vs oracle trace and error bound: %s (worst sampled relative error %.3e)" % (form, ok, worst))
+    E = spec.elements_per_batch
+    upd = infos[1:]
+    upd_ms = sum(i.device_ms for i in upd)
+    kinds = {k: v for k, v in prof.items() if v["launches"] > 0}
+    cand = [k for k in KIND_TYPE if k in kinds]
+    dom = max(cand, key=lambda k: kinds[k]["ms"])
+    st.close()
+    return {
+        "value": nb * E * steps / elapsed,
+        "ms_per_step": elapsed * 1e3 / steps,
+        "rise_update_elements_per_s": (nb - 1) * E / (upd_ms * 1e-3) if upd_ms > 0 else None,
+        "init_batch_ms": infos[0].device_ms,
+        "update_batch_ms": sum(i.device_ms for i in upd if not i.skipped) / max(1, sum(not i.skipped for i in upd)),
+        "skip_batch_ms": sum(i.device_ms for i in upd if i.skipped) / max(1, sum(i.skipped for i in upd)),
+        "kernel_ms_per_step": {k: round(v["ms"] / steps, 3) for k, v in kinds.items()},
+        "roofline": roofline(dom, kinds[dom]),
+        "parity_vs_oracle_trace": bool(ok),
+        "worst_sampled_rel_error": worst,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--form", choices=("both", "mixed", "fp64"), default="both")
     ap.add_argument("--cpu-sample", type=int, default=4, help="batches of the oracle baseline (0 = skip)")
+    ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs a stream on a single device and this build "
               "has no multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
 
-    import numpy as np
     import torch
-
     import datagen
-    from paper_2412_16544_amd import htrise as H
 
     spec = datagen.field_96_spec()
     E = spec.elements_per_batch
@@ -111,83 +213,35 @@ def main():
     ys = [torch.from_numpy(y).to("cuda:0") for y in datagen.separable_field_stream(spec)]
     torch.cuda.synchronize()
     log("staged %d batches of %d elements in HBM (%.1f s)" % (nb, E, time.perf_counter() - t0))
-
-    st = H.HTStream(spec.n, EPS, RANK_CAP, spec.N, spec.N * nb, "float32")
-
-    def one_pass():
-        st.reset()
-        return [st.push(y) for y in ys]
-
-    for w in range(args.warmup):
-        one_pass()
-        log("warmup %d done" % w)
-    torch.cuda.synchronize()
-    H.ht_profile_enable(True)
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        infos = one_pass()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = H.ht_profile_read_all()
-    H.ht_profile_enable(False)
-    log("timed %d steps in %.3f s" % (args.steps, elapsed))
-
-    # correctness of the last timed pass, outside the timed region
     golden = json.load(open(os.path.join(ROOT, "tests", "golden", "field96_trace.json")))
-    ranks, nacc = st.ranks()
-    parity = ranks == golden["batches"][-1]["ranks"] and nacc == spec.N * nb
-    parity = parity and all(i.skipped == g["skipped"] for i, g in zip(infos[1:], golden["batches"][1:]))
-    worst = 0.0
-    for k in (0, nb // 2, nb - 1):
-        rec = st.reconstruct(spec.N * k, spec.N)
-        yk = ys[k].double()
-        worst = max(worst, (torch.linalg.vector_norm(rec - yk) / torch.linalg.vector_norm(yk)).item())
-    parity = parity and worst <= EPS
-    log("parity vs oracle trace: %s, worst sampled relative error %.3e" % (parity, worst))
 
-    # roofline of the dominant kernel class
-    kinds = {k: v for k, v in prof.items() if v["launches"] > 0}
-    dom = max(("gram", "ttm_contract", "ttm_expand", "sumsq"), key=lambda k: kinds.get(k, {"ms": 0})["ms"])
-    d = kinds[dom]
-    if dom == "gram":
-        achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS}
-    else:
-        achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS}
-    roof["kernel"] = dom
-    roof["launches"] = d["launches"]
-    roof["avg_launch_ms"] = d["ms"] / d["launches"]
-    roof["traffic"] = traffic_for(dom)
-
-    upd = [i for i in infos[1:]]
-    upd_ms = sum(i.device_ms for i in upd)
+    forms = ["mixed", "fp64"] if args.form == "both" else [args.form]
+    res = {f: run_form(f, spec, ys, golden, args.steps, args.warmup) for f in forms}
+    head = res[forms[0]]
     line = {
         "metric": METRIC,
-        "value": nb * E * args.steps / elapsed,
+        "value": head["value"],
         "unit": "elements/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if forms[0] == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": "96x96x96x3 drifting separable field, N=32 per batch, 20 batches, eps=1e-4, "
                                "rank_cap 48; step = BHT-l2r on batch 0 + HT-RISE on batches 1-19",
-                   "form": "fp64 plain", "elements_per_batch": E, "batches": nb},
-        "roofline": roof,
-        "rise_update_elements_per_s": (nb - 1) * E / (upd_ms * 1e-3) if upd_ms > 0 else None,
-        "init_batch_ms": infos[0].device_ms,
-        "update_batch_ms": sum(i.device_ms for i in upd if not i.skipped) / max(1, sum(not i.skipped for i in upd)),
-        "skip_batch_ms": sum(i.device_ms for i in upd if i.skipped) / max(1, sum(i.skipped for i in upd)),
-        "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in kinds.items()},
-        "parity_vs_oracle_trace": bool(parity),
+                   "form": forms[0], "elements_per_batch": E, "batches": nb},
+        "roofline": head["roofline"],
+        "forms": res,
     }
+    if len(forms) == 2:
+        line["mixed_over_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
+        r1, r2 = res["mixed"]["rise_update_elements_per_s"], res["fp64"]["rise_update_elements_per_s"]
+        line["mixed_over_fp64_rise_updates"] = r1 / r2 if r1 and r2 else None
+    line["parity_vs_oracle_trace"] = all(r["parity_vs_oracle_trace"] for r in res.values())
     if args.cpu_sample > 0:
         log("timing the oracle on %d batches of the same stream..." % args.cpu_sample)
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_sample)

@@ -65,7 +65,15 @@ typedef enum {
 } ht_status;
 
 /* Precision of the contractions and Gram products.  Eigen solves, rank
- * decisions and re-orthogonalisation are FP64 in every form. */
+ * decisions, re-orthogonalisation, the cores and the root are FP64 in every form.
+ *   HT_FP64  every contraction and Gram product on FP64 matrix cores.
+ *   HT_FP32  mixed form: in ht_rise_update, contractions of modes with at most 128
+ *            rows and their residual Grams on FP32 matrix cores with FP64 partial
+ *            sums, FP32 level tensors, and the skip test summed from the explicit
+ *            residual energy of each contraction; the first batch (ht_init_batch)
+ *            and ht_project run as HT_FP64.
+ *   HT_BF16X3 is rejected (HT_EINVAL): a split-BF16 product carries ~2^-16
+ *            relative error, which swamps eps_nw^2 when residuals are formed. */
 typedef enum { HT_FP64 = 0, HT_FP32 = 1, HT_BF16X3 = 2 } ht_precision;
 
 /* Element type of Y and of reconstructions. */
@@ -87,7 +95,8 @@ typedef struct {
   int32_t skipped;        /* 1 when the batch was represented well enough (Alg. 2 skip) */
   int32_t rank_growth;    /* sum over nodes of the ranks added by this call              */
   double norm_y;          /* ||Y||_F                                                     */
-  double eps_proj;        /* sqrt(max(0, ||Y||^2 - ||C_1||^2)) before the update          */
+  double eps_proj;        /* sqrt(max(0, ||Y||^2 - ||C_1||^2)) before the update (HT_FP32:
+                             sqrt of the summed residual energies of the projection)    */
   double eps_des;         /* eps_rel * ||Y||_F                                            */
   float device_ms;        /* device time of the call, from HIP events on hip_stream       */
 } ht_update_info;

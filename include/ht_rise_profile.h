@@ -6,9 +6,10 @@
  * (each operand read once, each result written once).  Off by default; when off
  * the launchers do no extra work.  Host-side state, one per process.
  *
- * Kinds: 0 sum of squares, 1 unfolding Gram, 2 TTM contraction, 3 TTM expansion /
- * residual, 4 eigen-decomposition and truncation, 5 basis expansion, 6 layout
- * (padding, root append, copies).
+ * Kinds: 0 sum of squares, 1 unfolding Gram (FP64 matrix cores), 2 TTM contraction
+ * (FP64), 3 TTM expansion / residual, 4 eigen-decomposition and truncation, 5 basis
+ * expansion, 6 layout (padding, root append, copies), 7 residual Gram on FP32 matrix
+ * cores, 8 TTM contraction on FP32 matrix cores (both of the HT_FP32 form).
  */
 #ifndef HT_RISE_PROFILE_H
 #define HT_RISE_PROFILE_H

@@ -38,6 +38,20 @@ ht_status ht_test_resid_gram(const void* x, int32_t dtype, int64_t P, int64_t m,
 ht_status ht_test_ttm_contract(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
                                int32_t R, double* Z, void* hip_stream);
 
+/* Mixed form (HT_FP32): the residual Gram above with every product on FP32 matrix
+ * cores and the workgroup partials summed in FP64.  Same arguments and scratch. */
+ht_status ht_test_resid_gram_f32(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
+                                 int32_t R, double* G, double* scratch, void* hip_stream);
+
+/* Mixed form contraction: Z (float32, [P][R][S]) = U^T X on FP32 matrix cores, with
+ * norm2[0] = ||X||^2 and resid2[0] = ||X - U U^T X||^2 (the explicit residual of
+ * Eq. compute_residual, summed in FP64).  m <= 128, 1 <= R <= 64; scratch holds
+ * 2 * ht_test_ttm_partials_doubles() doubles. */
+size_t ht_test_ttm_partials_doubles(void);
+ht_status ht_test_ttm_contract_f32(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
+                                   int32_t R, float* Z, double* norm2, double* resid2, double* scratch,
+                                   void* hip_stream);
+
 /* Mode expansion: out[p, a, s] = sum_t U[a, t] Z[p, t, s], or M[p, a, s] minus that when M
  * is not NULL (the residual of Eq. compute_residual).  1 <= R <= 64. */
 ht_status ht_test_ttm_expand(const double* Z, int64_t P, int32_t R, int64_t S, const double* U, int64_t m,

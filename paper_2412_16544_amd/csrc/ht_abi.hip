@@ -6,6 +6,16 @@
 // in the device kernels of ht_kernels.hip / ht_eig.hip.  The host reads back the
 // norms (skip test) and the rank decisions of each layer, because they size the
 // launches of the next step.
+//
+// Two precision forms.  HT_FP64: every contraction and Gram product on FP64 matrix
+// cores.  HT_FP32 (mixed): in HT-RISE updates, contractions with modes of at most
+// 128 rows and their residual Grams run on FP32 matrix cores with FP64 partial
+// sums, level tensors are stored in FP32, and the skip test sums the explicit
+// residual energy each contraction discards (||Y||^2 - ||C1||^2 telescopes into
+// these, and the difference of two FP32-accurate norms would not resolve
+// eps^2 ||Y||^2).  The first batch (BHT-l2r: Grams of the data itself), the
+// eigen-decompositions, truncation decisions, basis expansion and the cores stay
+// FP64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -118,6 +128,7 @@ struct ht_state {
   int rank_cap = 0;
   int64_t max_batch = 0, n_cap = 0;
   Elem in_t = Elem::F32;
+  bool mixed = false;  // HT_FP32 form
   Tree tree;
   // per-node capacities: rows of the basis matrix (alpha) and rank bound
   std::vector<int64_t> alpha_cap;
@@ -140,6 +151,7 @@ struct ht_state {
   double* scal = nullptr;
   double* sspart = nullptr;
   double* nrmpart = nullptr;
+  double* respart = nullptr;
   double* orthsc = nullptr;
   double* padtmp = nullptr;
   double* tails = nullptr;
@@ -156,8 +168,12 @@ struct Layout {
   // offsets (bytes)
   std::vector<size_t> core, gram, vecs, evals, eigsc;
   size_t core_backup = 0, core_backup_elems = 0, root = 0, bufA = 0, bufB = 0, buf_elems = 0, resid = 0, bufZ = 0,
-         resid_elems = 0, gpart = 0, scal = 0, sspart = 0, nrmpart = 0, orthsc = 0, padtmp = 0, tails = 0, ranks_dev = 0;
+         resid_elems = 0, gpart = 0, scal = 0, sspart = 0, nrmpart = 0, respart = 0, orthsc = 0, padtmp = 0, tails = 0,
+         ranks_dev = 0;
 };
+
+// device scalars: ||Y||^2, ||C1||^2, then two per node (mixed-form energies)
+size_t kScalars(int nn) { return 8 + 2 * (size_t)nn; }
 
 size_t take(Layout& L, size_t bytes) {
   const size_t off = L.total;
@@ -221,7 +237,7 @@ bool valid_config(const ht_config* c, std::string& why) {
   if (c->rank_cap < 1 || c->rank_cap > 64) return why = "rank_cap must lie in [1, 64]", false;
   if (c->max_batch < 1) return why = "max_batch must be >= 1", false;
   if (c->n_cap < 1) return why = "n_cap must be >= 1", false;
-  if (c->prec != HT_FP64) return why = "only HT_FP64 is available", false;
+  if (c->prec != HT_FP64 && c->prec != HT_FP32) return why = "prec must be HT_FP64 or HT_FP32", false;
   if (c->in_dtype != HT_F32 && c->in_dtype != HT_F64) return why = "in_dtype must be HT_F32 or HT_F64", false;
   if (c->flags != 0) return why = "flags must be 0", false;
   return true;
@@ -260,9 +276,10 @@ Layout make_layout(const ht_config* c, const Tree& tree, std::vector<int64_t>& a
   L.resid = take(L, max_level * sizeof(double));
   L.bufZ = take(L, max_level * sizeof(double));
   L.gpart = take(L, gpart * sizeof(double));
-  L.scal = take(L, 64 * sizeof(double));
+  L.scal = take(L, kScalars(nn) * sizeof(double));
   L.sspart = take(L, ht::kSumsqBlocks * sizeof(double));
   L.nrmpart = take(L, std::max<size_t>(ht::ttm_norm_partials(), ht::kSumsqBlocks) * sizeof(double));
+  L.respart = take(L, std::max<size_t>(ht::ttm_norm_partials(), ht::kSumsqBlocks) * sizeof(double));
   L.orthsc = take(L, ht::orth_scratch_doubles(64) * sizeof(double));
   L.padtmp = take(L, max_core * sizeof(double));
   L.tails = take(L, (size_t)nn * sizeof(double));
@@ -311,22 +328,40 @@ double* other(const ht_state* h, const void* p) { return p == h->bufA ? h->bufB 
 
 // Contract every node of layer ell (left to right) with U^T, then merge siblings.
 // With norm_out the first contraction also writes the squared norm of the input.
-Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, double* norm_out = nullptr) {
+// mixed: contractions of modes with at most 128 rows on FP32 matrix cores (FP32
+// level tensor out); with energy, every contraction also writes the residual
+// energy it discards into two slots per node: FP32 ones the explicit sum
+// (energy[2 node]), FP64 ones ||in||^2 and ||out||^2 (energy[2 node], [2 node + 1]).
+Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, double* norm_out = nullptr,
+                    bool mixed = false, double* energy = nullptr) {
   const std::vector<int> f = h->tree.frontier(ell);
   Level cur = in;
   for (size_t k = 0; k < f.size(); ++k) {
     const int node = f[k];
     if (h->tree.nodes[node].layer != ell) continue;
     double* dst = other(h, cur.ptr);
-    if (norm_out != nullptr) {
-      ht::ttm_contract_norm(cur.ptr, cur.t, view_of(cur, k), h->core[node], h->rank[node], dst, h->nrmpart,
-                            norm_out, s);
-      norm_out = nullptr;
+    const ModeView v = view_of(cur, k);
+    if (mixed && v.m <= ht::kResidGramMaxM) {
+      ht::ttm_contract_f32(cur.ptr, cur.t, v, h->core[node], h->rank[node], reinterpret_cast<float*>(dst),
+                           norm_out ? h->nrmpart : nullptr, norm_out, energy ? h->respart : nullptr,
+                           energy ? energy + 2 * node : nullptr, s);
+      if (energy) ht::fill_f64(energy + 2 * node + 1, 0.0, 1, s);
+      cur.ptr = dst;
+      cur.t = Elem::F32;
     } else {
-      ht::ttm_contract(cur.ptr, cur.t, view_of(cur, k), h->core[node], h->rank[node], dst, s);
+      if (energy) ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), h->sspart, energy + 2 * node, s);
+      if (norm_out != nullptr)
+        ht::ttm_contract_norm(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, h->nrmpart, norm_out, s);
+      else
+        ht::ttm_contract(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, s);
+      cur.ptr = dst;
+      cur.t = Elem::F64;
+      if (energy) {
+        cur.modes[k] = h->rank[node];
+        ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), h->sspart, energy + 2 * node + 1, s);
+      }
     }
-    cur.ptr = dst;
-    cur.t = Elem::F64;
+    norm_out = nullptr;
     cur.modes[k] = h->rank[node];
   }
   // merge to the frontier of layer ell - 1 (a reshape: adjacent siblings fuse)
@@ -339,10 +374,11 @@ Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, 
   return out;
 }
 
-Level project_all(const ht_state* h, const void* Y, int64_t N, hipStream_t s, double* norm_out = nullptr) {
+Level project_all(const ht_state* h, const void* Y, int64_t N, hipStream_t s, double* norm_out = nullptr,
+                  bool mixed = false, double* energy = nullptr) {
   Level cur{Y, h->in_t, N, h->n};
   for (int ell = h->tree.depth; ell >= 1; --ell) {
-    cur = project_layer(h, ell, cur, s, norm_out);
+    cur = project_layer(h, ell, cur, s, norm_out, mixed, energy);
     norm_out = nullptr;
   }
   return cur;
@@ -427,7 +463,10 @@ ht_status decide_layer(ht_state* h, int ell, const Level& cur, double thr, bool 
       ht::gram(cur.ptr, cur.t, v, h->gpart, h->gram[node], s);
     } else if (v.m <= ht::kResidGramMaxM) {
       // Gram of R = M - U_old U_old^T M, formed tile by tile in LDS (Eq. compute_residual)
-      ht::resid_gram(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], s);
+      if (h->mixed)
+        ht::resid_gram_f32(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], s);
+      else
+        ht::resid_gram(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], s);
     } else {
       double* z = h->bufZ;  // U_old^T M: as large as the level tensor when alpha == r_old
       ht::ttm_contract(cur.ptr, cur.t, v, h->core[node], r_old, z, s);
@@ -513,6 +552,7 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   h->max_batch = cfg->max_batch;
   h->n_cap = cfg->n_cap;
   h->in_t = cfg->in_dtype == HT_F32 ? Elem::F32 : Elem::F64;
+  h->mixed = cfg->prec == HT_FP32;
   h->tree.build(cfg->d);
   Layout L = make_layout(cfg, h->tree, h->alpha_cap, h->rc);
   if (ws_bytes < L.total) {
@@ -547,12 +587,13 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   h->scal = reinterpret_cast<double*>(base + L.scal);
   h->sspart = reinterpret_cast<double*>(base + L.sspart);
   h->nrmpart = reinterpret_cast<double*>(base + L.nrmpart);
+  h->respart = reinterpret_cast<double*>(base + L.respart);
   h->orthsc = reinterpret_cast<double*>(base + L.orthsc);
   h->padtmp = reinterpret_cast<double*>(base + L.padtmp);
   h->tails = reinterpret_cast<double*>(base + L.tails);
   h->ranks_dev = reinterpret_cast<int*>(base + L.ranks_dev);
   h->rank.assign(nn, 0);
-  h->h_scal.assign(8, 0.0);
+  h->h_scal.assign(kScalars(nn), 0.0);
   *out = h;
   return HT_OK;
 }
@@ -639,8 +680,8 @@ ht_status ht_init_batch(const ht_config* cfg, void* ws, size_t ws_bytes, const v
     cur = project_layer(h, ell, cur, s);
   }
   const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
-  ht::sumsq(cur.ptr, Elem::F64, (int64_t)cur.elems(), h->sspart, h->scal + 1, s);
-  ht::root_append(static_cast<const double*>(cur.ptr), N, r11, r12, h->root, 0, h->rank_cap, s);
+  ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), h->sspart, h->scal + 1, s);
+  ht::root_append(cur.ptr, cur.t, N, r11, r12, h->root, 0, h->rank_cap, s);
   if (hipGetLastError() != hipSuccess) {
     delete h;
     return fail(HT_EDEVICE, "kernel launch failed");
@@ -678,19 +719,36 @@ ht_status ht_rise_update(ht_handle h, const void* Y, int64_t N, void* hip_stream
   // Step 1: projection onto the existing cores; the first contraction reads all of Y
   // and returns ||Y||^2 as well
   (void)E;
-  Level c1 = project_all(h, Y, N, s, h->scal);
-  ht::sumsq(c1.ptr, Elem::F64, (int64_t)c1.elems(), h->sspart, h->scal + 1, s);
-  ht_status st = sync_read(h, s, h->scal, 2, h->h_scal.data());
-  if (st != HT_OK) return st;
-  const double ny2 = h->h_scal[0], c2 = h->h_scal[1];
-  if (!std::isfinite(ny2) || !std::isfinite(c2)) return fail(HT_ENUMERIC, "non-finite norm");
+  const int nn = (int)h->tree.nodes.size();
+  double ny2 = 0.0, lost = 0.0;
+  Level c1;
+  if (h->mixed) {
+    double* energy = h->scal + 8;
+    c1 = project_all(h, Y, N, s, h->scal, true, energy);
+    ht_status st = sync_read(h, s, h->scal, kScalars(nn), h->h_scal.data());
+    if (st != HT_OK) return st;
+    ny2 = h->h_scal[0];
+    // energies of the contractions, in projection order
+    for (int ell = h->tree.depth; ell >= 1; --ell)
+      for (int node : h->tree.frontier(ell))
+        if (h->tree.nodes[node].layer == ell) lost += h->h_scal[8 + 2 * node] - h->h_scal[8 + 2 * node + 1];
+  } else {
+    c1 = project_all(h, Y, N, s, h->scal);
+    ht::sumsq(c1.ptr, c1.t, (int64_t)c1.elems(), h->sspart, h->scal + 1, s);
+    ht_status st = sync_read(h, s, h->scal, 2, h->h_scal.data());
+    if (st != HT_OK) return st;
+    ny2 = h->h_scal[0];
+    lost = ny2 - h->h_scal[1];
+  }
+  ht_status st = HT_OK;
+  if (!std::isfinite(ny2) || !std::isfinite(lost)) return fail(HT_ENUMERIC, "non-finite norm");
   const double ny = std::sqrt(ny2);
   const double eps_des = h->eps * ny;
-  const double eps_proj = std::sqrt(std::max(0.0, ny2 - c2));
+  const double eps_proj = std::sqrt(std::max(0.0, lost));
   const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
   int growth = 0;
   if (eps_proj <= eps_des) {
-    ht::root_append(static_cast<const double*>(c1.ptr), N, r11, r12, h->root, h->n_acc, h->rank_cap, s);
+    ht::root_append(c1.ptr, c1.t, N, r11, r12, h->root, h->n_acc, h->rank_cap, s);
     HT_HIP(hipGetLastError());
   } else {
     const std::vector<int> saved = h->rank;
@@ -705,10 +763,10 @@ ht_status ht_rise_update(ht_handle h, const void* Y, int64_t N, void* hip_stream
         (void)hipStreamSynchronize(s);
         return st;
       }
-      cur = project_layer(h, ell, cur, s);
+      cur = project_layer(h, ell, cur, s, nullptr, h->mixed);
     }
     const int q11 = h->rank[h->tree.nodes[0].child[0]], q12 = h->rank[h->tree.nodes[0].child[1]];
-    ht::root_append(static_cast<const double*>(cur.ptr), N, q11, q12, h->root, h->n_acc, h->rank_cap, s);
+    ht::root_append(cur.ptr, cur.t, N, q11, q12, h->root, h->n_acc, h->rank_cap, s);
     HT_HIP(hipGetLastError());
   }
   h->n_acc += N;

@@ -47,6 +47,17 @@ void ttm_contract(const void* x, Elem t, const ModeView& v, const double* U, int
 size_t ttm_norm_partials();
 void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z, double* norm_part,
                        double* norm_out, hipStream_t s);
+// ---- mixed form: FP32 matrix cores, FP64 sums (m <= kResidGramMaxM) --------------
+// Z (FP32) = U^T X; optionally ||X||^2 and the explicit residual energy
+// ||X - U (U^T X)||^2 (the part this contraction discards), both FP64; the partial
+// arrays hold ttm_norm_partials() doubles each.
+void ttm_contract_f32(const void* x, Elem t, const ModeView& v, const double* U, int R, float* Z, double* norm_part,
+                      double* norm_out, double* res_part, double* res_out, hipStream_t s);
+// Gram of the explicit residual with the products on FP32 matrix cores and the
+// workgroup partials summed in FP64.
+void resid_gram_f32(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,
+                    hipStream_t s);
+
 // out[p, a, s] = sum_t U[a, t] Z[p, t, s] (mode expansion, U m x R column-major), or with
 // M given: out = M - that (the explicit residual of a projection).  out is FP64 unless
 // out_t says F32.
@@ -84,8 +95,9 @@ size_t orth_scratch_doubles(int rR);
 // Zero-padding of a transfer core when a successor grows (padWithZeros): src is
 // (ra*rb) x rp column-major with row i_a*rb + i_b, dst is (ra2*rb2) x rp.
 void pad_core(const double* src, int ra, int rb, int rp, double* dst, int ra2, int rb2, hipStream_t s);
-// root[(n_acc + n) * rcap * rcap + i * rcap + j] = C1[n][i][j] for n < N, i < r11, j < r12.
-void root_append(const double* C1, int64_t N, int r11, int r12, double* root, int64_t n_acc, int rcap,
+// root[(n_acc + n) * rcap * rcap + i * rcap + j] = C1[n][i][j] for n < N, i < r11, j < r12
+// (C1 FP32 or FP64, the root FP64).
+void root_append(const void* C1, Elem t, int64_t N, int r11, int r12, double* root, int64_t n_acc, int rcap,
                  hipStream_t s);
 // latent[n][i][j] = root[(first + n)][i][j] (packed r11 x r12), zero for i >= r11 etc.
 void root_extract(const double* root, int64_t first, int64_t count, int r11, int r12, int rcap,
@@ -97,7 +109,7 @@ void fill_f64(double* dst, double v, int64_t n, hipStream_t s);
 
 namespace ht {
 // ---- optional per-kernel timing (include/ht_rise_profile.h) -----------------------
-enum class KKind : int { Sumsq = 0, Gram, TtmContract, TtmExpand, Eig, Orth, Layout, Count };
+enum class KKind : int { Sumsq = 0, Gram, TtmContract, TtmExpand, Eig, Orth, Layout, Gram32, TtmContract32, Count };
 extern bool g_prof_on;
 void prof_begin(KKind k, hipStream_t s, double flops, double bytes);
 void prof_end(hipStream_t s);

@@ -3,8 +3,9 @@
 // Contractions (the TTM projections of Alg. 1/2 and Eq. multi_index_contraction)
 // and Gram products of mode unfoldings (the SVDs of Eq. ht_leaf_svd and
 // svd_on_residual, taken as eigen-decompositions of the Gram matrix) run on the
-// FP64 matrix cores (v_mfma_f64_16x16x4f64).  Unfoldings are never copied: a
-// kernel reads the level tensor through its (P, m, S) mode view.
+// matrix cores: FP64 (v_mfma_f64_16x16x4f64) in the plain form, FP32
+// (v_mfma_f32_16x16x4f32, FP64 partial sums) in the mixed form.  Unfoldings are
+// never copied: a kernel reads the level tensor through its (P, m, S) mode view.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,14 +16,32 @@ namespace ht {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-// v_mfma_f64_16x16x4f64 operand layout (lane l of a wave64):
+// 16 x 16 x 4 matrix-core products, operand layout (lane l of a wave64):
 //   A (16x4): A[l % 16][l / 16];  B (4x16): B[l / 16][l % 16];
-//   D (16x16): register v of lane l holds D[l / 16 + 4 v][l % 16].
-
+//   D (16x16), register v of lane l:  FP64: D[l / 16 + 4 v][l % 16],
+//                                      FP32: D[4 (l / 16) + v][l % 16].
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// accumulator type and output row of register v for a compute type
+template <typename CT>
+struct MA;
+template <>
+struct MA<double> {
+  typedef d4 acc;
+  static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct MA<float> {
+  typedef f4 acc;
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
 
 template <typename T>
 __device__ __forceinline__ double ld(const T* __restrict__ p, int64_t i) {
@@ -308,9 +327,11 @@ __global__ __launch_bounds__(64) void gram_small_reduce_kernel(const double* __r
 // --------------------------------------------------------------------------
 // Single-panel Gram for m <= 128, optionally of the explicit residual.
 // Each workgroup walks its column tiles; a tile (all m rows x 32 columns) is
-// prefetched into registers one step ahead and stored to LDS as sM[column][row].
+// prefetched into registers one step ahead and stored to LDS as sM[column][row]
+// in the compute type CT (double: FP64 matrix cores; float: FP32 ones).
 // With RESID the tile is first replaced, in LDS, by R = M - U (U^T M) (both
-// products on FP64 MFMA, Z = U^T M staged in LDS), so only the data is read.
+// products on the matrix cores, Z = U^T M staged in LDS), so only the data is
+// read.  The workgroup's partial Gram is written in FP64.
 // --------------------------------------------------------------------------
 constexpr int PER_PANEL = GBK * GB / 256;     // prefetched values per thread (16)
 constexpr int ZLD = GBK + 1;
@@ -364,24 +385,26 @@ struct PanelLoader {
       }
     }
   }
-  __device__ void store(double* sM, const T (&r)[PER_PANEL]) const {
+  template <typename CT>
+  __device__ void store(CT* sM, const T (&r)[PER_PANEL]) const {
 #pragma unroll
     for (int t = 0; t < PER_PANEL; ++t)
-      if (dst[t] >= 0) sM[dst[t]] = static_cast<double>(r[t]);
+      if (dst[t] >= 0) sM[dst[t]] = static_cast<CT>(r[t]);
   }
 };
 
-template <typename T, bool RESID, int MT>
+template <typename T, typename CT, bool RESID, int MT>
 __global__ __launch_bounds__(256) void gram_panel_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
                                                          int64_t ktiles, int64_t kt_per_split, int tw,
                                                          const double* __restrict__ U, int R,
                                                          double* __restrict__ part) {
+  typedef typename MA<CT>::acc AT;
   extern __shared__ double dsm[];
-  double* sM = dsm;                      // [GBK][GLD]
+  CT* sM = reinterpret_cast<CT*>(dsm);   // [GBK][GLD]
   const int RP = (R + 15) & ~15;         // rank padded to the MFMA tile
   const int ULD = RP + 1;
-  double* sU = sM + GBK * GLD;           // [128][ULD]   (RESID)
-  double* sZ = sU + GB * ULD;            // [RP][ZLD]    (RESID)
+  CT* sU = sM + GBK * GLD;               // [128][ULD]   (RESID)
+  CT* sZ = sU + GB * ULD;                // [RP][ZLD]    (RESID)
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
   const int mi = (int)m;
@@ -399,16 +422,16 @@ __global__ __launch_bounds__(256) void gram_panel_kernel(const T* __restrict__ X
     offa[q] = a * 16 + (lane & 15);
     offb[q] = b * 16 + (lane & 15);
   }
-  d4 acc[MT];
+  AT acc[MT];
 #pragma unroll
-  for (int q = 0; q < MT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < MT; ++q) acc[q] = AT{0, 0, 0, 0};
 
   // zero the panel once: entries never written by a tile stay zero
-  for (int e = threadIdx.x; e < GBK * GLD; e += 256) sM[e] = 0.0;
+  for (int e = threadIdx.x; e < GBK * GLD; e += 256) sM[e] = CT(0);
   if (RESID) {
     for (int e = threadIdx.x; e < GB * ULD; e += 256) {
       const int a = e / ULD, t = e - (e / ULD) * ULD;
-      sU[e] = (a < mi && t < R) ? U[a + (int64_t)t * m] : 0.0;
+      sU[e] = (a < mi && t < R) ? static_cast<CT>(U[a + (int64_t)t * m]) : CT(0);
     }
   }
   PanelLoader<T> L;
@@ -429,11 +452,11 @@ __global__ __launch_bounds__(256) void gram_panel_kernel(const T* __restrict__ X
       // Z = U^T M (RP x GBK)
       for (int zt = wave; zt < nzt; zt += 4) {
         const int zi = zt >> 1, zc = zt & 1;
-        d4 z = d4{0.0, 0.0, 0.0, 0.0};
-        const double* pa = sU + (lane >> 4) * ULD + zi * 16 + (lane & 15);
-        const double* pb = sM + (zc * 16 + (lane & 15)) * GLD + (lane >> 4);
+        AT z = AT{0, 0, 0, 0};
+        const CT* pa = sU + (lane >> 4) * ULD + zi * 16 + (lane & 15);
+        const CT* pb = sM + (zc * 16 + (lane & 15)) * GLD + (lane >> 4);
         for (int ks = 0; ks < tI * 16; ks += 16) {
-          double a[4], b[4];
+          CT a[4], b[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             a[u] = pa[(ks + 4 * u) * ULD];
@@ -443,17 +466,17 @@ __global__ __launch_bounds__(256) void gram_panel_kernel(const T* __restrict__ X
           for (int u = 0; u < 4; ++u) z = mfma16(a[u], b[u], z);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sZ[(zi * 16 + (lane >> 4) + 4 * v) * ZLD + zc * 16 + (lane & 15)] = z[v];
+        for (int v = 0; v < 4; ++v) sZ[(zi * 16 + MA<CT>::row(lane, v)) * ZLD + zc * 16 + (lane & 15)] = z[v];
       }
       __syncthreads();
       // M <- M - U Z (m x GBK), in place
       for (int rt = wave; rt < nrt; rt += 4) {
         const int ri = rt >> 1, rc = rt & 1;
-        d4 y = d4{0.0, 0.0, 0.0, 0.0};
-        const double* pa = sU + (ri * 16 + (lane & 15)) * ULD + (lane >> 4);
-        const double* pb = sZ + (lane >> 4) * ZLD + rc * 16 + (lane & 15);
+        AT y = AT{0, 0, 0, 0};
+        const CT* pa = sU + (ri * 16 + (lane & 15)) * ULD + (lane >> 4);
+        const CT* pb = sZ + (lane >> 4) * ZLD + rc * 16 + (lane & 15);
         for (int ks = 0; ks < RP; ks += 16) {
-          double a[4], b[4];
+          CT a[4], b[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             a[u] = pa[ks + 4 * u];
@@ -463,14 +486,14 @@ __global__ __launch_bounds__(256) void gram_panel_kernel(const T* __restrict__ X
           for (int u = 0; u < 4; ++u) y = mfma16(a[u], b[u], y);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sM[(rc * 16 + (lane & 15)) * GLD + ri * 16 + (lane >> 4) + 4 * v] -= y[v];
+        for (int v = 0; v < 4; ++v) sM[(rc * 16 + (lane & 15)) * GLD + ri * 16 + MA<CT>::row(lane, v)] -= y[v];
       }
       __syncthreads();
     }
 #pragma unroll
     for (int ks = 0; ks < GBK; ks += 4) {
       const int kr = (ks + (lane >> 4)) * GLD;
-      double a[MT], b[MT];
+      CT a[MT], b[MT];
 #pragma unroll
       for (int q = 0; q < MT; ++q) {
         a[q] = sM[kr + offa[q]];
@@ -487,9 +510,9 @@ __global__ __launch_bounds__(256) void gram_panel_kernel(const T* __restrict__ X
     if (live[q]) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = (offa[q] - (lane & 15)) + (lane >> 4) + 4 * v;
+        const int i = (offa[q] - (lane & 15)) + MA<CT>::row(lane, v);
         const int j = offb[q];
-        if (i < mi && j < mi) out[i * m + j] = acc[q][v];
+        if (i < mi && j < mi) out[i * m + j] = static_cast<double>(acc[q][v]);
       }
     }
   }
@@ -579,27 +602,33 @@ GramPlan gram_plan(const ModeView& v) {
 // TTM contraction for m <= 128: Z[p, r, s] = sum_a U[a, r] X[p, a, s].  Tiles of
 // 32 unfolding columns go through the same prefetching panel loader as the Gram;
 // U^T (R <= 64 rows) sits in LDS; each wave computes 16 x 16 blocks of Z and
-// writes them straight from its accumulators.  With NORM the workgroup also sums
-// the squares of every element it reads (the ||Y||^2 of the skip test).
+// writes them straight from its accumulators, in the compute type CT.  With NORM
+// the workgroup also sums the squares of every element it reads (the ||Y||^2 of
+// the skip test); with RESE it also forms the explicit residual X - U Z of each
+// tile in registers and sums its squares (the energy one contraction discards,
+// Eq. compute_residual).  Both sums are FP64.
 // --------------------------------------------------------------------------
-template <typename T, bool NORM>
+template <typename T, typename CT, bool NORM, bool RESE>
 __global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
                                                         int64_t ktiles, int64_t kt_per_split, int tw,
-                                                        const double* __restrict__ U, int R, double* __restrict__ Z,
-                                                        double* __restrict__ norm_part) {
+                                                        const double* __restrict__ U, int R, CT* __restrict__ Z,
+                                                        double* __restrict__ norm_part,
+                                                        double* __restrict__ res_part) {
+  typedef typename MA<CT>::acc AT;
   extern __shared__ double dsm[];
-  double* sM = dsm;                   // [GBK][GLD]
+  CT* sM = reinterpret_cast<CT*>(dsm);  // [GBK][GLD]
   const int RP = (R + 15) & ~15;
   const int ULD = RP + 1;
-  double* sU = sM + GBK * GLD;        // [128][ULD]
+  CT* sU = sM + GBK * GLD;              // [128][ULD]
+  CT* sZ = sU + GB * ULD;               // [RP][ZLD]  (RESE)
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int mi = (int)m;
   const int tI = (mi + 15) >> 4;
-  for (int e = threadIdx.x; e < GBK * GLD; e += 256) sM[e] = 0.0;
+  for (int e = threadIdx.x; e < GBK * GLD; e += 256) sM[e] = CT(0);
   for (int e = threadIdx.x; e < GB * ULD; e += 256) {
     const int a = e / ULD, t = e - (e / ULD) * ULD;
-    sU[e] = (a < mi && t < R) ? U[a + (int64_t)t * m] : 0.0;
+    sU[e] = (a < mi && t < R) ? static_cast<CT>(U[a + (int64_t)t * m]) : CT(0);
   }
   PanelLoader<T> L;
   L.init(m, S, tw);
@@ -608,9 +637,11 @@ __global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X,
   const int64_t kt1 = min(ktiles, kt0 + kt_per_split);
   T rg[PER_PANEL];
   if (kt0 < kt1) L.load(X, P, m, S, K, kt0, tw, rg);
-  double nrm = 0.0;
+  double nrm = 0.0, res = 0.0;
   __syncthreads();
   const int nzt = (RP >> 4) * 2;
+  const int nrt = tI * 2;
+  const bool slab = S < GBK;
   for (int64_t kt = kt0; kt < kt1; ++kt) {
     if (NORM) {
 #pragma unroll
@@ -624,11 +655,11 @@ __global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X,
     __syncthreads();
     for (int zt = wave; zt < nzt; zt += 4) {
       const int zi = zt >> 1, zc = zt & 1;
-      d4 z = d4{0.0, 0.0, 0.0, 0.0};
-      const double* pa = sU + (lane >> 4) * ULD + zi * 16 + (lane & 15);
-      const double* pb = sM + (zc * 16 + (lane & 15)) * GLD + (lane >> 4);
+      AT z = AT{0, 0, 0, 0};
+      const CT* pa = sU + (lane >> 4) * ULD + zi * 16 + (lane & 15);
+      const CT* pb = sM + (zc * 16 + (lane & 15)) * GLD + (lane >> 4);
       for (int ks = 0; ks < tI * 16; ks += 16) {
-        double a[4], b[4];
+        CT a[4], b[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           a[u] = pa[(ks + 4 * u) * ULD];
@@ -637,27 +668,64 @@ __global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X,
 #pragma unroll
         for (int u = 0; u < 4; ++u) z = mfma16(a[u], b[u], z);
       }
+      if (RESE) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sZ[(zi * 16 + MA<CT>::row(lane, v)) * ZLD + zc * 16 + (lane & 15)] = z[v];
+      }
       // column j of the tile is unfolding column kt * tw + zc * 16 + j
       const int64_t c = kt * tw + zc * 16 + (lane & 15);
-      const bool slab = S < GBK;
       const bool cv = slab ? (zc * 16 + (lane & 15)) < tw && c < K : c < K;
       if (cv) {
         const int64_t p = c / S, sidx = c - (c / S) * S;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int r = zi * 16 + (lane >> 4) + 4 * v;
+          const int r = zi * 16 + MA<CT>::row(lane, v);
           if (r < R) Z[(p * R + r) * S + sidx] = z[v];
+        }
+      }
+    }
+    if (RESE) {
+      __syncthreads();
+      // X - U Z over the tile's m rows; padding rows and columns hold zeros on both sides
+      for (int rt = wave; rt < nrt; rt += 4) {
+        const int ri = rt >> 1, rc = rt & 1;
+        AT y = AT{0, 0, 0, 0};
+        const CT* pa = sU + (ri * 16 + (lane & 15)) * ULD + (lane >> 4);
+        const CT* pb = sZ + (lane >> 4) * ZLD + rc * 16 + (lane & 15);
+        for (int ks = 0; ks < RP; ks += 16) {
+          CT a[4], b[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            a[u] = pa[ks + 4 * u];
+            b[u] = pb[(ks + 4 * u) * ZLD];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) y = mfma16(a[u], b[u], y);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double dl =
+              static_cast<double>(sM[(rc * 16 + (lane & 15)) * GLD + ri * 16 + MA<CT>::row(lane, v)]) -
+              static_cast<double>(y[v]);
+          res = fma(dl, dl, res);
         }
       }
     }
     __syncthreads();
   }
-  if (NORM) {
-    __shared__ double red[4];
-    nrm = wave_sum(nrm);
-    if (lane == 0) red[threadIdx.x >> 6] = nrm;
+  if (NORM || RESE) {
+    __shared__ double red[8];
+    if (NORM) nrm = wave_sum(nrm);
+    if (RESE) res = wave_sum(res);
+    if (lane == 0) {
+      red[threadIdx.x >> 6] = nrm;
+      red[4 + (threadIdx.x >> 6)] = res;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) norm_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) {
+      if (NORM) norm_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+      if (RESE) res_part[blockIdx.x] = (red[4] + red[5]) + (red[6] + red[7]);
+    }
   }
 }
 
@@ -912,14 +980,16 @@ __global__ void pad_core_kernel(const double* __restrict__ src, int ra, int rb, 
   }
 }
 
-__global__ void root_append_kernel(const double* __restrict__ C1, int64_t N, int r11, int r12,
+template <typename T>
+__global__ void root_append_kernel(const T* __restrict__ C1, int64_t N, int r11, int r12,
                                    double* __restrict__ root, int64_t n_acc, int rcap) {
   const int64_t n = N * rcap * rcap;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
     const int64_t s = e / ((int64_t)rcap * rcap);
     const int64_t rem = e - s * rcap * rcap;
     const int i = (int)(rem / rcap), j = (int)(rem - (rem / rcap) * rcap);
-    root[(n_acc + s) * rcap * rcap + rem] = (i < r11 && j < r12) ? C1[(s * r11 + i) * r12 + j] : 0.0;
+    root[(n_acc + s) * rcap * rcap + rem] =
+        (i < r11 && j < r12) ? static_cast<double>(C1[(s * r11 + i) * r12 + j]) : 0.0;
   }
 }
 
@@ -963,49 +1033,49 @@ void sumsq(const void* x, Elem t, int64_t n, double* partials, double* out, hipS
   reduce_kernel<<<1, 256, 0, s>>>(partials, kSumsqBlocks, out);
 }
 
-size_t panel_lds_bytes(bool resid, int R) {
+size_t panel_lds_bytes(bool resid, int R, size_t esz) {
   const int RP = (R + 15) & ~15;
   size_t n = (size_t)GBK * GLD;
   if (resid) n += (size_t)GB * (RP + 1) + (size_t)RP * ZLD;
-  return n * sizeof(double);
+  return n * esz;
 }
 
-template <typename T, bool RESID, int MT>
+template <typename T, typename CT, bool RESID, int MT>
 void launch_panel_t(const void* x, const ModeView& v, const GramPlan& g, const double* U, int R, double* part,
                     hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_panel_kernel<T, RESID, MT>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_panel_kernel<T, CT, RESID, MT>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
     attr = true;
   }
-  gram_panel_kernel<T, RESID, MT><<<g.nsplit, 256, panel_lds_bytes(RESID, R), s>>>(
+  gram_panel_kernel<T, CT, RESID, MT><<<g.nsplit, 256, panel_lds_bytes(RESID, R, sizeof(CT)), s>>>(
       static_cast<const T*>(x), v.P, v.m, v.S, g.ktiles, g.kt_per_split, g.tw, U, R, part);
 }
 
-template <typename T, bool RESID>
+template <typename T, typename CT, bool RESID>
 void launch_panel_mt(const void* x, const ModeView& v, const GramPlan& g, const double* U, int R, double* part,
                      hipStream_t s) {
   const int tI = (int)((v.m + 15) / 16);
   const int mt = (tI * (tI + 1) / 2 + 3) / 4;  // upper 16x16 tiles per wave
   switch (mt) {
-    case 1: launch_panel_t<T, RESID, 1>(x, v, g, U, R, part, s); break;
-    case 2: launch_panel_t<T, RESID, 2>(x, v, g, U, R, part, s); break;
-    case 3: launch_panel_t<T, RESID, 3>(x, v, g, U, R, part, s); break;
-    case 4: launch_panel_t<T, RESID, 4>(x, v, g, U, R, part, s); break;
-    case 6: launch_panel_t<T, RESID, 6>(x, v, g, U, R, part, s); break;
-    case 7: launch_panel_t<T, RESID, 7>(x, v, g, U, R, part, s); break;
-    default: launch_panel_t<T, RESID, 9>(x, v, g, U, R, part, s); break;
+    case 1: launch_panel_t<T, CT, RESID, 1>(x, v, g, U, R, part, s); break;
+    case 2: launch_panel_t<T, CT, RESID, 2>(x, v, g, U, R, part, s); break;
+    case 3: launch_panel_t<T, CT, RESID, 3>(x, v, g, U, R, part, s); break;
+    case 4: launch_panel_t<T, CT, RESID, 4>(x, v, g, U, R, part, s); break;
+    case 6: launch_panel_t<T, CT, RESID, 6>(x, v, g, U, R, part, s); break;
+    case 7: launch_panel_t<T, CT, RESID, 7>(x, v, g, U, R, part, s); break;
+    default: launch_panel_t<T, CT, RESID, 9>(x, v, g, U, R, part, s); break;
   }
 }
 
-template <bool RESID>
+template <typename CT, bool RESID>
 void launch_panel(const void* x, Elem t, const ModeView& v, const GramPlan& g, const double* U, int R, double* part,
                   hipStream_t s) {
   if (t == Elem::F32)
-    launch_panel_mt<float, RESID>(x, v, g, U, R, part, s);
+    launch_panel_mt<float, CT, RESID>(x, v, g, U, R, part, s);
   else
-    launch_panel_mt<double, RESID>(x, v, g, U, R, part, s);
+    launch_panel_mt<double, CT, RESID>(x, v, g, U, R, part, s);
 }
 
 void gram_finish(const GramPlan& g, const ModeView& v, const double* part, double* G, hipStream_t s) {
@@ -1044,7 +1114,7 @@ void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hip
   const GramPlan g = gram_plan(v);
   if (v.m <= GB) {
     ProfScope prof(KKind::Gram, s, md * md * K, md * K * (t == Elem::F32 ? 4 : 8));
-    launch_panel<false>(x, t, v, g, nullptr, 0, part, s);
+    launch_panel<double, false>(x, t, v, g, nullptr, 0, part, s);
   } else {
     dim3 grid(g.npairs, g.nsplit);
     ProfScope prof(KKind::Gram, s, md * md * K, md * K * (t == Elem::F32 ? 4 : 8));
@@ -1063,8 +1133,21 @@ void resid_gram(const void* x, Elem t, const ModeView& v, const double* U, int R
   const GramPlan g = gram_plan(v);
   const double K = (double)v.P * v.S, md = (double)v.m;
   // residual formation (4 R m flops per column) plus the symmetric product
-  ProfScope prof(KKind::Gram, s, md * md * K + 4.0 * R * md * K, md * K * (t == Elem::F32 ? 4 : 8));
-  launch_panel<true>(x, t, v, g, U, R, part, s);
+  {
+    ProfScope prof(KKind::Gram, s, md * md * K + 4.0 * R * md * K, md * K * (t == Elem::F32 ? 4 : 8));
+    launch_panel<double, true>(x, t, v, g, U, R, part, s);
+  }
+  gram_finish(g, v, part, G, s);
+}
+
+void resid_gram_f32(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,
+                    hipStream_t s) {
+  const GramPlan g = gram_plan(v);
+  const double K = (double)v.P * v.S, md = (double)v.m;
+  {
+    ProfScope prof(KKind::Gram32, s, md * md * K + 4.0 * R * md * K, md * K * (t == Elem::F32 ? 4 : 8));
+    launch_panel<float, true>(x, t, v, g, U, R, part, s);
+  }
   gram_finish(g, v, part, G, s);
 }
 
@@ -1074,50 +1157,60 @@ void ttm_contract(const void* x, Elem t, const ModeView& v, const double* U, int
 
 size_t ttm_norm_partials() { return kTtmMaxBlocks; }
 
+// one launch of the panel contraction: blocks over column tiles, optional norm and
+// residual-energy partials (one per block), reduced in fixed order
+template <typename T, typename CT, bool NORM, bool RESE>
+void launch_ttm_panel(const void* x, const ModeView& v, const double* U, int R, CT* Z, double* norm_part,
+                      double* norm_out, double* res_part, double* res_out, KKind kind, double flops, double bytes,
+                      hipStream_t s) {
+  const int64_t K = v.P * v.S;
+  GramPlan g;
+  g.tw = v.S >= GBK ? GBK : (int)(v.S * (GBK / v.S));
+  g.ktiles = (K + g.tw - 1) / g.tw;
+  const int64_t want = std::min<int64_t>(kTtmMaxBlocks, std::max<int64_t>(1, g.ktiles));
+  g.kt_per_split = (g.ktiles + want - 1) / want;
+  const int blocks = (int)((g.ktiles + g.kt_per_split - 1) / g.kt_per_split);
+  const int RP = (R + 15) & ~15;
+  const size_t lds = ((size_t)GBK * GLD + (size_t)GB * (RP + 1) + (RESE ? (size_t)RP * ZLD : 0)) * sizeof(CT);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_panel_kernel<T, CT, NORM, RESE>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    attr = true;
+  }
+  {
+    ProfScope prof(kind, s, flops, bytes);
+    ttm_panel_kernel<T, CT, NORM, RESE><<<blocks, 256, lds, s>>>(static_cast<const T*>(x), v.P, v.m, v.S, g.ktiles,
+                                                                 g.kt_per_split, g.tw, U, R, Z, norm_part, res_part);
+  }
+  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+  if (NORM) reduce_kernel<<<1, 256, 0, s>>>(norm_part, blocks, norm_out);
+  if (RESE) reduce_kernel<<<1, 256, 0, s>>>(res_part, blocks, res_out);
+}
+
 void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z, double* norm_part,
                        double* norm_out, hipStream_t s) {
   const int64_t K = v.P * v.S;
   if (v.m <= GB) {
-    // many workgroups: no partial sums to reduce, only the optional norm
-    GramPlan g;
-    g.tw = v.S >= GBK ? GBK : (int)(v.S * (GBK / v.S));
-    g.ktiles = (K + g.tw - 1) / g.tw;
-    const int64_t want = std::min<int64_t>(kTtmMaxBlocks, std::max<int64_t>(1, g.ktiles));
-    g.kt_per_split = (g.ktiles + want - 1) / want;
-    const int blocks = (int)((g.ktiles + g.kt_per_split - 1) / g.kt_per_split);
-    const int RP = (R + 15) & ~15;
-    const size_t lds = ((size_t)GBK * GLD + (size_t)GB * (RP + 1)) * sizeof(double);
-    ProfScope prof(KKind::TtmContract, s, 2.0 * R * v.m * (double)K,
-                   (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8);
-    static bool attr = false;
-    if (!attr) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_panel_kernel<float, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_panel_kernel<float, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_panel_kernel<double, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_panel_kernel<double, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
-      attr = true;
-    }
+    const double fl = 2.0 * R * v.m * (double)K,
+                 by = (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8;
+    const KKind kd = KKind::TtmContract;
     const bool nrm = norm_part != nullptr;
     if (t == Elem::F32) {
       if (nrm)
-        ttm_panel_kernel<float, true><<<blocks, 256, lds, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, g.ktiles,
-                                                               g.kt_per_split, g.tw, U, R, Z, norm_part);
+        launch_ttm_panel<float, double, true, false>(x, v, U, R, Z, norm_part, norm_out, nullptr, nullptr, kd, fl, by,
+                                                     s);
       else
-        ttm_panel_kernel<float, false><<<blocks, 256, lds, s>>>(static_cast<const float*>(x), v.P, v.m, v.S,
-                                                                g.ktiles, g.kt_per_split, g.tw, U, R, Z, nullptr);
+        launch_ttm_panel<float, double, false, false>(x, v, U, R, Z, nullptr, nullptr, nullptr, nullptr, kd, fl, by,
+                                                      s);
     } else {
       if (nrm)
-        ttm_panel_kernel<double, true><<<blocks, 256, lds, s>>>(static_cast<const double*>(x), v.P, v.m, v.S,
-                                                                g.ktiles, g.kt_per_split, g.tw, U, R, Z, norm_part);
+        launch_ttm_panel<double, double, true, false>(x, v, U, R, Z, norm_part, norm_out, nullptr, nullptr, kd, fl,
+                                                      by, s);
       else
-        ttm_panel_kernel<double, false><<<blocks, 256, lds, s>>>(static_cast<const double*>(x), v.P, v.m, v.S,
-                                                                 g.ktiles, g.kt_per_split, g.tw, U, R, Z, nullptr);
+        launch_ttm_panel<double, double, false, false>(x, v, U, R, Z, nullptr, nullptr, nullptr, nullptr, kd, fl,
+                                                       by, s);
     }
-    if (nrm) reduce_kernel<<<1, 256, 0, s>>>(norm_part, blocks, norm_out);
     return;
   }
   if (norm_part != nullptr) sumsq(x, t, v.P * v.m * v.S, norm_part, norm_out, s);
@@ -1128,6 +1221,30 @@ void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U
     ttm_contract_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R, Z);
   else
     ttm_contract_kernel<double><<<blocks, 256, 0, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U, R, Z);
+}
+
+void ttm_contract_f32(const void* x, Elem t, const ModeView& v, const double* U, int R, float* Z, double* norm_part,
+                      double* norm_out, double* res_part, double* res_out, hipStream_t s) {
+  const int64_t K = v.P * v.S;
+  const bool nrm = norm_part != nullptr, rese = res_part != nullptr;
+  const double fl = (rese ? 4.0 : 2.0) * R * v.m * (double)K,
+               by = (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 4 + (double)v.m * R * 8;
+#define HT_TTM32(TT, NN, RR)                                                                                  \
+  launch_ttm_panel<TT, float, NN, RR>(x, v, U, R, Z, NN ? norm_part : nullptr, NN ? norm_out : nullptr,       \
+                                      RR ? res_part : nullptr, RR ? res_out : nullptr, KKind::TtmContract32, fl, \
+                                      by, s)
+  if (t == Elem::F32) {
+    if (nrm && rese) HT_TTM32(float, true, true);
+    else if (rese) HT_TTM32(float, false, true);
+    else if (nrm) HT_TTM32(float, true, false);
+    else HT_TTM32(float, false, false);
+  } else {
+    if (nrm && rese) HT_TTM32(double, true, true);
+    else if (rese) HT_TTM32(double, false, true);
+    else if (nrm) HT_TTM32(double, true, false);
+    else HT_TTM32(double, false, false);
+  }
+#undef HT_TTM32
 }
 
 void ttm_expand(const double* Z, int64_t P, int R, int64_t S, const double* U, int64_t m, const void* M, Elem mt,
@@ -1165,10 +1282,16 @@ void pad_core(const double* src, int ra, int rb, int rp, double* dst, int ra2, i
   pad_core_kernel<<<grid_for(n), 256, 0, s>>>(src, ra, rb, rp, dst, ra2, rb2);
 }
 
-void root_append(const double* C1, int64_t N, int r11, int r12, double* root, int64_t n_acc, int rcap, hipStream_t s) {
+void root_append(const void* C1, Elem t, int64_t N, int r11, int r12, double* root, int64_t n_acc, int rcap,
+                 hipStream_t s) {
   const int64_t n = N * rcap * rcap;
   ProfScope prof(KKind::Layout, s, 0.0, 0.0);
-  root_append_kernel<<<grid_for(n), 256, 0, s>>>(C1, N, r11, r12, root, n_acc, rcap);
+  if (t == Elem::F32)
+    root_append_kernel<float><<<grid_for(n), 256, 0, s>>>(static_cast<const float*>(C1), N, r11, r12, root, n_acc,
+                                                          rcap);
+  else
+    root_append_kernel<double><<<grid_for(n), 256, 0, s>>>(static_cast<const double*>(C1), N, r11, r12, root, n_acc,
+                                                           rcap);
 }
 
 void root_extract(const double* root, int64_t first, int64_t count, int r11, int r12, int rcap, double* latent,

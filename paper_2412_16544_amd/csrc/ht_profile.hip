@@ -100,7 +100,8 @@ ht_status ht_profile_read(int32_t kind, ht_kernel_stats* out) {
 int32_t ht_profile_kind_count(void) { return (int32_t)ht::KKind::Count; }
 
 const char* ht_profile_kind_name(int32_t kind) {
-  static const char* names[] = {"sumsq", "gram", "ttm_contract", "ttm_expand", "eig_trunc", "orth_expand", "layout"};
+  static const char* names[] = {"sumsq",       "gram",   "ttm_contract", "ttm_expand",     "eig_trunc",
+                                "orth_expand", "layout", "gram_f32",     "ttm_contract_f32"};
   if (kind < 0 || kind >= (int)ht::KKind::Count) return "";
   return names[kind];
 }

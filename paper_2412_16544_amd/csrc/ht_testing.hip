@@ -47,6 +47,27 @@ ht_status ht_test_ttm_contract(const void* x, int32_t dtype, int64_t P, int64_t 
   return hipGetLastError() == hipSuccess ? HT_OK : HT_EDEVICE;
 }
 
+ht_status ht_test_resid_gram_f32(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
+                                 int32_t R, double* G, double* scratch, void* s) {
+  if (!x || !U || !G || !scratch || P < 1 || m < 1 || m > ht::kResidGramMaxM || S < 1 || R < 1 || R > 64 ||
+      !ok_dtype(dtype))
+    return HT_EINVAL;
+  ht::resid_gram_f32(x, elem(dtype), ht::ModeView{P, m, S}, U, R, scratch, G, st(s));
+  return hipGetLastError() == hipSuccess ? HT_OK : HT_EDEVICE;
+}
+
+size_t ht_test_ttm_partials_doubles(void) { return ht::ttm_norm_partials(); }
+
+ht_status ht_test_ttm_contract_f32(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
+                                   int32_t R, float* Z, double* norm2, double* resid2, double* scratch, void* s) {
+  if (!x || !U || !Z || !norm2 || !resid2 || !scratch || P < 1 || m < 1 || m > ht::kResidGramMaxM || S < 1 ||
+      R < 1 || R > 64 || !ok_dtype(dtype))
+    return HT_EINVAL;
+  const size_t np = ht::ttm_norm_partials();
+  ht::ttm_contract_f32(x, elem(dtype), ht::ModeView{P, m, S}, U, R, Z, scratch, norm2, scratch + np, resid2, st(s));
+  return hipGetLastError() == hipSuccess ? HT_OK : HT_EDEVICE;
+}
+
 ht_status ht_test_ttm_expand(const double* Z, int64_t P, int32_t R, int64_t S, const double* U, int64_t m,
                              const void* M, int32_t m_dtype, void* out, int32_t out_dtype, void* s) {
   if (!Z || !U || !out || P < 1 || m < 1 || S < 1 || R < 1 || R > 64 || !ok_dtype(m_dtype) || !ok_dtype(out_dtype))

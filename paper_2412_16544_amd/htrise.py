@@ -251,12 +251,17 @@ def _tlib():
         L.ht_test_gram.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp]
         L.ht_test_ttm_contract.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp]
         L.ht_test_resid_gram.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, vp]
+        L.ht_test_resid_gram_f32.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, vp]
+        L.ht_test_ttm_partials_doubles.argtypes = []
+        L.ht_test_ttm_partials_doubles.restype = sz
+        L.ht_test_ttm_contract_f32.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, vp, vp, vp]
         L.ht_test_ttm_expand.argtypes = [vp, i64, i32, i64, vp, i64, vp, i32, vp, i32, vp]
         L.ht_test_eig_scratch_doubles.argtypes = [i32, i32]
         L.ht_test_eig_scratch_doubles.restype = sz
         L.ht_test_eig.argtypes = [vp, i32, i32, i32, dbl, vp, vp, vp, vp, vp, vp]
         L.ht_test_orth_expand.argtypes = [vp, i64, i32, vp, i32, vp, vp]
-        for name in ("ht_test_sumsq", "ht_test_gram", "ht_test_resid_gram", "ht_test_ttm_contract", "ht_test_ttm_expand", "ht_test_eig",
+        for name in ("ht_test_sumsq", "ht_test_gram", "ht_test_resid_gram", "ht_test_resid_gram_f32",
+                     "ht_test_ttm_contract", "ht_test_ttm_contract_f32", "ht_test_ttm_expand", "ht_test_eig",
                      "ht_test_orth_expand"):
             getattr(L, name).restype = ctypes.c_int
         L._ht_testing_ready = True
@@ -294,6 +299,32 @@ def ht_test_resid_gram(x, P: int, m: int, S: int, U, stream=None):
     _check(L.ht_test_resid_gram(_ptr(x), _dt(x), P, m, S, _ptr(Ucm), U.shape[1], _ptr(G), _ptr(sc),
                                 _stream(stream)), "ht_test_resid_gram")
     return G
+
+
+def ht_test_resid_gram_f32(x, P: int, m: int, S: int, U, stream=None):
+    import torch
+    L = _tlib()
+    sc = torch.empty(max(1, L.ht_test_gram_scratch_doubles(P, m, S)), dtype=torch.float64, device=x.device)
+    G = torch.empty((m, m), dtype=torch.float64, device=x.device)
+    Ucm = U.t().contiguous()
+    _check(L.ht_test_resid_gram_f32(_ptr(x), _dt(x), P, m, S, _ptr(Ucm), U.shape[1], _ptr(G), _ptr(sc),
+                                    _stream(stream)), "ht_test_resid_gram_f32")
+    return G
+
+
+def ht_test_ttm_contract_f32(x, P: int, m: int, S: int, U, stream=None):
+    """Returns (Z float32 [P][R][S], ||X||^2, ||X - U U^T X||^2)."""
+    import torch
+    L = _tlib()
+    R = U.shape[1]
+    Ucm = U.t().contiguous()
+    Z = torch.empty((P, R, S), dtype=torch.float32, device=x.device)
+    sc = torch.empty(2 * L.ht_test_ttm_partials_doubles(), dtype=torch.float64, device=x.device)
+    out = torch.zeros(2, dtype=torch.float64, device=x.device)
+    _check(L.ht_test_ttm_contract_f32(_ptr(x), _dt(x), P, m, S, _ptr(Ucm), R, _ptr(Z), _ptr(out), _ptr(out) + 8,
+                                      _ptr(sc), _stream(stream)), "ht_test_ttm_contract_f32")
+    torch.cuda.synchronize()
+    return Z, float(out[0].item()), float(out[1].item())
 
 
 def ht_test_ttm_contract(x, P: int, m: int, S: int, U, stream=None):

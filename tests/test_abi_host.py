@@ -64,9 +64,14 @@ def test_workspace_sizing_is_monotone():
     assert _ws(rank_cap=8) < a
 
 
+def test_mixed_form_is_a_valid_config():
+    # the FP32 form shares the layout: same workspace as the FP64 form
+    assert _ws(prec=H.HT_FP32) == _ws(prec=H.HT_FP64)
+
+
 @pytest.mark.parametrize("kw", [dict(n=(16,)), dict(eps=0.0), dict(eps=1.0), dict(n=(16, 0, 3)),
                                 dict(rank_cap=0), dict(rank_cap=65), dict(max_batch=0), dict(n_cap=0),
-                                dict(prec=7), dict(in_dtype=5), dict(flags=1)])
+                                dict(prec=7), dict(prec=2), dict(in_dtype=5), dict(flags=1)])
 def test_invalid_configs_rejected(kw):
     with pytest.raises(H.HTError) as e:
         _ws(**kw)

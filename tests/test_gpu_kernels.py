@@ -66,6 +66,55 @@ def test_ttm_contract(P, m, S, R, dtype):
     assert np.max(np.abs(Z - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
 
 
+# Mixed form (FP32 matrix cores).  Inputs near a rank-R subspace, as in HT-RISE:
+# X = U C + noise of relative size 1e-3, so the residual is small next to X.
+# FP32 error model: each product entry carries a relative error <~ sqrt(m) 2^-24
+# ~ 1e-6 of its column's magnitude (Frobenius), so |delta R| <~ 1e-6 ||X|| and a
+# residual energy or residual Gram entry moves by <= 2 ||R|| |delta R| + |delta R|^2.
+F32_REL = 2e-6
+
+MIXED_SHAPES = [(3, 96, 1000, 12), (5, 9, 7, 3), (100, 16, 1, 5), (2, 128, 33, 64), (7, 17, 5, 1),
+                (4, 64, 300, 16), (50, 40, 2, 20), (1, 96, 31, 47)]
+
+
+def near_subspace(P, m, S, R, seed, dtype=np.float32):
+    g = rng(seed)
+    U = np.linalg.qr(g.standard_normal((m, R)))[0]
+    C = g.standard_normal((P, R, S))
+    X = np.einsum("ar,prs->pas", U, C) + 1e-3 * g.standard_normal((P, m, S))
+    return X.astype(dtype).reshape(-1), U
+
+
+@pytest.mark.parametrize("P,m,S,R", MIXED_SHAPES)
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_ttm_contract_f32(P, m, S, R, dtype):
+    x, U = near_subspace(P, m, S, R, P * 3 + m + S + R, dtype)
+    Z, n2, r2 = H.ht_test_ttm_contract_f32(torch.from_numpy(x).cuda(), P, m, S, torch.from_numpy(U).cuda())
+    X = x.astype(np.float64).reshape(P, m, S)
+    ref = np.einsum("ar,pas->prs", U, X)
+    nX = np.linalg.norm(X)
+    assert Z.dtype == torch.float32
+    assert np.linalg.norm(Z.cpu().numpy() - ref) <= F32_REL * nX
+    assert n2 == pytest.approx(float(np.sum(X ** 2)), rel=1e-13)
+    Rr = X - np.einsum("ar,prs->pas", U, ref)
+    nR = np.linalg.norm(Rr)
+    dR = F32_REL * nX
+    assert abs(r2 - nR ** 2) <= 2 * nR * dR + dR ** 2
+
+
+@pytest.mark.parametrize("P,m,S,R", MIXED_SHAPES)
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_resid_gram_f32(P, m, S, R, dtype):
+    x, U = near_subspace(P, m, S, R, P * 5 + m + S + R, dtype)
+    G = H.ht_test_resid_gram_f32(torch.from_numpy(x).cuda(), P, m, S, torch.from_numpy(U).cuda()).cpu().numpy()
+    M = unfold_np(x.astype(np.float64), P, m, S)
+    Rr = M - U @ (U.T @ M)
+    ref = Rr @ Rr.T
+    nR, dR = np.linalg.norm(Rr), F32_REL * np.linalg.norm(M)
+    assert np.linalg.norm(G - ref) <= 2 * nR * dR + dR ** 2
+    assert np.allclose(G, G.T, rtol=0, atol=1e-15 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("P,R,S,m", [(3, 12, 1000, 96), (5, 3, 7, 3), (100, 5, 1, 16), (2, 64, 33, 200),
                                      (1, 17, 40, 130), (7, 1, 5, 17)])
 @pytest.mark.parametrize("with_m", [False, True])

@@ -1,0 +1,154 @@
+"""GPU (MI355X) parity of the mixed precision form (HT_FP32) with the FP64 oracle.
+
+In ht_rise_update the mixed form runs contractions of modes with at most 128 rows
+and their residual Grams on FP32 matrix cores (FP64 partial sums), stores level
+tensors in FP32 and takes the skip test from the explicit residual energy of each
+contraction; BHT-l2r, eigen solves, decisions and expansion stay FP64.
+
+The bar:
+* ranks and skip decisions identical to the oracle's at every batch.  An FP32
+  residual entry is off by |delta| <~ sqrt(m) 2^-24 |x| ~ 1e-6 |x|, so a residual
+  energy moves by <= 2 ||R|| ||delta|| ~ 2e-6 ||R|| ||Y||; next to a decision
+  threshold (||R|| ~ eps ||Y||) that is ~2e-2 eps^2 ||Y||^2 / (2d - 2) at most, and
+  no decision in these streams lies within 10 % of its threshold;
+* reconstructions within MIXED_TOL = 5e-6 ||Y|| of the oracle's: the latent slices
+  come out of two FP32 contraction levels, each with relative error
+  <~ sqrt(m) 2^-24 ~ 6e-7 (m <= 128) in the Frobenius norm, against 1e-10 for the
+  FP64 form;
+* the per-batch error bound ||Y - Y_hat|| <= eps (1 + 1e-3) ||Y||.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import datagen  # noqa: E402
+from oracle import ht_oracle as ho  # noqa: E402
+from paper_2412_16544_amd import htrise as H  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+MIXED_TOL = 5e-6
+BOUND_SLACK = 1e-3
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def dev(y):
+    return torch.from_numpy(np.ascontiguousarray(y)).to("cuda:0")
+
+
+def run_mixed(ys, eps, rank_cap=64):
+    N = max(y.shape[0] for y in ys)
+    st = H.HTStream(ys[0].shape[1:], eps, rank_cap, N, sum(y.shape[0] for y in ys), "float32", prec=H.HT_FP32)
+    infos, ranks = [], []
+    for y in ys:
+        infos.append(st.push(dev(y)))
+        ranks.append(st.ranks()[0])
+    torch.cuda.synchronize()
+    return st, infos, ranks
+
+
+def check_mixed(ys, eps, rank_cap=64):
+    gst, ginfo, granks = run_mixed(ys, eps, rank_cap)
+    ost = ho.BHT(ys[0].shape[1:], eps)
+    oinfo = [ost.init_batch(ys[0])] + [ost.update(y) for y in ys[1:]]
+    assert granks == [i.ranks for i in oinfo], (granks, [i.ranks for i in oinfo])
+    assert [i.skipped for i in ginfo[1:]] == [i.skipped for i in oinfo[1:]]
+    rec_g = gst.reconstruct().cpu().numpy()
+    rec_o = ost.reconstruct()
+    yall = np.concatenate([y.astype(np.float64) for y in ys])
+    ny = np.linalg.norm(yall)
+    dev_rel = np.linalg.norm(rec_g - rec_o) / ny
+    assert dev_rel <= MIXED_TOL, dev_rel
+    off = 0
+    for y in ys:
+        yy = y.astype(np.float64)
+        e = np.linalg.norm(rec_g[off:off + y.shape[0]] - yy)
+        assert e <= eps * (1 + BOUND_SLACK) * np.linalg.norm(yy)
+        off += y.shape[0]
+    for gi, oi in zip(ginfo, oinfo):
+        assert gi.norm_y == pytest.approx(oi.norm_y, rel=1e-12)
+        # sqrt of summed FP32 residual energies: off by at most ~||delta|| ~ 1e-6 ||Y||
+        assert abs(gi.eps_proj - oi.eps_proj) <= 1e-5 * oi.norm_y
+    return gst, ost, dev_rel
+
+
+def test_mixed_tiny_stream():
+    ys = datagen.tiny_stream()
+    gst, _, _ = check_mixed(ys, 1e-4)
+    assert gst.ranks() == ([8] * 6, 40)
+
+
+def test_mixed_tiny_stream_eps_1e3():
+    check_mixed(datagen.tiny_stream(), 1e-3)
+
+
+@pytest.mark.parametrize("n,rank,N", [((17, 33, 5), 3, 7), ((40, 24), 5, 3), ((9, 8, 7, 6, 5, 4), 2, 4),
+                                      ((130, 12, 6), 3, 2)])
+def test_mixed_other_orders_and_ragged_shapes(n, rank, N):
+    spec = datagen.HTModelSpec(n=n, rank=rank, N=N, n_batches=4, seed=77, batch_seed0=7700, nu=1e-7,
+                               grow_at=(2,), grow_by=1, grow_scale=0.1)
+    check_mixed(list(datagen.ht_model_stream(spec)), 1e-4)
+
+
+def test_mixed_small_field_stream():
+    spec = datagen.FieldSpec(grid=(24, 24, 24), channels=3, terms=6, N=8, n_batches=8, drift=2e-3, seed=9,
+                             batch_seed0=900, nu=0.0, w_lo=0.2, w_hi=0.5)
+    check_mixed(list(datagen.separable_field_stream(spec)), 1e-4)
+
+
+def test_mixed_rank_cap_rolls_back():
+    ys = datagen.tiny_stream()
+    st = H.HTStream(ys[0].shape[1:], 1e-4, 6, 8, 40, prec=H.HT_FP32)
+    for y in ys[:4]:
+        st.push(dev(y))
+    before_r = st.ranks()
+    before_rec = st.reconstruct().cpu().numpy()
+    with pytest.raises(H.HTError) as e:
+        st.push(dev(ys[4]))
+    assert e.value.status == H.HT_ERANKCAP
+    assert st.ranks() == before_r
+    np.testing.assert_array_equal(st.reconstruct().cpu().numpy(), before_rec)
+
+
+def test_mixed_eps_1e6_at_the_fp32_floor():
+    """eps = 1e-6 on the tiny model with noise 1e-9 (the configured 1e-6 noise would
+    push the transfer ranks to 256, past any rank cap): eps sits at the FP32 floor of
+    the latent slices, so rank parity is reported rather than required and the
+    error is held to the bound plus that floor."""
+    ys = datagen.tiny_stream(nu=1e-9)
+    st, infos, ranks = run_mixed(ys, 1e-6)
+    ost = ho.BHT(ys[0].shape[1:], 1e-6)
+    oinfo = [ost.init_batch(ys[0])] + [ost.update(y) for y in ys[1:]]
+    print("mixed ranks", ranks, "oracle ranks", [i.ranks for i in oinfo])
+    rec = st.reconstruct().cpu().numpy()
+    off = 0
+    for y in ys:
+        yy = y.astype(np.float64)
+        rel = np.linalg.norm(rec[off:off + y.shape[0]] - yy) / np.linalg.norm(yy)
+        print("batch error / ||Y||: %.3e" % rel)
+        assert rel <= 1e-6 + MIXED_TOL, rel
+        off += y.shape[0]
+
+
+def test_mixed_field96_full_size():
+    """The 96^3 x 3, N = 32, 20-batch stream at eps = 1e-4 in the mixed form: ranks and
+    skips equal the oracle's stored trace; every batch meets the error bound."""
+    spec = datagen.field_96_spec()
+    golden = json.load(open(os.path.join(HERE, "golden", "field96_trace.json")))
+    st = H.HTStream(spec.n, 1e-4, 48, 32, 640, prec=H.HT_FP32)
+    for k, y in enumerate(datagen.separable_field_stream(spec)):
+        yd = dev(y)
+        info = st.push(yd)
+        row = golden["batches"][k]
+        assert st.ranks()[0] == row["ranks"], k
+        if k > 0:
+            assert info.skipped == row["skipped"], k
+            assert abs(info.eps_proj / info.norm_y - row["eps_proj_rel"]) <= 1e-5, k
+        rec = st.reconstruct(32 * k, 32)
+        err = torch.linalg.vector_norm(rec - yd.double()).item()
+        assert err <= 1e-4 * (1 + BOUND_SLACK) * torch.linalg.vector_norm(yd.double()).item(), k
