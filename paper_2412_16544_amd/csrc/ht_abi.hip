@@ -330,10 +330,10 @@ double* other(const ht_state* h, const void* p) { return p == h->bufA ? h->bufB 
 // With norm_out the first contraction also writes the squared norm of the input.
 // mixed: contractions of modes with at most 128 rows on FP32 matrix cores (FP32
 // level tensor out); with energy, every contraction also writes the residual
-// energy it discards into two slots per node: FP32 ones the explicit sum
-// (energy[2 node]), FP64 ones ||in||^2 and ||out||^2 (energy[2 node], [2 node + 1]).
+// energy it discards: FP32 ones the explicit sum into energy[2 node] (explicit[node]
+// set), FP64 ones ||in||^2 and ||out||^2 into energy[2 node] and [2 node + 1].
 Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, double* norm_out = nullptr,
-                    bool mixed = false, double* energy = nullptr) {
+                    bool mixed = false, double* energy = nullptr, std::vector<char>* expl = nullptr) {
   const std::vector<int> f = h->tree.frontier(ell);
   Level cur = in;
   for (size_t k = 0; k < f.size(); ++k) {
@@ -345,11 +345,12 @@ Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, 
       ht::ttm_contract_f32(cur.ptr, cur.t, v, h->core[node], h->rank[node], reinterpret_cast<float*>(dst),
                            norm_out ? h->nrmpart : nullptr, norm_out, energy ? h->respart : nullptr,
                            energy ? energy + 2 * node : nullptr, s);
-      if (energy) ht::fill_f64(energy + 2 * node + 1, 0.0, 1, s);
+      if (expl) (*expl)[node] = 1;
       cur.ptr = dst;
       cur.t = Elem::F32;
     } else {
       if (energy) ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), h->sspart, energy + 2 * node, s);
+      if (expl) (*expl)[node] = 0;
       if (norm_out != nullptr)
         ht::ttm_contract_norm(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, h->nrmpart, norm_out, s);
       else
@@ -375,10 +376,10 @@ Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, 
 }
 
 Level project_all(const ht_state* h, const void* Y, int64_t N, hipStream_t s, double* norm_out = nullptr,
-                  bool mixed = false, double* energy = nullptr) {
+                  bool mixed = false, double* energy = nullptr, std::vector<char>* expl = nullptr) {
   Level cur{Y, h->in_t, N, h->n};
   for (int ell = h->tree.depth; ell >= 1; --ell) {
-    cur = project_layer(h, ell, cur, s, norm_out, mixed, energy);
+    cur = project_layer(h, ell, cur, s, norm_out, mixed, energy, expl);
     norm_out = nullptr;
   }
   return cur;
@@ -724,14 +725,16 @@ ht_status ht_rise_update(ht_handle h, const void* Y, int64_t N, void* hip_stream
   Level c1;
   if (h->mixed) {
     double* energy = h->scal + 8;
-    c1 = project_all(h, Y, N, s, h->scal, true, energy);
+    std::vector<char> expl(nn, 0);
+    c1 = project_all(h, Y, N, s, h->scal, true, energy, &expl);
     ht_status st = sync_read(h, s, h->scal, kScalars(nn), h->h_scal.data());
     if (st != HT_OK) return st;
     ny2 = h->h_scal[0];
     // energies of the contractions, in projection order
     for (int ell = h->tree.depth; ell >= 1; --ell)
       for (int node : h->tree.frontier(ell))
-        if (h->tree.nodes[node].layer == ell) lost += h->h_scal[8 + 2 * node] - h->h_scal[8 + 2 * node + 1];
+        if (h->tree.nodes[node].layer == ell)
+          lost += expl[node] ? h->h_scal[8 + 2 * node] : h->h_scal[8 + 2 * node] - h->h_scal[8 + 2 * node + 1];
   } else {
     c1 = project_all(h, Y, N, s, h->scal);
     ht::sumsq(c1.ptr, c1.t, (int64_t)c1.elems(), h->sspart, h->scal + 1, s);

@@ -729,66 +729,74 @@ __global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X,
   }
 }
 
-constexpr int TAC = 64;
-constexpr int TUS = 65;  // LDS row stride (doubles) of the staged U chunk
+constexpr int TUS = 65;  // LDS row stride (doubles) of the staged U chunk of the expansion
+
+// --------------------------------------------------------------------------
+// TTM contraction for modes with more than 128 rows (transfer nodes, large
+// leaves): Z[p, r, s] = sum_a U[a, r] X[p, a, s] on FP64 matrix cores.  One wave
+// per 16 unfolding columns and every output row (R <= 64); U^T is staged in LDS
+// in chunks of rows of a shared by the block's four waves, and each wave keeps
+// the X operands of its next eight steps in flight, so small column counts still
+// spread over many waves and the loop is not bound by one load latency per step.
+// --------------------------------------------------------------------------
+constexpr int kDirectLdsDoubles = 8192;  // U chunk: chunk x (RP + 1) doubles
 
 template <typename T>
-__global__ __launch_bounds__(256) void ttm_contract_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
-                                                           const double* __restrict__ U, int R,
-                                                           double* __restrict__ Z) {
-  __shared__ double sU[TAC * TUS];
+__global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
+                                                         const double* __restrict__ U, int R, int chunk,
+                                                         double* __restrict__ Z) {
+  __shared__ double sU[kDirectLdsDoubles];  // sU[a][r]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int RP = (R + 15) & ~15, ULD = RP + 1, rt = RP >> 4;
   const int64_t K = P * S;
-  const int64_t colw = ((int64_t)blockIdx.x * 4 + wave) * 64;
-  const int rt = (R + 15) >> 4;
-  d4 acc[4][4];
+  const int64_t c = ((int64_t)blockIdx.x * 4 + wave) * 16 + (lane & 15);
+  const bool cv = c < K;
+  const int64_t base = cv ? col_base(c, m, S) : 0;
+  const int kr = lane >> 4;  // row of the 4-row step this lane feeds
+  d4 acc[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  int64_t base[4];
-  bool valid[4];
-#pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int64_t c = colw + ct * 16 + (lane & 15);
-    valid[ct] = c < K;
-    base[ct] = valid[ct] ? col_base(c, m, S) : 0;
-  }
-  for (int64_t a0 = 0; a0 < m; a0 += TAC) {
-    const int ac = (int)min<int64_t>(TAC, m - a0);
+  for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t a0 = 0; a0 < m; a0 += chunk) {
+    const int ac = (int)min<int64_t>(chunk, m - a0);
+    const int ac4 = (ac + 3) & ~3;
     __syncthreads();
-    for (int e = threadIdx.x; e < TAC * 64; e += 256) {
-      const int a = e >> 6, r = e & 63;
-      sU[a * TUS + r] = (a < ac && r < R) ? U[(a0 + a) + (int64_t)r * m] : 0.0;
+    for (int e = threadIdx.x; e < ac4 * RP; e += 256) {
+      const int a = e / RP, r = e - (e / RP) * RP;
+      sU[a * ULD + r] = (a < ac && r < R) ? U[(a0 + a) + (int64_t)r * m] : 0.0;
     }
     __syncthreads();
-    for (int ks = 0; ks < ac; ks += 4) {
-      const int a = ks + (lane >> 4);
-      double b[4];
+    const int nst = ac4 >> 2;
+    const T* xp = X + base + a0 * S;
+    double b[8];
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) b[ct] = (valid[ct] && a < ac) ? ld(X, base[ct] + (a0 + a) * S) : 0.0;
+    for (int q = 0; q < 8; ++q) {
+      const int a = 4 * q + kr;
+      b[q] = (cv && a < ac) ? static_cast<double>(xp[(int64_t)a * S]) : 0.0;
+    }
+    for (int st = 0; st < nst; st += 8) {
 #pragma unroll
-      for (int rti = 0; rti < 4; ++rti) {
-        if (rti < rt) {
-          const double av = sU[a * TUS + rti * 16 + (lane & 15)];
+      for (int q = 0; q < 8; ++q) {
+        if (st + q < nst) {
+          const double bv = b[q];
+          const int an = 4 * (st + q + 8) + kr;
+          b[q] = (cv && an < ac) ? static_cast<double>(xp[(int64_t)an * S]) : 0.0;
+          const double* ua = sU + (4 * (st + q) + kr) * ULD + (lane & 15);
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[rti][ct] = mfma16(av, b[ct], acc[rti][ct]);
+          for (int t = 0; t < 4; ++t)
+            if (t < rt) acc[t] = mfma16(ua[t * 16], bv, acc[t]);
         }
       }
     }
   }
+  if (cv) {
+    const int64_t p = c / S, sidx = c - (c / S) * S;
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int64_t c = colw + ct * 16 + (lane & 15);
-    if (c >= K) continue;
-    const int64_t p = c / S, s = c - (c / S) * S;
-#pragma unroll
-    for (int rti = 0; rti < 4; ++rti) {
-      if (rti < rt) {
+    for (int t = 0; t < 4; ++t) {
+      if (t < rt) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int r = rti * 16 + (lane >> 4) + 4 * v;
-          if (r < R) Z[(p * R + r) * S + s] = acc[rti][ct][v];
+          const int r = t * 16 + MA<double>::row(lane, v);
+          if (r < R) Z[(p * R + r) * S + sidx] = acc[t][v];
         }
       }
     }
@@ -797,7 +805,8 @@ __global__ __launch_bounds__(256) void ttm_contract_kernel(const T* __restrict__
 
 // --------------------------------------------------------------------------
 // TTM expansion out[p, a, s] = (M[p,a,s] -) sum_t U[a, t] Z[p, t, s]  (FP64 MFMA)
-// Block = 4 waves x 64 columns, blockIdx.y selects 64 rows of a.
+// One wave per 16 columns and 64 rows of a (blockIdx.y); all of the wave's Z
+// operands (R <= 64: at most 16 steps of 4) are loaded before the first product.
 // --------------------------------------------------------------------------
 template <typename TM, typename TO>
 __global__ __launch_bounds__(256) void ttm_expand_kernel(const double* __restrict__ Z, int64_t P, int R, int64_t S,
@@ -807,59 +816,49 @@ __global__ __launch_bounds__(256) void ttm_expand_kernel(const double* __restric
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t K = P * S;
   const int64_t a0 = (int64_t)blockIdx.y * 64;
-  const int64_t colw = ((int64_t)blockIdx.x * 4 + wave) * 64;
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int t = e >> 6, al = e & 63;
     sU[t * TUS + al] = (t < R && a0 + al < m) ? U[(a0 + al) + (int64_t)t * m] : 0.0;
   }
-  __syncthreads();
-  d4 acc[4][4];
+  const int64_t c = ((int64_t)blockIdx.x * 4 + wave) * 16 + (lane & 15);
+  const bool cv = c < K;
+  const int64_t p = cv ? c / S : 0;
+  const int64_t sidx = cv ? c - p * S : 0;
+  const int64_t zb = p * R * S + sidx;
+  const int kr = lane >> 4;
+  const int nst = (R + 3) >> 2;
+  double b[16];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  int64_t zb[4];
-  bool valid[4];
-#pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int64_t c = colw + ct * 16 + (lane & 15);
-    valid[ct] = c < K;
-    const int64_t p = valid[ct] ? c / S : 0;
-    const int64_t s = valid[ct] ? c - p * S : 0;
-    zb[ct] = p * R * S + s;
+  for (int q = 0; q < 16; ++q) {
+    const int t = 4 * q + kr;
+    b[q] = (cv && t < R) ? Z[zb + (int64_t)t * S] : 0.0;
   }
+  __syncthreads();
+  d4 acc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
   const int at_n = (int)min<int64_t>(4, (m - a0 + 15) >> 4);
-  for (int t0 = 0; t0 < R; t0 += 4) {
-    const int t = t0 + (lane >> 4);
-    double b[4];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) b[ct] = (valid[ct] && t < R) ? Z[zb[ct] + (int64_t)t * S] : 0.0;
+  for (int q = 0; q < 16; ++q) {
+    if (q < nst) {
+      const int t = 4 * q + kr;
 #pragma unroll
-    for (int at = 0; at < 4; ++at) {
-      if (at < at_n) {
-        const double av = sU[t * TUS + at * 16 + (lane & 15)];
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[at][ct] = mfma16(av, b[ct], acc[at][ct]);
-      }
+      for (int at = 0; at < 4; ++at)
+        if (at < at_n) acc[at] = mfma16(sU[t * TUS + at * 16 + (lane & 15)], b[q], acc[at]);
     }
   }
+  if (!cv) return;
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int64_t c = colw + ct * 16 + (lane & 15);
-    if (c >= K) continue;
-    const int64_t p = c / S, s = c - (c / S) * S;
+  for (int at = 0; at < 4; ++at) {
+    if (at < at_n) {
 #pragma unroll
-    for (int at = 0; at < 4; ++at) {
-      if (at < at_n) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t a = a0 + at * 16 + (lane >> 4) + 4 * v;
-          if (a < m) {
-            const int64_t idx = (p * m + a) * S + s;
-            double val = acc[at][ct][v];
-            if (M != nullptr) val = ld(M, idx) - val;
-            out[idx] = static_cast<TO>(val);
-          }
+      for (int v = 0; v < 4; ++v) {
+        const int64_t a = a0 + at * 16 + MA<double>::row(lane, v);
+        if (a < m) {
+          const int64_t idx = (p * m + a) * S + sidx;
+          double val = acc[at][v];
+          if (M != nullptr) val = ld(M, idx) - val;
+          out[idx] = static_cast<TO>(val);
         }
       }
     }
@@ -1216,11 +1215,13 @@ void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U
   if (norm_part != nullptr) sumsq(x, t, v.P * v.m * v.S, norm_part, norm_out, s);
   ProfScope prof(KKind::TtmContract, s, 2.0 * R * v.m * (double)K,
                  (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8);
-  const unsigned blocks = (unsigned)((K + 255) / 256);
+  const unsigned blocks = (unsigned)((K + 63) / 64);
+  const int RP = (R + 15) & ~15;
+  const int chunk = (int)std::min<int64_t>(((kDirectLdsDoubles / (RP + 1)) / 4) * 4, (v.m + 3) & ~3);
   if (t == Elem::F32)
-    ttm_contract_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R, Z);
+    ttm_direct_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R, chunk, Z);
   else
-    ttm_contract_kernel<double><<<blocks, 256, 0, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U, R, Z);
+    ttm_direct_kernel<double><<<blocks, 256, 0, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U, R, chunk, Z);
 }
 
 void ttm_contract_f32(const void* x, Elem t, const ModeView& v, const double* U, int R, float* Z, double* norm_part,
@@ -1253,7 +1254,7 @@ void ttm_expand(const double* Z, int64_t P, int R, int64_t S, const double* U, i
   ProfScope prof(KKind::TtmExpand, s, 2.0 * R * m * (double)K,
                  (double)R * K * 8 + (double)m * K * (out_t == Elem::F32 ? 4 : 8) +
                      (M ? (double)m * K * (mt == Elem::F32 ? 4 : 8) : 0.0));
-  dim3 grid((unsigned)((K + 255) / 256), (unsigned)((m + 63) / 64));
+  dim3 grid((unsigned)((K + 63) / 64), (unsigned)((m + 63) / 64));
   if (out_t == Elem::F32) {
     ttm_expand_kernel<double, float><<<grid, 256, 0, s>>>(Z, P, R, S, U, m, nullptr, static_cast<float*>(out));
   } else if (M == nullptr) {
