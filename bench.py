@@ -20,7 +20,12 @@ per-batch error bound.  Also reported: the roofline position of the mixed form's
 dominant kernel class (HIP-event timing inside the library, on the launch
 stream), and the FP64 NumPy oracle timed on this host on a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--form both|mixed|fp64]
+Beside it, the many-streams form: 64 independent exact-rank streams of uneven
+shapes (3-4 modes of 16..128, 4-32 samples, at most 2^20 elements per batch),
+10 HT-RISE updates each, timed one stream at a time (ht_rise_update) and in lock
+step (ht_rise_update_many), in both precision forms.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--form both|mixed|fp64] [--no-many]
     python bench.py --copy-probe      # a plain 256 MiB device copy (counter calibration)
 """
 
@@ -186,6 +191,62 @@ def run_form(form, spec, ys, golden, steps, warmup):
     }
 
 
+def run_many(count=64, cap=1 << 20):
+    """The many-streams workload: updates timed one by one and in lock step, both forms."""
+    import torch
+    import datagen
+    from paper_2412_16544_amd import htrise as H
+    # 16^5 N >= 4.2M exceeds the cap: 3- and 4-mode streams at this size
+    specs = datagen.multi_stream_specs(count=count, max_elements=cap, d_choices=(3, 4))
+    t0 = time.perf_counter()
+    data = []
+    for i, sp in enumerate(specs):
+        data.append([torch.from_numpy(y).to("cuda:0") for y in datagen.ht_model_stream(sp)])
+        if i % 16 == 15:
+            log("many streams: generated %d of %d (%.1f s)" % (i + 1, count, time.perf_counter() - t0))
+    torch.cuda.synchronize()
+    nb = len(data[0])
+    upd_elems = sum(sp.elements_per_batch for sp in specs) * (nb - 1)
+    log("many streams: %d streams staged (%.1f s), %d update elements" % (count, time.perf_counter() - t0, upd_elems))
+
+    def one(prec, batched):
+        sts = [H.HTStream(sp.n, EPS, 32, sp.N, sp.N * nb, prec=prec) for sp in specs]
+        for st, ys in zip(sts, data):
+            st.push(ys[0])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(1, nb):
+            if batched:
+                code, _ = H.HTStream.update_many(sts, [ys[k] for ys in data])
+                assert code == H.HT_OK
+            else:
+                for st, ys in zip(sts, data):
+                    st.update(ys[k])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        ranks = [st.ranks() for st in sts]
+        for st in sts:
+            st.close()
+        return upd_elems / dt, dt, ranks
+
+    one(H.HT_FP64, False)  # warm-up: first launches of every kernel shape
+    res = {}
+    for name, prec, batched in (("fp64_one_by_one", H.HT_FP64, False), ("fp64_batched", H.HT_FP64, True),
+                                ("mixed_one_by_one", H.HT_FP32, False), ("mixed_batched", H.HT_FP32, True)):
+        v, dt, ranks = one(prec, batched)
+        res[name] = {"elements_per_s": v, "seconds": dt, "ranks": ranks}
+        log("many streams %s: %.3e elements/s (%.3f s)" % (name, v, dt))
+    same = all(res[k]["ranks"] == res["fp64_one_by_one"]["ranks"] for k in res)
+    out = {"workload": "%d exact-rank streams (d 3-4, n_i 16-128, N 4-32, <= %d elements per batch), "
+                       "10 HT-RISE updates each, eps=1e-4" % (count, cap),
+           "update_elements": upd_elems, "ranks_agree_across_runs": bool(same)}
+    for k, v in res.items():
+        out[k] = v["elements_per_s"]
+    out["mixed_batched_over_fp64_one_by_one"] = res["mixed_batched"]["elements_per_s"] / res["fp64_one_by_one"][
+        "elements_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +255,7 @@ def main():
     ap.add_argument("--form", choices=("both", "mixed", "fp64"), default="both")
     ap.add_argument("--cpu-sample", type=int, default=4, help="batches of the oracle baseline (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-many", action="store_true", help="skip the many-streams measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs a stream on a single device and this build "
@@ -242,6 +304,8 @@ def main():
         r1, r2 = res["mixed"]["rise_update_elements_per_s"], res["fp64"]["rise_update_elements_per_s"]
         line["mixed_over_fp64_rise_updates"] = r1 / r2 if r1 and r2 else None
     line["parity_vs_oracle_trace"] = all(r["parity_vs_oracle_trace"] for r in res.values())
+    if not args.no_many and args.form == "both":
+        line["many_streams"] = run_many()
     if args.cpu_sample > 0:
         log("timing the oracle on %d batches of the same stream..." % args.cpu_sample)
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_sample)

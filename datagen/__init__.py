@@ -383,24 +383,33 @@ def field_48_stream(n_batches: int = 100, N: int = 16, nu: float = 1e-6) -> Iter
 
 
 def multi_stream_specs(count: int = 64, seed0: int = 4000, n_batches: int = 11,
-                       max_elements: int = 1 << 25, nu: float = 1e-5) -> List[HTModelSpec]:
-    """``count`` exact-rank streams: d in {3,4,5}, n_i in [16,128], N in [4,32].
+                       max_elements: int = 1 << 25, nu: float = 1e-5,
+                       d_choices: Sequence[int] = (3, 4, 5)) -> List[HTModelSpec]:
+    """``count`` exact-rank streams: d from ``d_choices``, n_i in [16,128], N in [4,32].
 
-    Mode sizes are redrawn until N * prod(n) <= ``max_elements``.  The generating
-    rank r0 is drawn from [2,12]; batches 4 and 8 add 2 fresh directions at every
-    node.  ``n_batches`` counts the initial batch, so 11 means 10 updates.
+    Mode sizes are drawn uniformly; while N * prod(n) exceeds ``max_elements`` the
+    largest mode is redrawn uniformly below its current size (at least 16), which
+    ends quickly even for d = 5 (plain redrawing of all modes almost never meets
+    the cap there).  A cap below N * 16^d cannot be met; smaller caps therefore
+    come with fewer modes in ``d_choices``.  The generating rank r0 is drawn from
+    [2,12] and capped by what the modes allow; batches 4 and 8 add 2 fresh
+    directions at every node.  ``n_batches`` counts the initial batch, so 11 means
+    10 updates.
     """
     specs = []
     for s in range(count):
         g = rng(seed0 + s)
-        d = int(g.integers(3, 6))
+        d = int(d_choices[int(g.integers(0, len(d_choices)))])
         N = int(g.integers(4, 33))
-        while True:
-            n = tuple(int(x) for x in g.integers(16, 129, size=d))
-            if N * int(np.prod(n)) <= max_elements:
+        n = [int(x) for x in g.integers(16, 129, size=d)]
+        while N * int(np.prod(n)) > max_elements:
+            i = int(np.argmax(n))
+            if n[i] <= 16:
                 break
+            n[i] = int(g.integers(16, n[i]))
         r0 = int(g.integers(2, 13))
-        specs.append(HTModelSpec(n=n, rank=r0, N=N, n_batches=n_batches, seed=seed0 + s,
+        r0 = min(r0, min(n) - 4)
+        specs.append(HTModelSpec(n=tuple(n), rank=r0, N=N, n_batches=n_batches, seed=seed0 + s,
                                  batch_seed0=(seed0 + s) * 100, nu=nu, grow_at=(4, 8),
                                  grow_by=2, grow_scale=0.1))
     return specs

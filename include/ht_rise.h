@@ -99,6 +99,8 @@ typedef struct {
                              sqrt of the summed residual energies of the projection)    */
   double eps_des;         /* eps_rel * ||Y||_F                                            */
   float device_ms;        /* device time of the call, from HIP events on hip_stream       */
+  int32_t status;         /* ht_status of this handle's update (HT_OK, or why it was
+                             rolled back; ht_rise_update_many reports one per handle)   */
 } ht_update_info;
 
 /* Bytes of device workspace a handle with this configuration needs.  Host only.
@@ -122,6 +124,22 @@ ht_status ht_init_batch(const ht_config* cfg, void* ws, size_t ws_bytes, const v
  * root grows by the N new latent slices (Eq. incremental_root_concatenate).
  * info may be NULL. */
 ht_status ht_rise_update(ht_handle h, const void* Y, int64_t N, void* hip_stream, ht_update_info* info);
+
+/* HT-RISE on count independent handles at once (each with its own configuration,
+ * tree and workspace), all on hip_stream: handle i takes batch Ys[i] of Ns[i]
+ * samples, exactly as ht_rise_update would.  The handles advance in lock step:
+ * every projection (Step 1) is launched before one read-back of all skip tests,
+ * and then, layer by layer from the leaves (trees of different depths aligned at
+ * their leaves), the Gram products of every updating handle precede one shared
+ * eigen launch (one workgroup per node of every handle) and one read-back of the
+ * decisions, so a call costs a few host round trips instead of a few per handle.
+ * infos (may be NULL) receives one entry per handle; device_ms is the time of the
+ * whole call.  Argument errors are returned before any work, leaving every handle
+ * unchanged.  A handle whose update fails (HT_ERANKCAP, HT_ENUMERIC) is rolled
+ * back alone, its infos[i].status says why, the others commit, and the call
+ * returns the first failing handle's status.  A handle may appear once. */
+ht_status ht_rise_update_many(ht_handle* hs, const void* const* Ys, const int64_t* Ns, int32_t count,
+                              void* hip_stream, ht_update_info* infos);
 
 /* Latent codes of a batch in the current cores, without changing the handle:
  * latent is a device buffer of N * r_{1,1} * r_{1,2} float64, C-order [N][r11][r12]. */

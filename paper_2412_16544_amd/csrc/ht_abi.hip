@@ -445,12 +445,16 @@ void restore_cores(ht_state* h, hipStream_t s) {
 
 // One layer of rank decisions: Gram (of the data, or of the explicit residual
 // R = M - U_old U_old^T M), eigen-decomposition, truncation, expansion.
-// rmin = 1 / r_old = 0 for BHT-l2r; rmin = 0 for HT-RISE.
-ht_status decide_layer(ht_state* h, int ell, const Level& cur, double thr, bool initial, hipStream_t s,
-                       int* growth) {
-  const std::vector<int> f = h->tree.frontier(ell);
+// rmin = 1 / r_old = 0 for BHT-l2r; rmin = 0 for HT-RISE.  Split in two so that
+// the layers of many handles can share one eigen launch and one read-back.
+struct LayerJobs {
   std::vector<ht::EigJob> jobs;
-  std::vector<int> job_node, job_rold;
+  std::vector<int> node, rold;
+};
+
+// Gram launches of layer ell and the eigen jobs they feed.
+void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initial, hipStream_t s, LayerJobs& L) {
+  const std::vector<int> f = h->tree.frontier(ell);
   for (size_t k = 0; k < f.size(); ++k) {
     const int node = f[k];
     if (h->tree.nodes[node].layer != ell) continue;
@@ -486,47 +490,57 @@ ht_status decide_layer(ht_state* h, int ell, const Level& cur, double thr, bool 
     j.rmin = initial ? 1 : 0;
     j.rmax = room;
     j.pad = 0;
-    jobs.push_back(j);
-    job_node.push_back(node);
-    job_rold.push_back(r_old);
+    L.jobs.push_back(j);
+    L.node.push_back(node);
+    L.rold.push_back(r_old);
   }
+}
+
+void launch_eig(const std::vector<ht::EigJob>& jobs, hipStream_t s) {
   for (size_t b = 0; b < jobs.size(); b += ht::kMaxEigJobs)
     ht::eig_trunc(jobs.data() + b, (int)std::min<size_t>(ht::kMaxEigJobs, jobs.size() - b), s);
-  HT_HIP(hipGetLastError());
-  // read back the decisions of this layer
+}
+
+// Ranks and discarded energies of the layer (device -> host, not yet synchronised).
+ht_status layer_readback(ht_state* h, hipStream_t s, std::vector<int>& rk, std::vector<double>& tl) {
   const int nn = (int)h->tree.nodes.size();
-  std::vector<int> rk(nn, 0);
-  std::vector<double> tl(nn, 0.0);
+  rk.assign(nn, 0);
+  tl.assign(nn, 0.0);
   HT_HIP(hipMemcpyAsync(rk.data(), h->ranks_dev, nn * sizeof(int), hipMemcpyDeviceToHost, s));
   HT_HIP(hipMemcpyAsync(tl.data(), h->tails, nn * sizeof(double), hipMemcpyDeviceToHost, s));
-  HT_HIP(hipStreamSynchronize(s));
-  for (size_t q = 0; q < jobs.size(); ++q) {
-    const int node = job_node[q];
+  return HT_OK;
+}
+
+// After the read-back: capacity and finiteness checks, then [U_old, U_R] with U_R
+// re-orthogonalised, and the zero padding of the parents.
+ht_status layer_finish(ht_state* h, double thr, bool initial, hipStream_t s, const LayerJobs& L,
+                       const std::vector<int>& rk, const std::vector<double>& tl, int* growth) {
+  for (size_t q = 0; q < L.jobs.size(); ++q) {
+    const int node = L.node[q];
     const int r = rk[node];
-    const int alpha = jobs[q].k;
-    const int room = jobs[q].rmax;
-    if (r == room && tl[node] > thr && job_rold[q] + room < alpha)
+    const int alpha = L.jobs[q].k;
+    const int room = L.jobs[q].rmax;
+    if (r == room && tl[node] > thr && L.rold[q] + room < alpha)
       return fail(HT_ERANKCAP, "rank of node " + std::to_string(node) + " would exceed rank_cap " +
                                    std::to_string(h->rank_cap));
     if (!std::isfinite(tl[node])) return fail(HT_ENUMERIC, "non-finite eigenvalues at node " + std::to_string(node));
   }
-  // expansion: [U_old, U_R] with U_R re-orthogonalised, then parents padded
   std::vector<int> old_rank = h->rank;
-  for (size_t q = 0; q < jobs.size(); ++q) {
-    const int node = job_node[q];
+  for (size_t q = 0; q < L.jobs.size(); ++q) {
+    const int node = L.node[q];
     const int r = rk[node];
     if (r == 0) continue;
-    ht::orth_expand(h->core[node], jobs[q].k, job_rold[q], h->vecs[node], r, h->core[node], h->orthsc, s);
-    h->rank[node] = job_rold[q] + r;
+    ht::orth_expand(h->core[node], L.jobs[q].k, L.rold[q], h->vecs[node], r, h->core[node], h->orthsc, s);
+    h->rank[node] = L.rold[q] + r;
     *growth += initial ? 0 : r;
   }
   // padWithZeros on every parent whose successors grew (the root's capacity layout pads itself)
-  for (size_t q = 0; q < jobs.size(); ++q) {
-    const int node = job_node[q];
+  for (size_t q = 0; q < L.jobs.size(); ++q) {
+    const int node = L.node[q];
     const int par = h->tree.nodes[node].parent;
     if (par <= 0 || initial) continue;
     if (h->tree.nodes[node].child_pos != 0 &&
-        std::find(job_node.begin(), job_node.end(), h->tree.nodes[par].child[0]) != job_node.end())
+        std::find(L.node.begin(), L.node.end(), h->tree.nodes[par].child[0]) != L.node.end())
       continue;  // parent handled once, at its first successor
     const int a = h->tree.nodes[par].child[0], b = h->tree.nodes[par].child[1];
     const int ra = old_rank[a], rb = old_rank[b], ra2 = h->rank[a], rb2 = h->rank[b];
@@ -537,6 +551,20 @@ ht_status decide_layer(ht_state* h, int ell, const Level& cur, double thr, bool 
   }
   HT_HIP(hipGetLastError());
   return HT_OK;
+}
+
+ht_status decide_layer(ht_state* h, int ell, const Level& cur, double thr, bool initial, hipStream_t s,
+                       int* growth) {
+  LayerJobs L;
+  layer_grams(h, ell, cur, thr, initial, s, L);
+  launch_eig(L.jobs, s);
+  HT_HIP(hipGetLastError());
+  std::vector<int> rk;
+  std::vector<double> tl;
+  ht_status st = layer_readback(h, s, rk, tl);
+  if (st != HT_OK) return st;
+  HT_HIP(hipStreamSynchronize(s));
+  return layer_finish(h, thr, initial, s, L, rk, tl, growth);
 }
 
 ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state** out) {
@@ -596,6 +624,172 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   h->rank.assign(nn, 0);
   h->h_scal.assign(kScalars(nn), 0.0);
   *out = h;
+  return HT_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// HT-RISE over one or many handles (Alg. 2).  The handles advance in lock step:
+// the projections of every handle are launched before the one read-back of the
+// skip tests; then, layer by layer from the leaves, every updating handle's Gram
+// launches precede one shared eigen launch and one read-back of the decisions.
+// A handle whose update fails is rolled back alone.
+// ============================================================================
+namespace {
+
+struct Upd {
+  ht_state* h = nullptr;
+  const void* Y = nullptr;
+  int64_t N = 0;
+  Level c1, cur;
+  std::vector<char> expl;
+  std::vector<int> saved;
+  double ny = 0, eps_des = 0, eps_proj = 0, thr = 0;
+  bool skip = false, busy = false;
+  int growth = 0;
+  ht_status st = HT_OK;
+  std::string err;
+  LayerJobs L;
+  std::vector<int> rk;
+  std::vector<double> tl;
+};
+
+ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* Ns, int count, hipStream_t s,
+                    ht_update_info* infos) {
+  std::vector<Upd> U(count);
+  for (int i = 0; i < count; ++i) {
+    Upd& u = U[i];
+    u.h = hs[i];
+    u.Y = Ys[i];
+    u.N = Ns[i];
+    if (u.h == nullptr) return fail(HT_EINVAL, "handle " + std::to_string(i) + " is NULL");
+    if (u.Y == nullptr) return fail(HT_EINVAL, "Y of handle " + std::to_string(i) + " is NULL");
+    if (u.N < 1) return fail(HT_EINVAL, "N of handle " + std::to_string(i) + " must be >= 1");
+    if (u.N > u.h->max_batch) return fail(HT_ESHAPE, "N of handle " + std::to_string(i) + " exceeds max_batch");
+    if (u.h->n_acc + u.N > u.h->n_cap)
+      return fail(HT_ESHAPE, "accumulation of handle " + std::to_string(i) + " would exceed n_cap");
+  }
+  Timer timer(s);
+  // ---- Step 1 for every handle: projection onto the existing cores; the first
+  //      contraction also returns ||Y||^2 (mixed form: and the residual energies)
+  for (Upd& u : U) {
+    ht_state* h = u.h;
+    h->last_stream = s;
+    const int nn = (int)h->tree.nodes.size();
+    if (h->mixed) {
+      u.expl.assign(nn, 0);
+      u.c1 = project_all(h, u.Y, u.N, s, h->scal, true, h->scal + 8, &u.expl);
+      HT_HIP(hipMemcpyAsync(h->h_scal.data(), h->scal, kScalars(nn) * sizeof(double), hipMemcpyDeviceToHost, s));
+    } else {
+      u.c1 = project_all(h, u.Y, u.N, s, h->scal);
+      ht::sumsq(u.c1.ptr, u.c1.t, (int64_t)u.c1.elems(), h->sspart, h->scal + 1, s);
+      HT_HIP(hipMemcpyAsync(h->h_scal.data(), h->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+  }
+  HT_HIP(hipGetLastError());
+  HT_HIP(hipStreamSynchronize(s));
+  // ---- skip tests (Eq. relative_error_threshold)
+  for (Upd& u : U) {
+    ht_state* h = u.h;
+    const double ny2 = h->h_scal[0];
+    double lost = 0.0;
+    if (h->mixed) {
+      for (int ell = h->tree.depth; ell >= 1; --ell)
+        for (int node : h->tree.frontier(ell))
+          if (h->tree.nodes[node].layer == ell)
+            lost += u.expl[node] ? h->h_scal[8 + 2 * node] : h->h_scal[8 + 2 * node] - h->h_scal[8 + 2 * node + 1];
+    } else {
+      lost = ny2 - h->h_scal[1];
+    }
+    if (!std::isfinite(ny2) || !std::isfinite(lost)) {
+      u.st = HT_ENUMERIC;
+      u.err = "non-finite norm";
+      continue;
+    }
+    u.ny = std::sqrt(ny2);
+    u.eps_des = h->eps * u.ny;
+    u.eps_proj = std::sqrt(std::max(0.0, lost));
+    u.skip = u.eps_proj <= u.eps_des;
+    if (u.skip) {
+      const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
+      ht::root_append(u.c1.ptr, u.c1.t, u.N, r11, r12, h->root, h->n_acc, h->rank_cap, s);
+    } else {
+      u.busy = true;
+      u.saved = h->rank;
+      backup_cores(h, s);
+      const double eps_nw = u.eps_des / std::sqrt(2.0 * h->d - 2.0);
+      u.thr = eps_nw * eps_nw;
+      u.cur = Level{u.Y, h->in_t, u.N, h->n};
+    }
+  }
+  // ---- Step 2, layer by layer from the leaves (trees of different depths aligned
+  //      at their leaves)
+  int max_depth = 0;
+  for (const Upd& u : U)
+    if (u.busy) max_depth = std::max(max_depth, u.h->tree.depth);
+  for (int t = 0; t < max_depth; ++t) {
+    std::vector<ht::EigJob> all;
+    for (Upd& u : U) {
+      const int ell = u.busy ? u.h->tree.depth - t : 0;
+      u.L = LayerJobs();
+      if (ell < 1) continue;
+      layer_grams(u.h, ell, u.cur, u.thr, false, s, u.L);
+      all.insert(all.end(), u.L.jobs.begin(), u.L.jobs.end());
+    }
+    launch_eig(all, s);
+    HT_HIP(hipGetLastError());
+    for (Upd& u : U) {
+      if (!u.busy || u.h->tree.depth - t < 1) continue;
+      const ht_status st = layer_readback(u.h, s, u.rk, u.tl);
+      if (st != HT_OK) return st;
+    }
+    HT_HIP(hipStreamSynchronize(s));
+    for (Upd& u : U) {
+      const int ell = u.busy ? u.h->tree.depth - t : 0;
+      if (ell < 1) continue;
+      ht_status st = layer_finish(u.h, u.thr, false, s, u.L, u.rk, u.tl, &u.growth);
+      if (st != HT_OK) {
+        // roll this handle back: cores from the backup, ranks from before the call
+        u.st = st;
+        u.err = g_last_error;
+        restore_cores(u.h, s);
+        u.h->rank = u.saved;
+        u.busy = false;
+        continue;
+      }
+      u.cur = project_layer(u.h, ell, u.cur, s, nullptr, u.h->mixed);
+    }
+  }
+  for (Upd& u : U) {
+    if (!u.busy) continue;
+    ht_state* h = u.h;
+    const int q11 = h->rank[h->tree.nodes[0].child[0]], q12 = h->rank[h->tree.nodes[0].child[1]];
+    ht::root_append(u.cur.ptr, u.cur.t, u.N, q11, q12, h->root, h->n_acc, h->rank_cap, s);
+  }
+  HT_HIP(hipGetLastError());
+  const float ms = timer.stop();
+  ht_status first = HT_OK;
+  std::string first_err;
+  for (int i = 0; i < count; ++i) {
+    Upd& u = U[i];
+    if (u.st == HT_OK) u.h->n_acc += u.N;
+    if (u.st != HT_OK && first == HT_OK) {
+      first = u.st;
+      first_err = count > 1 ? "handle " + std::to_string(i) + ": " + u.err : u.err;
+    }
+    if (infos) {
+      ht_update_info& in = infos[i];
+      in.skipped = (u.st == HT_OK && u.skip) ? 1 : 0;
+      in.rank_growth = u.st == HT_OK ? u.growth : 0;
+      in.norm_y = u.ny;
+      in.eps_des = u.eps_des;
+      in.eps_proj = u.eps_proj;
+      in.device_ms = ms;
+      in.status = u.st;
+    }
+  }
+  if (first != HT_OK) return fail(first, first_err);
   return HT_OK;
 }
 
@@ -709,81 +903,21 @@ ht_status ht_init_batch(const ht_config* cfg, void* ws, size_t ws_bytes, const v
 ht_status ht_rise_update(ht_handle h, const void* Y, int64_t N, void* hip_stream, ht_update_info* info) {
   g_last_error.clear();
   if (h == nullptr) return fail(HT_EINVAL, "handle is NULL");
-  if (Y == nullptr) return fail(HT_EINVAL, "Y is NULL");
-  if (N < 1) return fail(HT_EINVAL, "N must be >= 1");
-  if (N > h->max_batch) return fail(HT_ESHAPE, "N exceeds max_batch");
-  if (h->n_acc + N > h->n_cap) return fail(HT_ESHAPE, "accumulation would exceed n_cap");
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  h->last_stream = s;
-  Timer timer(s);
-  const int64_t E = N * prod(h->n, 0, h->n.size());
-  // Step 1: projection onto the existing cores; the first contraction reads all of Y
-  // and returns ||Y||^2 as well
-  (void)E;
-  const int nn = (int)h->tree.nodes.size();
-  double ny2 = 0.0, lost = 0.0;
-  Level c1;
-  if (h->mixed) {
-    double* energy = h->scal + 8;
-    std::vector<char> expl(nn, 0);
-    c1 = project_all(h, Y, N, s, h->scal, true, energy, &expl);
-    ht_status st = sync_read(h, s, h->scal, kScalars(nn), h->h_scal.data());
-    if (st != HT_OK) return st;
-    ny2 = h->h_scal[0];
-    // energies of the contractions, in projection order
-    for (int ell = h->tree.depth; ell >= 1; --ell)
-      for (int node : h->tree.frontier(ell))
-        if (h->tree.nodes[node].layer == ell)
-          lost += expl[node] ? h->h_scal[8 + 2 * node] : h->h_scal[8 + 2 * node] - h->h_scal[8 + 2 * node + 1];
-  } else {
-    c1 = project_all(h, Y, N, s, h->scal);
-    ht::sumsq(c1.ptr, c1.t, (int64_t)c1.elems(), h->sspart, h->scal + 1, s);
-    ht_status st = sync_read(h, s, h->scal, 2, h->h_scal.data());
-    if (st != HT_OK) return st;
-    ny2 = h->h_scal[0];
-    lost = ny2 - h->h_scal[1];
-  }
-  ht_status st = HT_OK;
-  if (!std::isfinite(ny2) || !std::isfinite(lost)) return fail(HT_ENUMERIC, "non-finite norm");
-  const double ny = std::sqrt(ny2);
-  const double eps_des = h->eps * ny;
-  const double eps_proj = std::sqrt(std::max(0.0, lost));
-  const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
-  int growth = 0;
-  if (eps_proj <= eps_des) {
-    ht::root_append(c1.ptr, c1.t, N, r11, r12, h->root, h->n_acc, h->rank_cap, s);
-    HT_HIP(hipGetLastError());
-  } else {
-    const std::vector<int> saved = h->rank;
-    backup_cores(h, s);
-    const double eps_nw = eps_des / std::sqrt(2.0 * h->d - 2.0);
-    Level cur{Y, h->in_t, N, h->n};
-    for (int ell = h->tree.depth; ell >= 1; --ell) {
-      st = decide_layer(h, ell, cur, eps_nw * eps_nw, false, s, &growth);
-      if (st != HT_OK) {
-        restore_cores(h, s);
-        h->rank = saved;
-        (void)hipStreamSynchronize(s);
-        return st;
-      }
-      cur = project_layer(h, ell, cur, s, nullptr, h->mixed);
-    }
-    const int q11 = h->rank[h->tree.nodes[0].child[0]], q12 = h->rank[h->tree.nodes[0].child[1]];
-    ht::root_append(cur.ptr, cur.t, N, q11, q12, h->root, h->n_acc, h->rank_cap, s);
-    HT_HIP(hipGetLastError());
-  }
-  h->n_acc += N;
-  const float ms = timer.stop();
-  HT_HIP(hipGetLastError());
-  if (info) {
-    info->skipped = eps_proj <= eps_des ? 1 : 0;
-    info->rank_growth = growth;
-    info->norm_y = ny;
-    info->eps_des = eps_des;
-    info->eps_proj = eps_proj;
-    info->device_ms = ms;
-  }
-  return HT_OK;
+  const void* ys[1] = {Y};
+  const int64_t ns[1] = {N};
+  ht_handle hs[1] = {h};
+  return rise_many(hs, ys, ns, 1, static_cast<hipStream_t>(hip_stream), info);
+}
+
+ht_status ht_rise_update_many(ht_handle* hs, const void* const* Ys, const int64_t* Ns, int32_t count,
+                              void* hip_stream, ht_update_info* infos) {
+  g_last_error.clear();
+  if (hs == nullptr || Ys == nullptr || Ns == nullptr) return fail(HT_EINVAL, "NULL argument");
+  if (count < 1) return fail(HT_EINVAL, "count must be >= 1");
+  for (int i = 0; i < count; ++i)
+    for (int j = 0; j < i; ++j)
+      if (hs[i] == hs[j]) return fail(HT_EINVAL, "a handle appears twice");
+  return rise_many(hs, Ys, Ns, count, static_cast<hipStream_t>(hip_stream), infos);
 }
 
 ht_status ht_project(ht_handle h, const void* Y, int64_t N, void* latent, void* hip_stream) {

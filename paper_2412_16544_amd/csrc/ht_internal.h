@@ -78,7 +78,7 @@ struct EigJob {
   int rmax;
   int pad;
 };
-constexpr int kMaxEigJobs = 8;
+constexpr int kMaxEigJobs = 32;
 size_t eig_scratch_doubles(int k, int rmax);
 // Runs up to kMaxEigJobs independent problems in one launch (one workgroup each).
 void eig_trunc(const EigJob* jobs, int count, hipStream_t s);

@@ -33,7 +33,8 @@ class ht_config(ctypes.Structure):
 
 class ht_update_info(ctypes.Structure):
     _fields_ = [("skipped", ctypes.c_int32), ("rank_growth", ctypes.c_int32), ("norm_y", ctypes.c_double),
-                ("eps_proj", ctypes.c_double), ("eps_des", ctypes.c_double), ("device_ms", ctypes.c_float)]
+                ("eps_proj", ctypes.c_double), ("eps_des", ctypes.c_double), ("device_ms", ctypes.c_float),
+                ("status", ctypes.c_int32)]
 
 
 class HTError(RuntimeError):
@@ -56,6 +57,8 @@ def lib() -> ctypes.CDLL:
         L.ht_init_batch.argtypes = [ctypes.POINTER(ht_config), vp, sz, vp, i64, vp, ctypes.POINTER(vp),
                                     ctypes.POINTER(ht_update_info)]
         L.ht_rise_update.argtypes = [vp, vp, i64, vp, ctypes.POINTER(ht_update_info)]
+        L.ht_rise_update_many.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64), i32, vp,
+                                          ctypes.POINTER(ht_update_info)]
         L.ht_project.argtypes = [vp, vp, i64, vp, vp]
         L.ht_reconstruct.argtypes = [vp, i64, i64, vp, i32, vp]
         L.ht_query_ranks.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]
@@ -66,8 +69,8 @@ def lib() -> ctypes.CDLL:
         L.ht_status_str.restype = ctypes.c_char_p
         L.ht_last_error.argtypes = []
         L.ht_last_error.restype = ctypes.c_char_p
-        for name in ("ht_workspace_bytes", "ht_init_batch", "ht_rise_update", "ht_project", "ht_reconstruct",
-                     "ht_query_ranks", "ht_export_cores"):
+        for name in ("ht_workspace_bytes", "ht_init_batch", "ht_rise_update", "ht_rise_update_many", "ht_project",
+                     "ht_reconstruct", "ht_query_ranks", "ht_export_cores"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -119,6 +122,23 @@ def ht_rise_update(h: int, Y, stream=None) -> ht_update_info:
     return info
 
 
+def ht_rise_update_many(handles: Sequence[int], Ys, stream=None):
+    """HT-RISE on several handles in lock step; returns (status, [ht_update_info]).
+
+    Raises HTError for argument errors; a handle whose update failed is rolled back
+    and reported through its info's status (the call's status is the first failure).
+    """
+    n = len(handles)
+    hs = (ctypes.c_void_p * n)(*[ctypes.c_void_p(h) for h in handles])
+    ys = (ctypes.c_void_p * n)(*[ctypes.c_void_p(_ptr(y)) for y in Ys])
+    ns = (ctypes.c_int64 * n)(*[int(y.shape[0]) for y in Ys])
+    infos = (ht_update_info * n)()
+    st = lib().ht_rise_update_many(hs, ys, ns, n, _stream(stream), infos)
+    if st not in (HT_OK, HT_ERANKCAP, HT_ENUMERIC):
+        _check(st, "ht_rise_update_many")
+    return st, list(infos)
+
+
 def ht_project(h: int, Y, latent, stream=None) -> None:
     _check(lib().ht_project(h, _ptr(Y), Y.shape[0], _ptr(latent), _stream(stream)), "ht_project")
 
@@ -163,11 +183,12 @@ class UpdateInfo:
     eps_proj: float
     eps_des: float
     device_ms: float
+    status: int = HT_OK
 
     @staticmethod
     def of(i: ht_update_info) -> "UpdateInfo":
         return UpdateInfo(bool(i.skipped), int(i.rank_growth), float(i.norm_y), float(i.eps_proj),
-                          float(i.eps_des), float(i.device_ms))
+                          float(i.eps_des), float(i.device_ms), int(i.status))
 
 
 class HTStream:
@@ -196,6 +217,12 @@ class HTStream:
 
     def push(self, Y, stream=None) -> UpdateInfo:
         return self.init_batch(Y, stream) if not self.h else self.update(Y, stream)
+
+    @staticmethod
+    def update_many(streams: Sequence["HTStream"], Ys, stream=None) -> Tuple[int, List[UpdateInfo]]:
+        """HT-RISE on several initialised streams at once (ht_rise_update_many)."""
+        st, infos = ht_rise_update_many([s.h for s in streams], Ys, stream)
+        return st, [UpdateInfo.of(i) for i in infos]
 
     def ranks(self) -> Tuple[List[int], int]:
         return ht_query_ranks(self.h)

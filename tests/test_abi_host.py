@@ -100,6 +100,25 @@ def test_null_arguments_rejected_before_device_work():
     L.ht_destroy(None)
 
 
+def test_update_many_argument_errors_before_device_work():
+    L = H.lib()
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)
+    hs = (vp * 2)(fake, fake)
+    ys = (vp * 2)(vp(1), vp(1))
+    ns = (ctypes.c_int64 * 2)(1, 1)
+    infos = (H.ht_update_info * 2)()
+    assert L.ht_rise_update_many(None, ys, ns, 2, None, infos) == H.HT_EINVAL
+    assert L.ht_rise_update_many(hs, None, ns, 2, None, infos) == H.HT_EINVAL
+    assert L.ht_rise_update_many(hs, ys, None, 2, None, infos) == H.HT_EINVAL
+    assert L.ht_rise_update_many(hs, ys, ns, 0, None, infos) == H.HT_EINVAL
+    # the same handle twice is rejected before any handle is touched
+    assert L.ht_rise_update_many(hs, ys, ns, 2, None, infos) == H.HT_EINVAL
+    assert "twice" in L.ht_last_error().decode()
+    nulls = (vp * 1)(vp(0))
+    assert L.ht_rise_update_many(nulls, ys, ns, 1, None, infos) == H.HT_EINVAL
+
+
 def test_binding_refuses_missing_library(monkeypatch):
     monkeypatch.setattr(H, "_lib", None)
     monkeypatch.setattr(H, "LIB_PATH", "/nonexistent/libhtrise.so")
