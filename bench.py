@@ -27,6 +27,7 @@ step (ht_rise_update_many), in both precision forms.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--form both|mixed|fp64] [--no-many]
     python bench.py --copy-probe      # a plain 256 MiB device copy (counter calibration)
+    python bench.py --ingest-counters FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB
 """
 
 import argparse
@@ -247,6 +248,53 @@ def run_many(count=64, cap=1 << 20):
     return out
 
 
+# kernel-name patterns of each profile kind (the template's second argument is the
+# compute type of the panel kernels)
+KIND_KERNELS = {
+    "ttm_contract_f32": ("ttm_panel_kernel<float, float", "ttm_panel_kernel<double, float"),
+    "ttm_contract": ("ttm_panel_kernel<float, double", "ttm_panel_kernel<double, double", "ttm_direct_kernel<"),
+    "gram_f32": ("gram_panel_kernel<float, float", "gram_panel_kernel<double, float"),
+    "gram": ("gram_panel_kernel<float, double", "gram_panel_kernel<double, double", "gram_partial_kernel<",
+             "gram_small_kernel<"),
+    "ttm_expand": ("ttm_expand_kernel<",),
+    "sumsq": ("sumsq_partial_kernel<",),
+}
+
+
+def ingest_counters(fetch_db, write_db, copy_fetch_db, copy_write_db, out_path):
+    """HBM bytes per launch of each kernel kind from two rocprofv3 --pmc runs (FETCH_SIZE,
+    WRITE_SIZE, KiB per dispatch), scaled by what the same counters read for a plain
+    copy of known size."""
+    import sqlite3
+
+    def rows(db, counter):
+        con = sqlite3.connect(db)
+        q = "select kernel_name, value from counters_collection where counter_name = ?"
+        return list(con.execute(q, (counter,)))
+
+    copy_bytes = (1 << 25) * 8
+    cf = [v for n, v in rows(copy_fetch_db, "FETCH_SIZE") if "copyBuffer" in n and v * 1024 > copy_bytes / 4]
+    cw = [v for n, v in rows(copy_write_db, "WRITE_SIZE") if "copyBuffer" in n and v * 1024 > copy_bytes / 4]
+    f_fetch = copy_bytes / (sum(cf) / len(cf) * 1024)
+    f_write = copy_bytes / (sum(cw) / len(cw) * 1024)
+    fr, wr = rows(fetch_db, "FETCH_SIZE"), rows(write_db, "WRITE_SIZE")
+    kernels = {}
+    for kind, pats in KIND_KERNELS.items():
+        fv = [v for n, v in fr if any(p in n for p in pats)]
+        wv = [v for n, v in wr if any(p in n for p in pats)]
+        if not fv or not wv:
+            continue
+        fb = sum(fv) / len(fv) * 1024 * f_fetch
+        wb = sum(wv) / len(wv) * 1024 * f_write
+        kernels[kind] = {"dispatches": len(fv), "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                         "hbm_bytes_per_launch": fb + wb}
+    out = {"source_digest": source_digest(), "copy_probe_bytes": copy_bytes,
+           "counter_scale": {"FETCH_SIZE": f_fetch, "WRITE_SIZE": f_write}, "kernels": kernels}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +304,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4, help="batches of the oracle baseline (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-many", action="store_true", help="skip the many-streams measurement")
+    ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
+                    help="write profiles/traffic.json from rocprofv3 --pmc databases (host only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs a stream on a single device and this build "
@@ -263,6 +313,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters, os.path.join(ROOT, "profiles", "traffic.json"))
         return
 
     import torch
