@@ -403,6 +403,36 @@ __device__ __forceinline__ void put_column(const double (&A)[tile_base(TA)], int
   }
 }
 
+// The owners of column c publish the part below the diagonal that the next
+// reflector annihilates: rows c + 2 .. k - 1 go to buf (rows c and c + 1 of buf are
+// set to zero, rows above stay zero from earlier steps), the diagonal entry to
+// *dg and the subdiagonal one to *sd.
+template <int TA>
+__device__ __forceinline__ void put_lower(const double (&A)[tile_base(TA)], int c, int k, int tr, int tc,
+                                          double* buf, double* dg, double* sd) {
+  if (tc != (c & 31)) return;
+  const int bc = c >> 5;
+#pragma unroll
+  for (int b = 0; b < (TA + 1) / 2; ++b) {
+    if (b == bc) {
+#pragma unroll
+      for (int a = 2 * b; a < TA; ++a) {
+        const int i = 16 * a + tr;
+        const double val = A[tile_base(a) + b];
+        if (i == c) {
+          *dg = val;
+          buf[i] = 0.0;
+        } else if (i == c + 1) {
+          *sd = val;
+          buf[i] = 0.0;
+        } else if (i > c + 1 && i < k) {
+          buf[i] = val;
+        }
+      }
+    }
+  }
+}
+
 template <int TA>
 __device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k, double* xb, double* cb,
                                             double* vbuf, double* pbuf, double* rowpart, double* colpart, double* d,
@@ -421,32 +451,28 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k,
       A[tile_base(a) + b] = (i < k && l < k) ? G[(int64_t)i * k + l] : 0.0;
     }
   }
-  for (int i = tid; i < 32 * TB; i += ET) {
+  // xb, vbuf and pbuf hold exact zeros outside the entries a step defines, so the
+  // loads below need no masks
+  for (int i = tid; i < 256; i += ET) {
+    xb[i] = 0.0;
     vbuf[i] = 0.0;
     pbuf[i] = 0.0;
   }
+  __syncthreads();
   for (int j = 0; j + 2 < k; ++j) {
     const int r0 = j + 1;
     const int a0 = r0 >> 4, b0 = r0 >> 5;  // first row / column tiles that meet the trailing block
-    // ---- A
-    put_column<TA>(A, j, k, tr, tc, xb);
+    // ---- A: x' (column j below row r0) into xb, column r0 into cb
+    put_lower<TA>(A, j, k, tr, tc, xb, s_red + 2, s_red + 3);
     put_column<TA>(A, r0, k, tr, tc, cb);
     __syncthreads();
-    // ---- B: partial sums of y = A x', x'_i = xb[i] for r0 < i < k
+    // ---- B: partial sums of y = A x', and the reflector on wave 0
     {
       double xr[TA], xc[TB];
 #pragma unroll
-      for (int a = 0; a < TA; ++a) {
-        const int i = 16 * a + tr;
-        const double x = xb[i];
-        xr[a] = (i > r0 && i < k) ? x : 0.0;
-      }
+      for (int a = 0; a < TA; ++a) xr[a] = xb[16 * a + tr];
 #pragma unroll
-      for (int b = 0; b < TB; ++b) {
-        const int l = 32 * b + tc;
-        const double x = xb[l];
-        xc[b] = (l > r0 && l < k) ? x : 0.0;
-      }
+      for (int b = 0; b < TB; ++b) xc[b] = xb[32 * b + tc];
       double colacc[TB];
 #pragma unroll
       for (int b = 0; b < TB; ++b) colacc[b] = 0.0;
@@ -469,17 +495,13 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k,
         if (b >= b0) colpart[tr * CP + 32 * b + tc] = colacc[b];
       if (wave == 0) {
         double sq = 0.0;
-        double xv[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          const int i = r0 + 1 + lane + 64 * m;
-          const double x = xb[i < 256 ? i : 255];
-          xv[m] = (i < k) ? x : 0.0;
+          const double x = xb[lane + 64 * m];
+          sq = fma(x, x, sq);
         }
-        const double alpha = xb[r0], dj = xb[j];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) sq = fma(xv[m], xv[m], sq);
         const double xn2 = dpp_wave_sum(sq);
+        const double alpha = s_red[3], dj = s_red[2];
         double beta, tj, scale;
         if (xn2 == 0.0) {
           beta = alpha;
@@ -502,31 +524,31 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k,
     __syncthreads();
     const double tj = s_red[0], scale = s_red[1];
     if (tj == 0.0) continue;  // the column is already reduced (uniform)
-    // ---- C: p_i = tau (s y_i + A[i][r0]) and v_i for i >= 32 b0; two threads per entry
+    // ---- C: v and p = tau (s y + A[:, r0]) for every index; two threads per entry
     {
-      const int i = 32 * b0 + (tid >> 1), h = tid & 1;
-      const int ic = i < k ? i : k - 1;
+      const int i = tid >> 1, h = tid & 1;
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
       for (int m = 0; m < 16; m += 4) {
-        s0 += rowpart[(h + 2 * m) * RP + ic];
-        s1 += rowpart[(h + 2 * m + 2) * RP + ic];
-        s2 += rowpart[(h + 2 * m + 4) * RP + ic];
-        s3 += rowpart[(h + 2 * m + 6) * RP + ic];
+        s0 += rowpart[(h + 2 * m) * RP + i];
+        s1 += rowpart[(h + 2 * m + 2) * RP + i];
+        s2 += rowpart[(h + 2 * m + 4) * RP + i];
+        s3 += rowpart[(h + 2 * m + 6) * RP + i];
       }
 #pragma unroll
       for (int m = 0; m < 8; m += 2) {
-        s0 += colpart[(h + 2 * m) * CP + ic];
-        s1 += colpart[(h + 2 * m + 2) * CP + ic];
+        s0 += colpart[(h + 2 * m) * CP + i];
+        s1 += colpart[(h + 2 * m + 2) * CP + i];
       }
-      const double x = xb[ic], c = cb[ic];
+      const double x = xb[i], c = cb[i];
       double y = (s0 + s1) + (s2 + s3);
       y += dpp_mov<0xB1, 0xf>(y);  // quad_perm [1,0,3,2]: the pair's sum
-      if (h == 0 && i < k) {
-        const double v = (i == r0) ? 1.0 : (i > r0 ? x * scale : 0.0);
+      if (h == 0 && i < 32 * TB) {
+        const bool live = i >= r0 && i < k;
+        const double v = (i == r0) ? 1.0 : x * scale;
         vbuf[i] = v;
-        pbuf[i] = (i < r0) ? 0.0 : tj * fma(scale, y, c);
-        if (i >= r0) hv[(int64_t)j * k + i] = v;
+        pbuf[i] = live ? tj * fma(scale, y, c) : 0.0;
+        if (live) hv[(int64_t)j * k + i] = v;
       }
     }
     __syncthreads();
@@ -545,10 +567,8 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k,
       }
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        const int i = r0 + lane + 64 * m;
-        const int ii = i < 32 * TB ? i : 0;
-        dv[m] = vbuf[ii];
-        dp[m] = (i < 32 * TB) ? pbuf[ii] : 0.0;
+        dv[m] = vbuf[lane + 64 * m];
+        dp[m] = pbuf[lane + 64 * m];
       }
       double dl = 0.0;
 #pragma unroll
