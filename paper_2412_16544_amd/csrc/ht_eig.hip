@@ -385,31 +385,11 @@ __host__ __device__ constexpr int tile_base(int a) {
   return s;
 }
 
-// the owners of column c copy its entries of rows >= c into buf
+// The owners of column c (lanes with tc == c % 32, in column tile c / 32) copy the
+// column's stored rows into buf.  Rows below c come out of stale tiles and are
+// never read; rows >= k are zero.  Straight-line stores, no per-row branches.
 template <int TA>
-__device__ __forceinline__ void put_column(const double (&A)[tile_base(TA)], int c, int k, int tr, int tc,
-                                           double* buf) {
-  if (tc != (c & 31)) return;
-  const int bc = c >> 5;
-#pragma unroll
-  for (int a = 0; a < TA; ++a) {
-#pragma unroll
-    for (int b = 0; b <= a / 2; ++b) {
-      if (b == bc) {
-        const int i = 16 * a + tr;
-        if (i >= c && i < k) buf[i] = A[tile_base(a) + b];
-      }
-    }
-  }
-}
-
-// The owners of column c publish the part below the diagonal that the next
-// reflector annihilates: rows c + 2 .. k - 1 go to buf (rows c and c + 1 of buf are
-// set to zero, rows above stay zero from earlier steps), the diagonal entry to
-// *dg and the subdiagonal one to *sd.
-template <int TA>
-__device__ __forceinline__ void put_lower(const double (&A)[tile_base(TA)], int c, int k, int tr, int tc,
-                                          double* buf, double* dg, double* sd) {
+__device__ __forceinline__ void put_column(const double (&A)[tile_base(TA)], int c, int tr, int tc, double* buf) {
   if (tc != (c & 31)) return;
   const int bc = c >> 5;
 #pragma unroll
@@ -417,18 +397,39 @@ __device__ __forceinline__ void put_lower(const double (&A)[tile_base(TA)], int 
     if (b == bc) {
 #pragma unroll
       for (int a = 2 * b; a < TA; ++a) {
-        const int i = 16 * a + tr;
-        const double val = A[tile_base(a) + b];
-        if (i == c) {
-          *dg = val;
-          buf[i] = 0.0;
-        } else if (i == c + 1) {
-          *sd = val;
-          buf[i] = 0.0;
-        } else if (i > c + 1 && i < k) {
-          buf[i] = val;
-        }
+        double val = A[tile_base(a) + b];
+        asm volatile("" : "+v"(val));  // keeps the case blocks apart, so A stays in registers
+        buf[16 * a + tr] = val;
       }
+    }
+  }
+}
+
+// The owners of column c publish the part below the diagonal that the next
+// reflector annihilates: rows c + 2 .. of buf get the column, rows 32 (c / 32) ..
+// c + 1 get zero (rows above were zeroed by earlier steps, rows >= k hold zeros of
+// A), the diagonal entry goes to *dg and the subdiagonal one to *sd.
+template <int TA>
+__device__ __forceinline__ void put_lower(const double (&A)[tile_base(TA)], int c, int tr, int tc, double* buf,
+                                          double* dg, double* sd) {
+  if (tc != (c & 31)) return;
+  const int bc = c >> 5;
+#pragma unroll
+  for (int b = 0; b < (TA + 1) / 2; ++b) {
+    if (b == bc) {
+      double dgv = 0.0, sdv = 0.0;
+#pragma unroll
+      for (int a = 2 * b; a < TA; ++a) {
+        const int i = 16 * a + tr;
+        double val = A[tile_base(a) + b];
+        asm volatile("" : "+v"(val));
+        buf[i] = i > c + 1 ? val : 0.0;
+        dgv = i == c ? val : dgv;
+        sdv = i == c + 1 ? val : sdv;
+      }
+      // row c sits in this lane's tile c / 16 >= 2 b, row c + 1 in tile (c + 1) / 16
+      if (tr == (c & 15)) *dg = dgv;
+      if (tr == ((c + 1) & 15)) *sd = sdv;
     }
   }
 }
@@ -463,8 +464,8 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k,
     const int r0 = j + 1;
     const int a0 = r0 >> 4, b0 = r0 >> 5;  // first row / column tiles that meet the trailing block
     // ---- A: x' (column j below row r0) into xb, column r0 into cb
-    put_lower<TA>(A, j, k, tr, tc, xb, s_red + 2, s_red + 3);
-    put_column<TA>(A, r0, k, tr, tc, cb);
+    put_lower<TA>(A, j, tr, tc, xb, s_red + 2, s_red + 3);
+    put_column<TA>(A, r0, tr, tc, cb);
     __syncthreads();
     // ---- B: partial sums of y = A x', and the reflector on wave 0
     {
@@ -482,10 +483,8 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k,
           double racc = 0.0;
 #pragma unroll
           for (int b = 0; b <= a / 2; ++b) {
-            if (b >= b0) {
-              racc = fma(A[tile_base(a) + b], xc[b], racc);
-              if (b < a / 2) colacc[b] = fma(A[tile_base(a) + b], xr[a], colacc[b]);
-            }
+            racc = fma(A[tile_base(a) + b], xc[b], racc);
+            if (b < a / 2) colacc[b] = fma(A[tile_base(a) + b], xr[a], colacc[b]);
           }
           rowpart[tc * RP + 16 * a + tr] = racc;
         }
@@ -579,16 +578,15 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k,
         if (a >= a0) {
           const double wr = fma(kk, vr[a], pr[a]);
 #pragma unroll
-          for (int b = 0; b <= a / 2; ++b)
-            if (b >= b0) A[tile_base(a) + b] -= fma(vr[a], fma(kk, vc[b], pc[b]), wr * vc[b]);
+          for (int b = 0; b <= a / 2; ++b) A[tile_base(a) + b] -= fma(vr[a], fma(kk, vc[b], pc[b]), wr * vc[b]);
         }
       }
     }
   }
   // the trailing 2 x 2 (or 1 x 1) block
   __syncthreads();
-  if (k >= 2) put_column<TA>(A, k - 2, k, tr, tc, xb);
-  put_column<TA>(A, k - 1, k, tr, tc, cb);
+  if (k >= 2) put_column<TA>(A, k - 2, tr, tc, xb);
+  put_column<TA>(A, k - 1, tr, tc, cb);
   __syncthreads();
   if (tid == 0) {
     if (k >= 2) {

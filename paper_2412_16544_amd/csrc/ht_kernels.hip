@@ -308,10 +308,13 @@ __global__ __launch_bounds__(256) void gram_small_kernel(const T* __restrict__ X
     part[(int64_t)blockIdx.x * (kSmallM * (kSmallM + 1) / 2) + q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
 }
 
-__global__ __launch_bounds__(64) void gram_small_reduce_kernel(const double* __restrict__ part, int m, int nblk,
-                                                               double* __restrict__ G) {
-  const int e = threadIdx.x;
-  if (e >= m * m) return;
+// One workgroup per entry of the small Gram: 256 threads sum the block partials in
+// a fixed order (strided, then a fixed tree), so the result does not depend on
+// timing.
+__global__ __launch_bounds__(256) void gram_small_reduce_kernel(const double* __restrict__ part, int m, int nblk,
+                                                                double* __restrict__ G) {
+  __shared__ double red[4];
+  const int e = blockIdx.x;
   int a = e / m, b = e % m;
   if (b > a) {
     const int t = a;
@@ -320,8 +323,11 @@ __global__ __launch_bounds__(64) void gram_small_reduce_kernel(const double* __r
   }
   const int q = a * (a + 1) / 2 + b;
   double acc = 0.0;
-  for (int i = 0; i < nblk; ++i) acc += part[(int64_t)i * (kSmallM * (kSmallM + 1) / 2) + q];
-  G[e] = acc;
+  for (int i = threadIdx.x; i < nblk; i += 256) acc += part[(int64_t)i * (kSmallM * (kSmallM + 1) / 2) + q];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) G[e] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // --------------------------------------------------------------------------
@@ -877,18 +883,18 @@ __device__ double block_sum256(double v, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ __launch_bounds__(256) void orth_expand_kernel(const double* __restrict__ Uold, int64_t alpha, int r_old,
-                                                          double* __restrict__ V, int rR, double* __restrict__ core,
-                                                          double* __restrict__ scratch) {
-  __shared__ double red[4];
-  __shared__ double Cs[64 * 64];
+// U (alpha x r_old) and V (alpha x rR), column-major with leading dimension alpha,
+// live in LDS or in global memory (a compile-time choice through the inlined
+// pointers); Cs is rR x max(r_old, rR) of LDS.
+__device__ __forceinline__ void orth_body(const double* U, int64_t alpha, int r_old, double* V, int rR, double* Cs,
+                                          double* core, const double* Uold_g) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // ---- two passes of classical Gram-Schmidt against the old basis
   for (int pass = 0; pass < 2 && r_old > 0; ++pass) {
     for (int e = wave; e < r_old * rR; e += 4) {
       const int i = e / rR, j = e - (e / rR) * rR;
       double acc = 0.0;
-      for (int64_t a = lane; a < alpha; a += 64) acc = fma(Uold[a + (int64_t)i * alpha], V[a + (int64_t)j * alpha], acc);
+      for (int64_t a = lane; a < alpha; a += 64) acc = fma(U[a + (int64_t)i * alpha], V[a + (int64_t)j * alpha], acc);
       acc = wave_sum(acc);
       if (lane == 0) Cs[i * rR + j] = acc;
     }
@@ -897,7 +903,7 @@ __global__ __launch_bounds__(256) void orth_expand_kernel(const double* __restri
       const int64_t a = e % alpha;
       const int j = (int)(e / alpha);
       double acc = V[a + (int64_t)j * alpha];
-      for (int i = 0; i < r_old; ++i) acc = fma(-Uold[a + (int64_t)i * alpha], Cs[i * rR + j], acc);
+      for (int i = 0; i < r_old; ++i) acc = fma(-U[a + (int64_t)i * alpha], Cs[i * rR + j], acc);
       V[a + (int64_t)j * alpha] = acc;
     }
     __syncthreads();
@@ -921,9 +927,9 @@ __global__ __launch_bounds__(256) void orth_expand_kernel(const double* __restri
         d = sqrt(d > 0.0 ? d : 1e-300);
         Cs[j * rR + j] = d;
         for (int i = j + 1; i < rR; ++i) {
-          double s = Cs[i * rR + j];
-          for (int k = 0; k < j; ++k) s -= Cs[i * rR + k] * Cs[j * rR + k];
-          Cs[i * rR + j] = s / d;
+          double sum = Cs[i * rR + j];
+          for (int k = 0; k < j; ++k) sum -= Cs[i * rR + k] * Cs[j * rR + k];
+          Cs[i * rR + j] = sum / d;
         }
       }
     }
@@ -931,9 +937,9 @@ __global__ __launch_bounds__(256) void orth_expand_kernel(const double* __restri
     // each row x of V solves x_new L^T = x  (forward substitution over columns)
     for (int64_t a = threadIdx.x; a < alpha; a += 256) {
       for (int j = 0; j < rR; ++j) {
-        double s = V[a + (int64_t)j * alpha];
-        for (int k = 0; k < j; ++k) s -= V[a + (int64_t)k * alpha] * Cs[j * rR + k];
-        V[a + (int64_t)j * alpha] = s / Cs[j * rR + j];
+        double sum = V[a + (int64_t)j * alpha];
+        for (int k = 0; k < j; ++k) sum -= V[a + (int64_t)k * alpha] * Cs[j * rR + k];
+        V[a + (int64_t)j * alpha] = sum / Cs[j * rR + j];
       }
     }
     __syncthreads();
@@ -960,8 +966,28 @@ __global__ __launch_bounds__(256) void orth_expand_kernel(const double* __restri
     const double sg = V[bidx + (int64_t)j * alpha] < 0.0 ? -1.0 : 1.0;
     for (int64_t a = lane; a < alpha; a += 64) core[a + (int64_t)(r_old + j) * alpha] = sg * V[a + (int64_t)j * alpha];
   }
-  if (core != Uold)
-    for (int64_t e = threadIdx.x; e < alpha * r_old; e += 256) core[e] = Uold[e];
+  if (core != Uold_g)
+    for (int64_t e = threadIdx.x; e < alpha * r_old; e += 256) core[e] = Uold_g[e];
+}
+
+constexpr int kOrthLdsDoubles = 12288;  // U_old and V staged in LDS up to this size (96 KiB)
+
+__global__ __launch_bounds__(256) void orth_expand_kernel(const double* __restrict__ Uold, int64_t alpha, int r_old,
+                                                          double* __restrict__ V, int rR, double* __restrict__ core,
+                                                          double* __restrict__ scratch) {
+  extern __shared__ double osm[];
+  double* Cs = osm;  // 64 x 64
+  const int64_t need = alpha * (int64_t)(r_old + rR);
+  if (need <= kOrthLdsDoubles) {
+    double* sU = osm + 64 * 64;
+    double* sV = sU + alpha * r_old;
+    for (int64_t e = threadIdx.x; e < alpha * r_old; e += 256) sU[e] = Uold[e];
+    for (int64_t e = threadIdx.x; e < alpha * rR; e += 256) sV[e] = V[e];
+    __syncthreads();
+    orth_body(sU, alpha, r_old, sV, rR, Cs, core, Uold);
+  } else {
+    orth_body(Uold, alpha, r_old, V, rR, Cs, core, Uold);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -1107,7 +1133,7 @@ void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hip
         gram_small_kernel<double><<<kSmallBlocks, 256, 0, s>>>(static_cast<const double*>(x), v.m, v.S, Ki, part);
     }
     ProfScope prof(KKind::Layout, s, 0.0, 0.0);
-    gram_small_reduce_kernel<<<1, 64, 0, s>>>(part, (int)v.m, kSmallBlocks, G);
+    gram_small_reduce_kernel<<<(unsigned)(v.m * v.m), 256, 0, s>>>(part, (int)v.m, kSmallBlocks, G);
     return;
   }
   const GramPlan g = gram_plan(v);
@@ -1273,8 +1299,16 @@ size_t orth_scratch_doubles(int rR) { return (size_t)64 * 64 + (size_t)rR; }
 void orth_expand(const double* U_old, int64_t alpha, int r_old, double* V, int rR, double* core, double* scratch,
                  hipStream_t s) {
   if (rR <= 0) return;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&orth_expand_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (64 * 64 + kOrthLdsDoubles) * 8);
+    attr = true;
+  }
+  const int64_t need = alpha * (int64_t)(r_old + rR);
+  const size_t lds = (size_t)(64 * 64 + (need <= kOrthLdsDoubles ? need : 0)) * sizeof(double);
   ProfScope prof(KKind::Orth, s, 0.0, 0.0);
-  orth_expand_kernel<<<1, 256, 0, s>>>(U_old, alpha, r_old, V, rR, core, scratch);
+  orth_expand_kernel<<<1, 256, lds, s>>>(U_old, alpha, r_old, V, rR, core, scratch);
 }
 
 void pad_core(const double* src, int ra, int rb, int rp, double* dst, int ra2, int rb2, hipStream_t s) {

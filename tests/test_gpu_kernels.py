@@ -191,7 +191,7 @@ def test_eig_degenerate_cluster_spans_the_eigenspace():
     assert np.linalg.norm(P - Pref) < 1e-10
 
 
-@pytest.mark.parametrize("alpha,r_old,rR", [(96, 12, 3), (16, 0, 4), (200, 40, 8), (9, 4, 5)])
+@pytest.mark.parametrize("alpha,r_old,rR", [(96, 12, 3), (16, 0, 4), (200, 40, 8), (9, 4, 5), (400, 30, 8)])
 def test_orth_expand(alpha, r_old, rR):
     g = rng(alpha + r_old)
     U = np.linalg.qr(g.standard_normal((alpha, r_old)))[0] if r_old else None
