@@ -32,6 +32,16 @@ constexpr int NW = ET / 64;
 constexpr int kLdsDoubles = 19968;  // 156 KiB of dynamic LDS per workgroup
 constexpr int kSmallMax = 1024;     // the 6k work vectors live in LDS up to this k
 
+// global-memory view of a pointer (stores through it wait on the vector counter only)
+typedef __attribute__((address_space(1))) double gdouble;
+
+// a value that every lane holds alike, moved to scalar registers
+__device__ __forceinline__ double uniform(double x) {
+  const uint64_t b = __double_as_longlong(x);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b), hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 struct EigBatch {
   EigJob j[kMaxEigJobs];
 };
@@ -443,6 +453,10 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k,
   constexpr int RP = 16 * TA + 1;  // row strides of the partials (odd: spreads the LDS banks)
   constexpr int CP = 32 * TB + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, tr = tid >> 5, tc = tid & 31;
+  // the size and the reflector store are the same for every lane: keep them scalar,
+  // so the step loop runs on scalar branches
+  k = __builtin_amdgcn_readfirstlane(k);
+  gdouble* hvg = reinterpret_cast<gdouble*>(reinterpret_cast<uintptr_t>(hv));
   double A[NT];
 #pragma unroll
   for (int a = 0; a < TA; ++a) {
@@ -521,8 +535,8 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k,
       }
     }
     __syncthreads();
-    const double tj = s_red[0], scale = s_red[1];
-    if (tj == 0.0) continue;  // the column is already reduced (uniform)
+    const double tj = uniform(s_red[0]), scale = s_red[1];
+    if (tj == 0.0) continue;  // the column is already reduced
     // ---- C: v and p = tau (s y + A[:, r0]) for every index; two threads per entry
     {
       const int i = tid >> 1, h = tid & 1;
@@ -547,7 +561,7 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k,
         const double v = (i == r0) ? 1.0 : x * scale;
         vbuf[i] = v;
         pbuf[i] = live ? tj * fma(scale, y, c) : 0.0;
-        if (live) hv[(int64_t)j * k + i] = v;
+        if (live) hvg[(int64_t)j * k + i] = v;
       }
     }
     __syncthreads();
@@ -573,12 +587,16 @@ __device__ __forceinline__ void tridiag_reg(const double* __restrict__ G, int k,
 #pragma unroll
       for (int m = 0; m < 4; ++m) dl = fma(dp[m], dv[m], dl);
       const double kk = -0.5 * tj * dpp_wave_sum(dl);
+      double wc[TB];
+#pragma unroll
+      for (int b = 0; b < TB; ++b) wc[b] = fma(kk, vc[b], pc[b]);
 #pragma unroll
       for (int a = 0; a < TA; ++a) {
         if (a >= a0) {
           const double wr = fma(kk, vr[a], pr[a]);
 #pragma unroll
-          for (int b = 0; b <= a / 2; ++b) A[tile_base(a) + b] -= fma(vr[a], fma(kk, vc[b], pc[b]), wr * vc[b]);
+          for (int b = 0; b <= a / 2; ++b)
+            A[tile_base(a) + b] = fma(-wr, vc[b], fma(-vr[a], wc[b], A[tile_base(a) + b]));
         }
       }
     }
