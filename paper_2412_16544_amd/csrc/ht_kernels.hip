@@ -735,6 +735,127 @@ __global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X,
   }
 }
 
+// --------------------------------------------------------------------------
+// FP32 contraction Z = U^T X for a mode with m <= 16 TI rows whose column runs
+// have a length divisible by 32 (S % 32 == 0), operands straight from registers.
+// A wave takes blocks of 32 unfolding columns (one p, consecutive s): lane l loads
+// columns 2 (l % 16) and 2 (l % 16) + 1 of rows 4 t + l / 16 as one float2, the B
+// operands of two 16-column halves (the even and the odd columns).  U^T (RT row
+// tiles of 16) sits in LDS.  With RESE the residual X - U Z is formed in registers
+// as well: register v of the Z accumulators is a valid B operand for the step
+// whose k index l / 16 stands for row 16 rt + 4 (l / 16) + v of Z, and reading
+// the rows of U in the order pi(q) = 4 (q % 4) + q / 4 makes row q of the product
+// the row that the lane holds in its X registers.  Many waves per SIMD and a
+// whole block of loads per wave keep the HBM pipe full without LDS staging.
+// --------------------------------------------------------------------------
+template <int TI, int RT, bool NORM, bool RESE>
+__global__ __launch_bounds__(256) void ttm_reg_kernel(const float* __restrict__ X, int64_t P, int m, int64_t S,
+                                                      const double* __restrict__ U, int R, float* __restrict__ Z,
+                                                      double* __restrict__ norm_part, double* __restrict__ res_part) {
+  constexpr int NT = 4 * TI;
+  constexpr int ULD = 16 * RT + 1;
+  extern __shared__ float sUr[];  // sUr[a * ULD + r]: U in FP32, zero outside m x R
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g4 = lane >> 4, c16 = lane & 15;
+  for (int e = threadIdx.x; e < 16 * TI * ULD; e += 256) {
+    const int a = e / ULD, r = e - (e / ULD) * ULD;
+    sUr[e] = (a < m && r < R) ? static_cast<float>(U[a + (int64_t)r * m]) : 0.f;
+  }
+  __syncthreads();
+  // byte offsets inside one p slab (m S < 2^29 and P S < 2^31 are checked by the
+  // launcher); with m % 4 == 0 the rows of step t are all valid or all padding
+  const int lane_off = (2 * c16 + g4 * (int)S) * 4;
+  const int step = 16 * (int)S;
+  const int S32 = (int)S;
+  const int nblk = (int)(P * S / 32);
+  const int pr = 4 * (c16 & 3) + (c16 >> 2);  // permuted row of U read by this lane
+  double nrm = 0.0, res = 0.0;
+  for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
+    asm volatile("" ::: "memory");  // U^T is re-read from LDS per block, not held in registers
+    const int c0 = blk * 32;
+    const int p = c0 / S32, s0 = c0 - p * S32;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(X) + (int64_t)p * m * S + s0, (short)0, (m * S32 - s0) * 4, 0x00020000);
+    float2 x[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (4 * t < m) {
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, t * step, 0);
+        x[t] = make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+      } else {
+        x[t] = make_float2(0.f, 0.f);
+      }
+    }
+    if (NORM) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        nrm = fma((double)x[t].x, (double)x[t].x, nrm);
+        nrm = fma((double)x[t].y, (double)x[t].y, nrm);
+      }
+    }
+    f4 ze[RT], zo[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      f4 e0 = f4{0, 0, 0, 0}, e1 = e0, o0 = e0, o1 = e0;
+#pragma unroll
+      for (int t = 0; t < NT; t += 2) {
+        const float a0 = sUr[(4 * t + g4) * ULD + 16 * rt + c16];
+        const float a1 = sUr[(4 * t + 4 + g4) * ULD + 16 * rt + c16];
+        e0 = mfma16(a0, x[t].x, e0);
+        o0 = mfma16(a0, x[t].y, o0);
+        e1 = mfma16(a1, x[t + 1].x, e1);
+        o1 = mfma16(a1, x[t + 1].y, o1);
+      }
+      ze[rt] = e0 + e1;
+      zo[rt] = o0 + o1;
+      // register v: row 16 rt + 4 (l / 16) + v of Z, columns c0 + 2 (l % 16) + {0, 1}
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * rt + 4 * g4 + v;
+        if (r < R) *reinterpret_cast<float2*>(Z + (p * R + r) * S + s0 + 2 * c16) = make_float2(ze[rt][v], zo[rt][v]);
+      }
+    }
+    if (RESE) {
+#pragma unroll
+      for (int it = 0; it < TI; ++it) {
+        f4 ye = f4{0, 0, 0, 0}, yo = ye;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float a = sUr[(16 * it + pr) * ULD + 16 * rt + 4 * g4 + v];
+            ye = mfma16(a, ze[rt][v], ye);
+            yo = mfma16(a, zo[rt][v], yo);
+          }
+        }
+        // register v of the product: row 16 it + 4 v + l / 16 = the row of x[4 it + v]
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double de = (double)x[4 * it + v].x - (double)ye[v];
+          const double dd = (double)x[4 * it + v].y - (double)yo[v];
+          res = fma(de, de, res);
+          res = fma(dd, dd, res);
+        }
+      }
+    }
+  }
+  if (NORM || RESE) {
+    __shared__ double red[8];
+    if (NORM) nrm = wave_sum(nrm);
+    if (RESE) res = wave_sum(res);
+    if (lane == 0) {
+      red[wave] = nrm;
+      red[4 + wave] = res;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (NORM) norm_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+      if (RESE) res_part[blockIdx.x] = (red[4] + red[5]) + (red[6] + red[7]);
+    }
+  }
+}
+
 constexpr int TUS = 65;  // LDS row stride (doubles) of the staged U chunk of the expansion
 
 // --------------------------------------------------------------------------
@@ -1250,6 +1371,42 @@ void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U
     ttm_direct_kernel<double><<<blocks, 256, 0, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U, R, chunk, Z);
 }
 
+// the register-direct FP32 contraction applies to FP32 level tensors whose column
+// runs split into whole blocks of 32 (S % 32 == 0), modes of at most 128 rows in
+// steps of four, and sizes with 32-bit offsets
+bool ttm_reg_applies(Elem t, const ModeView& v, int R) {
+  return t == Elem::F32 && v.S % 32 == 0 && v.m % 4 == 0 && v.m <= 128 && v.m * v.S < (int64_t(1) << 29) &&
+         v.P * v.S < (int64_t(1) << 31) && R >= 1 && R <= 64;
+}
+
+template <bool NN, bool RR>
+void launch_ttm_reg(const float* x, const ModeView& v, const double* U, int R, float* Z, double* norm_part,
+                    double* norm_out, double* res_part, double* res_out, double fl, double by, hipStream_t s) {
+  const int ti = ((int)((v.m + 15) / 16) + 1) & ~1;  // 2, 4, 6 or 8 row tiles
+  const int rt = (R + 15) / 16;
+  const int64_t nblk = v.P * v.S / 32;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kTtmMaxBlocks, (nblk + 3) / 4));
+  const size_t lds = (size_t)16 * ti * (16 * rt + 1) * sizeof(float);
+  {
+    ProfScope prof(KKind::TtmContract32, s, fl, by);
+#define HT_REG(TI, RTT)                                                                                          \
+  case TI * 8 + RTT:                                                                                             \
+    ttm_reg_kernel<TI, RTT, NN, RR><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part, res_part); \
+    break;
+    switch (ti * 8 + rt) {
+      HT_REG(2, 1) HT_REG(2, 2) HT_REG(2, 3) HT_REG(2, 4)
+      HT_REG(4, 1) HT_REG(4, 2) HT_REG(4, 3) HT_REG(4, 4)
+      HT_REG(6, 1) HT_REG(6, 2) HT_REG(6, 3) HT_REG(6, 4)
+      HT_REG(8, 1) HT_REG(8, 2) HT_REG(8, 3) HT_REG(8, 4)
+      default: break;
+    }
+#undef HT_REG
+  }
+  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+  if (NN) reduce_kernel<<<1, 256, 0, s>>>(norm_part, blocks, norm_out);
+  if (RR) reduce_kernel<<<1, 256, 0, s>>>(res_part, blocks, res_out);
+}
+
 void ttm_contract_f32(const void* x, Elem t, const ModeView& v, const double* U, int R, float* Z, double* norm_part,
                       double* norm_out, double* res_part, double* res_out, hipStream_t s) {
   const int64_t K = v.P * v.S;
@@ -1260,7 +1417,13 @@ void ttm_contract_f32(const void* x, Elem t, const ModeView& v, const double* U,
   launch_ttm_panel<TT, float, NN, RR>(x, v, U, R, Z, NN ? norm_part : nullptr, NN ? norm_out : nullptr,       \
                                       RR ? res_part : nullptr, RR ? res_out : nullptr, KKind::TtmContract32, fl, \
                                       by, s)
-  if (t == Elem::F32) {
+  if (ttm_reg_applies(t, v, R)) {
+    const float* xf = static_cast<const float*>(x);
+    if (nrm && rese) launch_ttm_reg<true, true>(xf, v, U, R, Z, norm_part, norm_out, res_part, res_out, fl, by, s);
+    else if (rese) launch_ttm_reg<false, true>(xf, v, U, R, Z, nullptr, nullptr, res_part, res_out, fl, by, s);
+    else if (nrm) launch_ttm_reg<true, false>(xf, v, U, R, Z, norm_part, norm_out, nullptr, nullptr, fl, by, s);
+    else launch_ttm_reg<false, false>(xf, v, U, R, Z, nullptr, nullptr, nullptr, nullptr, fl, by, s);
+  } else if (t == Elem::F32) {
     if (nrm && rese) HT_TTM32(float, true, true);
     else if (rese) HT_TTM32(float, false, true);
     else if (nrm) HT_TTM32(float, true, false);

@@ -74,7 +74,10 @@ def test_ttm_contract(P, m, S, R, dtype):
 F32_REL = 2e-6
 
 MIXED_SHAPES = [(3, 96, 1000, 12), (5, 9, 7, 3), (100, 16, 1, 5), (2, 128, 33, 64), (7, 17, 5, 1),
-                (4, 64, 300, 16), (50, 40, 2, 20), (1, 96, 31, 47)]
+                (4, 64, 300, 16), (50, 40, 2, 20), (1, 96, 31, 47),
+                # column runs in whole blocks of 32 with m % 4 == 0: the register-direct FP32 contraction
+                (3, 96, 1024, 12), (2, 128, 64, 64), (5, 40, 96, 20), (3, 4, 32, 1), (2, 96, 288, 47),
+                (64, 8, 16384, 3)]
 
 
 def near_subspace(P, m, S, R, seed, dtype=np.float32):
