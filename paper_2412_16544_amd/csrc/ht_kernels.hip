@@ -856,6 +856,153 @@ __global__ __launch_bounds__(256) void ttm_reg_kernel(const float* __restrict__ 
   }
 }
 
+// --------------------------------------------------------------------------
+// FP32 Gram G = M M^T of a mode unfolding (RESID: of the residual M - U U^T M)
+// for the same shapes as ttm_reg_kernel.  A wave loads a block of 32 columns the
+// same way, forms Z = U^T M and the residual in registers, and then feeds the
+// matrix cores through a wave-private LDS transpose, 16 columns at a time: the
+// Gram operands want the row index on l % 16, the loaded layout has the column
+// there.  Every wave accumulates all TI (TI + 1) / 2 upper 16 x 16 tiles; the four
+// waves of a workgroup add theirs in wave order and the workgroup writes one
+// FP64 partial (upper tiles of an m x m array), summed over the workgroups in a
+// fixed order afterwards.
+// --------------------------------------------------------------------------
+constexpr int kGramRegLd = 17;  // row stride (floats) of a wave's 16-column transpose buffer
+
+template <int TI, int RT, bool RESID>
+__global__ __launch_bounds__(256) void gram_reg_kernel(const float* __restrict__ X, int64_t P, int m, int64_t S,
+                                                       const double* __restrict__ U, int R,
+                                                       double* __restrict__ part) {
+  constexpr int NT = 4 * TI;
+  constexpr int ULD = 16 * RT + 1;
+  constexpr int NTILE = TI * (TI + 1) / 2;
+  constexpr int WREG = 16 * TI * kGramRegLd;  // floats of one wave's transpose buffer
+  extern __shared__ float sgr[];
+  float* sUr = sgr;                                    // U (RESID), 16 TI x ULD
+  float* sT = sgr + (RESID ? 16 * TI * ULD : 0);       // 4 transpose buffers, later the tile sums
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g4 = lane >> 4, c16 = lane & 15;
+  if (RESID) {
+    for (int e = threadIdx.x; e < 16 * TI * ULD; e += 256) {
+      const int a = e / ULD, r = e - (e / ULD) * ULD;
+      sUr[e] = (a < m && r < R) ? static_cast<float>(U[a + (int64_t)r * m]) : 0.f;
+    }
+    __syncthreads();
+  }
+  float* myT = sT + wave * WREG;
+  const int lane_off = (2 * c16 + g4 * (int)S) * 4;
+  const int step = 16 * (int)S;
+  const int S32 = (int)S;
+  const int nblk = (int)(P * S / 32);
+  const int pr = 4 * (c16 & 3) + (c16 >> 2);
+  f4 acc[NTILE];
+#pragma unroll
+  for (int q = 0; q < NTILE; ++q) acc[q] = f4{0, 0, 0, 0};
+  for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
+    asm volatile("" ::: "memory");
+    const int c0 = blk * 32;
+    const int p = c0 / S32, s0 = c0 - p * S32;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(X) + (int64_t)p * m * S + s0, (short)0, (m * S32 - s0) * 4, 0x00020000);
+    float2 x[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (4 * t < m) {
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, t * step, 0);
+        x[t] = make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+      } else {
+        x[t] = make_float2(0.f, 0.f);
+      }
+    }
+    if (RESID) {
+      f4 ze[RT], zo[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        f4 e0 = f4{0, 0, 0, 0}, e1 = e0, o0 = e0, o1 = e0;
+#pragma unroll
+        for (int t = 0; t < NT; t += 2) {
+          const float a0 = sUr[(4 * t + g4) * ULD + 16 * rt + c16];
+          const float a1 = sUr[(4 * t + 4 + g4) * ULD + 16 * rt + c16];
+          e0 = mfma16(a0, x[t].x, e0);
+          o0 = mfma16(a0, x[t].y, o0);
+          e1 = mfma16(a1, x[t + 1].x, e1);
+          o1 = mfma16(a1, x[t + 1].y, o1);
+        }
+        ze[rt] = e0 + e1;
+        zo[rt] = o0 + o1;
+      }
+#pragma unroll
+      for (int it = 0; it < TI; ++it) {
+        f4 ye = f4{0, 0, 0, 0}, yo = ye;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float a = sUr[(16 * it + pr) * ULD + 16 * rt + 4 * g4 + v];
+            ye = mfma16(a, ze[rt][v], ye);
+            yo = mfma16(a, zo[rt][v], yo);
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          x[4 * it + v].x -= ye[v];
+          x[4 * it + v].y -= yo[v];
+        }
+      }
+    }
+    // Gram of the block, one 16-column half (even, then odd columns) at a time
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) myT[(4 * t + g4) * kGramRegLd + c16] = h ? x[t].y : x[t].x;
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) {
+        float op[TI];
+#pragma unroll
+        for (int i = 0; i < TI; ++i) op[i] = myT[(16 * i + c16) * kGramRegLd + 4 * k4 + g4];
+        int q = 0;
+#pragma unroll
+        for (int i = 0; i < TI; ++i) {
+#pragma unroll
+          for (int j = i; j < TI; ++j) {
+            acc[q] = mfma16(op[i], op[j], acc[q]);
+            ++q;
+          }
+        }
+      }
+    }
+  }
+  // the workgroup's sum in wave order, then one FP64 partial: tile (i, j), register
+  // v of lane l is G[16 i + 4 (l / 16) + v][16 j + l % 16]
+  __syncthreads();
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int q = 0; q < NTILE; ++q) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float* d = sT + (q * 256 + v * 64 + lane);
+          *d = (w == 0) ? acc[q][v] : *d + acc[q][v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.x * m * m;
+  for (int e = threadIdx.x; e < NTILE * 256; e += 256) {
+    const int q = e >> 8, v = (e >> 6) & 3, l = e & 63;
+    int i = 0, qq = q;
+    while (qq >= TI - i) {
+      qq -= TI - i;
+      ++i;
+    }
+    const int j = i + qq;
+    const int row = 16 * i + 4 * (l >> 4) + v, col = 16 * j + (l & 15);
+    if (row < m && col < m) out[row * m + col] = static_cast<double>(sT[e]);
+  }
+}
+
 constexpr int TUS = 65;  // LDS row stride (doubles) of the staged U chunk of the expansion
 
 // --------------------------------------------------------------------------
@@ -1242,6 +1389,57 @@ size_t gram_partial_doubles(const ModeView& v) {
   return (size_t)g.nsplit * g.npairs * g.blk;
 }
 
+bool gram_reg_applies(Elem t, const ModeView& v, int R) {
+  return t == Elem::F32 && v.S % 32 == 0 && v.m % 4 == 0 && v.m <= 128 && v.m * v.S < (int64_t(1) << 29) &&
+         v.P * v.S < (int64_t(1) << 31) && R >= 1 && R <= 64;
+}
+
+// residual Gram through gram_reg_kernel; at most 512 workgroup partials, the
+// bound the partial buffer is sized for
+void gram_reg(const float* x, const ModeView& v, const double* U, int R, double* part, double* G, hipStream_t s) {
+  const int ti = ((int)((v.m + 15) / 16) + 1) & ~1;
+  const int rt = R > 0 ? (R + 15) / 16 : 1;
+  const int64_t nblk = v.P * v.S / 32;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(512, (nblk + 3) / 4));
+  const size_t lds =
+      ((R > 0 ? (size_t)16 * ti * (16 * rt + 1) : 0) +
+       std::max<size_t>((size_t)4 * 16 * ti * kGramRegLd, (size_t)(ti * (ti + 1) / 2) * 256)) * sizeof(float);
+  static bool attr = false;
+  if (!attr) {
+#define HT_GA(TI, RTT, RS)                                                                   \
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_reg_kernel<TI, RTT, RS>), \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    HT_GA(2, 1, true) HT_GA(2, 2, true) HT_GA(2, 3, true) HT_GA(2, 4, true)
+    HT_GA(4, 1, true) HT_GA(4, 2, true) HT_GA(4, 3, true) HT_GA(4, 4, true)
+    HT_GA(6, 1, true) HT_GA(6, 2, true) HT_GA(6, 3, true) HT_GA(6, 4, true)
+    HT_GA(8, 1, true) HT_GA(8, 2, true) HT_GA(8, 3, true) HT_GA(8, 4, true)
+#undef HT_GA
+    attr = true;
+  }
+  const double K = (double)v.P * v.S, md = (double)v.m;
+  {
+    ProfScope prof(KKind::Gram32, s, md * md * K + (R > 0 ? 4.0 * R * md * K : 0.0), md * K * 4);
+#define HT_GR(TI, RTT, RS)                                                                                 \
+  case TI * 16 + RTT * 2 + (RS ? 1 : 0):                                                                   \
+    gram_reg_kernel<TI, RTT, RS><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, part);              \
+    break;
+    switch (ti * 16 + rt * 2 + (R > 0 ? 1 : 0)) {
+      HT_GR(2, 1, true) HT_GR(2, 2, true) HT_GR(2, 3, true) HT_GR(2, 4, true)
+      HT_GR(4, 1, true) HT_GR(4, 2, true) HT_GR(4, 3, true) HT_GR(4, 4, true)
+      HT_GR(6, 1, true) HT_GR(6, 2, true) HT_GR(6, 3, true) HT_GR(6, 4, true)
+      HT_GR(8, 1, true) HT_GR(8, 2, true) HT_GR(8, 3, true) HT_GR(8, 4, true)
+      default: break;
+    }
+#undef HT_GR
+  }
+  GramPlan g;
+  g.nb = 1;
+  g.npairs = 1;
+  g.nsplit = blocks;
+  g.blk = v.m * v.m;
+  gram_finish(g, v, part, G, s);
+}
+
 void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hipStream_t s) {
   const double K = (double)v.P * v.S, md = (double)v.m;
   if (v.m <= kSmallM) {
@@ -1288,6 +1486,10 @@ void resid_gram(const void* x, Elem t, const ModeView& v, const double* U, int R
 
 void resid_gram_f32(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,
                     hipStream_t s) {
+  if (gram_reg_applies(t, v, R)) {
+    gram_reg(static_cast<const float*>(x), v, U, R, part, G, s);
+    return;
+  }
   const GramPlan g = gram_plan(v);
   const double K = (double)v.P * v.S, md = (double)v.m;
   {
