@@ -1007,11 +1007,13 @@ constexpr int TUS = 65;  // LDS row stride (doubles) of the staged U chunk of th
 
 // --------------------------------------------------------------------------
 // TTM contraction for modes with more than 128 rows (transfer nodes, large
-// leaves): Z[p, r, s] = sum_a U[a, r] X[p, a, s] on FP64 matrix cores.  One wave
-// per 16 unfolding columns and every output row (R <= 64); U^T is staged in LDS
-// in chunks of rows of a shared by the block's four waves, and each wave keeps
-// the X operands of its next eight steps in flight, so small column counts still
-// spread over many waves and the loop is not bound by one load latency per step.
+// leaves): Z[p, r, s] = sum_a U[a, r] X[p, a, s] on FP64 matrix cores.  A
+// workgroup owns 16 unfolding columns and every output row (R <= 64); its four
+// waves split the row steps of a (step q of a chunk goes to wave q % 4), so small
+// column counts (the level tensors of transfer nodes) still spread over many
+// waves.  U^T is staged in LDS in chunks of rows of a; each wave keeps the X
+// operands of its next eight steps in flight.  The four partial products are
+// added in wave order through LDS.
 // --------------------------------------------------------------------------
 constexpr int kDirectLdsDoubles = 8192;  // U chunk: chunk x (RP + 1) doubles
 
@@ -1019,11 +1021,11 @@ template <typename T>
 __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
                                                          const double* __restrict__ U, int R, int chunk,
                                                          double* __restrict__ Z) {
-  __shared__ double sU[kDirectLdsDoubles];  // sU[a][r]
+  __shared__ double sU[kDirectLdsDoubles];  // sU[a][r], then the wave partials
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int RP = (R + 15) & ~15, ULD = RP + 1, rt = RP >> 4;
   const int64_t K = P * S;
-  const int64_t c = ((int64_t)blockIdx.x * 4 + wave) * 16 + (lane & 15);
+  const int64_t c = (int64_t)blockIdx.x * 16 + (lane & 15);
   const bool cv = c < K;
   const int64_t base = cv ? col_base(c, m, S) : 0;
   const int kr = lane >> 4;  // row of the 4-row step this lane feeds
@@ -1044,17 +1046,18 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
     double b[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int a = 4 * q + kr;
+      const int a = 4 * (wave + 4 * q) + kr;
       b[q] = (cv && a < ac) ? static_cast<double>(xp[(int64_t)a * S]) : 0.0;
     }
-    for (int st = 0; st < nst; st += 8) {
+    for (int j = 0; wave + 4 * j < nst; j += 8) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        if (st + q < nst) {
+        const int st = wave + 4 * (j + q);
+        if (st < nst) {
           const double bv = b[q];
-          const int an = 4 * (st + q + 8) + kr;
+          const int an = 4 * (st + 32) + kr;
           b[q] = (cv && an < ac) ? static_cast<double>(xp[(int64_t)an * S]) : 0.0;
-          const double* ua = sU + (4 * (st + q) + kr) * ULD + (lane & 15);
+          const double* ua = sU + (4 * st + kr) * ULD + (lane & 15);
 #pragma unroll
           for (int t = 0; t < 4; ++t)
             if (t < rt) acc[t] = mfma16(ua[t * 16], bv, acc[t]);
@@ -1062,15 +1065,29 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
       }
     }
   }
-  if (cv) {
+  // partials of waves 1-3 through LDS, added to wave 0's in wave order
+  __syncthreads();
+  if (wave > 0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < rt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sU[(((wave - 1) * 4 + t) * 4 + v) * 64 + lane] = acc[t][v];
+      }
+  }
+  __syncthreads();
+  if (wave == 0 && cv) {
     const int64_t p = c / S, sidx = c - (c / S) * S;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if (t < rt) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+          double z = acc[t][v];
+#pragma unroll
+          for (int w = 0; w < 3; ++w) z += sU[((w * 4 + t) * 4 + v) * 64 + lane];
           const int r = t * 16 + MA<double>::row(lane, v);
-          if (r < R) Z[(p * R + r) * S + sidx] = acc[t][v];
+          if (r < R) Z[(p * R + r) * S + sidx] = z;
         }
       }
     }
@@ -1564,7 +1581,7 @@ void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U
   if (norm_part != nullptr) sumsq(x, t, v.P * v.m * v.S, norm_part, norm_out, s);
   ProfScope prof(KKind::TtmContract, s, 2.0 * R * v.m * (double)K,
                  (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8);
-  const unsigned blocks = (unsigned)((K + 63) / 64);
+  const unsigned blocks = (unsigned)((K + 15) / 16);
   const int RP = (R + 15) & ~15;
   const int chunk = (int)std::min<int64_t>(((kDirectLdsDoubles / (RP + 1)) / 4) * 4, (v.m + 3) & ~3);
   if (t == Elem::F32)
