@@ -761,10 +761,21 @@ __device__ __forceinline__ int top_eigen_rank(const double* dn, const double* e2
   }
 }
 
+// reciprocal of a nonzero double: the hardware estimate and two Newton steps
+__device__ __forceinline__ double recip(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double t = fma(-x, y, 1.0);
+  y = fma(y, t, y);
+  t = fma(-x, y, 1.0);
+  return fma(y, t, y);
+}
+
 // ---- phase 4a: inverse iteration (two sweeps from a fixed pseudo-random start),
-//      one thread per vector, for the r leading eigenvalues (top, descending).  W holds 4 k r doubles: the iterate Z and the
-//      three rows of U of the partial-pivoting LU of T - lambda I; entry (i, j) of
-//      each at i * r + j.
+//      one thread per vector, for the r leading eigenvalues (top, descending).  W
+//      holds 4 k r doubles: the iterate Z and the three rows of U of the
+//      partial-pivoting LU of T - lambda I (the pivot stored as its reciprocal);
+//      entry (i, j) of each at i * r + j.  Row choices are selects, so vectors
+//      that pivot differently do not split the wave.
 __device__ __forceinline__ void inverse_iteration(double* W, int k, int r, const double* top, const double* d,
                                                   const double* e, double tnorm) {
   const int tid = threadIdx.x;
@@ -782,32 +793,23 @@ __device__ __forceinline__ void inverse_iteration(double* W, int k, int r, const
       double bi = Z[j];
       for (int i = 0; i + 1 < k; ++i) {
         const double l0 = e[i], l1 = d[i + 1] - lm, l2 = (i + 2 < k) ? e[i + 1] : 0.0;
-        double bn = Z[(size_t)(i + 1) * r + j];
-        double nu0, nu1;
-        if (fabs(u0) >= fabs(l0)) {
-          if (u0 == 0.0) u0 = tiny;
-          const double mlt = l0 / u0;
-          U0[(size_t)i * r + j] = u0;
-          U1[(size_t)i * r + j] = u1;
-          U2[(size_t)i * r + j] = u2;
-          Z[(size_t)i * r + j] = bi;
-          nu0 = l1 - mlt * u1;
-          nu1 = l2 - mlt * u2;
-          bn = bn - mlt * bi;
-        } else {
-          const double mlt = u0 / l0;
-          U0[(size_t)i * r + j] = l0;
-          U1[(size_t)i * r + j] = l1;
-          U2[(size_t)i * r + j] = l2;
-          Z[(size_t)i * r + j] = bn;
-          nu0 = u1 - mlt * l1;
-          nu1 = u2 - mlt * l2;
-          bn = bi - mlt * bn;
-        }
-        u0 = nu0;
-        u1 = nu1;
+        const double bn = Z[(size_t)(i + 1) * r + j];
+        const bool sw = fabs(u0) < fabs(l0);  // the next row becomes the pivot row
+        double p0 = sw ? l0 : u0;
+        const double p1 = sw ? l1 : u1, p2 = sw ? l2 : u2, bp = sw ? bn : bi;
+        const double o0 = sw ? u0 : l0, o1 = sw ? u1 : l1, o2 = sw ? u2 : l2, bo = sw ? bi : bn;
+        if (p0 == 0.0) p0 = tiny;  // both candidates zero
+        const double ip = recip(p0);
+        const double mlt = o0 * ip;
+        // the back substitution divides by the pivot held away from zero
+        U0[(size_t)i * r + j] = fabs(p0) < tiny ? recip(p0 < 0.0 ? -tiny : tiny) : ip;
+        U1[(size_t)i * r + j] = p1;
+        U2[(size_t)i * r + j] = p2;
+        Z[(size_t)i * r + j] = bp;
+        u0 = fma(-mlt, p1, o1);
+        u1 = fma(-mlt, p2, o2);
         u2 = 0.0;
-        bi = bn;
+        bi = fma(-mlt, bp, bo);
       }
       if (fabs(u0) < tiny) u0 = (u0 < 0.0) ? -tiny : tiny;
       // backward substitution, the two previous unknowns kept in registers and the
@@ -820,9 +822,7 @@ __device__ __forceinline__ void inverse_iteration(double* W, int k, int r, const
         for (int i = k - 2; i >= 0; --i) {
           const size_t on = (i > 0) ? o - r : o;
           const double n0 = U0[on], n1 = U1[on], n2 = U2[on], nz = Z[on];
-          double piv = q0;
-          if (fabs(piv) < tiny) piv = (piv < 0.0) ? -tiny : tiny;
-          const double x = (qz - q1 * x1 - q2 * x2) / piv;
+          const double x = (qz - q1 * x1 - q2 * x2) * q0;
           Z[o] = x;
           x2 = x1;
           x1 = x;
