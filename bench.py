@@ -303,7 +303,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", choices=("both", "mixed", "fp64"), default="both")
-    ap.add_argument("--cpu-sample", type=int, default=4, help="batches of the oracle baseline (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=10, help="batches of the oracle baseline (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-many", action="store_true", help="skip the many-streams measurement")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),

@@ -1007,6 +1007,97 @@ __global__ __launch_bounds__(256) void gram_reg_kernel(const float* __restrict__
   }
 }
 
+// --------------------------------------------------------------------------
+// FP64 contraction Z = U^T X (FP32 or FP64 X) for the shapes of ttm_reg_kernel, on
+// FP64 matrix cores with operands straight from registers: the same blocks of 32
+// columns and the same loads (two adjacent columns per lane and row), U^T in LDS,
+// the R / 16 output row tiles one after another.  FP64 accumulator register v of
+// lane l is row l / 16 + 4 v of the tile.
+// --------------------------------------------------------------------------
+template <typename T, int TI, bool NORM>
+__global__ __launch_bounds__(256) void ttm_reg64_kernel(const T* __restrict__ X, int64_t P, int m, int64_t S,
+                                                        const double* __restrict__ U, int R, double* __restrict__ Z,
+                                                        double* __restrict__ norm_part) {
+  constexpr int NT = 4 * TI;
+  extern __shared__ double sUd[];  // sUd[a * uld + r]: U, zero outside m x R
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g4 = lane >> 4, c16 = lane & 15;
+  const int nrt = (R + 15) >> 4, uld = 16 * nrt + 1;
+  for (int e = threadIdx.x; e < 16 * TI * uld; e += 256) {
+    const int a = e / uld, r = e - (e / uld) * uld;
+    sUd[e] = (a < m && r < R) ? U[a + (int64_t)r * m] : 0.0;
+  }
+  __syncthreads();
+  constexpr int esz = (int)sizeof(T);
+  const int lane_off = (2 * c16 + g4 * (int)S) * esz;
+  const int step = 4 * (int)S * esz;
+  const int S32 = (int)S;
+  const int nblk = (int)(P * S / 32);
+  double nrm = 0.0;
+  for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
+    asm volatile("" ::: "memory");  // U^T is re-read from LDS per block, not held in registers
+    const int c0 = blk * 32;
+    const int p = c0 / S32, s0 = c0 - p * S32;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T*>(X) + (int64_t)p * m * S + s0, (short)0, (m * S32 - s0) * esz, 0x00020000);
+    T x0[NT], x1[NT];  // converted to FP64 where they feed the matrix cores
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (4 * t < m) {
+        if constexpr (esz == 4) {
+          typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+          const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, t * step, 0);
+          x0[t] = __uint_as_float(v.x);
+          x1[t] = __uint_as_float(v.y);
+        } else {
+          typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+          const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, lane_off, t * step, 0);
+          x0[t] = __hiloint2double((int)v.y, (int)v.x);
+          x1[t] = __hiloint2double((int)v.w, (int)v.z);
+        }
+      } else {
+        x0[t] = T(0);
+        x1[t] = T(0);
+      }
+    }
+    if (NORM) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        nrm = fma((double)x0[t], (double)x0[t], nrm);
+        nrm = fma((double)x1[t], (double)x1[t], nrm);
+      }
+    }
+    for (int rt = 0; rt < nrt; ++rt) {
+      d4 e0 = d4{0, 0, 0, 0}, e1 = e0, o0 = e0, o1 = e0;
+#pragma unroll
+      for (int t = 0; t < NT; t += 2) {
+        const double a0 = sUd[(4 * t + g4) * uld + 16 * rt + c16];
+        const double a1 = sUd[(4 * t + 4 + g4) * uld + 16 * rt + c16];
+        T b0 = x0[t], b1 = x1[t], b2 = x0[t + 1], b3 = x1[t + 1];
+        if constexpr (esz == 4) asm volatile("" : "+v"(b0), "+v"(b1), "+v"(b2), "+v"(b3));  // convert here
+        e0 = mfma16(a0, (double)b0, e0);
+        o0 = mfma16(a0, (double)b1, o0);
+        e1 = mfma16(a1, (double)b2, e1);
+        o1 = mfma16(a1, (double)b3, o1);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * rt + g4 + 4 * v;
+        if (r < R)
+          *reinterpret_cast<double2*>(Z + (p * R + r) * S + s0 + 2 * c16) =
+              make_double2(e0[v] + e1[v], o0[v] + o1[v]);
+      }
+    }
+  }
+  if (NORM) {
+    __shared__ double red[4];
+    nrm = wave_sum(nrm);
+    if (lane == 0) red[wave] = nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) norm_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
 constexpr int TUS = 65;  // LDS row stride (doubles) of the staged U chunk of the expansion
 
 // --------------------------------------------------------------------------
@@ -1557,6 +1648,35 @@ void launch_ttm_panel(const void* x, const ModeView& v, const double* U, int R, 
   if (RESE) reduce_kernel<<<1, 256, 0, s>>>(res_part, blocks, res_out);
 }
 
+bool ttm_reg64_applies(Elem t, const ModeView& v, int R) {
+  const int64_t esz = t == Elem::F32 ? 4 : 8;
+  return v.S % 32 == 0 && v.m % 4 == 0 && v.m <= 128 && v.m * v.S * esz < (int64_t(1) << 31) &&
+         v.P * v.S < (int64_t(1) << 31) && R >= 1 && R <= 64;
+}
+
+template <typename T, bool NN>
+void launch_ttm_reg64(const T* x, const ModeView& v, const double* U, int R, double* Z, double* norm_part,
+                      double* norm_out, double fl, double by, hipStream_t s) {
+  const int ti = ((int)((v.m + 15) / 16) + 1) & ~1;  // 2, 4, 6 or 8 row tiles
+  const int nrt = (R + 15) / 16;
+  const int64_t nblk = v.P * v.S / 32;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kTtmMaxBlocks, (nblk + 3) / 4));
+  const size_t lds = (size_t)16 * ti * (16 * nrt + 1) * sizeof(double);
+  {
+    ProfScope prof(KKind::TtmContract, s, fl, by);
+    switch (ti) {
+      case 2: ttm_reg64_kernel<T, 2, NN><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part); break;
+      case 4: ttm_reg64_kernel<T, 4, NN><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part); break;
+      case 6: ttm_reg64_kernel<T, 6, NN><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part); break;
+      default: ttm_reg64_kernel<T, 8, NN><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part); break;
+    }
+  }
+  if (NN) {
+    ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+    reduce_kernel<<<1, 256, 0, s>>>(norm_part, blocks, norm_out);
+  }
+}
+
 void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z, double* norm_part,
                        double* norm_out, hipStream_t s) {
   const int64_t K = v.P * v.S;
@@ -1565,6 +1685,18 @@ void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U
                  by = (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8;
     const KKind kd = KKind::TtmContract;
     const bool nrm = norm_part != nullptr;
+    if (ttm_reg64_applies(t, v, R)) {
+      if (t == Elem::F32) {
+        const float* xf = static_cast<const float*>(x);
+        if (nrm) launch_ttm_reg64<float, true>(xf, v, U, R, Z, norm_part, norm_out, fl, by, s);
+        else launch_ttm_reg64<float, false>(xf, v, U, R, Z, nullptr, nullptr, fl, by, s);
+      } else {
+        const double* xd = static_cast<const double*>(x);
+        if (nrm) launch_ttm_reg64<double, true>(xd, v, U, R, Z, norm_part, norm_out, fl, by, s);
+        else launch_ttm_reg64<double, false>(xd, v, U, R, Z, nullptr, nullptr, fl, by, s);
+      }
+      return;
+    }
     if (t == Elem::F32) {
       if (nrm)
         launch_ttm_panel<float, double, true, false>(x, v, U, R, Z, norm_part, norm_out, nullptr, nullptr, kd, fl, by,

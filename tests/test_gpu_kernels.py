@@ -55,7 +55,10 @@ def test_resid_gram(P, m, S, R, dtype):
 
 
 @pytest.mark.parametrize("P,m,S,R", [(3, 96, 1000, 12), (5, 3, 7, 3), (100, 16, 1, 5), (2, 200, 33, 64),
-                                     (1, 130, 40, 17), (7, 17, 5, 1), (4, 64, 300, 16), (50, 9, 1, 9)])
+                                     (1, 130, 40, 17), (7, 17, 5, 1), (4, 64, 300, 16), (50, 9, 1, 9),
+                                     # column runs in whole blocks of 32, m % 4 == 0: register-direct FP64
+                                     (3, 96, 1024, 12), (2, 128, 64, 64), (5, 40, 96, 20), (2, 96, 288, 47),
+                                     (64, 8, 16384, 3), (3, 4, 32, 1)])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_ttm_contract(P, m, S, R, dtype):
     g = rng(P + m + S + R)
