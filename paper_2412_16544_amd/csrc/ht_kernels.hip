@@ -749,7 +749,7 @@ __global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X,
 // whole block of loads per wave keep the HBM pipe full without LDS staging.
 // --------------------------------------------------------------------------
 template <int TI, int RT, bool NORM, bool RESE>
-__global__ __launch_bounds__(256) void ttm_reg_kernel(const float* __restrict__ X, int64_t P, int m, int64_t S,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TI * RT <= 6 ? 4 : 1))) void ttm_reg_kernel(const float* __restrict__ X, int64_t P, int m, int64_t S,
                                                       const double* __restrict__ U, int R, float* __restrict__ Z,
                                                       double* __restrict__ norm_part, double* __restrict__ res_part) {
   constexpr int NT = 4 * TI;
