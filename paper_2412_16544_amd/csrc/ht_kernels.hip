@@ -788,11 +788,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TI * RT <= 
       }
     }
     if (NORM) {
+      double n0 = 0.0, n1 = 0.0;  // two chains: the sums are not latency-bound
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        nrm = fma((double)x[t].x, (double)x[t].x, nrm);
-        nrm = fma((double)x[t].y, (double)x[t].y, nrm);
+        n0 = fma((double)x[t].x, (double)x[t].x, n0);
+        n1 = fma((double)x[t].y, (double)x[t].y, n1);
       }
+      nrm += n0 + n1;
     }
     f4 ze[RT], zo[RT];
 #pragma unroll
@@ -817,7 +819,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TI * RT <= 
       }
     }
     if (RESE) {
-      float res32 = 0.f;
+      float res32 = 0.f, res32b = 0.f;
 #pragma unroll
       for (int it = 0; it < TI; ++it) {
         f4 ye = f4{0, 0, 0, 0}, yo = ye;
@@ -838,10 +840,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TI * RT <= 
           const float de = x[4 * it + v].x - ye[v];
           const float dd = x[4 * it + v].y - yo[v];
           res32 = fmaf(de, de, res32);
-          res32 = fmaf(dd, dd, res32);
+          res32b = fmaf(dd, dd, res32b);
         }
       }
-      res += (double)res32;
+      res += (double)res32 + (double)res32b;
     }
   }
   if (NORM || RESE) {
