@@ -253,9 +253,10 @@ def run_many(count=64, cap=1 << 20):
 # kernel-name patterns of each profile kind (the template's second argument is the
 # compute type of the panel kernels)
 KIND_KERNELS = {
-    "ttm_contract_f32": ("ttm_panel_kernel<float, float", "ttm_panel_kernel<double, float"),
-    "ttm_contract": ("ttm_panel_kernel<float, double", "ttm_panel_kernel<double, double", "ttm_direct_kernel<"),
-    "gram_f32": ("gram_panel_kernel<float, float", "gram_panel_kernel<double, float"),
+    "ttm_contract_f32": ("ttm_panel_kernel<float, float", "ttm_panel_kernel<double, float", "ttm_reg_kernel<"),
+    "ttm_contract": ("ttm_panel_kernel<float, double", "ttm_panel_kernel<double, double", "ttm_direct_kernel<",
+                     "ttm_reg64_kernel<"),
+    "gram_f32": ("gram_panel_kernel<float, float", "gram_panel_kernel<double, float", "gram_reg_kernel<"),
     "gram": ("gram_panel_kernel<float, double", "gram_panel_kernel<double, double", "gram_partial_kernel<",
              "gram_small_kernel<"),
     "ttm_expand": ("ttm_expand_kernel<",),

@@ -736,24 +736,108 @@ __global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X,
 }
 
 // --------------------------------------------------------------------------
-// FP32 contraction Z = U^T X for a mode with m <= 16 TI rows whose column runs
-// have a length divisible by 32 (S % 32 == 0), operands straight from registers.
-// A wave takes blocks of 32 unfolding columns (one p, consecutive s): lane l loads
-// columns 2 (l % 16) and 2 (l % 16) + 1 of rows 4 t + l / 16 as one float2, the B
-// operands of two 16-column halves (the even and the odd columns).  U^T (RT row
-// tiles of 16) sits in LDS.  With RESE the residual X - U Z is formed in registers
-// as well: register v of the Z accumulators is a valid B operand for the step
-// whose k index l / 16 stands for row 16 rt + 4 (l / 16) + v of Z, and reading
-// the rows of U in the order pi(q) = 4 (q % 4) + q / 4 makes row q of the product
-// the row that the lane holds in its X registers.  Many waves per SIMD and a
-// whole block of loads per wave keep the HBM pipe full without LDS staging.
+// Register-direct FP32 blocks.  A wave takes a block of unfolding columns and
+// loads rows 4 t + l / 16 (t < 4 TI) of 16 columns per "half" straight into the
+// B-operand layout of the 16 x 16 x 4 matrix cores (row on l / 16, column on
+// l % 16), NH halves per block:
+//   SL = 0, column runs in whole blocks of 32 (S % 32 == 0): one p, 32
+//     consecutive s; lane l loads columns 2 (l % 16) and 2 (l % 16) + 1 as one
+//     float2, so the halves are the even and the odd columns (NH = 2);
+//   SL = S <= 4 (short runs): 16 consecutive p, all S values of s; lane l loads
+//     the S entries of row a of slab p0 + l % 16 in one load, half h = s (NH = S).
+// Loads are buffer loads with the row step as a scalar offset; lanes past the
+// last slab fall outside the buffer's extent and read zeros.
 // --------------------------------------------------------------------------
-template <int TI, int RT, bool NORM, bool RESE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TI * RT <= 6 ? 4 : 1))) void ttm_reg_kernel(const float* __restrict__ X, int64_t P, int m, int64_t S,
-                                                      const double* __restrict__ U, int R, float* __restrict__ Z,
-                                                      double* __restrict__ norm_part, double* __restrict__ res_part) {
+template <int SL>
+struct RegBlock {
+  static constexpr int NH = SL == 0 ? 2 : SL;
+  __amdgpu_buffer_rsrc_t rs;
+  int lane_off, step;
+  int64_t p;   // SL = 0: the block's p; else the lane's slab
+  int s0;      // SL = 0: first s of the block
+  bool live;   // the lane's columns exist
+
+  __device__ __forceinline__ void setup(const float* X, int64_t P, int m, int64_t S, int blk, int g4, int c16) {
+    if (SL == 0) {
+      const int S32 = (int)S;
+      const int c0 = blk * 32;
+      p = c0 / S32;
+      s0 = c0 - (int)p * S32;
+      rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X) + p * m * S + s0, (short)0,
+                                             (m * S32 - s0) * 4, 0x00020000);
+      lane_off = (2 * c16 + g4 * S32) * 4;
+      step = 16 * S32;
+      live = true;
+    } else {
+      const int64_t p0 = (int64_t)blk * 16;
+      p = p0 + c16;
+      s0 = 0;
+      const int64_t left = P - p0 < 16 ? P - p0 : 16;
+      rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X) + p0 * m * SL, (short)0,
+                                             (int)(left * m * SL * 4), 0x00020000);
+      lane_off = (c16 * m * SL + g4 * SL) * 4;
+      step = 16 * SL;
+      live = p < P;
+    }
+  }
+  template <int NT>
+  __device__ __forceinline__ void load(float (&x)[NT][NH], int m) const {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    typedef unsigned int u3 __attribute__((ext_vector_type(3)));
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (4 * t < m) {
+        if (SL == 1) {
+          x[t][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, lane_off, t * step, 0));
+        } else if (SL == 0 || SL == 2) {
+          const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, t * step, 0);
+          x[t][0] = __uint_as_float(v.x);
+          x[t][1] = __uint_as_float(v.y);
+        } else if (SL == 3) {
+          const u3 v = __builtin_amdgcn_raw_buffer_load_b96(rs, lane_off, t * step, 0);
+          x[t][0] = __uint_as_float(v.x);
+          x[t][1] = __uint_as_float(v.y);
+          x[t][NH > 2 ? 2 : 0] = __uint_as_float(v.z);
+        } else {
+          const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, lane_off, t * step, 0);
+          x[t][0] = __uint_as_float(v.x);
+          x[t][1] = __uint_as_float(v.y);
+          x[t][NH > 2 ? 2 : 0] = __uint_as_float(v.z);
+          x[t][NH > 3 ? 3 : 0] = __uint_as_float(v.w);
+        }
+      } else {
+#pragma unroll
+        for (int h = 0; h < NH; ++h) x[t][h] = 0.f;
+      }
+    }
+  }
+  // address of (row r, half h) of the lane's column in the (P, R, S) output
+  __device__ __forceinline__ int64_t out_index(int R, int64_t S, int r, int h, int c16) const {
+    return SL == 0 ? (p * R + r) * S + s0 + 2 * c16 + h : (p * R + r) * SL + h;
+  }
+  __device__ __forceinline__ static int64_t blocks(int64_t P, int64_t S) {
+    return SL == 0 ? P * S / 32 : (P + 15) / 16;
+  }
+};
+
+// --------------------------------------------------------------------------
+// FP32 contraction Z = U^T X for a mode with m <= 16 TI rows (m % 4 == 0) on
+// register-direct blocks.  U^T (RT row tiles of 16) sits in LDS.  With RESE the
+// residual X - U Z is formed in registers as well: register v of the Z
+// accumulators is a valid B operand for the step whose k index l / 16 stands for
+// row 16 rt + 4 (l / 16) + v of Z, and reading the rows of U in the order
+// pi(q) = 4 (q % 4) + q / 4 makes row q of the product the row that the lane
+// holds in its X registers.  Many waves per SIMD and a whole block of loads per
+// wave keep the HBM pipe full without LDS staging.
+// --------------------------------------------------------------------------
+template <int TI, int RT, bool NORM, bool RESE, int SL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SL == 0 && TI * RT <= 6 ? 4 : 1))) void ttm_reg_kernel(
+    const float* __restrict__ X, int64_t P, int m, int64_t S, const double* __restrict__ U, int R,
+    float* __restrict__ Z, double* __restrict__ norm_part, double* __restrict__ res_part) {
   constexpr int NT = 4 * TI;
   constexpr int ULD = 16 * RT + 1;
+  constexpr int NH = RegBlock<SL>::NH;
   extern __shared__ float sUr[];  // sUr[a * ULD + r]: U in FP32, zero outside m x R
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g4 = lane >> 4, c16 = lane & 15;
@@ -762,88 +846,91 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TI * RT <= 
     sUr[e] = (a < m && r < R) ? static_cast<float>(U[a + (int64_t)r * m]) : 0.f;
   }
   __syncthreads();
-  // byte offsets inside one p slab (m S < 2^29 and P S < 2^31 are checked by the
-  // launcher); with m % 4 == 0 the rows of step t are all valid or all padding
-  const int lane_off = (2 * c16 + g4 * (int)S) * 4;
-  const int step = 16 * (int)S;
-  const int S32 = (int)S;
-  const int nblk = (int)(P * S / 32);
+  const int nblk = (int)RegBlock<SL>::blocks(P, S);
   const int pr = 4 * (c16 & 3) + (c16 >> 2);  // permuted row of U read by this lane
   double nrm = 0.0, res = 0.0;
   for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
     asm volatile("" ::: "memory");  // U^T is re-read from LDS per block, not held in registers
-    const int c0 = blk * 32;
-    const int p = c0 / S32, s0 = c0 - p * S32;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(X) + (int64_t)p * m * S + s0, (short)0, (m * S32 - s0) * 4, 0x00020000);
-    float2 x[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (4 * t < m) {
-        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, t * step, 0);
-        x[t] = make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
-      } else {
-        x[t] = make_float2(0.f, 0.f);
-      }
-    }
+    RegBlock<SL> B;
+    B.setup(X, P, m, S, blk, g4, c16);
+    float x[NT][NH];
+    B.load(x, m);
     if (NORM) {
       double n0 = 0.0, n1 = 0.0;  // two chains: the sums are not latency-bound
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        n0 = fma((double)x[t].x, (double)x[t].x, n0);
-        n1 = fma((double)x[t].y, (double)x[t].y, n1);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          if (h & 1) n1 = fma((double)x[t][h], (double)x[t][h], n1);
+          else n0 = fma((double)x[t][h], (double)x[t][h], n0);
+        }
       }
       nrm += n0 + n1;
     }
-    f4 ze[RT], zo[RT];
+    f4 zz[RT][NH];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      f4 e0 = f4{0, 0, 0, 0}, e1 = e0, o0 = e0, o1 = e0;
+      f4 c0[NH], c1[NH];
+#pragma unroll
+      for (int h = 0; h < NH; ++h) c0[h] = c1[h] = f4{0, 0, 0, 0};
 #pragma unroll
       for (int t = 0; t < NT; t += 2) {
         const float a0 = sUr[(4 * t + g4) * ULD + 16 * rt + c16];
         const float a1 = sUr[(4 * t + 4 + g4) * ULD + 16 * rt + c16];
-        e0 = mfma16(a0, x[t].x, e0);
-        o0 = mfma16(a0, x[t].y, o0);
-        e1 = mfma16(a1, x[t + 1].x, e1);
-        o1 = mfma16(a1, x[t + 1].y, o1);
-      }
-      ze[rt] = e0 + e1;
-      zo[rt] = o0 + o1;
-      // register v: row 16 rt + 4 (l / 16) + v of Z, columns c0 + 2 (l % 16) + {0, 1}
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * rt + 4 * g4 + v;
-        if (r < R) *reinterpret_cast<float2*>(Z + (p * R + r) * S + s0 + 2 * c16) = make_float2(ze[rt][v], zo[rt][v]);
+        for (int h = 0; h < NH; ++h) {
+          c0[h] = mfma16(a0, x[t][h], c0[h]);
+          c1[h] = mfma16(a1, x[t + 1][h], c1[h]);
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < NH; ++h) zz[rt][h] = c0[h] + c1[h];
+      // register v: row 16 rt + 4 (l / 16) + v of Z
+      if (B.live) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * rt + 4 * g4 + v;
+          if (r < R) {
+            if (SL == 0) {
+              *reinterpret_cast<float2*>(Z + B.out_index(R, S, r, 0, c16)) = make_float2(zz[rt][0][v], zz[rt][1][v]);
+            } else {
+#pragma unroll
+              for (int h = 0; h < NH; ++h) Z[B.out_index(R, S, r, h, c16)] = zz[rt][h][v];
+            }
+          }
+        }
       }
     }
     if (RESE) {
-      float res32 = 0.f, res32b = 0.f;
+      // the block's residual energy is summed in FP32 (relative error ~1e-5, far
+      // below what the skip test resolves) and added to an FP64 total
+      float e0 = 0.f, e1 = 0.f;
 #pragma unroll
       for (int it = 0; it < TI; ++it) {
-        f4 ye = f4{0, 0, 0, 0}, yo = ye;
+        f4 y[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) y[h] = f4{0, 0, 0, 0};
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const float a = sUr[(16 * it + pr) * ULD + 16 * rt + 4 * g4 + v];
-            ye = mfma16(a, ze[rt][v], ye);
-            yo = mfma16(a, zo[rt][v], yo);
+#pragma unroll
+            for (int h = 0; h < NH; ++h) y[h] = mfma16(a, zz[rt][h][v], y[h]);
           }
         }
-        // register v of the product: row 16 it + 4 v + l / 16 = the row of x[4 it + v];
-        // the block's residual energy is summed in FP32 (relative error ~1e-5, far
-        // below what the skip test resolves) and added to an FP64 total
+        // register v of the product: row 16 it + 4 v + l / 16 = the row of x[4 it + v]
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const float de = x[4 * it + v].x - ye[v];
-          const float dd = x[4 * it + v].y - yo[v];
-          res32 = fmaf(de, de, res32);
-          res32b = fmaf(dd, dd, res32b);
+#pragma unroll
+          for (int h = 0; h < NH; ++h) {
+            const float d = x[4 * it + v][h] - y[h][v];
+            if (h & 1) e1 = fmaf(d, d, e1);
+            else e0 = fmaf(d, d, e0);
+          }
         }
       }
-      res += (double)res32 + (double)res32b;
+      res += (double)e0 + (double)e1;
     }
   }
   if (NORM || RESE) {
@@ -863,19 +950,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TI * RT <= 
 }
 
 // --------------------------------------------------------------------------
-// FP32 Gram G = M M^T of a mode unfolding (RESID: of the residual M - U U^T M)
-// for the same shapes as ttm_reg_kernel.  A wave loads a block of 32 columns the
-// same way, forms Z = U^T M and the residual in registers, and then feeds the
-// matrix cores through a wave-private LDS transpose, 16 columns at a time: the
-// Gram operands want the row index on l % 16, the loaded layout has the column
-// there.  Every wave accumulates all TI (TI + 1) / 2 upper 16 x 16 tiles; the four
-// waves of a workgroup add theirs in wave order and the workgroup writes one
-// FP64 partial (upper tiles of an m x m array), summed over the workgroups in a
-// fixed order afterwards.
+// FP32 residual Gram R R^T, R = M - U U^T M, on register-direct blocks (the
+// shapes of ttm_reg_kernel).  A wave forms Z = U^T M and the residual of its block
+// in registers, then feeds the matrix cores through a wave-private LDS transpose,
+// one 16-column half at a time: the Gram operands want the row index on l % 16,
+// the loaded layout has the column there.  Every wave accumulates all
+// TI (TI + 1) / 2 upper 16 x 16 tiles; the four waves of a workgroup add theirs
+// in wave order and the workgroup writes one FP64 partial (upper tiles of an
+// m x m array), summed over the workgroups in a fixed order afterwards.
 // --------------------------------------------------------------------------
 constexpr int kGramRegLd = 17;  // row stride (floats) of a wave's 16-column transpose buffer
 
-template <int TI, int RT, bool RESID>
+template <int TI, int RT, int SL>
 __global__ __launch_bounds__(256) void gram_reg_kernel(const float* __restrict__ X, int64_t P, int m, int64_t S,
                                                        const double* __restrict__ U, int R,
                                                        double* __restrict__ part) {
@@ -883,85 +969,75 @@ __global__ __launch_bounds__(256) void gram_reg_kernel(const float* __restrict__
   constexpr int ULD = 16 * RT + 1;
   constexpr int NTILE = TI * (TI + 1) / 2;
   constexpr int WREG = 16 * TI * kGramRegLd;  // floats of one wave's transpose buffer
+  constexpr int NH = RegBlock<SL>::NH;
   extern __shared__ float sgr[];
-  float* sUr = sgr;                                    // U (RESID), 16 TI x ULD
-  float* sT = sgr + (RESID ? 16 * TI * ULD : 0);       // 4 transpose buffers, later the tile sums
+  float* sUr = sgr;                  // U, 16 TI x ULD
+  float* sT = sgr + 16 * TI * ULD;   // 4 transpose buffers, later the tile sums
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g4 = lane >> 4, c16 = lane & 15;
-  if (RESID) {
-    for (int e = threadIdx.x; e < 16 * TI * ULD; e += 256) {
-      const int a = e / ULD, r = e - (e / ULD) * ULD;
-      sUr[e] = (a < m && r < R) ? static_cast<float>(U[a + (int64_t)r * m]) : 0.f;
-    }
-    __syncthreads();
+  for (int e = threadIdx.x; e < 16 * TI * ULD; e += 256) {
+    const int a = e / ULD, r = e - (e / ULD) * ULD;
+    sUr[e] = (a < m && r < R) ? static_cast<float>(U[a + (int64_t)r * m]) : 0.f;
   }
+  __syncthreads();
   float* myT = sT + wave * WREG;
-  const int lane_off = (2 * c16 + g4 * (int)S) * 4;
-  const int step = 16 * (int)S;
-  const int S32 = (int)S;
-  const int nblk = (int)(P * S / 32);
+  const int nblk = (int)RegBlock<SL>::blocks(P, S);
   const int pr = 4 * (c16 & 3) + (c16 >> 2);
   f4 acc[NTILE];
 #pragma unroll
   for (int q = 0; q < NTILE; ++q) acc[q] = f4{0, 0, 0, 0};
   for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
     asm volatile("" ::: "memory");
-    const int c0 = blk * 32;
-    const int p = c0 / S32, s0 = c0 - p * S32;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(X) + (int64_t)p * m * S + s0, (short)0, (m * S32 - s0) * 4, 0x00020000);
-    float2 x[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (4 * t < m) {
-        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, t * step, 0);
-        x[t] = make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
-      } else {
-        x[t] = make_float2(0.f, 0.f);
-      }
-    }
-    if (RESID) {
-      f4 ze[RT], zo[RT];
+    RegBlock<SL> B;
+    B.setup(X, P, m, S, blk, g4, c16);
+    float x[NT][NH];
+    B.load(x, m);
+    {
+      f4 zz[RT][NH];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
-        f4 e0 = f4{0, 0, 0, 0}, e1 = e0, o0 = e0, o1 = e0;
+        f4 c0[NH], c1[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) c0[h] = c1[h] = f4{0, 0, 0, 0};
 #pragma unroll
         for (int t = 0; t < NT; t += 2) {
           const float a0 = sUr[(4 * t + g4) * ULD + 16 * rt + c16];
           const float a1 = sUr[(4 * t + 4 + g4) * ULD + 16 * rt + c16];
-          e0 = mfma16(a0, x[t].x, e0);
-          o0 = mfma16(a0, x[t].y, o0);
-          e1 = mfma16(a1, x[t + 1].x, e1);
-          o1 = mfma16(a1, x[t + 1].y, o1);
+#pragma unroll
+          for (int h = 0; h < NH; ++h) {
+            c0[h] = mfma16(a0, x[t][h], c0[h]);
+            c1[h] = mfma16(a1, x[t + 1][h], c1[h]);
+          }
         }
-        ze[rt] = e0 + e1;
-        zo[rt] = o0 + o1;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) zz[rt][h] = c0[h] + c1[h];
       }
 #pragma unroll
       for (int it = 0; it < TI; ++it) {
-        f4 ye = f4{0, 0, 0, 0}, yo = ye;
+        f4 y[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) y[h] = f4{0, 0, 0, 0};
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const float a = sUr[(16 * it + pr) * ULD + 16 * rt + 4 * g4 + v];
-            ye = mfma16(a, ze[rt][v], ye);
-            yo = mfma16(a, zo[rt][v], yo);
+#pragma unroll
+            for (int h = 0; h < NH; ++h) y[h] = mfma16(a, zz[rt][h][v], y[h]);
           }
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          x[4 * it + v].x -= ye[v];
-          x[4 * it + v].y -= yo[v];
+#pragma unroll
+          for (int h = 0; h < NH; ++h) x[4 * it + v][h] -= y[h][v];
         }
       }
     }
-    // Gram of the block, one 16-column half (even, then odd columns) at a time
+    // Gram of the block, one 16-column half at a time
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NH; ++h) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) myT[(4 * t + g4) * kGramRegLd + c16] = h ? x[t].y : x[t].x;
+      for (int t = 0; t < NT; ++t) myT[(4 * t + g4) * kGramRegLd + c16] = x[t][h];
 #pragma unroll
       for (int k4 = 0; k4 < 4; ++k4) {
         float op[TI];
@@ -1503,45 +1579,55 @@ size_t gram_partial_doubles(const ModeView& v) {
   return (size_t)g.nsplit * g.npairs * g.blk;
 }
 
-bool gram_reg_applies(Elem t, const ModeView& v, int R) {
-  return t == Elem::F32 && v.S % 32 == 0 && v.m % 4 == 0 && v.m <= 128 && v.m * v.S < (int64_t(1) << 29) &&
-         v.P * v.S < (int64_t(1) << 31) && R >= 1 && R <= 64;
+// Register-direct block mode of an FP32 mode view: 0 for column runs in blocks of
+// 32, S for runs of 1-4 (with at most 32 rows of U and 36 to 96 rows), -1 when
+// neither applies; offsets must fit 32 bits.
+int reg_mode(Elem t, const ModeView& v, int R) {
+  if (t != Elem::F32 || v.m % 4 != 0 || v.m > 128 || R < 1 || R > 64) return -1;
+  if (v.m * v.S >= (int64_t(1) << 29) || v.P * v.S >= (int64_t(1) << 31)) return -1;
+  if (v.S % 32 == 0) return 0;
+  if (v.S <= 4 && R <= 32 && v.m > 32 && v.m <= 96) return (int)v.S;
+  return -1;
 }
+
+#define HT_REG_CASES(X)                                                                                \
+  X(2, 1, 0) X(2, 2, 0) X(2, 3, 0) X(2, 4, 0) X(4, 1, 0) X(4, 2, 0) X(4, 3, 0) X(4, 4, 0)                 \
+  X(6, 1, 0) X(6, 2, 0) X(6, 3, 0) X(6, 4, 0) X(8, 1, 0) X(8, 2, 0) X(8, 3, 0) X(8, 4, 0)                 \
+  X(4, 1, 1) X(4, 2, 1) X(6, 1, 1) X(6, 2, 1) X(4, 1, 2) X(4, 2, 2) X(6, 1, 2) X(6, 2, 2)                 \
+  X(4, 1, 3) X(4, 2, 3) X(6, 1, 3) X(6, 2, 3) X(4, 1, 4) X(4, 2, 4) X(6, 1, 4) X(6, 2, 4)
+#define HT_REG_KEY(TI, RT, SL) ((TI) * 64 + (RT) * 8 + (SL))
+
+int64_t reg_blocks(const ModeView& v, int mode) { return mode == 0 ? v.P * v.S / 32 : (v.P + 15) / 16; }
 
 // residual Gram through gram_reg_kernel; at most 512 workgroup partials, the
 // bound the partial buffer is sized for
-void gram_reg(const float* x, const ModeView& v, const double* U, int R, double* part, double* G, hipStream_t s) {
+void gram_reg(const float* x, const ModeView& v, int mode, const double* U, int R, double* part, double* G,
+              hipStream_t s) {
   const int ti = ((int)((v.m + 15) / 16) + 1) & ~1;
-  const int rt = R > 0 ? (R + 15) / 16 : 1;
-  const int64_t nblk = v.P * v.S / 32;
+  const int rt = (R + 15) / 16;
+  const int64_t nblk = reg_blocks(v, mode);
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(512, (nblk + 3) / 4));
-  const size_t lds =
-      ((R > 0 ? (size_t)16 * ti * (16 * rt + 1) : 0) +
-       std::max<size_t>((size_t)4 * 16 * ti * kGramRegLd, (size_t)(ti * (ti + 1) / 2) * 256)) * sizeof(float);
+  const size_t lds = ((size_t)16 * ti * (16 * rt + 1) +
+                      std::max<size_t>((size_t)4 * 16 * ti * kGramRegLd, (size_t)(ti * (ti + 1) / 2) * 256)) *
+                     sizeof(float);
   static bool attr = false;
   if (!attr) {
-#define HT_GA(TI, RTT, RS)                                                                   \
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_reg_kernel<TI, RTT, RS>), \
+#define HT_GA(TI, RT, SL)                                                                  \
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_reg_kernel<TI, RT, SL>), \
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
-    HT_GA(2, 1, true) HT_GA(2, 2, true) HT_GA(2, 3, true) HT_GA(2, 4, true)
-    HT_GA(4, 1, true) HT_GA(4, 2, true) HT_GA(4, 3, true) HT_GA(4, 4, true)
-    HT_GA(6, 1, true) HT_GA(6, 2, true) HT_GA(6, 3, true) HT_GA(6, 4, true)
-    HT_GA(8, 1, true) HT_GA(8, 2, true) HT_GA(8, 3, true) HT_GA(8, 4, true)
+    HT_REG_CASES(HT_GA)
 #undef HT_GA
     attr = true;
   }
   const double K = (double)v.P * v.S, md = (double)v.m;
   {
-    ProfScope prof(KKind::Gram32, s, md * md * K + (R > 0 ? 4.0 * R * md * K : 0.0), md * K * 4);
-#define HT_GR(TI, RTT, RS)                                                                                 \
-  case TI * 16 + RTT * 2 + (RS ? 1 : 0):                                                                   \
-    gram_reg_kernel<TI, RTT, RS><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, part);              \
+    ProfScope prof(KKind::Gram32, s, md * md * K + 4.0 * R * md * K, md * K * 4);
+#define HT_GR(TI, RT, SL)                                                                \
+  case HT_REG_KEY(TI, RT, SL):                                                           \
+    gram_reg_kernel<TI, RT, SL><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, part); \
     break;
-    switch (ti * 16 + rt * 2 + (R > 0 ? 1 : 0)) {
-      HT_GR(2, 1, true) HT_GR(2, 2, true) HT_GR(2, 3, true) HT_GR(2, 4, true)
-      HT_GR(4, 1, true) HT_GR(4, 2, true) HT_GR(4, 3, true) HT_GR(4, 4, true)
-      HT_GR(6, 1, true) HT_GR(6, 2, true) HT_GR(6, 3, true) HT_GR(6, 4, true)
-      HT_GR(8, 1, true) HT_GR(8, 2, true) HT_GR(8, 3, true) HT_GR(8, 4, true)
+    switch (HT_REG_KEY(ti, rt, mode)) {
+      HT_REG_CASES(HT_GR)
       default: break;
     }
 #undef HT_GR
@@ -1600,8 +1686,9 @@ void resid_gram(const void* x, Elem t, const ModeView& v, const double* U, int R
 
 void resid_gram_f32(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,
                     hipStream_t s) {
-  if (gram_reg_applies(t, v, R)) {
-    gram_reg(static_cast<const float*>(x), v, U, R, part, G, s);
+  const int mode = reg_mode(t, v, R);
+  if (mode >= 0) {
+    gram_reg(static_cast<const float*>(x), v, mode, U, R, part, G, s);
     return;
   }
   const GramPlan g = gram_plan(v);
@@ -1731,33 +1818,27 @@ void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U
 // the register-direct FP32 contraction applies to FP32 level tensors whose column
 // runs split into whole blocks of 32 (S % 32 == 0), modes of at most 128 rows in
 // steps of four, and sizes with 32-bit offsets
-bool ttm_reg_applies(Elem t, const ModeView& v, int R) {
-  return t == Elem::F32 && v.S % 32 == 0 && v.m % 4 == 0 && v.m <= 128 && v.m * v.S < (int64_t(1) << 29) &&
-         v.P * v.S < (int64_t(1) << 31) && R >= 1 && R <= 64;
-}
-
 template <bool NN, bool RR>
-void launch_ttm_reg(const float* x, const ModeView& v, const double* U, int R, float* Z, double* norm_part,
-                    double* norm_out, double* res_part, double* res_out, double fl, double by, hipStream_t s) {
+void launch_ttm_reg(const float* x, const ModeView& v, int mode, const double* U, int R, float* Z,
+                    double* norm_part, double* norm_out, double* res_part, double* res_out, double fl, double by,
+                    hipStream_t s) {
   const int ti = ((int)((v.m + 15) / 16) + 1) & ~1;  // 2, 4, 6 or 8 row tiles
   const int rt = (R + 15) / 16;
-  const int64_t nblk = v.P * v.S / 32;
+  const int64_t nblk = reg_blocks(v, mode);
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kTtmMaxBlocks, (nblk + 3) / 4));
   const size_t lds = (size_t)16 * ti * (16 * rt + 1) * sizeof(float);
   {
     ProfScope prof(KKind::TtmContract32, s, fl, by);
-#define HT_REG(TI, RTT)                                                                                          \
-  case TI * 8 + RTT:                                                                                             \
-    ttm_reg_kernel<TI, RTT, NN, RR><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part, res_part); \
+#define HT_TR(TI, RT, SL)                                                                                    \
+  case HT_REG_KEY(TI, RT, SL):                                                                               \
+    ttm_reg_kernel<TI, RT, NN, RR, SL><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part, \
+                                                                res_part);                                 \
     break;
-    switch (ti * 8 + rt) {
-      HT_REG(2, 1) HT_REG(2, 2) HT_REG(2, 3) HT_REG(2, 4)
-      HT_REG(4, 1) HT_REG(4, 2) HT_REG(4, 3) HT_REG(4, 4)
-      HT_REG(6, 1) HT_REG(6, 2) HT_REG(6, 3) HT_REG(6, 4)
-      HT_REG(8, 1) HT_REG(8, 2) HT_REG(8, 3) HT_REG(8, 4)
+    switch (HT_REG_KEY(ti, rt, mode)) {
+      HT_REG_CASES(HT_TR)
       default: break;
     }
-#undef HT_REG
+#undef HT_TR
   }
   ProfScope prof(KKind::Layout, s, 0.0, 0.0);
   if (NN) reduce_kernel<<<1, 256, 0, s>>>(norm_part, blocks, norm_out);
@@ -1774,12 +1855,12 @@ void ttm_contract_f32(const void* x, Elem t, const ModeView& v, const double* U,
   launch_ttm_panel<TT, float, NN, RR>(x, v, U, R, Z, NN ? norm_part : nullptr, NN ? norm_out : nullptr,       \
                                       RR ? res_part : nullptr, RR ? res_out : nullptr, KKind::TtmContract32, fl, \
                                       by, s)
-  if (ttm_reg_applies(t, v, R)) {
+  const int mode = reg_mode(t, v, R);
+  if (mode >= 0 && (rese || !nrm)) {
     const float* xf = static_cast<const float*>(x);
-    if (nrm && rese) launch_ttm_reg<true, true>(xf, v, U, R, Z, norm_part, norm_out, res_part, res_out, fl, by, s);
-    else if (rese) launch_ttm_reg<false, true>(xf, v, U, R, Z, nullptr, nullptr, res_part, res_out, fl, by, s);
-    else if (nrm) launch_ttm_reg<true, false>(xf, v, U, R, Z, norm_part, norm_out, nullptr, nullptr, fl, by, s);
-    else launch_ttm_reg<false, false>(xf, v, U, R, Z, nullptr, nullptr, nullptr, nullptr, fl, by, s);
+    if (nrm) launch_ttm_reg<true, true>(xf, v, mode, U, R, Z, norm_part, norm_out, res_part, res_out, fl, by, s);
+    else if (rese) launch_ttm_reg<false, true>(xf, v, mode, U, R, Z, nullptr, nullptr, res_part, res_out, fl, by, s);
+    else launch_ttm_reg<false, false>(xf, v, mode, U, R, Z, nullptr, nullptr, nullptr, nullptr, fl, by, s);
   } else if (t == Elem::F32) {
     if (nrm && rese) HT_TTM32(float, true, true);
     else if (rese) HT_TTM32(float, false, true);

@@ -80,7 +80,9 @@ MIXED_SHAPES = [(3, 96, 1000, 12), (5, 9, 7, 3), (100, 16, 1, 5), (2, 128, 33, 6
                 (4, 64, 300, 16), (50, 40, 2, 20), (1, 96, 31, 47),
                 # column runs in whole blocks of 32 with m % 4 == 0: the register-direct FP32 contraction
                 (3, 96, 1024, 12), (2, 128, 64, 64), (5, 40, 96, 20), (3, 4, 32, 1), (2, 96, 288, 47),
-                (64, 8, 16384, 3)]
+                (64, 8, 16384, 3),
+                # runs of 1-4 columns: 16 slabs per register block (partial last block, several per wave)
+                (100, 96, 3, 14), (37, 64, 1, 5), (50, 48, 2, 20), (19, 96, 4, 32), (300000, 40, 1, 3)]
 
 
 def near_subspace(P, m, S, R, seed, dtype=np.float32):
