@@ -106,7 +106,10 @@ __global__ __launch_bounds__(256) void sumsq_partial_kernel(const T* __restrict_
 
 __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+  int i = threadIdx.x;
+  for (; i + 3 * 256 < n; i += 4 * 256)  // four loads in flight, fixed order
+    acc += (part[i] + part[i + 256]) + (part[i + 512] + part[i + 768]);
+  for (; i < n; i += 256) acc += part[i];
   __shared__ double red[4];
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -544,7 +547,16 @@ __global__ __launch_bounds__(1024) void gram_reduce2_kernel(const double* __rest
     const int pair = bi * nb - bi * (bi - 1) / 2 + (bj - bi);
     const int ld_out = (int)min<int64_t>(GB, m);
     const int64_t off = (int64_t)pair * blk + li * ld_out + lj;
-    for (int sp = g; sp < nsplit; sp += 16) acc += part[(int64_t)sp * npairs * blk + off];
+    const int64_t stride = (int64_t)npairs * blk;
+    // eight independent loads in flight per thread, summed in a fixed order
+    int sp = g;
+    for (; sp + 7 * 16 < nsplit; sp += 8 * 16) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(sp + 16 * q) * stride + off];
+      acc += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    }
+    for (; sp < nsplit; sp += 16) acc += part[(int64_t)sp * stride + off];
   }
   red[g][l] = acc;
   __syncthreads();
