@@ -528,7 +528,9 @@ __global__ __launch_bounds__(256) void gram_panel_kernel(const T* __restrict__ X
 }
 
 // Fixed-order sum of the split partials: 16 groups of 64 lanes split the partial
-// range for 64 consecutive outputs, then add their sums in group order.
+// range for 64 consecutive entries, then add their sums in group order.  Only the
+// entries of the stored (upper) tiles are summed, so a wave's reads are
+// consecutive; an entry of a strictly upper tile is also written to its mirror.
 __global__ __launch_bounds__(1024) void gram_reduce2_kernel(const double* __restrict__ part, int64_t m, int nb,
                                                             int npairs, int nsplit, int64_t blk,
                                                             double* __restrict__ G) {
@@ -536,35 +538,39 @@ __global__ __launch_bounds__(1024) void gram_reduce2_kernel(const double* __rest
   const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int64_t e = (int64_t)blockIdx.x * 64 + l;
   double acc = 0.0;
+  bool stored = false, mirror = false;
+  int64_t i = 0, j = 0;
   if (e < m * m) {
-    int64_t i = e / m, j = e - (e / m) * m;
-    int bi = (int)(i / GB), bj = (int)(j / GB);
-    int li = (int)(i - (int64_t)bi * GB), lj = (int)(j - (int64_t)bj * GB);
-    if (bi > bj || (bi == bj && (li >> 4) > (lj >> 4))) {
-      int t = bi; bi = bj; bj = t;
-      t = li; li = lj; lj = t;
-    }
-    const int pair = bi * nb - bi * (bi - 1) / 2 + (bj - bi);
-    const int ld_out = (int)min<int64_t>(GB, m);
-    const int64_t off = (int64_t)pair * blk + li * ld_out + lj;
-    const int64_t stride = (int64_t)npairs * blk;
-    // eight independent loads in flight per thread, summed in a fixed order
-    int sp = g;
-    for (; sp + 7 * 16 < nsplit; sp += 8 * 16) {
-      double v[8];
+    i = e / m;
+    j = e - (e / m) * m;
+    const int bi = (int)(i / GB), bj = (int)(j / GB);
+    const int li = (int)(i - (int64_t)bi * GB), lj = (int)(j - (int64_t)bj * GB);
+    stored = bi < bj || (bi == bj && (li >> 4) <= (lj >> 4));
+    mirror = bi < bj || (bi == bj && (li >> 4) < (lj >> 4));
+    if (stored) {
+      const int pair = bi * nb - bi * (bi - 1) / 2 + (bj - bi);
+      const int ld_out = (int)min<int64_t>(GB, m);
+      const int64_t off = (int64_t)pair * blk + li * ld_out + lj;
+      const int64_t stride = (int64_t)npairs * blk;
+      // eight independent loads in flight per thread, summed in a fixed order
+      int sp = g;
+      for (; sp + 7 * 16 < nsplit; sp += 8 * 16) {
+        double v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(sp + 16 * q) * stride + off];
-      acc += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+        for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(sp + 16 * q) * stride + off];
+        acc += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+      }
+      for (; sp < nsplit; sp += 16) acc += part[(int64_t)sp * stride + off];
     }
-    for (; sp < nsplit; sp += 16) acc += part[(int64_t)sp * stride + off];
   }
   red[g][l] = acc;
   __syncthreads();
-  if (g == 0 && e < m * m) {
+  if (g == 0 && stored) {
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) s += red[q][l];
     G[e] = s;
+    if (mirror) G[j * m + i] = s;
   }
 }
 
@@ -1098,6 +1104,186 @@ __global__ __launch_bounds__(256) void gram_reg_kernel(const float* __restrict__
 }
 
 // --------------------------------------------------------------------------
+// FP64 Gram of an FP32 mode unfolding on register-direct blocks: G = M M^T, or
+// with RESID the residual Gram R R^T, R = M - U U^T M, the residual formed in
+// FP64 registers (FP64 accumulator register v of lane l is row l / 16 + 4 v of a
+// tile, so the rows of U are read in their natural order).  FP64 accumulators
+// for every upper tile would not fit a wave's registers, so the four waves of a
+// workgroup cooperate: each loads and projects one block, writes the residual of
+// one half (16 columns) to its LDS region, and after a barrier every wave
+// accumulates its own rows of upper tiles over all four regions.  The waves' tile
+// sets are disjoint, so each writes its tiles of the workgroup's FP64 partial
+// directly.
+// --------------------------------------------------------------------------
+constexpr int kGram64Ld = 17;  // row stride (doubles) of a wave's residual half in LDS
+
+// Owner wave of the upper tiles in row i of a TI x TI tile grid: whole rows, paired
+// so the waves get near-equal tile counts (8 rows: i with 7 - i, 9 tiles each; 6
+// rows: 6 | 5 + 1 | 4 + 2 | 3), and a wave reads each operand row once per k step.
+__host__ __device__ constexpr int gram64_owner(int TI, int i) {
+  return TI == 8 ? (i < 7 - i ? i : 7 - i) : (i < 4 ? i : TI - i);
+}
+__host__ __device__ constexpr int gram64_tiles(int TI, int W) {
+  int n = 0;
+  for (int i = 0; i < TI; ++i)
+    if (gram64_owner(TI, i) == W) n += TI - i;
+  return n;
+}
+__host__ __device__ constexpr int gram64_max_tiles(int TI) {
+  int n = 0;
+  for (int w = 0; w < 4; ++w) n = gram64_tiles(TI, w) > n ? gram64_tiles(TI, w) : n;
+  return n;
+}
+
+// wave W's tiles, accumulated over the four waves' residual halves in LDS
+template <int TI, int W, int NA>
+__device__ __forceinline__ void gram64_accumulate(const double* sRw, int wreg, int c16, int g4, d4 (&acc)[NA]) {
+  int lo = TI;
+  for (int i = TI - 1; i >= 0; --i)
+    if (gram64_owner(TI, i) == W) lo = i;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const double* rw = sRw + w * wreg;
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) {
+      double op[TI];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) op[i] = i >= lo ? rw[(16 * i + c16) * kGram64Ld + 4 * k4 + g4] : 0.0;
+      int q = 0;
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        if (gram64_owner(TI, i) == W) {
+#pragma unroll
+          for (int j = i; j < TI; ++j) {
+            acc[q] = mfma16(op[i], op[j], acc[q]);
+            ++q;
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int TI, int W, int NA>
+__device__ __forceinline__ void gram64_store(const d4 (&acc)[NA], int m, int c16, int g4, double* out) {
+  int q = 0;
+#pragma unroll
+  for (int i = 0; i < TI; ++i) {
+    if (gram64_owner(TI, i) == W) {
+#pragma unroll
+      for (int j = i; j < TI; ++j) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * i + g4 + 4 * v, col = 16 * j + c16;
+          if (row < m && col < m) out[row * m + col] = acc[q][v];
+        }
+        ++q;
+      }
+    }
+  }
+}
+
+template <int TI, int RT, bool RESID, int SL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SL == 0 && TI * RT <= 6 ? 2 : 1))) void gram_reg64_kernel(const float* __restrict__ X, int64_t P, int m, int64_t S,
+                                                         const double* __restrict__ U, int R,
+                                                         double* __restrict__ part) {
+  constexpr int NT = 4 * TI;
+  constexpr int ULD = 16 * RT + 1;
+  constexpr int NH = RegBlock<SL>::NH;
+  constexpr int WREG = 16 * TI * kGram64Ld;
+  extern __shared__ double sg64[];
+  double* sUd = sg64;                                  // U (RESID), 16 TI x ULD
+  double* sRw = sg64 + (RESID ? 16 * TI * ULD : 0);    // four residual halves
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g4 = lane >> 4, c16 = lane & 15;
+  if (RESID) {
+    for (int e = threadIdx.x; e < 16 * TI * ULD; e += 256) {
+      const int a = e / ULD, r = e - (e / ULD) * ULD;
+      sUd[e] = (a < m && r < R) ? U[a + (int64_t)r * m] : 0.0;
+    }
+  }
+  constexpr int NA = gram64_max_tiles(TI);
+  d4 acc[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) acc[u] = d4{0, 0, 0, 0};
+  double* myR = sRw + wave * WREG;
+  const int nblk = (int)RegBlock<SL>::blocks(P, S);
+  __syncthreads();
+  for (int g0 = blockIdx.x * 4; g0 < nblk; g0 += gridDim.x * 4) {  // uniform over the workgroup
+    const int blk = g0 + wave;
+    float x[NT][NH];
+    if (blk < nblk) {
+      RegBlock<SL> B;
+      B.setup(X, P, m, S, blk, g4, c16);
+      B.load(x, m);
+    } else {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) x[t][h] = 0.f;
+    }
+    d4 zz[RESID ? RT : 1][NH];
+    if (RESID) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        d4 c0[NH], c1[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) c0[h] = c1[h] = d4{0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < NT; t += 2) {
+          const double a0 = sUd[(4 * t + g4) * ULD + 16 * rt + c16];
+          const double a1 = sUd[(4 * t + 4 + g4) * ULD + 16 * rt + c16];
+#pragma unroll
+          for (int h = 0; h < NH; ++h) {
+            c0[h] = mfma16(a0, (double)x[t][h], c0[h]);
+            c1[h] = mfma16(a1, (double)x[t + 1][h], c1[h]);
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < NH; ++h) zz[rt][h] = c0[h] + c1[h];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      // this wave's residual half into its region: row 4 t + l / 16, column l % 16
+#pragma unroll
+      for (int it = 0; it < TI; ++it) {
+        d4 y = d4{0, 0, 0, 0};
+        if (RESID) {
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const double a = sUd[(16 * it + c16) * ULD + 16 * rt + 4 * v + g4];
+              y = mfma16(a, zz[rt][h][v], y);
+            }
+          }
+        }
+        // register v of the product is row 16 it + l / 16 + 4 v = the row of x[4 it + v]
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          myR[(16 * it + 4 * v + g4) * kGram64Ld + c16] = (double)x[4 * it + v][h] - y[v];
+      }
+      __syncthreads();
+      switch (wave) {
+        case 0: gram64_accumulate<TI, 0>(sRw, WREG, c16, g4, acc); break;
+        case 1: gram64_accumulate<TI, 1>(sRw, WREG, c16, g4, acc); break;
+        case 2: gram64_accumulate<TI, 2>(sRw, WREG, c16, g4, acc); break;
+        default: gram64_accumulate<TI, 3>(sRw, WREG, c16, g4, acc); break;
+      }
+      __syncthreads();
+    }
+  }
+  double* out = part + (int64_t)blockIdx.x * m * m;
+  switch (wave) {
+    case 0: gram64_store<TI, 0>(acc, m, c16, g4, out); break;
+    case 1: gram64_store<TI, 1>(acc, m, c16, g4, out); break;
+    case 2: gram64_store<TI, 2>(acc, m, c16, g4, out); break;
+    default: gram64_store<TI, 3>(acc, m, c16, g4, out); break;
+  }
+}
+
+// --------------------------------------------------------------------------
 // FP64 contraction Z = U^T X (FP32 or FP64 X) for the shapes of ttm_reg_kernel, on
 // FP64 matrix cores with operands straight from registers: the same blocks of 32
 // columns and the same loads (two adjacent columns per lane and row), U^T in LDS,
@@ -1608,6 +1794,12 @@ int reg_mode(Elem t, const ModeView& v, int R) {
   X(4, 1, 1) X(4, 2, 1) X(6, 1, 1) X(6, 2, 1) X(4, 1, 2) X(4, 2, 2) X(6, 1, 2) X(6, 2, 2)                 \
   X(4, 1, 3) X(4, 2, 3) X(6, 1, 3) X(6, 2, 3) X(4, 1, 4) X(4, 2, 4) X(6, 1, 4) X(6, 2, 4)
 #define HT_REG_KEY(TI, RT, SL) ((TI) * 64 + (RT) * 8 + (SL))
+// the FP64 Gram's cases: without 128 rows and more than 32 basis columns
+#define HT_REG64_CASES(X)                                                                              \
+  X(2, 1, 0) X(2, 2, 0) X(2, 3, 0) X(2, 4, 0) X(4, 1, 0) X(4, 2, 0) X(4, 3, 0) X(4, 4, 0)                 \
+  X(6, 1, 0) X(6, 2, 0) X(6, 3, 0) X(6, 4, 0) X(8, 1, 0) X(8, 2, 0)                                       \
+  X(4, 1, 1) X(4, 2, 1) X(6, 1, 1) X(6, 2, 1) X(4, 1, 2) X(4, 2, 2) X(6, 1, 2) X(6, 2, 2)                 \
+  X(4, 1, 3) X(4, 2, 3) X(6, 1, 3) X(6, 2, 3) X(4, 1, 4) X(4, 2, 4) X(6, 1, 4) X(6, 2, 4)
 
 int64_t reg_blocks(const ModeView& v, int mode) { return mode == 0 ? v.P * v.S / 32 : (v.P + 15) / 16; }
 
@@ -1640,6 +1832,46 @@ void gram_reg(const float* x, const ModeView& v, int mode, const double* U, int 
     break;
     switch (HT_REG_KEY(ti, rt, mode)) {
       HT_REG_CASES(HT_GR)
+      default: break;
+    }
+#undef HT_GR
+  }
+  GramPlan g;
+  g.nb = 1;
+  g.npairs = 1;
+  g.nsplit = blocks;
+  g.blk = v.m * v.m;
+  gram_finish(g, v, part, G, s);
+}
+
+// FP64 residual Gram through gram_reg64_kernel (R >= 1); at most 512 workgroup
+// partials.  The plain Gram keeps the panel kernel, which is faster without the
+// projection.
+void gram_reg64(const float* x, const ModeView& v, int mode, const double* U, int R, double* part, double* G,
+                hipStream_t s) {
+  const int ti = ((int)((v.m + 15) / 16) + 1) & ~1;
+  const int rt = R > 0 ? (R + 15) / 16 : 1;
+  const int64_t nblk = reg_blocks(v, mode);
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(512, (nblk + 3) / 4));
+  const size_t lds = ((R > 0 ? (size_t)16 * ti * (16 * rt + 1) : 0) + (size_t)4 * 16 * ti * kGram64Ld) * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+#define HT_GA(TI, RT, SL)                                                                           \
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_reg64_kernel<TI, RT, true, SL>),  \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    HT_REG64_CASES(HT_GA)
+#undef HT_GA
+    attr = true;
+  }
+  const double K = (double)v.P * v.S, md = (double)v.m;
+  {
+    ProfScope prof(KKind::Gram, s, md * md * K + 4.0 * R * md * K, md * K * 4);
+#define HT_GR(TI, RT, SL)                                                                                  \
+  case HT_REG_KEY(TI, RT, SL):                                                                             \
+    gram_reg64_kernel<TI, RT, true, SL><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, part);       \
+    break;
+    switch (HT_REG_KEY(ti, rt, mode)) {
+      HT_REG64_CASES(HT_GR)
       default: break;
     }
 #undef HT_GR
@@ -1686,6 +1918,11 @@ void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hip
 
 void resid_gram(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,
                 hipStream_t s) {
+  const int mode = reg_mode(t, v, R);
+  if (mode >= 0 && (v.m <= 96 || R <= 32)) {  // (128 rows with 48+ basis columns spill)
+    gram_reg64(static_cast<const float*>(x), v, mode, U, R, part, G, s);
+    return;
+  }
   const GramPlan g = gram_plan(v);
   const double K = (double)v.P * v.S, md = (double)v.m;
   // residual formation (4 R m flops per column) plus the symmetric product

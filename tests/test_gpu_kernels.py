@@ -27,7 +27,10 @@ def test_sumsq(n, dtype):
 
 
 GRAM_SHAPES = [(1, 1, 1), (3, 8, 1), (2, 9, 31), (6, 33, 32), (3, 96, 1000), (5, 3, 7), (100, 16, 1), (2, 200, 33), (1, 130, 40), (7, 17, 5),
-               (4, 256, 3), (9, 40, 64), (1, 300, 2)]
+               (4, 256, 3), (9, 40, 64), (1, 300, 2),
+               # register-direct blocks (FP32 input): runs in blocks of 32, and runs of 1-4 columns
+               (3, 96, 1024), (2, 128, 64), (5, 40, 96), (64, 12, 16384), (100, 96, 3), (37, 64, 1), (50, 48, 2),
+               (19, 96, 4)]
 
 
 @pytest.mark.parametrize("P,m,S", GRAM_SHAPES)
@@ -41,7 +44,9 @@ def test_gram(P, m, S, dtype):
 
 
 @pytest.mark.parametrize("P,m,S,R", [(3, 96, 1000, 12), (5, 9, 7, 3), (100, 16, 1, 5), (2, 128, 33, 64), (7, 17, 5, 1),
-                                     (4, 64, 300, 16), (50, 40, 2, 20), (1, 96, 31, 47)])
+                                     (4, 64, 300, 16), (50, 40, 2, 20), (1, 96, 31, 47),
+                                     (3, 96, 1024, 12), (2, 128, 64, 64), (5, 40, 96, 20), (2, 96, 288, 47),
+                                     (100, 96, 3, 14), (37, 64, 1, 5), (50, 48, 2, 20), (19, 96, 4, 32)])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_resid_gram(P, m, S, R, dtype):
     g = rng(P * 7 + m + S + R)
