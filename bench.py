@@ -50,7 +50,8 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 PEAK_HBM_GBS = 8000.0
 # profile kind -> arithmetic type of its products
 KIND_TYPE = {"gram": "f64", "ttm_contract": "f64", "ttm_expand": "f64", "sumsq": "f64", "gram_f32": "f32",
-             "ttm_contract_f32": "f32"}
+             "ttm_contract_f32": "f32", "gram_f32_reg": "f32", "ttm_contract_f32_reg": "f32", "gram_reg64": "f64",
+             "ttm_contract_reg64": "f64"}
 
 
 def log(*a):
@@ -253,10 +254,13 @@ def run_many(count=64, cap=1 << 20):
 # kernel-name patterns of each profile kind (the template's second argument is the
 # compute type of the panel kernels)
 KIND_KERNELS = {
-    "ttm_contract_f32": ("ttm_panel_kernel<float, float", "ttm_panel_kernel<double, float", "ttm_reg_kernel<"),
-    "ttm_contract": ("ttm_panel_kernel<float, double", "ttm_panel_kernel<double, double", "ttm_direct_kernel<",
-                     "ttm_reg64_kernel<"),
-    "gram_f32": ("gram_panel_kernel<float, float", "gram_panel_kernel<double, float", "gram_reg_kernel<"),
+    "ttm_contract_f32_reg": ("ttm_reg_kernel<",),
+    "gram_f32_reg": ("gram_reg_kernel<",),
+    "ttm_contract_reg64": ("ttm_reg64_kernel<",),
+    "gram_reg64": ("gram_reg64_kernel<",),
+    "ttm_contract_f32": ("ttm_panel_kernel<float, float", "ttm_panel_kernel<double, float"),
+    "ttm_contract": ("ttm_panel_kernel<float, double", "ttm_panel_kernel<double, double", "ttm_direct_kernel<"),
+    "gram_f32": ("gram_panel_kernel<float, float", "gram_panel_kernel<double, float"),
     "gram": ("gram_panel_kernel<float, double", "gram_panel_kernel<double, double", "gram_partial_kernel<",
              "gram_small_kernel<"),
     "ttm_expand": ("ttm_expand_kernel<",),

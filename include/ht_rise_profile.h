@@ -9,7 +9,10 @@
  * Kinds: 0 sum of squares, 1 unfolding Gram (FP64 matrix cores), 2 TTM contraction
  * (FP64), 3 TTM expansion / residual, 4 eigen-decomposition and truncation, 5 basis
  * expansion, 6 layout (padding, root append, copies), 7 residual Gram on FP32 matrix
- * cores, 8 TTM contraction on FP32 matrix cores (both of the HT_FP32 form).
+ * cores, 8 TTM contraction on FP32 matrix cores (both of the HT_FP32 form, LDS-staged
+ * panels), 9 and 10 the same two on register-direct blocks (mode views whose column
+ * runs come in blocks of 32 or runs of 1-4), 11 FP64 residual Gram and 12 FP64 TTM
+ * contraction on register-direct blocks.
  */
 #ifndef HT_RISE_PROFILE_H
 #define HT_RISE_PROFILE_H

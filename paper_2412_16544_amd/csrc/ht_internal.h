@@ -109,7 +109,10 @@ void fill_f64(double* dst, double v, int64_t n, hipStream_t s);
 
 namespace ht {
 // ---- optional per-kernel timing (include/ht_rise_profile.h) -----------------------
-enum class KKind : int { Sumsq = 0, Gram, TtmContract, TtmExpand, Eig, Orth, Layout, Gram32, TtmContract32, Count };
+enum class KKind : int {
+  Sumsq = 0, Gram, TtmContract, TtmExpand, Eig, Orth, Layout, Gram32, TtmContract32,
+  Gram32Reg, TtmContract32Reg, GramReg64, TtmContractReg64, Count
+};
 extern bool g_prof_on;
 void prof_begin(KKind k, hipStream_t s, double flops, double bytes);
 void prof_end(hipStream_t s);

@@ -1825,7 +1825,7 @@ void gram_reg(const float* x, const ModeView& v, int mode, const double* U, int 
   }
   const double K = (double)v.P * v.S, md = (double)v.m;
   {
-    ProfScope prof(KKind::Gram32, s, md * md * K + 4.0 * R * md * K, md * K * 4);
+    ProfScope prof(KKind::Gram32Reg, s, md * md * K + 4.0 * R * md * K, md * K * 4);
 #define HT_GR(TI, RT, SL)                                                                \
   case HT_REG_KEY(TI, RT, SL):                                                           \
     gram_reg_kernel<TI, RT, SL><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, part); \
@@ -1865,7 +1865,7 @@ void gram_reg64(const float* x, const ModeView& v, int mode, const double* U, in
   }
   const double K = (double)v.P * v.S, md = (double)v.m;
   {
-    ProfScope prof(KKind::Gram, s, md * md * K + 4.0 * R * md * K, md * K * 4);
+    ProfScope prof(KKind::GramReg64, s, md * md * K + 4.0 * R * md * K, md * K * 4);
 #define HT_GR(TI, RT, SL)                                                                                  \
   case HT_REG_KEY(TI, RT, SL):                                                                             \
     gram_reg64_kernel<TI, RT, true, SL><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, part);       \
@@ -2001,7 +2001,7 @@ void launch_ttm_reg64(const T* x, const ModeView& v, const double* U, int R, dou
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kTtmMaxBlocks, (nblk + 3) / 4));
   const size_t lds = (size_t)16 * ti * (16 * nrt + 1) * sizeof(double);
   {
-    ProfScope prof(KKind::TtmContract, s, fl, by);
+    ProfScope prof(KKind::TtmContractReg64, s, fl, by);
     switch (ti) {
       case 2: ttm_reg64_kernel<T, 2, NN><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part); break;
       case 4: ttm_reg64_kernel<T, 4, NN><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part); break;
@@ -2077,7 +2077,7 @@ void launch_ttm_reg(const float* x, const ModeView& v, int mode, const double* U
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kTtmMaxBlocks, (nblk + 3) / 4));
   const size_t lds = (size_t)16 * ti * (16 * rt + 1) * sizeof(float);
   {
-    ProfScope prof(KKind::TtmContract32, s, fl, by);
+    ProfScope prof(KKind::TtmContract32Reg, s, fl, by);
 #define HT_TR(TI, RT, SL)                                                                                    \
   case HT_REG_KEY(TI, RT, SL):                                                                               \
     ttm_reg_kernel<TI, RT, NN, RR, SL><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part, \

@@ -100,8 +100,10 @@ ht_status ht_profile_read(int32_t kind, ht_kernel_stats* out) {
 int32_t ht_profile_kind_count(void) { return (int32_t)ht::KKind::Count; }
 
 const char* ht_profile_kind_name(int32_t kind) {
-  static const char* names[] = {"sumsq",       "gram",   "ttm_contract", "ttm_expand",     "eig_trunc",
-                                "orth_expand", "layout", "gram_f32",     "ttm_contract_f32"};
+  static const char* names[] = {"sumsq",        "gram",         "ttm_contract",         "ttm_expand",
+                                "eig_trunc",    "orth_expand",  "layout",               "gram_f32",
+                                "ttm_contract_f32", "gram_f32_reg", "ttm_contract_f32_reg", "gram_reg64",
+                                "ttm_contract_reg64"};
   if (kind < 0 || kind >= (int)ht::KKind::Count) return "";
   return names[kind];
 }
