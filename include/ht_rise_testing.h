@@ -69,6 +69,14 @@ ht_status ht_test_ttm_expand(const double* Z, int64_t P, int32_t R, int64_t S, c
 size_t ht_test_eig_scratch_doubles(int32_t k, int32_t rmax);
 ht_status ht_test_eig(const double* G, int32_t k, int32_t rmin, int32_t rmax, double thr, double* evals,
                       double* vecs, int32_t* rank, double* tail, double* scratch, void* hip_stream);
+/* The same with the solver chosen: method 0 as ht_test_eig (a Lanczos decision where
+ * it can be proven, else Householder tridiagonalisation), 1 Householder only, 2
+ * Lanczos only (rank[0] = -1 when the decision could not be proven).  After the call
+ * scratch[ht_test_eig_scratch_doubles(k, rmax) - 56] holds the Lanczos steps taken
+ * (negative when the decision was not proven, 0 when the fast path was not tried). */
+ht_status ht_test_eig_method(const double* G, int32_t k, int32_t rmin, int32_t rmax, double thr, int32_t method,
+                             double* evals, double* vecs, int32_t* rank, double* tail, double* scratch,
+                             void* hip_stream);
 
 /* Basis expansion (Eq. concatenating_orthonormal_vectors): V (alpha x rR) is made
  * orthogonal to U_old (alpha x r_old) twice, orthonormalised by CholeskyQR twice,

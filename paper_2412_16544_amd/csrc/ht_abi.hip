@@ -489,7 +489,7 @@ void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initia
     j.k = alpha;
     j.rmin = initial ? 1 : 0;
     j.rmax = room;
-    j.pad = 0;
+    j.method = ht::kEigAuto;
     L.jobs.push_back(j);
     L.node.push_back(node);
     L.rold.push_back(r_old);

@@ -657,13 +657,56 @@ __device__ __forceinline__ void finish_tridiag(int k, const double* d, const dou
   __syncthreads();
 }
 
+// Isolates eigenvalue idx (ascending index) of the scaled tridiagonal by
+// multisection: the T lanes of a group evaluate Sturm counts at T interior points
+// of its interval and keep the sub-interval that holds it.  u is the lane's place
+// in its group, gbase the group's first lane in the wave.
+template <int T>
+__device__ __forceinline__ double multisect(const double* dn, const double* e2n, int k, const double* sh, int idx,
+                                            int u, int gbase) {
+  const double atol = 2.2e-16 * sh[2], sc = sh[3];
+  double lo = sh[0], hi = sh[1];  // invariant: count(lo) <= idx < count(hi)
+  for (int it = 0; it < 160; ++it) {
+    const bool done = hi - lo <= fmax(2.2e-16 * fmax(fabs(lo), fabs(hi)), atol);
+    if (__all(done)) break;
+    const double w = (hi - lo) / (double)(T + 1);
+    const double x = lo + w * (double)(u + 1);
+    bool above = false;
+    if (!done && x < hi && x > lo) {
+      bool tiny;
+      int cnt = sturm_fast(dn, e2n, k, x * sc, tiny);
+      if (tiny) cnt = sturm_scaled(dn, e2n, k, x * sc);
+      above = cnt > idx;
+    } else {
+      above = !done && x >= hi;
+    }
+    const unsigned long long msk = __ballot(above);
+    if (!done) {
+      const unsigned long long gm = (msk >> gbase) & ((1ull << T) - 1);
+      double nlo, nhi;
+      if (gm == 0) {
+        nlo = lo + w * (double)T;
+        nhi = hi;
+      } else {
+        const int us = __builtin_ctzll(gm);
+        nhi = lo + w * (double)(us + 1);
+        nlo = us > 0 ? lo + w * (double)us : lo;
+      }
+      if (nhi > hi) nhi = hi;
+      if (nlo < lo) nlo = lo;
+      lo = nlo;
+      hi = nhi;
+    }
+  }
+  return 0.5 * (lo + hi);
+}
+
 // ---- phases 2 and 3: the leading eigenvalues and the truncation rule.  The
 //      discarded energy of rank c is trace(T) minus the sum of the c leading
 //      eigenvalues (clipped at 0); eigenvalues are found in descending chunks (8,
-//      then 32 at a time) only until the rule is decided.  Each eigenvalue is
-//      isolated by multisection: 16 lanes of a wave evaluate Sturm counts at 16
-//      interior points of its interval and keep the sub-interval that holds it.
-//      top[m] receives the m-th largest eigenvalue; returns how many were found.
+//      then 32 at a time) only until the rule is decided, each by multisection
+//      over 16 lanes.  top[m] receives the m-th largest eigenvalue; returns how
+//      many were found.
 __device__ __forceinline__ int top_eigen_rank(const double* dn, const double* e2n, const double* d, int k,
                                               const double* sh, int rmin, int rmax, double thr, double* top,
                                               int* rank_out, double* tail_out, int* s_rank, double* s_acc) {
@@ -680,47 +723,13 @@ __device__ __forceinline__ int top_eigen_rank(const double* dn, const double* e2
   }
   __syncthreads();
   const int kmax = min(k, rmax);
-  const double atol = 2.2e-16 * sh[2], sc = sh[3];
   const int slot = tid / T, u = tid % T, gbase = lane - (lane % T);
   int m0 = 0, chunk = 8;
   for (;;) {
     const int m = m0 + slot;
     if (slot < chunk && m < k) {
-      const int idx = k - 1 - m;      // ascending index
-      double lo = sh[0], hi = sh[1];  // invariant: count(lo) <= idx < count(hi)
-      for (int it = 0; it < 160; ++it) {
-        const bool done = hi - lo <= fmax(2.2e-16 * fmax(fabs(lo), fabs(hi)), atol);
-        if (__all(done)) break;
-        const double w = (hi - lo) / (double)(T + 1);
-        const double x = lo + w * (double)(u + 1);
-        bool above = false;
-        if (!done && x < hi && x > lo) {
-          bool tiny;
-          int cnt = sturm_fast(dn, e2n, k, x * sc, tiny);
-          if (tiny) cnt = sturm_scaled(dn, e2n, k, x * sc);
-          above = cnt > idx;
-        } else {
-          above = !done && x >= hi;
-        }
-        const unsigned long long msk = __ballot(above);
-        if (!done) {
-          const unsigned long long gm = (msk >> gbase) & ((1ull << T) - 1);
-          double nlo, nhi;
-          if (gm == 0) {
-            nlo = lo + w * (double)T;
-            nhi = hi;
-          } else {
-            const int us = __builtin_ctzll(gm);
-            nhi = lo + w * (double)(us + 1);
-            nlo = us > 0 ? lo + w * (double)us : lo;
-          }
-          if (nhi > hi) nhi = hi;
-          if (nlo < lo) nlo = lo;
-          lo = nlo;
-          hi = nhi;
-        }
-      }
-      if (u == 0) top[m] = 0.5 * (lo + hi);
+      const double v = multisect<T>(dn, e2n, k, sh, k - 1 - m, u, gbase);
+      if (u == 0) top[m] = v;
     }
     __syncthreads();
     if (tid == 0) {
@@ -1041,6 +1050,279 @@ __device__ __forceinline__ EigScratch carve(const EigJob& J) {
 #define HT_EIG_MARK(i) \
   if (threadIdx.x == 0) c.clk[i] = (double)wall_clock64();
 
+// ---- fast path: Lanczos with a certified truncation decision ------------------------
+// The leading eigenpairs are taken from a Krylov space of G (fully
+// re-orthogonalised: two classical Gram-Schmidt passes per step) whenever the rank
+// decision can be proven from it; otherwise the Householder path above runs.  With
+// T_m = Q^T G Q (m x m tridiagonal, Ritz values theta_1 >= ... >= theta_m, s the
+// last row of its eigenvector matrix) and beta the norm of the next Krylov
+// direction:
+//   * tail(r) = trace(G) - (lambda_1 + ... + lambda_r) is at most
+//     trace(G) - (theta_1 + ... + theta_r), since Ritz sums bound eigenvalue sums
+//     from below (Ky Fan); this gives the smallest r that surely meets the budget;
+//   * the first j = r - 1 Ritz pairs couple to the rest of the space only through
+//     beta, with norm E = beta |s_{1..j}|, and the rest has eigenvalues below
+//     max(theta_{j+1}, trace(G) - trace(T_m)) + beta |s_{j+1..m}| (G is positive
+//     semidefinite, so the unexplored part's largest eigenvalue is at most its
+//     trace); with delta = theta_j minus that bound, lambda_i <= theta_i + E^2 /
+//     delta for i <= j (quadratic residual bound of a 2 x 2 block partition), so
+//     tail(j) > thr is proven when trace(G) - sum_{i<=j} theta_i - j E^2 / delta
+//     exceeds it.
+// Both comparisons keep a margin of 64 k eps trace(G) for rounding (E is taken
+// twice as large), the kept Ritz values must be separated by more than
+// 1e-10 theta_1 and each kept pair's residual beta |s_i| must stay below
+// 1e-13 theta_1; otherwise the decision is left to the Householder path.
+constexpr int kLzSteps = 64;   // Krylov dimension limit
+constexpr int kLzMinK = 40;    // smaller problems go straight to the Householder path
+constexpr int kLzLdsK = 224;   // the Krylov basis sits in LDS up to this k, beyond in global scratch
+constexpr int kLzMaxK = 1024;  // larger problems go straight to the Householder path
+
+typedef __attribute__((address_space(1))) const double cgdouble;
+
+__device__ __forceinline__ bool lz_check_at(int m) {
+  return m == 4 || m == 8 || m == 12 || m == 14 || (m >= 16 && (m & 3) == 0);
+}
+
+// every eigenvalue of an m x m tridiagonal (m <= 64), descending
+__device__ __forceinline__ void tridiag_values(const double* dn, const double* e2n, int m, const double* sh,
+                                               double* top) {
+  constexpr int T = 16;
+  const int tid = threadIdx.x, lane = tid & 63, slot = tid / T, u = tid % T, gbase = lane - (lane % T);
+  for (int m0 = 0; m0 < m; m0 += ET / T) {
+    const int q = m0 + slot;
+    if (q < m) {
+      const double v = multisect<T>(dn, e2n, m, sh, m - 1 - q, u, gbase);
+      if (u == 0) top[q] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// Returns true when the decision and its eigenpairs are written; false leaves the
+// outputs untouched.  The last 64 doubles of the scratch record the attempt:
+// [8] = steps (negative when the decision was not proven), [9] = checks.
+template <bool QL>
+__device__ __noinline__ bool lanczos_solve(const EigJob& J, double* lds, double* sh, double* red, int* ctl) {
+  const EigScratch c = carve(J);
+  const int k = J.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  cgdouble* G = reinterpret_cast<cgdouble*>(reinterpret_cast<uintptr_t>(J.G));
+  const int mlim = min(k, kLzSteps);
+  double* Q = QL ? lds : c.hv;  // Krylov vector v at Q + v k
+  double* wv = lds + (QL ? (kLzSteps + 1) * k : 0);
+  double* qv = wv + k;      // the vector the product reads (a copy when Q is global)
+  double* part = qv + k;    // 512 partial sums of the product
+  double* hc = part + 512;  // projection coefficients
+  double* al = hc + kLzSteps;
+  double* be = al + kLzSteps;
+  double* e2 = be + kLzSteps;
+  double* dn = e2 + kLzSteps;
+  double* e2n = dn + kLzSteps;
+  double* top = e2n + kLzSteps;
+  double* pb = top + kLzSteps;
+  double* free_lds = pb + kLzSteps;
+  const int64_t free_cap = kLdsDoubles - (int64_t)(free_lds - lds);
+
+  double t = 0.0;
+  for (int i = tid; i < k; i += ET) t += G[(size_t)i * k + i];
+  const double tr = bsum(t, red);
+  if (!(tr > 0.0) || !(tr < DBL_MAX)) return false;
+  const double guard = 64.0 * k * DBL_EPSILON * tr;
+
+  // fixed pseudo-random start
+  double loc = 0.0;
+  for (int i = tid; i < k; i += ET) {
+    const double v = start_entry(kMaxEigJobs + 7, i) - 1.0;
+    wv[i] = v;
+    loc = fma(v, v, loc);
+  }
+  const double inv0 = 1.0 / sqrt(bsum(loc, red));
+  for (int i = tid; i < k; i += ET) {
+    const double v = wv[i] * inv0;
+    Q[i] = v;
+    qv[i] = v;
+  }
+  __syncthreads();
+
+  int checks = 0;
+  for (int m = 1; m <= mlim; ++m) {
+    const double* qs = QL ? Q + (size_t)(m - 1) * k : qv;
+    // w = G q_{m-1}; G is symmetric, so thread i walks column i (coalesced rows)
+    if (k <= 256) {
+      const int i = tid & 255, h = tid >> 8;
+      const int l0 = h ? (k >> 1) : 0, l1 = h ? k : (k >> 1);
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      if (i < k) {
+        int l = l0;
+        for (; l + 4 <= l1; l += 4) {
+          a0 = fma(G[(size_t)l * k + i], qs[l], a0);
+          a1 = fma(G[(size_t)(l + 1) * k + i], qs[l + 1], a1);
+          a2 = fma(G[(size_t)(l + 2) * k + i], qs[l + 2], a2);
+          a3 = fma(G[(size_t)(l + 3) * k + i], qs[l + 3], a3);
+        }
+        for (; l < l1; ++l) a0 = fma(G[(size_t)l * k + i], qs[l], a0);
+      }
+      part[tid] = (a0 + a1) + (a2 + a3);
+      __syncthreads();
+      if (tid < k) wv[tid] = part[tid] + part[256 + tid];
+    } else {
+      for (int i = tid; i < k; i += ET) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int l = 0;
+        for (; l + 4 <= k; l += 4) {
+          a0 = fma(G[(size_t)l * k + i], qs[l], a0);
+          a1 = fma(G[(size_t)(l + 1) * k + i], qs[l + 1], a1);
+          a2 = fma(G[(size_t)(l + 2) * k + i], qs[l + 2], a2);
+          a3 = fma(G[(size_t)(l + 3) * k + i], qs[l + 3], a3);
+        }
+        for (; l < k; ++l) a0 = fma(G[(size_t)l * k + i], qs[l], a0);
+        wv[i] = (a0 + a1) + (a2 + a3);
+      }
+    }
+    __syncthreads();
+    // two classical Gram-Schmidt passes against q_0 .. q_{m-1}; the coefficients
+    // on q_{m-1} add up to the diagonal entry of T
+    for (int pass = 0; pass < 2; ++pass) {
+      {
+        const int cc = tid >> 3, p = tid & 7;
+        double s = 0.0;
+        if (cc < m) {
+          const double* qc = Q + (size_t)cc * k;
+          for (int i = p; i < k; i += 8) s = fma(qc[i], wv[i], s);
+        }
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 4);
+        if (p == 0 && cc < m) hc[cc] = s;
+      }
+      __syncthreads();
+      if (tid == 0) al[m - 1] = pass ? al[m - 1] + hc[m - 1] : hc[m - 1];
+      for (int i = tid; i < k; i += ET) {
+        double v = wv[i];
+        for (int cc = 0; cc < m; ++cc) v = fma(-Q[(size_t)cc * k + i], hc[cc], v);
+        wv[i] = v;
+      }
+      __syncthreads();
+    }
+    double l2 = 0.0;
+    for (int i = tid; i < k; i += ET) l2 = fma(wv[i], wv[i], l2);
+    const double beta = sqrt(bsum(l2, red));
+    const bool brk = !(beta > 1e-14 * tr);  // the Krylov space is (numerically) invariant
+    if (tid == 0) be[m - 1] = beta;
+    if (brk || m == mlim || lz_check_at(m)) {
+      __syncthreads();
+      ++checks;
+      // T_m: diagonal al, off-diagonal be[0 .. m-2]; be[m-1] is the coupling beta
+      finish_tridiag(m, al, be, e2, dn, e2n, sh);
+      tridiag_values(dn, e2n, m, sh, top);
+      if (tid == 0) {
+        double tsum = 0.0;
+        for (int i = 0; i < m; ++i) tsum += al[i];
+        const int rlim = min(J.rmax, m);
+        double S = 0.0;
+        int rh = -1;
+        for (int r = 0; r <= rlim; ++r) {
+          if (r >= J.rmin && tr - S <= J.thr - guard) {
+            rh = r;
+            break;
+          }
+          if (r < rlim) S += top[r];
+        }
+        ctl[0] = rh;
+        sh[4] = tsum;
+      }
+      __syncthreads();
+      const int rh = ctl[0];
+      bool done = false;
+      if (rh == 0) {
+        if (tid == 0) {
+          *J.rank = 0;
+          *J.tail = tr;
+        }
+        done = true;
+      } else if (rh > 0) {
+        double* Z = (int64_t)4 * m * rh <= free_cap ? free_lds : c.gz;
+        inverse_iteration(Z, m, rh, top, al, be, sh[2]);  // Z[i rh + j], ends with a barrier
+        if (tid < 64 && lane < rh) {
+          double n2 = 0.0;
+          for (int i = 0; i < m; ++i) n2 = fma(Z[(size_t)i * rh + lane], Z[(size_t)i * rh + lane], n2);
+          pb[lane] = Z[(size_t)(m - 1) * rh + lane] / sqrt(n2);
+        }
+        __syncthreads();
+        if (tid == 0) {
+          const double th1 = top[0];
+          bool ok = th1 > 0.0;
+          const int nv = min(rh + 1, m);
+          for (int i = 0; i + 1 < nv; ++i) ok = ok && (top[i] - top[i + 1] > 1e-10 * th1);
+          for (int i = 0; i < rh; ++i) ok = ok && (beta * fabs(pb[i]) <= 1e-13 * th1);
+          const int jj = rh - 1;
+          if (ok && jj >= J.rmin) {
+            double lb = tr;
+            if (jj > 0) {
+              double s2 = 0.0, sj = 0.0;
+              for (int i = 0; i < jj; ++i) {
+                s2 = fma(pb[i], pb[i], s2);
+                sj += top[i];
+              }
+              const double e2b = 4.0 * beta * beta * s2;
+              const double tperp = fmax(tr - sh[4], 0.0);
+              const double lam_c = fmax(jj < m ? top[jj] : 0.0, tperp) + beta * sqrt(fmax(0.0, 1.0 - s2));
+              const double dl = top[jj - 1] - lam_c;
+              lb = dl > 0.0 ? tr - sj - (double)jj * e2b / dl : -DBL_MAX;
+            }
+            ok = lb > J.thr + guard;
+          }
+          ctl[1] = ok ? 1 : 0;
+        }
+        __syncthreads();
+        if (ctl[1]) {
+          cgs2_columns(Z, m, rh, pb, red);
+          // Ritz vectors Q z_j, one wave per vector, then the sign rule
+          for (int j = wave; j < rh; j += NW) {
+            double best = -1.0, at = 0.0;
+            int bidx = 0;
+            for (int i = lane; i < k; i += 64) {
+              double y = 0.0;
+              for (int q = 0; q < m; ++q) y = fma(Q[(size_t)q * k + i], Z[(size_t)q * rh + j], y);
+              J.vecs[(size_t)j * k + i] = y;
+              if (fabs(y) > best) {
+                best = fabs(y);
+                bidx = i;
+                at = y;
+              }
+            }
+            const double sg = sign_factor(best, bidx, at);
+            if (sg < 0.0)
+              for (int i = lane; i < k; i += 64) J.vecs[(size_t)j * k + i] = -J.vecs[(size_t)j * k + i];
+          }
+          for (int i = tid; i < rh; i += ET) J.evals[i] = top[i];
+          if (tid == 0) {
+            double S = 0.0;
+            for (int i = 0; i < rh; ++i) S += top[i];
+            *J.rank = rh;
+            *J.tail = fmax(tr - S, 0.0);
+          }
+          done = true;
+        }
+      }
+      if (done || brk || m == mlim) {
+        if (tid == 0) {
+          c.clk[8] = done ? m : -m;
+          c.clk[9] = checks;
+        }
+        return done;
+      }
+    }
+    const double ib = 1.0 / beta;
+    for (int i = tid; i < k; i += ET) {
+      const double v = wv[i] * ib;
+      Q[(size_t)m * k + i] = v;
+      if (!QL) qv[i] = v;
+    }
+    __syncthreads();
+  }
+  return false;
+}
+
 // LDS of the register path (doubles): d, e, e2, tau, dn, e2n, top, xb, cb, vbuf,
 // pbuf (256 each), then one region shared by the row and column partials (phase
 // 1), the inverse-iteration arrays (4a, 4b) and the reflector staging (4c).
@@ -1163,7 +1445,9 @@ __global__ __launch_bounds__(ET) void eig_trunc_kernel(EigBatch batch) {
   __shared__ double red[NW];
   __shared__ double sh[8];
   __shared__ int s_rank;
+  __shared__ int lz_ctl[2];
   const int k = J.k, tid = threadIdx.x;
+  if (tid == 0) c.clk[8] = 0.0;
 
   // all the energy already within the budget and no rank floor: the rule keeps
   // nothing (tail(0) = trace <= thr), so the decomposition is not needed
@@ -1178,6 +1462,16 @@ __global__ __launch_bounds__(ET) void eig_trunc_kernel(EigBatch batch) {
       }
       return;
     }
+  }
+  if (J.method != kEigHouseholder && k >= kLzMinK && k <= kLzMaxK && J.rmax > 0) {
+    const bool done = k <= kLzLdsK ? lanczos_solve<true>(J, lds, sh, red, lz_ctl)
+                                   : lanczos_solve<false>(J, lds, sh, red, lz_ctl);
+    if (done) return;
+    if (J.method == kEigLanczos) {
+      if (tid == 0) *J.rank = -1;
+      return;
+    }
+    __syncthreads();
   }
   if constexpr (SMALL_LDS) {
     if (k <= 16 * kRegRowTiles) {

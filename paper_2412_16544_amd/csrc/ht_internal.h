@@ -76,8 +76,11 @@ struct EigJob {
   int k;
   int rmin;
   int rmax;
-  int pad;
+  int method;          // kEigAuto, or (testing) kEigHouseholder / kEigLanczos alone
 };
+// kEigAuto: the certified Lanczos decision where it can be proven, else the
+// Householder path; kEigLanczos reports an unproven decision as rank -1.
+constexpr int kEigAuto = 0, kEigHouseholder = 1, kEigLanczos = 2;
 constexpr int kMaxEigJobs = 32;
 size_t eig_scratch_doubles(int k, int rmax);
 // Runs up to kMaxEigJobs independent problems in one launch (one workgroup each).

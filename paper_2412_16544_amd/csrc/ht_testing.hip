@@ -82,10 +82,10 @@ size_t ht_test_eig_scratch_doubles(int32_t k, int32_t rmax) {
   return ht::eig_scratch_doubles(k, rmax > 0 ? rmax : 1);
 }
 
-ht_status ht_test_eig(const double* G, int32_t k, int32_t rmin, int32_t rmax, double thr, double* evals, double* vecs,
-                      int32_t* rank, double* tail, double* scratch, void* s) {
+ht_status ht_test_eig_method(const double* G, int32_t k, int32_t rmin, int32_t rmax, double thr, int32_t method,
+                             double* evals, double* vecs, int32_t* rank, double* tail, double* scratch, void* s) {
   if (!G || !evals || !vecs || !rank || !tail || !scratch || k < 1 || k > 4096 || rmin < 0 || rmax < rmin ||
-      rmax > k)
+      rmax > k || method < ht::kEigAuto || method > ht::kEigLanczos)
     return HT_EINVAL;
   ht::EigJob j;
   j.G = G;
@@ -97,11 +97,15 @@ ht_status ht_test_eig(const double* G, int32_t k, int32_t rmin, int32_t rmax, do
   j.thr = thr;
   j.k = k;
   j.rmin = rmin;
-  j.rmax = rmax > 0 ? rmax : 1;
-  j.pad = 0;
-  if (rmax == 0) j.rmax = 0;
+  j.rmax = rmax;
+  j.method = method;
   ht::eig_trunc(&j, 1, st(s));
   return hipGetLastError() == hipSuccess ? HT_OK : HT_EDEVICE;
+}
+
+ht_status ht_test_eig(const double* G, int32_t k, int32_t rmin, int32_t rmax, double thr, double* evals, double* vecs,
+                      int32_t* rank, double* tail, double* scratch, void* s) {
+  return ht_test_eig_method(G, k, rmin, rmax, thr, ht::kEigAuto, evals, vecs, rank, tail, scratch, s);
 }
 
 ht_status ht_test_orth_expand(const double* U_old, int64_t alpha, int32_t r_old, double* V, int32_t rR, double* core,

@@ -286,10 +286,11 @@ def _tlib():
         L.ht_test_eig_scratch_doubles.argtypes = [i32, i32]
         L.ht_test_eig_scratch_doubles.restype = sz
         L.ht_test_eig.argtypes = [vp, i32, i32, i32, dbl, vp, vp, vp, vp, vp, vp]
+        L.ht_test_eig_method.argtypes = [vp, i32, i32, i32, dbl, i32, vp, vp, vp, vp, vp, vp]
         L.ht_test_orth_expand.argtypes = [vp, i64, i32, vp, i32, vp, vp]
         for name in ("ht_test_sumsq", "ht_test_gram", "ht_test_resid_gram", "ht_test_resid_gram_f32",
                      "ht_test_ttm_contract", "ht_test_ttm_contract_f32", "ht_test_ttm_expand", "ht_test_eig",
-                     "ht_test_orth_expand"):
+                     "ht_test_eig_method", "ht_test_orth_expand"):
             getattr(L, name).restype = ctypes.c_int
         L._ht_testing_ready = True
     return L
@@ -377,7 +378,12 @@ def ht_test_ttm_expand(Z, U, M=None, out_dtype=None, stream=None):
     return out
 
 
-def ht_test_eig(G, rmin: int, rmax: int, thr: float, stream=None):
+EIG_AUTO, EIG_HOUSEHOLDER, EIG_LANCZOS = 0, 1, 2
+
+
+def ht_test_eig(G, rmin: int, rmax: int, thr: float, stream=None, method: int = EIG_AUTO, info: bool = False):
+    """Eigen-decomposition with the truncation rule (ht_test_eig_method).  Returns
+    (evals, vecs, rank, tail), plus the Lanczos step count when info is set."""
     import torch
     k = G.shape[0]
     L = _tlib()
@@ -386,11 +392,14 @@ def ht_test_eig(G, rmin: int, rmax: int, thr: float, stream=None):
     vecs = torch.zeros((max(rmax, 1), k), dtype=torch.float64, device=G.device)
     rank = torch.zeros(1, dtype=torch.int32, device=G.device)
     tail = torch.zeros(1, dtype=torch.float64, device=G.device)
-    _check(L.ht_test_eig(_ptr(G.contiguous()), k, rmin, rmax, float(thr), _ptr(ev), _ptr(vecs), _ptr(rank),
-                         _ptr(tail), _ptr(sc), _stream(stream)), "ht_test_eig")
+    _check(L.ht_test_eig_method(_ptr(G.contiguous()), k, rmin, rmax, float(thr), int(method), _ptr(ev), _ptr(vecs),
+                                _ptr(rank), _ptr(tail), _ptr(sc), _stream(stream)), "ht_test_eig_method")
     torch.cuda.synchronize()
     r = int(rank.item())
-    return ev, vecs[:r].t(), r, float(tail.item())
+    out = (ev, vecs[:max(r, 0)].t(), r, float(tail.item()))
+    if info:
+        return out + (int(sc[-56].item()),)
+    return out
 
 
 def ht_test_orth_expand(U_old, V, stream=None):
