@@ -660,10 +660,12 @@ __device__ __forceinline__ void finish_tridiag(int k, const double* d, const dou
 // Isolates eigenvalue idx (ascending index) of the scaled tridiagonal by
 // multisection: the T lanes of a group evaluate Sturm counts at T interior points
 // of its interval and keep the sub-interval that holds it.  u is the lane's place
-// in its group, gbase the group's first lane in the wave.
-template <int T>
-__device__ __forceinline__ double multisect(const double* dn, const double* e2n, int k, const double* sh, int idx,
-                                            int u, int gbase) {
+// in its group, gbase the group's first lane in the wave; fast(x, tiny) counts
+// (raising tiny when a pivot fell below the floor) and scaled(x) is the careful
+// count that then replaces it.
+template <int T, class Fast, class Scaled>
+__device__ __forceinline__ double multisect_by(Fast fast, Scaled scaled, const double* sh, int idx, int u,
+                                               int gbase) {
   const double atol = 2.2e-16 * sh[2], sc = sh[3];
   double lo = sh[0], hi = sh[1];  // invariant: count(lo) <= idx < count(hi)
   for (int it = 0; it < 160; ++it) {
@@ -674,8 +676,8 @@ __device__ __forceinline__ double multisect(const double* dn, const double* e2n,
     bool above = false;
     if (!done && x < hi && x > lo) {
       bool tiny;
-      int cnt = sturm_fast(dn, e2n, k, x * sc, tiny);
-      if (tiny) cnt = sturm_scaled(dn, e2n, k, x * sc);
+      int cnt = fast(x * sc, tiny);
+      if (tiny) cnt = scaled(x * sc);
       above = cnt > idx;
     } else {
       above = !done && x >= hi;
@@ -699,6 +701,13 @@ __device__ __forceinline__ double multisect(const double* dn, const double* e2n,
     }
   }
   return 0.5 * (lo + hi);
+}
+
+template <int T>
+__device__ __forceinline__ double multisect(const double* dn, const double* e2n, int k, const double* sh, int idx,
+                                            int u, int gbase) {
+  return multisect_by<T>([&](double x, bool& tiny) { return sturm_fast(dn, e2n, k, x, tiny); },
+                         [&](double x) { return sturm_scaled(dn, e2n, k, x); }, sh, idx, u, gbase);
 }
 
 // ---- phases 2 and 3: the leading eigenvalues and the truncation rule.  The
@@ -1079,47 +1088,289 @@ constexpr int kLzMaxK = 1024;  // larger problems go straight to the Householder
 
 typedef __attribute__((address_space(1))) const double cgdouble;
 
-__device__ __forceinline__ bool lz_check_at(int m) {
-  return m == 4 || m == 8 || m == 12 || m == 14 || (m >= 16 && (m & 3) == 0);
+// steps at which the decision is checked (and at an invariant Krylov space)
+__device__ __forceinline__ bool lz_check_at(int m) { return m >= 6 && (m - 6) % 4 == 0; }
+
+constexpr int kLzPad = 72;  // length of the padded scaled copy of T_m
+
+// The Sturm count of sturm_fast on a copy of the (padded) tridiagonal held in
+// registers: d[i] the scaled diagonal, f[i] the squared scaled off-diagonal
+// entry above row i (f[0] = 0); the pair is rescaled every eight steps.
+template <int N>
+__device__ __forceinline__ int sturm_regs(const double (&d)[N], const double (&f)[N], double x, bool& tiny) {
+  double p1 = 1.0, p2 = 0.0;
+  int cnt = 0;
+  bool t = false;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double fl = DBL_MIN * fabs(p1);
+    const double p = fma(d[i] - x, p1, -(f[i] * p2));
+    t |= !(fabs(p) >= fl) | (p == 0.0);
+    cnt += (__double2hiint(p) ^ __double2hiint(p1)) < 0 ? 1 : 0;
+    p2 = p1;
+    p1 = p;
+    if ((i & 7) == 0) {
+      const int ex = __builtin_amdgcn_frexp_exp(p1);
+      p1 = __builtin_amdgcn_ldexp(p1, -ex);
+      p2 = __builtin_amdgcn_ldexp(p2, -ex);
+    }
+  }
+  tiny = t;
+  return cnt;
 }
 
-// every eigenvalue of an m x m tridiagonal (m <= 64), descending
-__device__ __forceinline__ void tridiag_values(const double* dn, const double* e2n, int m, const double* sh,
-                                               double* top) {
+// every eigenvalue of the (padded, length N) scaled tridiagonal, descending, the
+// counts on register copies
+template <int N>
+__device__ __forceinline__ void tridiag_values_regs(const double* dn, const double* e2n, int m, const double* sh,
+                                                    double* top) {
   constexpr int T = 16;
   const int tid = threadIdx.x, lane = tid & 63, slot = tid / T, u = tid % T, gbase = lane - (lane % T);
+  double d[N], f[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    d[i] = dn[i];
+    f[i] = i ? e2n[i - 1] : 0.0;
+  }
   for (int m0 = 0; m0 < m; m0 += ET / T) {
     const int q = m0 + slot;
     if (q < m) {
-      const double v = multisect<T>(dn, e2n, m, sh, m - 1 - q, u, gbase);
+      const double v = multisect_by<T>([&](double x, bool& tiny) { return sturm_regs<N>(d, f, x, tiny); },
+                                       [&](double x) { return sturm_scaled(dn, e2n, N, x); }, sh, m - 1 - q, u,
+                                       gbase);
       if (u == 0) top[q] = v;
+    }
+  }
+}
+
+// every eigenvalue of an m x m tridiagonal (m <= 64), descending.  The scaled copy
+// (dn, e2n) is padded to M entries with decoupled diagonal entries 4 > |T| /
+// scale, which add no Sturm count below any point of the search interval; up to
+// 33 entries the counts run on register copies, beyond in the prefetching blocks
+// of eight of sturm_fast (M = 1 + 8 ceil((m - 1) / 8)).
+__device__ __forceinline__ void tridiag_values(double* dn, double* e2n, int m, const double* sh, double* top) {
+  constexpr int T = 16;
+  const int tid = threadIdx.x, lane = tid & 63, slot = tid / T, u = tid % T, gbase = lane - (lane % T);
+  const int M = m <= 17 ? 17 : m <= 33 ? 33 : 1 + 8 * ((m + 6) / 8);
+  for (int i = m + tid; i < M; i += ET) {
+    dn[i] = 4.0;
+    e2n[i] = 0.0;
+  }
+  __syncthreads();
+  if (m <= 17) {
+    tridiag_values_regs<17>(dn, e2n, m, sh, top);
+  } else if (m <= 33) {
+    tridiag_values_regs<33>(dn, e2n, m, sh, top);
+  } else {
+    for (int m0 = 0; m0 < m; m0 += ET / T) {
+      const int q = m0 + slot;
+      if (q < m) {
+        const double v = multisect<T>(dn, e2n, M, sh, m - 1 - q, u, gbase);
+        if (u == 0) top[q] = v;
+      }
     }
   }
   __syncthreads();
 }
 
+// Orthonormalises the r columns of the m x r block Z (Z[i r + j], m <= 64) in
+// order with two classical Gram-Schmidt passes, on one wave (lane = row).
+__device__ __forceinline__ void cgs2_wave(double* Z, int m, int r) {
+  const int lane = threadIdx.x & 63;
+  const bool row = lane < m;
+  for (int j = 0; j < r; ++j) {
+    double z = row ? Z[(size_t)lane * r + j] : 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      double acc = 0.0;
+      for (int t = 0; t < j; ++t) {
+        const double zt = row ? Z[(size_t)lane * r + t] : 0.0;
+        acc = fma(zt, dpp_wave_sum(zt * z), acc);
+      }
+      z -= acc;
+    }
+    const double nrm = sqrt(dpp_wave_sum(z * z));
+    z = nrm > 0.0 ? z / nrm : 0.0;
+    if (row) Z[(size_t)lane * r + j] = z;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Buffers of the Lanczos solve used by the certification.
+struct LzView {
+  double* Q;
+  double* al;
+  double* be;
+  double* e2;
+  double* dn;
+  double* e2n;
+  double* top;
+  double* pb;
+  double* free_lds;
+  int64_t free_cap;
+};
+
+// The check at step m (kept out of line, so the solve's own registers need not
+// survive its code): returns true when the decision is proven and written.
+__device__ __noinline__ bool lz_certify(const EigJob& J, const LzView& v, int m, double beta, double tr, double guard,
+                                        double* sh, double* red, int* ctl) {
+  const EigScratch c = carve(J);
+  const int k = J.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* Q = v.Q;
+  double* al = v.al;
+  double* be = v.be;
+  double* e2 = v.e2;
+  double* dn = v.dn;
+  double* e2n = v.e2n;
+  double* top = v.top;
+  double* pb = v.pb;
+  double* free_lds = v.free_lds;
+  const int64_t free_cap = v.free_cap;
+  // T_m: diagonal al, off-diagonal be[0 .. m-2]; be[m-1] is the coupling beta
+  finish_tridiag(m, al, be, e2, dn, e2n, sh);
+  tridiag_values(dn, e2n, m, sh, top);
+  if (tid == 0) {
+    double tsum = 0.0;
+    for (int i = 0; i < m; ++i) tsum += al[i];
+    const int rlim = min(J.rmax, m);
+    double S = 0.0;
+    int rh = -1;
+    for (int r = 0; r <= rlim; ++r) {
+      if (r >= J.rmin && tr - S <= J.thr - guard) {
+        rh = r;
+        break;
+      }
+      if (r < rlim) S += top[r];
+    }
+    ctl[0] = rh;
+    sh[4] = tsum;
+  }
+  __syncthreads();
+  const int rh = ctl[0];
+  bool done = false;
+  if (rh > 0 && tid == 0) {
+    // the certificate without the eigenvector components, with E = 0: when even
+    // this fails (or the kept values are not separated) the check stops here
+    const double th1 = top[0];
+    bool ok = th1 > 0.0;
+    const int nv = min(rh + 1, m);
+    for (int i = 0; i + 1 < nv; ++i) ok = ok && (top[i] - top[i + 1] > 1e-10 * th1);
+    const int jj = rh - 1;
+    if (ok && jj >= J.rmin && jj > 0) {
+      double sj = 0.0;
+      for (int i = 0; i < jj; ++i) sj += top[i];
+      const double tperp = fmax(tr - sh[4], 0.0);
+      ok = top[jj - 1] > fmax(jj < m ? top[jj] : 0.0, tperp) && tr - sj > J.thr + guard;
+    }
+    ctl[1] = ok ? 1 : 0;
+  }
+  __syncthreads();
+  if (rh > 0 && !ctl[1]) return false;
+  if (rh == 0) {
+    if (tid == 0) {
+      *J.rank = 0;
+      *J.tail = tr;
+    }
+    done = true;
+  } else if (rh > 0) {
+    double* Z = (int64_t)4 * m * rh <= free_cap ? free_lds : c.gz;
+    inverse_iteration(Z, m, rh, top, al, be, sh[2]);  // Z[i rh + j], ends with a barrier
+    if (tid < 64 && lane < rh) {
+      double n2 = 0.0;
+      for (int i = 0; i < m; ++i) n2 = fma(Z[(size_t)i * rh + lane], Z[(size_t)i * rh + lane], n2);
+      pb[lane] = Z[(size_t)(m - 1) * rh + lane] / sqrt(n2);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double th1 = top[0];
+      bool ok = th1 > 0.0;
+      const int nv = min(rh + 1, m);
+      for (int i = 0; i + 1 < nv; ++i) ok = ok && (top[i] - top[i + 1] > 1e-10 * th1);
+      for (int i = 0; i < rh; ++i) ok = ok && (beta * fabs(pb[i]) <= 1e-13 * th1);
+      const int jj = rh - 1;
+      if (ok && jj >= J.rmin) {
+        double lb = tr;
+        if (jj > 0) {
+          double s2 = 0.0, sj = 0.0;
+          for (int i = 0; i < jj; ++i) {
+            s2 = fma(pb[i], pb[i], s2);
+            sj += top[i];
+          }
+          const double e2b = 4.0 * beta * beta * s2;
+          const double tperp = fmax(tr - sh[4], 0.0);
+          const double lam_c = fmax(jj < m ? top[jj] : 0.0, tperp) + beta * sqrt(fmax(0.0, 1.0 - s2));
+          const double dl = top[jj - 1] - lam_c;
+          lb = dl > 0.0 ? tr - sj - (double)jj * e2b / dl : -DBL_MAX;
+        }
+        ok = lb > J.thr + guard;
+      }
+      ctl[1] = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (ctl[1]) {
+      if (wave == 0) cgs2_wave(Z, m, rh);
+      __syncthreads();
+      // Ritz vectors Q z_j, one wave per vector, then the sign rule
+      for (int j = wave; j < rh; j += NW) {
+        double best = -1.0, at = 0.0;
+        int bidx = 0;
+        for (int i = lane; i < k; i += 64) {
+          double y = 0.0;
+          for (int q = 0; q < m; ++q) y = fma(Q[(size_t)q * k + i], Z[(size_t)q * rh + j], y);
+          J.vecs[(size_t)j * k + i] = y;
+          if (fabs(y) > best) {
+            best = fabs(y);
+            bidx = i;
+            at = y;
+          }
+        }
+        const double sg = sign_factor(best, bidx, at);
+        if (sg < 0.0)
+          for (int i = lane; i < k; i += 64) J.vecs[(size_t)j * k + i] = -J.vecs[(size_t)j * k + i];
+      }
+      for (int i = tid; i < rh; i += ET) J.evals[i] = top[i];
+      if (tid == 0) {
+        double S = 0.0;
+        for (int i = 0; i < rh; ++i) S += top[i];
+        *J.rank = rh;
+        *J.tail = fmax(tr - S, 0.0);
+      }
+      done = true;
+    }
+  }
+  return done;
+}
+
 // Returns true when the decision and its eigenpairs are written; false leaves the
 // outputs untouched.  The last 64 doubles of the scratch record the attempt:
 // [8] = steps (negative when the decision was not proven), [9] = checks.
-template <bool QL>
+// MV selects the product G q: 0 (k <= 128) G stays in registers, thread (i, h)
+// holding column i's rows 32 h .. 32 h + 31; 1 (k <= kLzLdsK) two halves of each
+// column streamed from the cache; 2 (k <= kLzMaxK) whole columns streamed, the
+// Krylov basis in global scratch.  G is symmetric, so column i serves row i and
+// every load is coalesced.
+template <int MV>
 __device__ __noinline__ bool lanczos_solve(const EigJob& J, double* lds, double* sh, double* red, int* ctl) {
+  constexpr bool QL = MV < 2;
+  constexpr int WS = QL ? 4 : 16;  // entries of w per lane in the projections (k <= 64 WS)
   const EigScratch c = carve(J);
   const int k = J.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   cgdouble* G = reinterpret_cast<cgdouble*>(reinterpret_cast<uintptr_t>(J.G));
   const int mlim = min(k, kLzSteps);
   double* Q = QL ? lds : c.hv;  // Krylov vector v at Q + v k
   double* wv = lds + (QL ? (kLzSteps + 1) * k : 0);
-  double* qv = wv + k;      // the vector the product reads (a copy when Q is global)
+  double* qv = wv + k;      // the scaled vector the product reads (MV == 2)
   double* part = qv + k;    // 512 partial sums of the product
   double* hc = part + 512;  // projection coefficients
   double* al = hc + kLzSteps;
   double* be = al + kLzSteps;
   double* e2 = be + kLzSteps;
   double* dn = e2 + kLzSteps;
-  double* e2n = dn + kLzSteps;
-  double* top = e2n + kLzSteps;
+  double* e2n = dn + kLzPad;
+  double* top = e2n + kLzPad;
   double* pb = top + kLzSteps;
-  double* free_lds = pb + kLzSteps;
+  double* lzred = pb + kLzSteps;  // two alternating NW-entry reduction buffers
+  double* free_lds = lzred + 2 * NW;
   const int64_t free_cap = kLdsDoubles - (int64_t)(free_lds - lds);
 
   double t = 0.0;
@@ -1128,6 +1379,17 @@ __device__ __noinline__ bool lanczos_solve(const EigJob& J, double* lds, double*
   if (!(tr > 0.0) || !(tr < DBL_MAX)) return false;
   const double guard = 64.0 * k * DBL_EPSILON * tr;
 
+  // MV == 0: rows 32 h .. 32 h + 31 of column i, kept for the whole solve
+  double g[MV == 0 ? 32 : 1];
+  if constexpr (MV == 0) {
+    const int i = tid & 127, h = tid >> 7;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      const int l = 32 * h + q;
+      g[q] = (i < k && l < k) ? G[(size_t)l * k + i] : 0.0;
+    }
+  }
+
   // fixed pseudo-random start
   double loc = 0.0;
   for (int i = tid; i < k; i += ET) {
@@ -1135,175 +1397,132 @@ __device__ __noinline__ bool lanczos_solve(const EigJob& J, double* lds, double*
     wv[i] = v;
     loc = fma(v, v, loc);
   }
-  const double inv0 = 1.0 / sqrt(bsum(loc, red));
-  for (int i = tid; i < k; i += ET) {
-    const double v = wv[i] * inv0;
-    Q[i] = v;
-    qv[i] = v;
-  }
-  __syncthreads();
+  double scl = 1.0 / sqrt(bsum(loc, red));  // q_{m-1} = scl w at the top of step m
 
   int checks = 0;
   for (int m = 1; m <= mlim; ++m) {
-    const double* qs = QL ? Q + (size_t)(m - 1) * k : qv;
-    // w = G q_{m-1}; G is symmetric, so thread i walks column i (coalesced rows)
-    if (k <= 256) {
-      const int i = tid & 255, h = tid >> 8;
-      const int l0 = h ? (k >> 1) : 0, l1 = h ? k : (k >> 1);
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      if (i < k) {
-        int l = l0;
-        for (; l + 4 <= l1; l += 4) {
-          a0 = fma(G[(size_t)l * k + i], qs[l], a0);
-          a1 = fma(G[(size_t)(l + 1) * k + i], qs[l + 1], a1);
-          a2 = fma(G[(size_t)(l + 2) * k + i], qs[l + 2], a2);
-          a3 = fma(G[(size_t)(l + 3) * k + i], qs[l + 3], a3);
-        }
-        for (; l < l1; ++l) a0 = fma(G[(size_t)l * k + i], qs[l], a0);
-      }
-      part[tid] = (a0 + a1) + (a2 + a3);
-      __syncthreads();
-      if (tid < k) wv[tid] = part[tid] + part[256 + tid];
-    } else {
+    // ---- w <- G q_{m-1}, and q_{m-1} into the basis
+    if constexpr (MV == 2) {
       for (int i = tid; i < k; i += ET) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int l = 0;
-        for (; l + 4 <= k; l += 4) {
-          a0 = fma(G[(size_t)l * k + i], qs[l], a0);
-          a1 = fma(G[(size_t)(l + 1) * k + i], qs[l + 1], a1);
-          a2 = fma(G[(size_t)(l + 2) * k + i], qs[l + 2], a2);
-          a3 = fma(G[(size_t)(l + 3) * k + i], qs[l + 3], a3);
-        }
-        for (; l < k; ++l) a0 = fma(G[(size_t)l * k + i], qs[l], a0);
-        wv[i] = (a0 + a1) + (a2 + a3);
+        const double v = wv[i] * scl;
+        qv[i] = v;
+        Q[(size_t)(m - 1) * k + i] = v;
       }
-    }
-    __syncthreads();
-    // two classical Gram-Schmidt passes against q_0 .. q_{m-1}; the coefficients
-    // on q_{m-1} add up to the diagonal entry of T
-    for (int pass = 0; pass < 2; ++pass) {
-      {
-        const int cc = tid >> 3, p = tid & 7;
-        double s = 0.0;
-        if (cc < m) {
-          const double* qc = Q + (size_t)cc * k;
-          for (int i = p; i < k; i += 8) s = fma(qc[i], wv[i], s);
+      __syncthreads();
+      for (int i = tid; i < k; i += ET) {
+        double a0 = 0.0, a1 = 0.0;
+        int l = 0;
+        for (; l + 16 <= k; l += 16) {
+          double gv[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) gv[q] = G[(size_t)(l + q) * k + i];
+#pragma unroll
+          for (int q = 0; q < 16; q += 2) {
+            a0 = fma(gv[q], qv[l + q], a0);
+            a1 = fma(gv[q + 1], qv[l + q + 1], a1);
+          }
         }
-        s += __shfl_xor(s, 1);
-        s += __shfl_xor(s, 2);
-        s += __shfl_xor(s, 4);
-        if (p == 0 && cc < m) hc[cc] = s;
+        for (; l < k; ++l) a0 = fma(G[(size_t)l * k + i], qv[l], a0);
+        wv[i] = a0 + a1;
+      }
+      __syncthreads();
+    } else {
+      if constexpr (MV == 0) {
+        const int h = tid >> 7;
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 32; q += 2) {
+          a0 = fma(g[q], wv[min(32 * h + q, k - 1)], a0);
+          a1 = fma(g[q + 1], wv[min(32 * h + q + 1, k - 1)], a1);
+        }
+        part[tid] = (a0 + a1) * scl;
+      } else {
+        const int i = tid & 255, h = tid >> 8;
+        const int half = (k + 1) >> 1;
+        const int l0 = h ? half : 0, l1 = h ? k : half;
+        double a0 = 0.0, a1 = 0.0;
+        if (i < k) {
+          int l = l0;
+          for (; l + 16 <= l1; l += 16) {
+            double gv[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) gv[q] = G[(size_t)(l + q) * k + i];
+#pragma unroll
+            for (int q = 0; q < 16; q += 2) {
+              a0 = fma(gv[q], wv[l + q], a0);
+              a1 = fma(gv[q + 1], wv[l + q + 1], a1);
+            }
+          }
+          for (; l < l1; ++l) a0 = fma(G[(size_t)l * k + i], wv[l], a0);
+        }
+        part[tid] = (a0 + a1) * scl;
+      }
+      for (int i = tid; i < k; i += ET) Q[(size_t)(m - 1) * k + i] = wv[i] * scl;
+      __syncthreads();
+      if (tid < k) {
+        wv[tid] = MV == 0 ? (part[tid] + part[128 + tid]) + (part[256 + tid] + part[384 + tid])
+                          : part[tid] + part[256 + tid];
+      }
+      __syncthreads();
+    }
+    // ---- two classical Gram-Schmidt passes against q_0 .. q_{m-1}, one wave per
+    //      basis vector; the coefficients on q_{m-1} add up to T's diagonal entry
+    double beta = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      double wr[WS];
+#pragma unroll
+      for (int s = 0; s < WS; ++s) {
+        const int i = lane + 64 * s;
+        wr[s] = i < k ? wv[i] : 0.0;
+      }
+      for (int cc = wave; cc < m; cc += NW) {
+        const double* qc = Q + (size_t)cc * k;
+        double a = 0.0;
+#pragma unroll
+        for (int s = 0; s < WS; ++s) {
+          const int i = lane + 64 * s;
+          if (i < k) a = fma(qc[i], wr[s], a);
+        }
+        a = dpp_wave_sum(a);
+        if (lane == 0) hc[cc] = a;
       }
       __syncthreads();
       if (tid == 0) al[m - 1] = pass ? al[m - 1] + hc[m - 1] : hc[m - 1];
+      double l2 = 0.0;
       for (int i = tid; i < k; i += ET) {
-        double v = wv[i];
-        for (int cc = 0; cc < m; ++cc) v = fma(-Q[(size_t)cc * k + i], hc[cc], v);
+        double v0 = wv[i], v1 = 0.0;
+        int cc = 0;
+        for (; cc + 2 <= m; cc += 2) {
+          v0 = fma(-Q[(size_t)cc * k + i], hc[cc], v0);
+          v1 = fma(-Q[(size_t)(cc + 1) * k + i], hc[cc + 1], v1);
+        }
+        if (cc < m) v0 = fma(-Q[(size_t)cc * k + i], hc[cc], v0);
+        const double v = v0 + v1;
         wv[i] = v;
+        l2 = fma(v, v, l2);
       }
-      __syncthreads();
+      if (pass == 0) {
+        __syncthreads();
+      } else {
+        // ||w||: each step alternates between two buffers, so the barriers of the
+        // step in between keep them apart
+        const double ws = dpp_wave_sum(l2);
+        double* rb = lzred + (m & 1) * NW;
+        if (lane == 0) rb[wave] = ws;
+        __syncthreads();
+        double tot = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) tot += rb[w];
+        beta = sqrt(tot);
+      }
     }
-    double l2 = 0.0;
-    for (int i = tid; i < k; i += ET) l2 = fma(wv[i], wv[i], l2);
-    const double beta = sqrt(bsum(l2, red));
     const bool brk = !(beta > 1e-14 * tr);  // the Krylov space is (numerically) invariant
     if (tid == 0) be[m - 1] = beta;
     if (brk || m == mlim || lz_check_at(m)) {
       __syncthreads();
       ++checks;
-      // T_m: diagonal al, off-diagonal be[0 .. m-2]; be[m-1] is the coupling beta
-      finish_tridiag(m, al, be, e2, dn, e2n, sh);
-      tridiag_values(dn, e2n, m, sh, top);
-      if (tid == 0) {
-        double tsum = 0.0;
-        for (int i = 0; i < m; ++i) tsum += al[i];
-        const int rlim = min(J.rmax, m);
-        double S = 0.0;
-        int rh = -1;
-        for (int r = 0; r <= rlim; ++r) {
-          if (r >= J.rmin && tr - S <= J.thr - guard) {
-            rh = r;
-            break;
-          }
-          if (r < rlim) S += top[r];
-        }
-        ctl[0] = rh;
-        sh[4] = tsum;
-      }
-      __syncthreads();
-      const int rh = ctl[0];
-      bool done = false;
-      if (rh == 0) {
-        if (tid == 0) {
-          *J.rank = 0;
-          *J.tail = tr;
-        }
-        done = true;
-      } else if (rh > 0) {
-        double* Z = (int64_t)4 * m * rh <= free_cap ? free_lds : c.gz;
-        inverse_iteration(Z, m, rh, top, al, be, sh[2]);  // Z[i rh + j], ends with a barrier
-        if (tid < 64 && lane < rh) {
-          double n2 = 0.0;
-          for (int i = 0; i < m; ++i) n2 = fma(Z[(size_t)i * rh + lane], Z[(size_t)i * rh + lane], n2);
-          pb[lane] = Z[(size_t)(m - 1) * rh + lane] / sqrt(n2);
-        }
-        __syncthreads();
-        if (tid == 0) {
-          const double th1 = top[0];
-          bool ok = th1 > 0.0;
-          const int nv = min(rh + 1, m);
-          for (int i = 0; i + 1 < nv; ++i) ok = ok && (top[i] - top[i + 1] > 1e-10 * th1);
-          for (int i = 0; i < rh; ++i) ok = ok && (beta * fabs(pb[i]) <= 1e-13 * th1);
-          const int jj = rh - 1;
-          if (ok && jj >= J.rmin) {
-            double lb = tr;
-            if (jj > 0) {
-              double s2 = 0.0, sj = 0.0;
-              for (int i = 0; i < jj; ++i) {
-                s2 = fma(pb[i], pb[i], s2);
-                sj += top[i];
-              }
-              const double e2b = 4.0 * beta * beta * s2;
-              const double tperp = fmax(tr - sh[4], 0.0);
-              const double lam_c = fmax(jj < m ? top[jj] : 0.0, tperp) + beta * sqrt(fmax(0.0, 1.0 - s2));
-              const double dl = top[jj - 1] - lam_c;
-              lb = dl > 0.0 ? tr - sj - (double)jj * e2b / dl : -DBL_MAX;
-            }
-            ok = lb > J.thr + guard;
-          }
-          ctl[1] = ok ? 1 : 0;
-        }
-        __syncthreads();
-        if (ctl[1]) {
-          cgs2_columns(Z, m, rh, pb, red);
-          // Ritz vectors Q z_j, one wave per vector, then the sign rule
-          for (int j = wave; j < rh; j += NW) {
-            double best = -1.0, at = 0.0;
-            int bidx = 0;
-            for (int i = lane; i < k; i += 64) {
-              double y = 0.0;
-              for (int q = 0; q < m; ++q) y = fma(Q[(size_t)q * k + i], Z[(size_t)q * rh + j], y);
-              J.vecs[(size_t)j * k + i] = y;
-              if (fabs(y) > best) {
-                best = fabs(y);
-                bidx = i;
-                at = y;
-              }
-            }
-            const double sg = sign_factor(best, bidx, at);
-            if (sg < 0.0)
-              for (int i = lane; i < k; i += 64) J.vecs[(size_t)j * k + i] = -J.vecs[(size_t)j * k + i];
-          }
-          for (int i = tid; i < rh; i += ET) J.evals[i] = top[i];
-          if (tid == 0) {
-            double S = 0.0;
-            for (int i = 0; i < rh; ++i) S += top[i];
-            *J.rank = rh;
-            *J.tail = fmax(tr - S, 0.0);
-          }
-          done = true;
-        }
-      }
+      const LzView v{Q, al, be, e2, dn, e2n, top, pb, free_lds, free_cap};
+      const bool done = lz_certify(J, v, m, beta, tr, guard, sh, red, ctl);
       if (done || brk || m == mlim) {
         if (tid == 0) {
           c.clk[8] = done ? m : -m;
@@ -1312,13 +1531,7 @@ __device__ __noinline__ bool lanczos_solve(const EigJob& J, double* lds, double*
         return done;
       }
     }
-    const double ib = 1.0 / beta;
-    for (int i = tid; i < k; i += ET) {
-      const double v = wv[i] * ib;
-      Q[(size_t)m * k + i] = v;
-      if (!QL) qv[i] = v;
-    }
-    __syncthreads();
+    scl = 1.0 / beta;
   }
   return false;
 }
@@ -1464,8 +1677,9 @@ __global__ __launch_bounds__(ET) void eig_trunc_kernel(EigBatch batch) {
     }
   }
   if (J.method != kEigHouseholder && k >= kLzMinK && k <= kLzMaxK && J.rmax > 0) {
-    const bool done = k <= kLzLdsK ? lanczos_solve<true>(J, lds, sh, red, lz_ctl)
-                                   : lanczos_solve<false>(J, lds, sh, red, lz_ctl);
+    const bool done = k <= 128       ? lanczos_solve<0>(J, lds, sh, red, lz_ctl)
+                      : k <= kLzLdsK ? lanczos_solve<1>(J, lds, sh, red, lz_ctl)
+                                     : lanczos_solve<2>(J, lds, sh, red, lz_ctl);
     if (done) return;
     if (J.method == kEigLanczos) {
       if (tid == 0) *J.rank = -1;

@@ -204,6 +204,87 @@ def test_eig_degenerate_cluster_spans_the_eigenspace():
     assert np.linalg.norm(P - Pref) < 1e-10
 
 
+def exact_rank(lam, thr, rmin, rmax):
+    """The truncation rule on a reference spectrum (descending): minimal r in
+    [rmin, rmax] whose discarded energy, summed from the smallest value up, is <= thr."""
+    tail = np.concatenate([np.cumsum(np.clip(lam[::-1], 0, None))[::-1], [0.0]])
+    for r in range(rmin, rmax + 1):
+        if tail[r] <= thr:
+            return r
+    return rmax
+
+
+def lowrank_gram(k, r0, seed, noise=1e-5, cols=3000):
+    g = rng(seed)
+    X = g.standard_normal((k, r0)) @ g.standard_normal((r0, cols)) + noise * g.standard_normal((k, cols))
+    return X @ X.T
+
+
+# Gram matrices shaped like the method's: a few strong directions over a floor.  The
+# Krylov basis sits in LDS up to k = 224 and in global scratch beyond.
+@pytest.mark.parametrize("k,r0,rmin", [(40, 3, 0), (96, 3, 0), (96, 12, 1), (182, 5, 0), (224, 30, 0),
+                                       (300, 12, 0), (768, 20, 1)])
+def test_eig_lanczos_certified_matches_householder(k, r0, rmin):
+    G = lowrank_gram(k, r0, k + r0)
+    thr = 1e-6 * np.trace(G)
+    rmax = min(k, 64)
+    lam = np.sort(np.linalg.eigvalsh(G))[::-1]
+    r_ref = exact_rank(lam, thr, rmin, rmax)
+    Gd = torch.from_numpy(G).cuda()
+    evh, vh, rh, th = H.ht_test_eig(Gd, rmin, rmax, thr, method=H.EIG_HOUSEHOLDER)
+    evl, vl, rl, tl, steps = H.ht_test_eig(Gd, rmin, rmax, thr, method=H.EIG_LANCZOS, info=True)
+    eva, va, ra, ta, sa = H.ht_test_eig(Gd, rmin, rmax, thr, info=True)
+    print("k %d: rank %d, Lanczos steps %d" % (k, rl, steps))
+    assert rh == rl == ra == r_ref
+    assert 0 < steps <= 64 and sa == steps  # the automatic choice took the proven decision
+    VL, VH = vl.cpu().numpy(), vh.cpu().numpy()
+    assert np.linalg.norm(VL.T @ VL - np.eye(rl)) < 1e-12
+    assert np.linalg.norm(VL @ VL.T - VH @ VH.T) < 1e-11
+    ev = evl.cpu().numpy()[:rl]
+    assert np.max(np.abs(ev - lam[:rl])) <= 1e-13 * lam[0]
+    assert np.max(np.abs(G @ VL - VL * ev[None, :])) <= 1e-12 * lam[0]
+    assert tl == pytest.approx(th, rel=1e-6, abs=1e-12 * lam[0])
+    piv = np.argmax(np.abs(VL), axis=0)
+    assert np.all(VL[piv, np.arange(rl)] > 0)
+    np.testing.assert_array_equal(va.cpu().numpy(), VL)
+
+
+def test_eig_lanczos_refuses_unprovable_decisions():
+    """A degenerate cluster (a single Krylov sequence sees one vector per eigenspace)
+    and a slowly decaying spectrum that needs more than 64 steps are left to the
+    Householder path, which the automatic choice then takes."""
+    lam = np.concatenate([np.full(4, 3.0), np.full(3, 1.0), np.full(53, 1e-9)])
+    G1, _ = psd_with_spectrum(60, lam, 17)
+    lam2 = np.logspace(0, -12, 150)
+    G2, _ = psd_with_spectrum(150, lam2, 150)
+    thr2 = 0.5 * np.sum(lam2[75:]) + 0.5 * np.sum(lam2[76:])
+    for G, thr, r_ref in ((G1, 1e-6, 7), (G2, thr2, 76)):
+        Gd = torch.from_numpy(G).cuda()
+        k = G.shape[0]
+        _, _, rl, _, steps = H.ht_test_eig(Gd, 1, k, thr, method=H.EIG_LANCZOS, info=True)
+        assert rl == -1 and steps < 0
+        _, va, ra, _ = H.ht_test_eig(Gd, 1, k, thr)
+        _, vh, rh, _ = H.ht_test_eig(Gd, 1, k, thr, method=H.EIG_HOUSEHOLDER)
+        assert ra == rh == r_ref
+        np.testing.assert_array_equal(va.cpu().numpy(), vh.cpu().numpy())
+
+
+def test_eig_lanczos_budget_edges():
+    """Exact low rank (the Krylov space becomes invariant), a threshold the trace
+    already meets with rmin = 1, and the rank capped below the rule's choice (the
+    Householder path then reports the capped rank with its larger tail)."""
+    G = lowrank_gram(96, 6, 5, noise=0.0)
+    Gd = torch.from_numpy(G).cuda()
+    lam = np.sort(np.linalg.eigvalsh(G))[::-1]
+    thr = 1e-9 * np.trace(G)
+    _, v, r, _, steps = H.ht_test_eig(Gd, 0, 64, thr, method=H.EIG_LANCZOS, info=True)
+    assert r == exact_rank(lam, thr, 0, 64) == 6 and 0 < steps <= 8
+    _, _, r1, t1, s1 = H.ht_test_eig(Gd, 1, 64, 2.0 * np.trace(G), info=True)
+    assert r1 == 1 and s1 > 0 and t1 == pytest.approx(np.sum(lam[1:]), rel=1e-9)
+    _, _, r2, t2, s2 = H.ht_test_eig(Gd, 0, 3, thr, info=True)
+    assert r2 == 3 and s2 < 0 and t2 == pytest.approx(np.sum(lam[3:]), rel=1e-9)
+
+
 @pytest.mark.parametrize("alpha,r_old,rR", [(96, 12, 3), (16, 0, 4), (200, 40, 8), (9, 4, 5), (400, 30, 8)])
 def test_orth_expand(alpha, r_old, rR):
     g = rng(alpha + r_old)
