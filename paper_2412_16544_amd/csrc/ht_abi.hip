@@ -513,8 +513,11 @@ ht_status layer_readback(ht_state* h, hipStream_t s, std::vector<int>& rk, std::
 
 // After the read-back: capacity and finiteness checks, then [U_old, U_R] with U_R
 // re-orthogonalised, and the zero padding of the parents.
+// The expansions are appended to *orth when given (the caller launches them, with
+// those of other handles, before anything reads the new cores), else launched here.
 ht_status layer_finish(ht_state* h, double thr, bool initial, hipStream_t s, const LayerJobs& L,
-                       const std::vector<int>& rk, const std::vector<double>& tl, int* growth) {
+                       const std::vector<int>& rk, const std::vector<double>& tl, int* growth,
+                       std::vector<ht::OrthJob>* orth = nullptr) {
   for (size_t q = 0; q < L.jobs.size(); ++q) {
     const int node = L.node[q];
     const int r = rk[node];
@@ -526,14 +529,17 @@ ht_status layer_finish(ht_state* h, double thr, bool initial, hipStream_t s, con
     if (!std::isfinite(tl[node])) return fail(HT_ENUMERIC, "non-finite eigenvalues at node " + std::to_string(node));
   }
   std::vector<int> old_rank = h->rank;
+  std::vector<ht::OrthJob> local;
+  std::vector<ht::OrthJob>& oj = orth ? *orth : local;
   for (size_t q = 0; q < L.jobs.size(); ++q) {
     const int node = L.node[q];
     const int r = rk[node];
     if (r == 0) continue;
-    ht::orth_expand(h->core[node], L.jobs[q].k, L.rold[q], h->vecs[node], r, h->core[node], h->orthsc, s);
+    oj.push_back(ht::OrthJob{h->core[node], h->vecs[node], h->core[node], L.jobs[q].k, L.rold[q], r});
     h->rank[node] = L.rold[q] + r;
     *growth += initial ? 0 : r;
   }
+  if (!orth && !local.empty()) ht::orth_expand_batch(local.data(), (int)local.size(), s);
   // padWithZeros on every parent whose successors grew (the root's capacity layout pads itself)
   for (size_t q = 0; q < L.jobs.size(); ++q) {
     const int node = L.node[q];
@@ -745,12 +751,14 @@ ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* N
       if (st != HT_OK) return st;
     }
     HT_HIP(hipStreamSynchronize(s));
+    std::vector<ht::OrthJob> orth;
     for (Upd& u : U) {
       const int ell = u.busy ? u.h->tree.depth - t : 0;
       if (ell < 1) continue;
-      ht_status st = layer_finish(u.h, u.thr, false, s, u.L, u.rk, u.tl, &u.growth);
+      ht_status st = layer_finish(u.h, u.thr, false, s, u.L, u.rk, u.tl, &u.growth, &orth);
       if (st != HT_OK) {
         // roll this handle back: cores from the backup, ranks from before the call
+        // (a failing handle has queued no expansion)
         u.st = st;
         u.err = g_last_error;
         restore_cores(u.h, s);
@@ -758,6 +766,11 @@ ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* N
         u.busy = false;
         continue;
       }
+    }
+    if (!orth.empty()) ht::orth_expand_batch(orth.data(), (int)orth.size(), s);
+    for (Upd& u : U) {
+      const int ell = u.busy ? u.h->tree.depth - t : 0;
+      if (ell < 1) continue;
       u.cur = project_layer(u.h, ell, u.cur, s, nullptr, u.h->mixed);
     }
   }

@@ -93,6 +93,18 @@ void eig_trunc(const EigJob* jobs, int count, hipStream_t s);
 void orth_expand(const double* U_old, int64_t alpha, int r_old, double* V, int rR, double* core,
                  double* scratch, hipStream_t s);
 size_t orth_scratch_doubles(int rR);
+// Several independent expansions (the growing nodes of a layer, of one or many
+// handles) in one launch per kMaxOrthJobs, one workgroup each.
+struct OrthJob {
+  const double* U_old;
+  double* V;
+  double* core;
+  int64_t alpha;
+  int r_old;
+  int rR;
+};
+constexpr int kMaxOrthJobs = 32;
+void orth_expand_batch(const OrthJob* jobs, int count, hipStream_t s);
 
 // ---- layout helpers ---------------------------------------------------------------
 // Zero-padding of a transfer core when a successor grows (padWithZeros): src is

@@ -1628,21 +1628,26 @@ __device__ __forceinline__ void orth_body(const double* U, int64_t alpha, int r_
 
 constexpr int kOrthLdsDoubles = 12288;  // U_old and V staged in LDS up to this size (96 KiB)
 
-__global__ __launch_bounds__(256) void orth_expand_kernel(const double* __restrict__ Uold, int64_t alpha, int r_old,
-                                                          double* __restrict__ V, int rR, double* __restrict__ core,
-                                                          double* __restrict__ scratch) {
+struct OrthBatch {
+  OrthJob j[kMaxOrthJobs];
+};
+
+__global__ __launch_bounds__(256) void orth_expand_kernel(OrthBatch b) {
+  const OrthJob J = b.j[blockIdx.x];
   extern __shared__ double osm[];
   double* Cs = osm;  // 64 x 64
+  const int64_t alpha = J.alpha;
+  const int r_old = J.r_old, rR = J.rR;
   const int64_t need = alpha * (int64_t)(r_old + rR);
   if (need <= kOrthLdsDoubles) {
     double* sU = osm + 64 * 64;
     double* sV = sU + alpha * r_old;
-    for (int64_t e = threadIdx.x; e < alpha * r_old; e += 256) sU[e] = Uold[e];
-    for (int64_t e = threadIdx.x; e < alpha * rR; e += 256) sV[e] = V[e];
+    for (int64_t e = threadIdx.x; e < alpha * r_old; e += 256) sU[e] = J.U_old[e];
+    for (int64_t e = threadIdx.x; e < alpha * rR; e += 256) sV[e] = J.V[e];
     __syncthreads();
-    orth_body(sU, alpha, r_old, sV, rR, Cs, core, Uold);
+    orth_body(sU, alpha, r_old, sV, rR, Cs, J.core, J.U_old);
   } else {
-    orth_body(Uold, alpha, r_old, V, rR, Cs, core, Uold);
+    orth_body(J.U_old, alpha, r_old, J.V, rR, Cs, J.core, J.U_old);
   }
 }
 
@@ -2146,19 +2151,34 @@ void ttm_expand(const double* Z, int64_t P, int R, int64_t S, const double* U, i
 
 size_t orth_scratch_doubles(int rR) { return (size_t)64 * 64 + (size_t)rR; }
 
-void orth_expand(const double* U_old, int64_t alpha, int r_old, double* V, int rR, double* core, double* scratch,
-                 hipStream_t s) {
-  if (rR <= 0) return;
+void orth_expand_batch(const OrthJob* jobs, int count, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&orth_expand_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (64 * 64 + kOrthLdsDoubles) * 8);
     attr = true;
   }
-  const int64_t need = alpha * (int64_t)(r_old + rR);
-  const size_t lds = (size_t)(64 * 64 + (need <= kOrthLdsDoubles ? need : 0)) * sizeof(double);
-  ProfScope prof(KKind::Orth, s, 0.0, 0.0);
-  orth_expand_kernel<<<1, 256, lds, s>>>(U_old, alpha, r_old, V, rR, core, scratch);
+  for (int b0 = 0; b0 < count; b0 += kMaxOrthJobs) {
+    const int n = std::min(kMaxOrthJobs, count - b0);
+    OrthBatch b;
+    int64_t staged = 0;
+    for (int i = 0; i < n; ++i) {
+      b.j[i] = jobs[b0 + i];
+      const int64_t need = b.j[i].alpha * (int64_t)(b.j[i].r_old + b.j[i].rR);
+      if (need <= kOrthLdsDoubles) staged = std::max(staged, need);
+    }
+    const size_t lds = (size_t)(64 * 64 + staged) * sizeof(double);
+    ProfScope prof(KKind::Orth, s, 0.0, 0.0);
+    orth_expand_kernel<<<n, 256, lds, s>>>(b);
+  }
+}
+
+void orth_expand(const double* U_old, int64_t alpha, int r_old, double* V, int rR, double* core, double* scratch,
+                 hipStream_t s) {
+  (void)scratch;
+  if (rR <= 0) return;
+  const OrthJob j{U_old, V, core, alpha, r_old, rR};
+  orth_expand_batch(&j, 1, s);
 }
 
 void pad_core(const double* src, int ra, int rb, int rp, double* dst, int ra2, int rb2, hipStream_t s) {
