@@ -19,8 +19,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -115,6 +117,59 @@ struct Tree {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// ---- page-locked staging for the small device -> host read-backs (the skip
+//      test's scalars, a layer's ranks and discarded energies).  A read-back into
+//      pageable memory goes through a runtime staging copy and costs tens of
+//      microseconds per synchronisation; each handle instead takes one block of
+//      kPinnedBytes from a process-wide pool when it is created and returns it
+//      when destroyed.  Blocks are kept until the process ends.
+constexpr size_t kPinnedBytes = 16384;
+std::mutex g_pin_mu;
+std::vector<void*> g_pin_free;
+
+void* pinned_take() {
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if (!g_pin_free.empty()) {
+      void* p = g_pin_free.back();
+      g_pin_free.pop_back();
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void pinned_give(void* p) {
+  if (p == nullptr) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.push_back(p);
+}
+
+// Waits for everything enqueued on s: the waits of an update are short (a few
+// kernels), so the stream is polled for up to 2 ms before the blocking call.
+hipError_t wait_stream(hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t e = hipStreamQuery(s);
+    if (e != hipErrorNotReady) return e;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) return hipStreamSynchronize(s);
+  }
+}
+
+hipError_t wait_event(hipEvent_t ev) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t e = hipEventQuery(ev);
+    if (e != hipErrorNotReady) return e;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) return hipEventSynchronize(ev);
+  }
+}
+
 }  // namespace
 
 // ============================================================================
@@ -156,9 +211,18 @@ struct ht_state {
   double* padtmp = nullptr;
   double* tails = nullptr;
   int* ranks_dev = nullptr;
-  // host staging for small read-backs
-  std::vector<double> h_scal;
+  // host staging for small read-backs: h_scal (kScalars doubles), h_tails and
+  // h_ranks (one per node), in a page-locked block when one was available
+  void* pin = nullptr;
+  std::vector<double> pin_fallback;
+  double* h_scal = nullptr;
+  double* h_tails = nullptr;
+  int* h_ranks = nullptr;
   hipStream_t last_stream = nullptr;
+  ht_state() = default;
+  ht_state(const ht_state&) = delete;
+  ht_state& operator=(const ht_state&) = delete;
+  ~ht_state() { pinned_give(pin); }
 };
 
 namespace {
@@ -387,7 +451,7 @@ Level project_all(const ht_state* h, const void* Y, int64_t N, hipStream_t s, do
 
 ht_status sync_read(ht_state* h, hipStream_t s, const double* dev, size_t count, double* host) {
   HT_HIP(hipMemcpyAsync(host, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
-  HT_HIP(hipStreamSynchronize(s));
+  HT_HIP(wait_stream(s));
   (void)h;
   return HT_OK;
 }
@@ -414,7 +478,7 @@ struct Timer {
     float ms = 0.f;
     if (a && b) {
       (void)hipEventRecord(b, s);
-      (void)hipEventSynchronize(b);
+      (void)wait_event(b);
       (void)hipEventElapsedTime(&ms, a, b);
     }
     return ms;
@@ -501,14 +565,19 @@ void launch_eig(const std::vector<ht::EigJob>& jobs, hipStream_t s) {
     ht::eig_trunc(jobs.data() + b, (int)std::min<size_t>(ht::kMaxEigJobs, jobs.size() - b), s);
 }
 
-// Ranks and discarded energies of the layer (device -> host, not yet synchronised).
-ht_status layer_readback(ht_state* h, hipStream_t s, std::vector<int>& rk, std::vector<double>& tl) {
+// Ranks and discarded energies of the layer (device -> host staging, not yet
+// synchronised), and after the wait their copies.
+ht_status layer_readback(ht_state* h, hipStream_t s) {
   const int nn = (int)h->tree.nodes.size();
-  rk.assign(nn, 0);
-  tl.assign(nn, 0.0);
-  HT_HIP(hipMemcpyAsync(rk.data(), h->ranks_dev, nn * sizeof(int), hipMemcpyDeviceToHost, s));
-  HT_HIP(hipMemcpyAsync(tl.data(), h->tails, nn * sizeof(double), hipMemcpyDeviceToHost, s));
+  HT_HIP(hipMemcpyAsync(h->h_ranks, h->ranks_dev, nn * sizeof(int), hipMemcpyDeviceToHost, s));
+  HT_HIP(hipMemcpyAsync(h->h_tails, h->tails, nn * sizeof(double), hipMemcpyDeviceToHost, s));
   return HT_OK;
+}
+
+void layer_collect(const ht_state* h, std::vector<int>& rk, std::vector<double>& tl) {
+  const int nn = (int)h->tree.nodes.size();
+  rk.assign(h->h_ranks, h->h_ranks + nn);
+  tl.assign(h->h_tails, h->h_tails + nn);
 }
 
 // After the read-back: capacity and finiteness checks, then [U_old, U_R] with U_R
@@ -565,11 +634,12 @@ ht_status decide_layer(ht_state* h, int ell, const Level& cur, double thr, bool 
   layer_grams(h, ell, cur, thr, initial, s, L);
   launch_eig(L.jobs, s);
   HT_HIP(hipGetLastError());
+  ht_status st = layer_readback(h, s);
+  if (st != HT_OK) return st;
+  HT_HIP(wait_stream(s));
   std::vector<int> rk;
   std::vector<double> tl;
-  ht_status st = layer_readback(h, s, rk, tl);
-  if (st != HT_OK) return st;
-  HT_HIP(hipStreamSynchronize(s));
+  layer_collect(h, rk, tl);
   return layer_finish(h, thr, initial, s, L, rk, tl, growth);
 }
 
@@ -628,7 +698,15 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   h->tails = reinterpret_cast<double*>(base + L.tails);
   h->ranks_dev = reinterpret_cast<int*>(base + L.ranks_dev);
   h->rank.assign(nn, 0);
-  h->h_scal.assign(kScalars(nn), 0.0);
+  {
+    const size_t nd = kScalars(nn) + 2 * (size_t)nn;  // the ranks take at most nn doubles
+    if (nd * sizeof(double) <= kPinnedBytes) h->pin = pinned_take();
+    if (h->pin == nullptr) h->pin_fallback.assign(nd, 0.0);
+    double* b = h->pin ? static_cast<double*>(h->pin) : h->pin_fallback.data();
+    h->h_scal = b;
+    h->h_tails = b + kScalars(nn);
+    h->h_ranks = reinterpret_cast<int*>(b + kScalars(nn) + nn);
+  }
   *out = h;
   return HT_OK;
 }
@@ -686,15 +764,15 @@ ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* N
     if (h->mixed) {
       u.expl.assign(nn, 0);
       u.c1 = project_all(h, u.Y, u.N, s, h->scal, true, h->scal + 8, &u.expl);
-      HT_HIP(hipMemcpyAsync(h->h_scal.data(), h->scal, kScalars(nn) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HT_HIP(hipMemcpyAsync(h->h_scal, h->scal, kScalars(nn) * sizeof(double), hipMemcpyDeviceToHost, s));
     } else {
       u.c1 = project_all(h, u.Y, u.N, s, h->scal);
       ht::sumsq(u.c1.ptr, u.c1.t, (int64_t)u.c1.elems(), h->sspart, h->scal + 1, s);
-      HT_HIP(hipMemcpyAsync(h->h_scal.data(), h->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HT_HIP(hipMemcpyAsync(h->h_scal, h->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     }
   }
   HT_HIP(hipGetLastError());
-  HT_HIP(hipStreamSynchronize(s));
+  HT_HIP(wait_stream(s));
   // ---- skip tests (Eq. relative_error_threshold)
   for (Upd& u : U) {
     ht_state* h = u.h;
@@ -747,10 +825,12 @@ ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* N
     HT_HIP(hipGetLastError());
     for (Upd& u : U) {
       if (!u.busy || u.h->tree.depth - t < 1) continue;
-      const ht_status st = layer_readback(u.h, s, u.rk, u.tl);
+      const ht_status st = layer_readback(u.h, s);
       if (st != HT_OK) return st;
     }
-    HT_HIP(hipStreamSynchronize(s));
+    HT_HIP(wait_stream(s));
+    for (Upd& u : U)
+      if (u.busy && u.h->tree.depth - t >= 1) layer_collect(u.h, u.rk, u.tl);
     std::vector<ht::OrthJob> orth;
     for (Upd& u : U) {
       const int ell = u.busy ? u.h->tree.depth - t : 0;
@@ -861,7 +941,7 @@ ht_status ht_init_batch(const ht_config* cfg, void* ws, size_t ws_bytes, const v
   Timer timer(s);
   const int64_t E = N * prod(h->n, 0, h->n.size());
   ht::sumsq(Y, h->in_t, E, h->sspart, h->scal, s);
-  st = sync_read(h, s, h->scal, 1, h->h_scal.data());
+  st = sync_read(h, s, h->scal, 1, h->h_scal);
   if (st != HT_OK) {
     delete h;
     return st;
@@ -894,7 +974,7 @@ ht_status ht_init_batch(const ht_config* cfg, void* ws, size_t ws_bytes, const v
     delete h;
     return fail(HT_EDEVICE, "kernel launch failed");
   }
-  st = sync_read(h, s, h->scal + 1, 1, h->h_scal.data() + 1);
+  st = sync_read(h, s, h->scal + 1, 1, h->h_scal + 1);
   if (st != HT_OK) {
     delete h;
     return st;
@@ -943,7 +1023,7 @@ ht_status ht_project(ht_handle h, const void* Y, int64_t N, void* latent, void* 
   Level c1 = project_all(h, Y, N, s);
   ht::copy_f64(static_cast<const double*>(c1.ptr), static_cast<double*>(latent), (int64_t)c1.elems(), s);
   HT_HIP(hipGetLastError());
-  HT_HIP(hipStreamSynchronize(s));
+  HT_HIP(wait_stream(s));
   return HT_OK;
 }
 
@@ -1010,7 +1090,7 @@ ht_status ht_reconstruct(ht_handle h, int64_t first, int64_t count, void* out, i
     if (h->tree.depth == 0) return fail(HT_EINVAL, "degenerate tree");
   }
   HT_HIP(hipGetLastError());
-  HT_HIP(hipStreamSynchronize(s));
+  HT_HIP(wait_stream(s));
   return HT_OK;
 }
 
@@ -1040,7 +1120,7 @@ ht_status ht_export_cores(ht_handle h, double* host_buf, size_t bytes, size_t* n
   if (host_buf == nullptr) return HT_OK;
   if (bytes < total * sizeof(double)) return fail(HT_ENOMEM, "export buffer too small");
   hipStream_t s = h->last_stream;
-  HT_HIP(hipStreamSynchronize(s));
+  HT_HIP(wait_stream(s));
   size_t off = 0;
   for (int i = 1; i < nn; ++i) {
     const size_t n = (size_t)alpha_now(h, i) * h->rank[i];
@@ -1050,7 +1130,7 @@ ht_status ht_export_cores(ht_handle h, double* host_buf, size_t bytes, size_t* n
   for (int64_t c0 = 0; c0 < h->n_acc; c0 += h->max_batch) {
     const int64_t cn = std::min<int64_t>(h->max_batch, h->n_acc - c0);
     ht::root_extract(h->root, c0, cn, r11, r12, h->rank_cap, h->bufA, s);
-    HT_HIP(hipStreamSynchronize(s));
+    HT_HIP(wait_stream(s));
     HT_HIP(hipMemcpy(host_buf + off, h->bufA, (size_t)cn * r11 * r12 * sizeof(double), hipMemcpyDeviceToHost));
     off += (size_t)cn * r11 * r12;
   }
