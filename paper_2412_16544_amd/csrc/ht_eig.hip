@@ -2,7 +2,10 @@
 //
 // The truncated SVD of an unfolding M (Eq. ht_leaf_svd, Eq. svd_on_residual) is
 // taken from the Gram matrix G = M M^T: sigma_i^2 = lambda_i(G) and the left
-// singular vectors are G's eigenvectors.  One workgroup solves one k x k problem:
+// singular vectors are G's eigenvectors.  One workgroup solves one k x k problem.
+// It first runs Lanczos with full re-orthogonalisation and takes the decision
+// from the Krylov space when a certificate proves it equal to the rule on the
+// exact spectrum (the Ritz vectors are then the kept vectors); otherwise:
 //
 //   1. Householder reduction G = Q T Q^T to tridiagonal T.  Up to k = 224 the
 //      matrix stays in registers (lower 32 x 32 tiles, one entry per thread per
