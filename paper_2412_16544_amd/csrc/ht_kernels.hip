@@ -1382,17 +1382,18 @@ constexpr int TUS = 65;  // LDS row stride (doubles) of the staged U chunk of th
 // workgroup owns 16 unfolding columns and every output row (R <= 64); its four
 // waves split the row steps of a (step q of a chunk goes to wave q % 4), so small
 // column counts (the level tensors of transfer nodes) still spread over many
-// waves.  U^T is staged in LDS in chunks of rows of a; each wave keeps the X
+// waves.  U^T is staged in dynamic LDS (reads coalesced along a), whole up to
+// kDirectLdsDoubles and otherwise in chunks of rows of a; each wave keeps the X
 // operands of its next eight steps in flight.  The four partial products are
 // added in wave order through LDS.
 // --------------------------------------------------------------------------
-constexpr int kDirectLdsDoubles = 8192;  // U chunk: chunk x (RP + 1) doubles
+constexpr int kDirectLdsDoubles = 19968;  // U chunk: chunk x (RP + 1) doubles of dynamic LDS
 
 template <typename T>
 __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
                                                          const double* __restrict__ U, int R, int chunk,
                                                          double* __restrict__ Z) {
-  __shared__ double sU[kDirectLdsDoubles];  // sU[a][r], then the wave partials
+  extern __shared__ double sU[];  // sU[a][r] (chunk rows of ULD), then the wave partials
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int RP = (R + 15) & ~15, ULD = RP + 1, rt = RP >> 4;
   const int64_t K = P * S;
@@ -1407,10 +1408,9 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
     const int ac = (int)min<int64_t>(chunk, m - a0);
     const int ac4 = (ac + 3) & ~3;
     __syncthreads();
-    for (int e = threadIdx.x; e < ac4 * RP; e += 256) {
-      const int a = e / RP, r = e - (e / RP) * RP;
-      sU[a * ULD + r] = (a < ac && r < R) ? U[(a0 + a) + (int64_t)r * m] : 0.0;
-    }
+    for (int r = wave; r < RP; r += 4)
+      for (int a = lane; a < ac4; a += 64)
+        sU[a * ULD + r] = (a < ac && r < R) ? U[(a0 + a) + (int64_t)r * m] : 0.0;
     __syncthreads();
     const int nst = ac4 >> 2;
     const T* xp = X + base + a0 * S;
@@ -2060,13 +2060,26 @@ void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U
   if (norm_part != nullptr) sumsq(x, t, v.P * v.m * v.S, norm_part, norm_out, s);
   ProfScope prof(KKind::TtmContract, s, 2.0 * R * v.m * (double)K,
                  (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_direct_kernel<float>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kDirectLdsDoubles * (int)sizeof(double));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_direct_kernel<double>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kDirectLdsDoubles * (int)sizeof(double));
+    attr = true;
+  }
   const unsigned blocks = (unsigned)((K + 15) / 16);
   const int RP = (R + 15) & ~15;
-  const int chunk = (int)std::min<int64_t>(((kDirectLdsDoubles / (RP + 1)) / 4) * 4, (v.m + 3) & ~3);
+  // few column blocks (transfer nodes): all of U in one chunk; many: at most 64 KiB,
+  // two workgroups per compute unit
+  const int cap = blocks >= 512 ? 8192 : kDirectLdsDoubles;
+  const int chunk = (int)std::min<int64_t>(((cap / (RP + 1)) / 4) * 4, (v.m + 3) & ~3);
+  // the wave partials (3 x 4 x 4 x 64 doubles) reuse the same space at the end
+  const size_t lds = (size_t)std::max<int64_t>((int64_t)chunk * (RP + 1), 3 * 4 * 4 * 64) * sizeof(double);
   if (t == Elem::F32)
-    ttm_direct_kernel<float><<<blocks, 256, 0, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R, chunk, Z);
+    ttm_direct_kernel<float><<<blocks, 256, lds, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R, chunk, Z);
   else
-    ttm_direct_kernel<double><<<blocks, 256, 0, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U, R, chunk, Z);
+    ttm_direct_kernel<double><<<blocks, 256, lds, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U, R, chunk, Z);
 }
 
 // the register-direct FP32 contraction applies to FP32 level tensors whose column

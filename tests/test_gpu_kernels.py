@@ -63,7 +63,9 @@ def test_resid_gram(P, m, S, R, dtype):
                                      (1, 130, 40, 17), (7, 17, 5, 1), (4, 64, 300, 16), (50, 9, 1, 9),
                                      # column runs in whole blocks of 32, m % 4 == 0: register-direct FP64
                                      (3, 96, 1024, 12), (2, 128, 64, 64), (5, 40, 96, 20), (2, 96, 288, 47),
-                                     (64, 8, 16384, 3), (3, 4, 32, 1)])
+                                     (64, 8, 16384, 3), (3, 4, 32, 1),
+                                     # modes of more than 128 rows: U staged once, or in chunks (m = 600)
+                                     (16, 182, 42, 40), (3, 600, 50, 40), (2, 131, 1, 64)])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_ttm_contract(P, m, S, R, dtype):
     g = rng(P + m + S + R)
