@@ -206,7 +206,8 @@ struct ht_state {
   double* scal = nullptr;
   double* sspart = nullptr;
   double* nrmpart = nullptr;
-  double* respart = nullptr;
+  double* respart = nullptr;  // one partial array per node (the skip test's sums are deferred)
+  double* ssnode = nullptr;   // two sum-of-squares partial arrays per node
   double* orthsc = nullptr;
   double* padtmp = nullptr;
   double* tails = nullptr;
@@ -232,12 +233,22 @@ struct Layout {
   // offsets (bytes)
   std::vector<size_t> core, gram, vecs, evals, eigsc;
   size_t core_backup = 0, core_backup_elems = 0, root = 0, bufA = 0, bufB = 0, buf_elems = 0, resid = 0, bufZ = 0,
-         resid_elems = 0, gpart = 0, scal = 0, sspart = 0, nrmpart = 0, respart = 0, orthsc = 0, padtmp = 0, tails = 0,
+         resid_elems = 0, gpart = 0, scal = 0, sspart = 0, nrmpart = 0, respart = 0, ssnode = 0, orthsc = 0, padtmp = 0,
+         tails = 0,
          ranks_dev = 0;
 };
 
 // device scalars: ||Y||^2, ||C1||^2, then two per node (mixed-form energies)
 size_t kScalars(int nn) { return 8 + 2 * (size_t)nn; }
+size_t res_stride() { return std::max<size_t>(ht::ttm_norm_partials(), ht::kSumsqBlocks); }
+
+// Queues this thread's final reduction sums for one batched launch while alive.
+struct DeferSums {
+  explicit DeferSums(std::vector<ht::SumJob>* list) { ht::sums_defer_begin(list); }
+  ~DeferSums() { ht::sums_defer_end(); }
+  DeferSums(const DeferSums&) = delete;
+  DeferSums& operator=(const DeferSums&) = delete;
+};
 
 size_t take(Layout& L, size_t bytes) {
   const size_t off = L.total;
@@ -343,7 +354,8 @@ Layout make_layout(const ht_config* c, const Tree& tree, std::vector<int64_t>& a
   L.scal = take(L, kScalars(nn) * sizeof(double));
   L.sspart = take(L, ht::kSumsqBlocks * sizeof(double));
   L.nrmpart = take(L, std::max<size_t>(ht::ttm_norm_partials(), ht::kSumsqBlocks) * sizeof(double));
-  L.respart = take(L, std::max<size_t>(ht::ttm_norm_partials(), ht::kSumsqBlocks) * sizeof(double));
+  L.respart = take(L, (size_t)nn * res_stride() * sizeof(double));
+  L.ssnode = take(L, (size_t)nn * 2 * ht::kSumsqBlocks * sizeof(double));
   L.orthsc = take(L, ht::orth_scratch_doubles(64) * sizeof(double));
   L.padtmp = take(L, max_core * sizeof(double));
   L.tails = take(L, (size_t)nn * sizeof(double));
@@ -407,13 +419,15 @@ Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, 
     const ModeView v = view_of(cur, k);
     if (mixed && v.m <= ht::kResidGramMaxM) {
       ht::ttm_contract_f32(cur.ptr, cur.t, v, h->core[node], h->rank[node], reinterpret_cast<float*>(dst),
-                           norm_out ? h->nrmpart : nullptr, norm_out, energy ? h->respart : nullptr,
+                           norm_out ? h->nrmpart : nullptr, norm_out,
+                           energy ? h->respart + (size_t)node * res_stride() : nullptr,
                            energy ? energy + 2 * node : nullptr, s);
       if (expl) (*expl)[node] = 1;
       cur.ptr = dst;
       cur.t = Elem::F32;
     } else {
-      if (energy) ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), h->sspart, energy + 2 * node, s);
+      double* ssp = h->ssnode + (size_t)node * 2 * ht::kSumsqBlocks;
+      if (energy) ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), ssp, energy + 2 * node, s);
       if (expl) (*expl)[node] = 0;
       if (norm_out != nullptr)
         ht::ttm_contract_norm(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, h->nrmpart, norm_out, s);
@@ -423,7 +437,7 @@ Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, 
       cur.t = Elem::F64;
       if (energy) {
         cur.modes[k] = h->rank[node];
-        ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), h->sspart, energy + 2 * node + 1, s);
+        ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), ssp + ht::kSumsqBlocks, energy + 2 * node + 1, s);
       }
     }
     norm_out = nullptr;
@@ -693,6 +707,7 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   h->sspart = reinterpret_cast<double*>(base + L.sspart);
   h->nrmpart = reinterpret_cast<double*>(base + L.nrmpart);
   h->respart = reinterpret_cast<double*>(base + L.respart);
+  h->ssnode = reinterpret_cast<double*>(base + L.ssnode);
   h->orthsc = reinterpret_cast<double*>(base + L.orthsc);
   h->padtmp = reinterpret_cast<double*>(base + L.padtmp);
   h->tails = reinterpret_cast<double*>(base + L.tails);
@@ -757,19 +772,30 @@ ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* N
   Timer timer(s);
   // ---- Step 1 for every handle: projection onto the existing cores; the first
   //      contraction also returns ||Y||^2 (mixed form: and the residual energies)
+  //      The final sums of every handle's reductions run as one launch.
+  {
+    std::vector<ht::SumJob> sums;
+    {
+      const DeferSums defer(&sums);
+      for (Upd& u : U) {
+        ht_state* h = u.h;
+        h->last_stream = s;
+        const int nn = (int)h->tree.nodes.size();
+        if (h->mixed) {
+          u.expl.assign(nn, 0);
+          u.c1 = project_all(h, u.Y, u.N, s, h->scal, true, h->scal + 8, &u.expl);
+        } else {
+          u.c1 = project_all(h, u.Y, u.N, s, h->scal);
+          ht::sumsq(u.c1.ptr, u.c1.t, (int64_t)u.c1.elems(), h->sspart, h->scal + 1, s);
+        }
+      }
+    }
+    ht::reduce_batch(sums, s);
+  }
   for (Upd& u : U) {
     ht_state* h = u.h;
-    h->last_stream = s;
-    const int nn = (int)h->tree.nodes.size();
-    if (h->mixed) {
-      u.expl.assign(nn, 0);
-      u.c1 = project_all(h, u.Y, u.N, s, h->scal, true, h->scal + 8, &u.expl);
-      HT_HIP(hipMemcpyAsync(h->h_scal, h->scal, kScalars(nn) * sizeof(double), hipMemcpyDeviceToHost, s));
-    } else {
-      u.c1 = project_all(h, u.Y, u.N, s, h->scal);
-      ht::sumsq(u.c1.ptr, u.c1.t, (int64_t)u.c1.elems(), h->sspart, h->scal + 1, s);
-      HT_HIP(hipMemcpyAsync(h->h_scal, h->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
+    const size_t ns = h->mixed ? kScalars((int)h->tree.nodes.size()) : 2;
+    HT_HIP(hipMemcpyAsync(h->h_scal, h->scal, ns * sizeof(double), hipMemcpyDeviceToHost, s));
   }
   HT_HIP(hipGetLastError());
   HT_HIP(wait_stream(s));

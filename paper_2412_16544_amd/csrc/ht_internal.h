@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace ht {
 
@@ -25,6 +26,20 @@ enum class Elem : int { F32 = 0, F64 = 1 };
 // partials must hold kSumsqBlocks doubles.
 constexpr int kSumsqBlocks = 1024;
 void sumsq(const void* x, Elem t, int64_t n, double* partials, double* out, hipStream_t s);
+
+// The second level of every split reduction (workgroup partials -> one FP64 sum,
+// in a fixed order).  Between sums_defer_begin and sums_defer_end the launchers of
+// this thread queue these final sums in *list instead of launching one kernel
+// each; reduce_batch then sums them all in one launch (the same order, so the same
+// bits).  While deferring, every queued sum must own its partial array.
+struct SumJob {
+  const double* part;
+  int n;
+  double* out;
+};
+void sums_defer_begin(std::vector<SumJob>* list);
+void sums_defer_end();
+void reduce_batch(const std::vector<SumJob>& jobs, hipStream_t s);
 
 // ---- Gram of a mode unfolding (FP64 MFMA) -----------------------------------
 // G (m x m, row-major, both triangles) = X_(k) X_(k)^T.  part is scratch of

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void sumsq_partial_kernel(const T* __restrict_
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
+__device__ __forceinline__ void reduce_body(const double* __restrict__ part, int n, double* __restrict__ out) {
   double acc = 0.0;
   int i = threadIdx.x;
   for (; i + 3 * 256 < n; i += 4 * 256)  // four loads in flight, fixed order
@@ -115,6 +115,31 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ 
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
+  reduce_body(part, n, out);
+}
+
+constexpr int kMaxSumJobs = 64;
+struct SumBatch {
+  SumJob j[kMaxSumJobs];
+};
+
+// one workgroup per queued sum
+__global__ __launch_bounds__(256) void reduce_many_kernel(SumBatch b) {
+  const SumJob J = b.j[blockIdx.x];
+  reduce_body(J.part, J.n, J.out);
+}
+
+thread_local std::vector<SumJob>* t_defer = nullptr;
+
+// the final sum of a split reduction: queued while this thread defers, else launched
+void finish_sum(const double* part, int n, double* out, hipStream_t s) {
+  if (t_defer != nullptr)
+    t_defer->push_back(SumJob{part, n, out});
+  else
+    reduce_kernel<<<1, 256, 0, s>>>(part, n, out);
 }
 
 // --------------------------------------------------------------------------
@@ -1710,13 +1735,26 @@ inline unsigned grid_for(int64_t n, int64_t cap = 4096) {
 // ============================================================================
 // host launchers
 // ============================================================================
+void sums_defer_begin(std::vector<SumJob>* list) { t_defer = list; }
+void sums_defer_end() { t_defer = nullptr; }
+
+void reduce_batch(const std::vector<SumJob>& jobs, hipStream_t s) {
+  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+  for (size_t b0 = 0; b0 < jobs.size(); b0 += kMaxSumJobs) {
+    const int n = (int)std::min<size_t>(kMaxSumJobs, jobs.size() - b0);
+    SumBatch b;
+    for (int i = 0; i < n; ++i) b.j[i] = jobs[b0 + i];
+    reduce_many_kernel<<<n, 256, 0, s>>>(b);
+  }
+}
+
 void sumsq(const void* x, Elem t, int64_t n, double* partials, double* out, hipStream_t s) {
   ProfScope prof(KKind::Sumsq, s, 2.0 * n, (double)n * (t == Elem::F32 ? 4 : 8));
   if (t == Elem::F32)
     sumsq_partial_kernel<float><<<kSumsqBlocks, 256, 0, s>>>(static_cast<const float*>(x), n, partials);
   else
     sumsq_partial_kernel<double><<<kSumsqBlocks, 256, 0, s>>>(static_cast<const double*>(x), n, partials);
-  reduce_kernel<<<1, 256, 0, s>>>(partials, kSumsqBlocks, out);
+  finish_sum(partials, kSumsqBlocks, out, s);
 }
 
 size_t panel_lds_bytes(bool resid, int R, size_t esz) {
@@ -1987,8 +2025,8 @@ void launch_ttm_panel(const void* x, const ModeView& v, const double* U, int R, 
                                                                  g.kt_per_split, g.tw, U, R, Z, norm_part, res_part);
   }
   ProfScope prof(KKind::Layout, s, 0.0, 0.0);
-  if (NORM) reduce_kernel<<<1, 256, 0, s>>>(norm_part, blocks, norm_out);
-  if (RESE) reduce_kernel<<<1, 256, 0, s>>>(res_part, blocks, res_out);
+  if (NORM) finish_sum(norm_part, blocks, norm_out, s);
+  if (RESE) finish_sum(res_part, blocks, res_out, s);
 }
 
 bool ttm_reg64_applies(Elem t, const ModeView& v, int R) {
@@ -2016,7 +2054,7 @@ void launch_ttm_reg64(const T* x, const ModeView& v, const double* U, int R, dou
   }
   if (NN) {
     ProfScope prof(KKind::Layout, s, 0.0, 0.0);
-    reduce_kernel<<<1, 256, 0, s>>>(norm_part, blocks, norm_out);
+    finish_sum(norm_part, blocks, norm_out, s);
   }
 }
 
@@ -2108,8 +2146,8 @@ void launch_ttm_reg(const float* x, const ModeView& v, int mode, const double* U
 #undef HT_TR
   }
   ProfScope prof(KKind::Layout, s, 0.0, 0.0);
-  if (NN) reduce_kernel<<<1, 256, 0, s>>>(norm_part, blocks, norm_out);
-  if (RR) reduce_kernel<<<1, 256, 0, s>>>(res_part, blocks, res_out);
+  if (NN) finish_sum(norm_part, blocks, norm_out, s);
+  if (RR) finish_sum(res_part, blocks, res_out, s);
 }
 
 void ttm_contract_f32(const void* x, Elem t, const ModeView& v, const double* U, int R, float* Z, double* norm_part,
