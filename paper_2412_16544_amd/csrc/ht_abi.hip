@@ -482,11 +482,29 @@ ht_status check_device() {
   return HT_OK;
 }
 
+// Device time of a call.  The two events are created once per host thread (and
+// again when the thread's current device changes) instead of per call.
 struct Timer {
   hipEvent_t a = nullptr, b = nullptr;
   hipStream_t s;
   explicit Timer(hipStream_t s_) : s(s_) {
-    if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) (void)hipEventRecord(a, s);
+    thread_local hipEvent_t ea = nullptr, eb = nullptr;
+    thread_local int dev = -1;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return;
+    if (cur != dev || ea == nullptr || eb == nullptr) {
+      if (ea) (void)hipEventDestroy(ea);
+      if (eb) (void)hipEventDestroy(eb);
+      ea = eb = nullptr;
+      if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+      }
+      dev = cur;
+    }
+    a = ea;
+    b = eb;
+    (void)hipEventRecord(a, s);
   }
   float stop() {
     float ms = 0.f;
@@ -496,10 +514,6 @@ struct Timer {
       (void)hipEventElapsedTime(&ms, a, b);
     }
     return ms;
-  }
-  ~Timer() {
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
   }
 };
 
