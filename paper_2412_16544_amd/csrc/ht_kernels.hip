@@ -370,6 +370,10 @@ __global__ __launch_bounds__(256) void gram_small_reduce_kernel(const double* __
 constexpr int PER_PANEL = GBK * GB / 256;     // prefetched values per thread (16)
 constexpr int ZLD = GBK + 1;
 constexpr int kTtmMaxBlocks = 4096;
+// The register-direct contractions run one resident round of workgroups (256
+// compute units x 4 workgroups of four waves), each looping over its blocks, so
+// the U staging of a workgroup is spread over several blocks.
+constexpr int kRegMaxBlocks = 1024;
 
 template <typename T>
 struct PanelLoader {
@@ -2130,7 +2134,7 @@ void launch_ttm_reg(const float* x, const ModeView& v, int mode, const double* U
   const int ti = ((int)((v.m + 15) / 16) + 1) & ~1;  // 2, 4, 6 or 8 row tiles
   const int rt = (R + 15) / 16;
   const int64_t nblk = reg_blocks(v, mode);
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kTtmMaxBlocks, (nblk + 3) / 4));
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kRegMaxBlocks, (nblk + 3) / 4));
   const size_t lds = (size_t)16 * ti * (16 * rt + 1) * sizeof(float);
   {
     ProfScope prof(KKind::TtmContract32Reg, s, fl, by);
