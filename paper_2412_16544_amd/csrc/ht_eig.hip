@@ -71,6 +71,16 @@ __device__ __forceinline__ double dpp_wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// sum over each half-wave, left in lanes 31 and 63
+__device__ __forceinline__ double dpp_half_sum(double v) {
+  v += dpp_mov<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_mov<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_mov<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_mov<0x118, 0xf>(v);  // row_shr:8  -> lane 15 of each row holds its row sum
+  v += dpp_mov<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  return v;
+}
+
 // sum over each aligned group of 4 lanes, returned to the 4 lanes
 __device__ __forceinline__ double dpp_quad_sum(double v) {
   v += dpp_mov<0xB1, 0xf>(v);  // quad_perm [1,0,3,2]
@@ -1348,10 +1358,12 @@ __device__ __noinline__ bool lz_certify(const EigJob& J, const LzView& v, int m,
 // outputs untouched.  The last 64 doubles of the scratch record the attempt:
 // [8] = steps (negative when the decision was not proven), [9] = checks.
 // MV selects the product G q: 0 (k <= 128) G stays in registers, thread (i, h)
-// holding column i's rows 32 h .. 32 h + 31; 1 (k <= kLzLdsK) two halves of each
-// column streamed from the cache; 2 (k <= kLzMaxK) whole columns streamed, the
-// Krylov basis in global scratch.  G is symmetric, so column i serves row i and
-// every load is coalesced.
+// holding column i's rows 32 h .. 32 h + 31 (G is symmetric, so column i serves
+// row i); 1 (k <= kLzLdsK) the tiles of the register Householder path that meet
+// the lower triangle stay in registers, row sums over each half-wave by DPP and
+// the transposed sums of the strictly lower tiles per wave through LDS; 2
+// (k <= kLzMaxK) whole columns streamed from the cache (coalesced), the Krylov
+// basis in global scratch.
 template <int MV>
 __device__ __noinline__ bool lanczos_solve(const EigJob& J, double* lds, double* sh, double* red, int* ctl) {
   constexpr bool QL = MV < 2;
@@ -1363,8 +1375,8 @@ __device__ __noinline__ bool lanczos_solve(const EigJob& J, double* lds, double*
   double* Q = QL ? lds : c.hv;  // Krylov vector v at Q + v k
   double* wv = lds + (QL ? (kLzSteps + 1) * k : 0);
   double* qv = wv + k;      // the scaled vector the product reads (MV == 2)
-  double* part = qv + k;    // 512 partial sums of the product
-  double* hc = part + 512;  // projection coefficients
+  double* part = qv + k;    // partial sums of the product (2048 >= 16 TA + NW 32 TB)
+  double* hc = part + 2048;  // projection coefficients
   double* al = hc + kLzSteps;
   double* be = al + kLzSteps;
   double* e2 = be + kLzSteps;
@@ -1382,14 +1394,26 @@ __device__ __noinline__ bool lanczos_solve(const EigJob& J, double* lds, double*
   if (!(tr > 0.0) || !(tr < DBL_MAX)) return false;
   const double guard = 64.0 * k * DBL_EPSILON * tr;
 
-  // MV == 0: rows 32 h .. 32 h + 31 of column i, kept for the whole solve
-  double g[MV == 0 ? 32 : 1];
+  // MV == 0: rows 32 h .. 32 h + 31 of column i; MV == 1: entry (16 a + trow,
+  // 32 b + tc) of every stored tile (a, b), b <= a / 2; kept for the whole solve
+  constexpr int TA = kRegRowTiles, TB = (TA + 1) / 2;
+  double g[MV == 0 ? 32 : MV == 1 ? tile_base(TA) : 1];
+  const int trow = tid >> 5, tc = tid & 31;
   if constexpr (MV == 0) {
     const int i = tid & 127, h = tid >> 7;
 #pragma unroll
     for (int q = 0; q < 32; ++q) {
       const int l = 32 * h + q;
       g[q] = (i < k && l < k) ? G[(size_t)l * k + i] : 0.0;
+    }
+  } else if constexpr (MV == 1) {
+#pragma unroll
+    for (int a = 0; a < TA; ++a) {
+#pragma unroll
+      for (int b = 0; b <= a / 2; ++b) {
+        const int i = 16 * a + trow, l = 32 * b + tc;
+        g[tile_base(a) + b] = (i < k && l < k) ? G[(size_t)i * k + l] : 0.0;
+      }
     }
   }
 
@@ -1440,31 +1464,44 @@ __device__ __noinline__ bool lanczos_solve(const EigJob& J, double* lds, double*
         }
         part[tid] = (a0 + a1) * scl;
       } else {
-        const int i = tid & 255, h = tid >> 8;
-        const int half = (k + 1) >> 1;
-        const int l0 = h ? half : 0, l1 = h ? k : half;
-        double a0 = 0.0, a1 = 0.0;
-        if (i < k) {
-          int l = l0;
-          for (; l + 16 <= l1; l += 16) {
-            double gv[16];
+        // row sums of the stored tiles (each row's lanes are one half-wave) and the
+        // transposed sums of the strictly lower tiles (b < a / 2), per wave
+        double xr[TA], xc[TB];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) gv[q] = G[(size_t)(l + q) * k + i];
+        for (int a = 0; a < TA; ++a) xr[a] = 16 * a + trow < k ? wv[16 * a + trow] : 0.0;
 #pragma unroll
-            for (int q = 0; q < 16; q += 2) {
-              a0 = fma(gv[q], wv[l + q], a0);
-              a1 = fma(gv[q + 1], wv[l + q + 1], a1);
-            }
+        for (int b = 0; b < TB; ++b) xc[b] = 32 * b + tc < k ? wv[32 * b + tc] : 0.0;
+        double colacc[TB];
+#pragma unroll
+        for (int b = 0; b < TB; ++b) colacc[b] = 0.0;
+#pragma unroll
+        for (int a = 0; a < TA; ++a) {
+          double racc = 0.0;
+#pragma unroll
+          for (int b = 0; b <= a / 2; ++b) {
+            racc = fma(g[tile_base(a) + b], xc[b], racc);
+            if (b < a / 2) colacc[b] = fma(g[tile_base(a) + b], xr[a], colacc[b]);
           }
-          for (; l < l1; ++l) a0 = fma(G[(size_t)l * k + i], wv[l], a0);
+          racc = dpp_half_sum(racc);
+          if ((lane & 31) == 31) part[16 * a + trow] = racc * scl;
         }
-        part[tid] = (a0 + a1) * scl;
+#pragma unroll
+        for (int b = 0; b < TB; ++b) {
+          const double cv = colacc[b] + __shfl_xor(colacc[b], 32);
+          if (lane < 32) part[16 * TA + wave * (32 * TB) + 32 * b + tc] = cv * scl;
+        }
       }
       for (int i = tid; i < k; i += ET) Q[(size_t)(m - 1) * k + i] = wv[i] * scl;
       __syncthreads();
       if (tid < k) {
-        wv[tid] = MV == 0 ? (part[tid] + part[128 + tid]) + (part[256 + tid] + part[384 + tid])
-                          : part[tid] + part[256 + tid];
+        if (MV == 0) {
+          wv[tid] = (part[tid] + part[128 + tid]) + (part[256 + tid] + part[384 + tid]);
+        } else {
+          double c = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) c += part[16 * TA + w * (32 * TB) + tid];
+          wv[tid] = part[tid] + c;
+        }
       }
       __syncthreads();
     }
