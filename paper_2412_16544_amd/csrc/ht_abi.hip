@@ -427,15 +427,23 @@ Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, 
       cur.t = Elem::F32;
     } else {
       double* ssp = h->ssnode + (size_t)node * 2 * ht::kSumsqBlocks;
-      if (energy) ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), ssp, energy + 2 * node, s);
       if (expl) (*expl)[node] = 0;
-      if (norm_out != nullptr)
-        ht::ttm_contract_norm(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, h->nrmpart, norm_out, s);
-      else
-        ht::ttm_contract(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, s);
+      // the energies before and after the contraction, from the contraction itself
+      // where it can, else by two sums of squares
+      const bool fused = energy != nullptr && norm_out == nullptr &&
+                         ht::ttm_contract_sq(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, ssp,
+                                             energy + 2 * node, ssp + ht::kSumsqBlocks, energy + 2 * node + 1,
+                                             ht::kSumsqBlocks, s);
+      if (!fused) {
+        if (energy) ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), ssp, energy + 2 * node, s);
+        if (norm_out != nullptr)
+          ht::ttm_contract_norm(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, h->nrmpart, norm_out, s);
+        else
+          ht::ttm_contract(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, s);
+      }
       cur.ptr = dst;
       cur.t = Elem::F64;
-      if (energy) {
+      if (energy && !fused) {
         cur.modes[k] = h->rank[node];
         ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), ssp + ht::kSumsqBlocks, energy + 2 * node + 1, s);
       }

@@ -62,6 +62,12 @@ void ttm_contract(const void* x, Elem t, const ModeView& v, const double* U, int
 size_t ttm_norm_partials();
 void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z, double* norm_part,
                        double* norm_out, hipStream_t s);
+// For modes of more than 128 rows: the contraction together with ||X||^2 and
+// ||Z||^2 (FP64) from its own workgroup partials (in_part and out_part hold at least
+// max_parts doubles each).  Returns false, launching nothing, for other shapes or
+// when more than max_parts workgroups would be needed.
+bool ttm_contract_sq(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z, double* in_part,
+                     double* in_out, double* out_part, double* out_out, int max_parts, hipStream_t s);
 // ---- mixed form: FP32 matrix cores, FP64 sums (m <= kResidGramMaxM) --------------
 // Z (FP32) = U^T X; optionally ||X||^2 and the explicit residual energy
 // ||X - U (U^T X)||^2 (the part this contraction discards), both FP64; the partial

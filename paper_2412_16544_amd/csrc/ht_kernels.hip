@@ -1418,10 +1418,12 @@ constexpr int TUS = 65;  // LDS row stride (doubles) of the staged U chunk of th
 // --------------------------------------------------------------------------
 constexpr int kDirectLdsDoubles = 19968;  // U chunk: chunk x (RP + 1) doubles of dynamic LDS
 
-template <typename T>
+// SQ: also the workgroup partials of ||X||^2 (in_part) and ||Z||^2 (out_part)
+template <typename T, bool SQ>
 __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
                                                          const double* __restrict__ U, int R, int chunk,
-                                                         double* __restrict__ Z) {
+                                                         double* __restrict__ Z, double* __restrict__ in_part,
+                                                         double* __restrict__ out_part) {
   extern __shared__ double sU[];  // sU[a][r] (chunk rows of ULD), then the wave partials
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int RP = (R + 15) & ~15, ULD = RP + 1, rt = RP >> 4;
@@ -1433,6 +1435,7 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
   d4 acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  double xsq = 0.0;
   for (int64_t a0 = 0; a0 < m; a0 += chunk) {
     const int ac = (int)min<int64_t>(chunk, m - a0);
     const int ac4 = (ac + 3) & ~3;
@@ -1455,6 +1458,7 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
         const int st = wave + 4 * (j + q);
         if (st < nst) {
           const double bv = b[q];
+          if (SQ) xsq = fma(bv, bv, xsq);
           const int an = 4 * (st + 32) + kr;
           b[q] = (cv && an < ac) ? static_cast<double>(xp[(int64_t)an * S]) : 0.0;
           const double* ua = sU + (4 * st + kr) * ULD + (lane & 15);
@@ -1476,6 +1480,7 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
       }
   }
   __syncthreads();
+  double zsq = 0.0;
   if (wave == 0 && cv) {
     const int64_t p = c / S, sidx = c - (c / S) * S;
 #pragma unroll
@@ -1487,9 +1492,23 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
 #pragma unroll
           for (int w = 0; w < 3; ++w) z += sU[((w * 4 + t) * 4 + v) * 64 + lane];
           const int r = t * 16 + MA<double>::row(lane, v);
-          if (r < R) Z[(p * R + r) * S + sidx] = z;
+          if (r < R) {
+            Z[(p * R + r) * S + sidx] = z;
+            if (SQ) zsq = fma(z, z, zsq);
+          }
         }
       }
+    }
+  }
+  if (SQ) {
+    __shared__ double red[4];
+    xsq = wave_sum(xsq);
+    zsq = wave_sum(zsq);
+    if (lane == 0) red[wave] = xsq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      in_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+      out_part[blockIdx.x] = zsq;
     }
   }
 }
@@ -2000,6 +2019,45 @@ void ttm_contract(const void* x, Elem t, const ModeView& v, const double* U, int
   ttm_contract_norm(x, t, v, U, R, Z, nullptr, nullptr, s);
 }
 
+// one launch of the direct contraction (modes of more than 128 rows); with SQ also
+// ||X||^2 and ||Z||^2 from the workgroup partials
+template <bool SQ>
+void launch_ttm_direct(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z, double* in_part,
+                       double* in_out, double* out_part, double* out_out, hipStream_t s) {
+  const int64_t K = v.P * v.S;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_direct_kernel<float, SQ>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kDirectLdsDoubles * (int)sizeof(double));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_direct_kernel<double, SQ>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kDirectLdsDoubles * (int)sizeof(double));
+    attr = true;
+  }
+  const unsigned blocks = (unsigned)((K + 15) / 16);
+  const int RP = (R + 15) & ~15;
+  // few column blocks (transfer nodes): all of U in one chunk; many: at most 64 KiB,
+  // two workgroups per compute unit
+  const int cap = blocks >= 512 ? 8192 : kDirectLdsDoubles;
+  const int chunk = (int)std::min<int64_t>(((cap / (RP + 1)) / 4) * 4, (v.m + 3) & ~3);
+  // the wave partials (3 x 4 x 4 x 64 doubles) reuse the same space at the end
+  const size_t lds = (size_t)std::max<int64_t>((int64_t)chunk * (RP + 1), 3 * 4 * 4 * 64) * sizeof(double);
+  {
+    ProfScope prof(KKind::TtmContract, s, 2.0 * R * v.m * (double)K,
+                   (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8);
+    if (t == Elem::F32)
+      ttm_direct_kernel<float, SQ><<<blocks, 256, lds, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R, chunk, Z,
+                                                            in_part, out_part);
+    else
+      ttm_direct_kernel<double, SQ><<<blocks, 256, lds, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U, R, chunk,
+                                                             Z, in_part, out_part);
+  }
+  if (SQ) {
+    ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+    finish_sum(in_part, (int)blocks, in_out, s);
+    finish_sum(out_part, (int)blocks, out_out, s);
+  }
+}
+
 size_t ttm_norm_partials() { return kTtmMaxBlocks; }
 
 // one launch of the panel contraction: blocks over column tiles, optional norm and
@@ -2100,28 +2158,15 @@ void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U
     return;
   }
   if (norm_part != nullptr) sumsq(x, t, v.P * v.m * v.S, norm_part, norm_out, s);
-  ProfScope prof(KKind::TtmContract, s, 2.0 * R * v.m * (double)K,
-                 (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8);
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_direct_kernel<float>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kDirectLdsDoubles * (int)sizeof(double));
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_direct_kernel<double>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kDirectLdsDoubles * (int)sizeof(double));
-    attr = true;
-  }
-  const unsigned blocks = (unsigned)((K + 15) / 16);
-  const int RP = (R + 15) & ~15;
-  // few column blocks (transfer nodes): all of U in one chunk; many: at most 64 KiB,
-  // two workgroups per compute unit
-  const int cap = blocks >= 512 ? 8192 : kDirectLdsDoubles;
-  const int chunk = (int)std::min<int64_t>(((cap / (RP + 1)) / 4) * 4, (v.m + 3) & ~3);
-  // the wave partials (3 x 4 x 4 x 64 doubles) reuse the same space at the end
-  const size_t lds = (size_t)std::max<int64_t>((int64_t)chunk * (RP + 1), 3 * 4 * 4 * 64) * sizeof(double);
-  if (t == Elem::F32)
-    ttm_direct_kernel<float><<<blocks, 256, lds, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R, chunk, Z);
-  else
-    ttm_direct_kernel<double><<<blocks, 256, lds, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U, R, chunk, Z);
+  launch_ttm_direct<false>(x, t, v, U, R, Z, nullptr, nullptr, nullptr, nullptr, s);
+}
+
+bool ttm_contract_sq(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z, double* in_part,
+                     double* in_out, double* out_part, double* out_out, int max_parts, hipStream_t s) {
+  const int64_t K = v.P * v.S;
+  if (v.m <= GB || (K + 15) / 16 > max_parts) return false;
+  launch_ttm_direct<true>(x, t, v, U, R, Z, in_part, in_out, out_part, out_out, s);
+  return true;
 }
 
 // the register-direct FP32 contraction applies to FP32 level tensors whose column
