@@ -65,7 +65,9 @@ def test_resid_gram(P, m, S, R, dtype):
                                      (3, 96, 1024, 12), (2, 128, 64, 64), (5, 40, 96, 20), (2, 96, 288, 47),
                                      (64, 8, 16384, 3), (3, 4, 32, 1),
                                      # modes of more than 128 rows: U staged once, or in chunks (m = 600)
-                                     (16, 182, 42, 40), (3, 600, 50, 40), (2, 131, 1, 64)])
+                                     (16, 182, 42, 40), (3, 600, 50, 40), (2, 131, 1, 64),
+                                     # small modes: one column per thread
+                                     (5824, 42, 1, 30), (1000, 3, 1, 3), (3, 47, 9, 47)])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_ttm_contract(P, m, S, R, dtype):
     g = rng(P + m + S + R)
@@ -89,7 +91,9 @@ MIXED_SHAPES = [(3, 96, 1000, 12), (5, 9, 7, 3), (100, 16, 1, 5), (2, 128, 33, 6
                 (3, 96, 1024, 12), (2, 128, 64, 64), (5, 40, 96, 20), (3, 4, 32, 1), (2, 96, 288, 47),
                 (64, 8, 16384, 3),
                 # runs of 1-4 columns: 16 slabs per register block (partial last block, several per wave)
-                (100, 96, 3, 14), (37, 64, 1, 5), (50, 48, 2, 20), (19, 96, 4, 32), (300000, 40, 1, 3)]
+                (100, 96, 3, 14), (37, 64, 1, 5), (50, 48, 2, 20), (19, 96, 4, 32), (300000, 40, 1, 3),
+                # modes of at most 48 rows outside the register kernels: one column per thread
+                (5824, 42, 1, 30), (220000, 3, 1, 3), (33, 47, 5, 47), (3000, 1, 2, 1)]
 
 
 def near_subspace(P, m, S, R, seed, dtype=np.float32):
