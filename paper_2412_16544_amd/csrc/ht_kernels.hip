@@ -1514,6 +1514,81 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
 }
 
 // --------------------------------------------------------------------------
+// Contraction of a mode of at most kSmallModeM rows (such as a channel mode), one
+// unfolding column per thread in FP64: z = U^T x (stored as CT), optionally
+// ||x||^2 and the residual energy ||x - U z||^2 of the column, summed per
+// workgroup in a fixed order.  Such modes have many columns of a few values each,
+// which the panel kernel's 128-row tiles would mostly leave empty.
+// --------------------------------------------------------------------------
+constexpr int kSmallModeM = 8;
+
+template <typename T, typename CT, bool NORM, bool RESE>
+__global__ __launch_bounds__(256) void ttm_small_kernel(const T* __restrict__ X, int64_t P, int m, int64_t S,
+                                                        const double* __restrict__ U, int R, CT* __restrict__ Z,
+                                                        double* __restrict__ norm_part,
+                                                        double* __restrict__ res_part) {
+  __shared__ double sUs[kSmallModeM * kSmallModeM];  // sUs[a * R + r]
+  for (int e = threadIdx.x; e < m * R; e += 256) {
+    const int a = e / R, r = e - (e / R) * R;
+    sUs[e] = U[a + (int64_t)r * m];
+  }
+  __syncthreads();
+  const int64_t K = P * S;
+  double nrm = 0.0, res = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < K; c += (int64_t)gridDim.x * 256) {
+    const int64_t p = c / S, sx = c - (c / S) * S;
+    const T* xp = X + p * m * S + sx;
+    double x[kSmallModeM], y[kSmallModeM];
+#pragma unroll
+    for (int a = 0; a < kSmallModeM; ++a) {
+      x[a] = a < m ? static_cast<double>(xp[(int64_t)a * S]) : 0.0;
+      y[a] = 0.0;
+    }
+    if (NORM) {
+#pragma unroll
+      for (int a = 0; a < kSmallModeM; ++a) nrm = fma(x[a], x[a], nrm);
+    }
+#pragma unroll
+    for (int r = 0; r < kSmallModeM; ++r) {
+      if (r < R) {
+        double z = 0.0;
+#pragma unroll
+        for (int a = 0; a < kSmallModeM; ++a)
+          if (a < m) z = fma(sUs[a * R + r], x[a], z);
+        Z[(p * R + r) * S + sx] = static_cast<CT>(z);
+        if (RESE) {
+#pragma unroll
+          for (int a = 0; a < kSmallModeM; ++a)
+            if (a < m) y[a] = fma(sUs[a * R + r], z, y[a]);
+        }
+      }
+    }
+    if (RESE) {
+#pragma unroll
+      for (int a = 0; a < kSmallModeM; ++a) {
+        const double d = x[a] - y[a];
+        res = fma(d, d, res);
+      }
+    }
+  }
+  if (NORM || RESE) {
+    __shared__ double red[8];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (NORM) nrm = wave_sum(nrm);
+    if (RESE) res = wave_sum(res);
+    if (lane == 0) {
+      red[wave] = nrm;
+      red[4 + wave] = res;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (NORM) norm_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+      if (RESE) res_part[blockIdx.x] = (red[4] + red[5]) + (red[6] + red[7]);
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
 // TTM expansion out[p, a, s] = (M[p,a,s] -) sum_t U[a, t] Z[p, t, s]  (FP64 MFMA)
 // One wave per 16 columns and 64 rows of a (blockIdx.y); all of the wave's Z
 // operands (R <= 64: at most 16 steps of 4) are loaded before the first product.
@@ -2058,6 +2133,24 @@ void launch_ttm_direct(const void* x, Elem t, const ModeView& v, const double* U
   }
 }
 
+// one launch of the small-mode contraction (m <= kSmallModeM), at most kTtmMaxBlocks
+// workgroup partials
+template <typename T, typename CT, bool NORM, bool RESE>
+void launch_ttm_small(const void* x, const ModeView& v, const double* U, int R, CT* Z, double* norm_part,
+                      double* norm_out, double* res_part, double* res_out, KKind kind, double flops, double bytes,
+                      hipStream_t s) {
+  const int64_t K = v.P * v.S;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kTtmMaxBlocks, (K + 255) / 256));
+  {
+    ProfScope prof(kind, s, flops, bytes);
+    ttm_small_kernel<T, CT, NORM, RESE><<<blocks, 256, 0, s>>>(static_cast<const T*>(x), v.P, (int)v.m, v.S, U, R, Z,
+                                                               norm_part, res_part);
+  }
+  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+  if (NORM) finish_sum(norm_part, blocks, norm_out, s);
+  if (RESE) finish_sum(res_part, blocks, res_out, s);
+}
+
 size_t ttm_norm_partials() { return kTtmMaxBlocks; }
 
 // one launch of the panel contraction: blocks over column tiles, optional norm and
@@ -2140,6 +2233,24 @@ void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U
       }
       return;
     }
+    if (v.m <= kSmallModeM && R <= kSmallModeM) {
+      if (t == Elem::F32) {
+        if (nrm)
+          launch_ttm_small<float, double, true, false>(x, v, U, R, Z, norm_part, norm_out, nullptr, nullptr, kd, fl,
+                                                       by, s);
+        else
+          launch_ttm_small<float, double, false, false>(x, v, U, R, Z, nullptr, nullptr, nullptr, nullptr, kd, fl, by,
+                                                        s);
+      } else {
+        if (nrm)
+          launch_ttm_small<double, double, true, false>(x, v, U, R, Z, norm_part, norm_out, nullptr, nullptr, kd, fl,
+                                                        by, s);
+        else
+          launch_ttm_small<double, double, false, false>(x, v, U, R, Z, nullptr, nullptr, nullptr, nullptr, kd, fl,
+                                                         by, s);
+      }
+      return;
+    }
     if (t == Elem::F32) {
       if (nrm)
         launch_ttm_panel<float, double, true, false>(x, v, U, R, Z, norm_part, norm_out, nullptr, nullptr, kd, fl, by,
@@ -2215,6 +2326,23 @@ void ttm_contract_f32(const void* x, Elem t, const ModeView& v, const double* U,
     if (nrm) launch_ttm_reg<true, true>(xf, v, mode, U, R, Z, norm_part, norm_out, res_part, res_out, fl, by, s);
     else if (rese) launch_ttm_reg<false, true>(xf, v, mode, U, R, Z, nullptr, nullptr, res_part, res_out, fl, by, s);
     else launch_ttm_reg<false, false>(xf, v, mode, U, R, Z, nullptr, nullptr, nullptr, nullptr, fl, by, s);
+  } else if (v.m <= kSmallModeM && R <= kSmallModeM) {
+#define HT_SM32(TT, NN, RR)                                                                                   \
+  launch_ttm_small<TT, float, NN, RR>(x, v, U, R, Z, NN ? norm_part : nullptr, NN ? norm_out : nullptr,       \
+                                      RR ? res_part : nullptr, RR ? res_out : nullptr, KKind::TtmContract32, fl, \
+                                      by, s)
+    if (t == Elem::F32) {
+      if (nrm && rese) HT_SM32(float, true, true);
+      else if (rese) HT_SM32(float, false, true);
+      else if (nrm) HT_SM32(float, true, false);
+      else HT_SM32(float, false, false);
+    } else {
+      if (nrm && rese) HT_SM32(double, true, true);
+      else if (rese) HT_SM32(double, false, true);
+      else if (nrm) HT_SM32(double, true, false);
+      else HT_SM32(double, false, false);
+    }
+#undef HT_SM32
   } else if (t == Elem::F32) {
     if (nrm && rese) HT_TTM32(float, true, true);
     else if (rese) HT_TTM32(float, false, true);
