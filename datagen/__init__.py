@@ -258,7 +258,11 @@ class FieldSpec:
     over ``len(grid)`` spatial modes and a channel mode of size ``channels``.
     mu drifts by ``drift * k * delta`` (delta = +-1), om by a factor
     (1 + drift * k); with ``reflect`` both are reflected into [mu_lo, mu_hi]
-    and [om_lo, om_hi].
+    and [om_lo, om_hi].  With ``period`` > 0 the drift oscillates instead:
+    mu = mu0 + drift * delta * sin(2 pi k / period), om = om0 (1 + drift *
+    sin(2 pi k / period)).  With ``active0`` > 0 only the first ``active0`` terms
+    are present at batch 0 and term t >= active0 switches on at batch
+    (t - active0 + 1) * ``onset_every`` (its coefficients are zero before).
     """
 
     grid: Tuple[int, ...]
@@ -277,6 +281,9 @@ class FieldSpec:
     mu_hi: float = 0.9
     om_lo: float = 1.0
     om_hi: float = 6.0
+    period: int = 0
+    active0: int = 0
+    onset_every: int = 0
 
     @property
     def n(self) -> Tuple[int, ...]:
@@ -310,8 +317,13 @@ def _field_params(spec: FieldSpec) -> dict:
 def field_mode_functions(spec: FieldSpec, k: int) -> List[np.ndarray]:
     """Per spatial mode m, the (terms x n_m) matrix of 1-D factors at batch k."""
     p = _field_params(spec)
-    mu = p["mu0"] + spec.drift * k * p["delta"]
-    om = p["om0"] * (1.0 + spec.drift * k)
+    if spec.period > 0:
+        ph = math.sin(2.0 * math.pi * k / spec.period)
+        mu = p["mu0"] + spec.drift * ph * p["delta"]
+        om = p["om0"] * (1.0 + spec.drift * ph)
+    else:
+        mu = p["mu0"] + spec.drift * k * p["delta"]
+        om = p["om0"] * (1.0 + spec.drift * k)
     if spec.reflect:
         mu = _reflect(mu, spec.mu_lo, spec.mu_hi)
         om = _reflect(om, spec.om_lo, spec.om_hi)
@@ -358,29 +370,33 @@ def field_96_spec(n_batches: int = 20, N: int = 32, drift: float = 3e-4) -> Fiel
     [0.2, 0.5]: at eps = 1e-4 every rank then stays <= 48 over 20 batches.  At
     1% per batch (widths [0.05, 0.2]) the (1,2) transfer rank reaches 194 and no
     batch is ever skipped; that setting is kept available through ``drift``.
+    Generated with ``exact_field_batch`` (host) or ``datagen.gpu`` (device).
     """
     return FieldSpec(grid=(96, 96, 96), channels=3, terms=12, N=N, n_batches=n_batches,
                      drift=drift, seed=2, batch_seed0=200, nu=0.0, w_lo=0.2, w_hi=0.5)
 
 
-def field_48_spec(n_batches: int = 100, N: int = 16, nu: float = 1e-6, drift: float = 1e-4) -> FieldSpec:
-    """48^4 grid x 4 channels, 24 terms, drift with reflection, relative noise nu.
+def field_48_spec(n_batches: int = 100, N: int = 16, nu: float = 1e-6) -> FieldSpec:
+    """48^4 grid x 4 channels, 16 terms, relative noise nu (seeds 5, 500+k).
 
-    Drift defaults to 0.01% per batch with bump widths in [0.2, 0.5]: at eps = 1e-4
-    the ranks then stay below 64 (24 at the first batch, the (1,2,3) transfer node
-    at 49 after three updates, the fourth batch skipped).  At 0.03% its rank is
-    already 61 after three updates, and at 2% per batch every batch adds about 24
-    directions to the upper transfer nodes."""
-    return FieldSpec(grid=(48, 48, 48, 48), channels=4, terms=24, N=N, n_batches=n_batches,
-                     drift=drift, seed=5, batch_seed0=500, nu=nu, reflect=True, w_lo=0.2, w_hi=0.5)
+    Six terms are present from the first batch and one more switches on every
+    nine batches (the last at batch 90); centres and frequencies oscillate with
+    amplitude 0.1% and a period of 25 batches; bump widths in [0.2, 0.5].  At
+    eps = 1e-4 the ranks then stay below 64 over 100 batches with about a quarter
+    of the batches updating.  A drift that keeps growing (0.01% per batch and up,
+    24 terms) passes rank 64 at the (1,2,3) transfer node within 12 batches.
+    Generated with ``exact_field_batch`` (host) or ``datagen.gpu`` (device)."""
+    return FieldSpec(grid=(48, 48, 48, 48), channels=4, terms=16, N=N, n_batches=n_batches,
+                     drift=1e-3, seed=5, batch_seed0=500, nu=nu, w_lo=0.2, w_hi=0.5,
+                     period=25, active0=6, onset_every=9)
 
 
 def field_96_stream(n_batches: int = 20, N: int = 32) -> Iterator[np.ndarray]:
-    return separable_field_stream(field_96_spec(n_batches, N))
+    return exact_field_stream(field_96_spec(n_batches, N))
 
 
 def field_48_stream(n_batches: int = 100, N: int = 16, nu: float = 1e-6) -> Iterator[np.ndarray]:
-    return separable_field_stream(field_48_spec(n_batches, N, nu))
+    return exact_field_stream(field_48_spec(n_batches, N, nu))
 
 
 # --------------------------------------------------------------------------- #
@@ -419,3 +435,135 @@ def multi_stream_specs(count: int = 64, seed0: int = 4000, n_batches: int = 11,
                                  batch_seed0=(seed0 + s) * 100, nu=nu, grow_at=(4, 8),
                                  grow_by=2, grow_scale=0.1))
     return specs
+
+
+# --------------------------------------------------------------------------- #
+# Separable fields that the host and the GPU generate bit for bit alike
+# --------------------------------------------------------------------------- #
+#
+# A batch of the drifting field is sum_t A_t (x) B_t with A_t[s, p1] the sample's
+# coefficient times the 1-D factors of the first half of the spatial modes and
+# B_t[p2] the factors of the rest times the channel vector.  A_t and B_t are
+# rounded to 24-bit fixed point (a power-of-two scale per batch), so every product
+# A_t[s, p1] B_t[p2] and every partial sum over the T <= 32 terms is an exact
+# FP64 number: the signal is the same in any summation order (a BLAS product on
+# the host, a loop on the GPU).  The noise is a counter-based generator: SplitMix64
+# (Steele, Lea & Flood, "Fast splittable pseudorandom number generators", 2014) of
+# the element's counter, whose four 16-bit fields give an Irwin-Hall sum
+# g = (n0 + n1 + n2 + n3 - 131070) 2^-16 (mean 0, variance ~1/3), again exact.  The
+# element is float32(signal + scale * g) with one FP64 multiply and one add.
+
+GOLDEN_GAMMA = 0x9E3779B97F4A7C15
+_MIX1 = 0xBF58476D1CE4E5B9
+_MIX2 = 0x94D049BB133111EB
+FIXED_BITS = 24
+
+
+def splitmix64(counter: np.ndarray) -> np.ndarray:
+    """SplitMix64 output for state (counter + 1) * gamma (uint64 arithmetic mod 2^64)."""
+    with np.errstate(over="ignore"):
+        z = (counter.astype(np.uint64) + np.uint64(1)) * np.uint64(GOLDEN_GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(_MIX1)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(_MIX2)
+        return z ^ (z >> np.uint64(31))
+
+
+def noise_unit(key: int, start: int, count: int) -> np.ndarray:
+    """Irwin-Hall noise g for elements [start, start + count) of the batch with this key."""
+    c = np.arange(start, start + count, dtype=np.uint64) + np.uint64((int(key) << 40) & (2 ** 64 - 1))
+    z = splitmix64(c)
+    m = np.uint64(0xFFFF)
+    s = (z & m) + ((z >> np.uint64(16)) & m) + ((z >> np.uint64(32)) & m) + (z >> np.uint64(48))
+    return (s.astype(np.int64) - 131070).astype(np.float64) * 2.0 ** -16
+
+
+def _fixed(x: np.ndarray) -> np.ndarray:
+    """x rounded to FIXED_BITS-bit fixed point with a power-of-two scale above max |x|."""
+    mx = float(np.max(np.abs(x)))
+    if mx == 0.0:
+        return np.zeros_like(x)
+    e = math.frexp(mx)[1]               # mx < 2^e
+    q = 2.0 ** (e - FIXED_BITS)
+    return np.round(x / q) * q
+
+
+def term_mask(spec: FieldSpec, k: int) -> np.ndarray:
+    """1 for the terms present at batch k, 0 for those not yet switched on."""
+    m = np.ones(spec.terms)
+    if spec.active0 > 0:
+        for t in range(spec.active0, spec.terms):
+            if k < (t - spec.active0 + 1) * spec.onset_every:
+                m[t] = 0.0
+    return m
+
+
+@dataclass
+class FieldFactors:
+    """One batch of an exactly reproducible field: A (T, N, P1), B (T, P2), noise scale and key."""
+    A: np.ndarray
+    B: np.ndarray
+    scale: float
+    key: int
+    shape: Tuple[int, ...]
+
+
+def exact_field_factors(spec: FieldSpec, k: int) -> FieldFactors:
+    p = _field_params(spec)
+    fs = field_mode_functions(spec, k)
+    t = spec.terms
+    m = len(spec.grid)
+    split = (m + 1) // 2
+    left = fs[0]
+    for f in fs[1:split]:
+        left = (left[:, :, None] * f[:, None, :]).reshape(t, -1)
+    right = p["v"]
+    for f in reversed(fs[split:]):
+        right = (f[:, :, None] * right[:, None, :]).reshape(t, -1)
+    a = rng(spec.batch_seed0 + k).standard_normal((spec.N, t))
+    a = a * term_mask(spec, k)[None, :]
+    A = np.ascontiguousarray(_fixed(a.T[:, :, None] * left[:, None, :]))   # (T, N, P1), C order
+    B = np.ascontiguousarray(_fixed(right))                                 # (T, P2), C order
+    # ||signal||^2 = sum_s sum_{t,t'} <A_t[s], A_t'[s]> <B_t, B_t'>  (for the noise scale)
+    gb = B @ B.T
+    e2 = 0.0
+    for s in range(spec.N):
+        ga = A[:, s, :] @ A[:, s, :].T
+        e2 += float(np.sum(ga * gb))
+    E = spec.N * left.shape[1] * right.shape[1]
+    rms = math.sqrt(max(e2, 0.0) / E)
+    scale = spec.nu * rms * math.sqrt(3.0)
+    return FieldFactors(A, B, scale, spec.batch_seed0 + k, (spec.N,) + spec.n)
+
+
+def exact_field_batch(spec: FieldSpec, k: int, chunk: int = 1 << 22, workers: int = 4) -> np.ndarray:
+    """Batch k of the exactly reproducible field as float32 (N, *grid, channels), on the host."""
+    ff = exact_field_factors(spec, k)
+    T, N, P1 = ff.A.shape
+    P2 = ff.B.shape[1]
+    out = np.empty(N * P1 * P2, dtype=np.float32)
+    per = P1 * P2
+
+    def one(s):
+        sig = (ff.A[:, s, :].T @ ff.B).reshape(-1)           # exact in any order
+        for c0 in range(0, per, chunk):
+            c1 = min(per, c0 + chunk)
+            if ff.scale != 0.0:
+                y = sig[c0:c1] + ff.scale * noise_unit(ff.key, s * per + c0, c1 - c0)
+            else:
+                y = sig[c0:c1]
+            out[s * per + c0:s * per + c1] = y.astype(np.float32)
+
+    if N * per >= (1 << 24) and workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one, range(N)))
+    else:
+        for s in range(N):
+            one(s)
+    return out.reshape(ff.shape)
+
+
+def exact_field_stream(spec: FieldSpec, batches: Sequence[int] | None = None) -> Iterator[np.ndarray]:
+    ks = range(spec.n_batches) if batches is None else batches
+    for k in ks:
+        yield exact_field_batch(spec, k)

@@ -112,6 +112,16 @@ def test_tiny_stream_parity():
     assert gst.ranks() == ([8] * 6, 40)
 
 
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_tiny_stream_other_tolerances(eps):
+    """The precision-form tolerances in the FP64 form.  At eps = 1e-6 the noise is
+    1e-9 (the configured 1e-6 would push every transfer rank to 256): the exact ranks
+    4, 4, 4, 6, 8 stand."""
+    ys = datagen.tiny_stream(nu=1e-9 if eps < 1e-5 else 1e-6)
+    gst, ost = check_stream(ys, eps)
+    assert gst.ranks()[0] == ost.ranks
+
+
 def test_tiny_stream_float64_input():
     ys = datagen.tiny_stream(3)
     check_stream([y.astype(np.float64) for y in ys], 1e-4, in_dtype="float64")
@@ -232,25 +242,28 @@ def test_small_field_stream_parity():
     """24^3 x 3 grid, N = 8, 8 batches of the drifting field family: every batch vs the oracle."""
     spec = datagen.FieldSpec(grid=(24, 24, 24), channels=3, terms=6, N=8, n_batches=8, drift=2e-3, seed=9,
                              batch_seed0=900, nu=0.0, w_lo=0.2, w_hi=0.5)
-    ys = list(datagen.separable_field_stream(spec))
+    ys = list(datagen.exact_field_stream(spec))
     check_stream(ys, 1e-4, cores_tol=None)
 
 
 @pytest.fixture(scope="module")
 def field96():
+    """The 20 batches generated on the device (bit for bit the host generator's, which
+    tests/test_gpu_datagen.py checks); the host copies of the first three for the oracle."""
+    from datagen import gpu as G
     spec = datagen.field_96_spec()
-    ys = list(datagen.separable_field_stream(spec))
+    yd = [G.field_batch(spec, k) for k in range(spec.n_batches)]
+    host = [datagen.exact_field_batch(spec, k) for k in range(3)]
     golden = json.load(open(os.path.join(HERE, "golden", "field96_trace.json")))
-    return ys, golden
+    return yd, host, golden
 
 
 def test_field96_full_size_ranks_and_error_bound(field96):
     """The 96^3 x 3, N = 32, 20-batch stream at eps = 1e-4: ranks and skips equal the
     oracle's stored trace, and every batch meets ||Y - Y_hat|| <= eps ||Y||."""
-    ys, golden = field96
+    ys, _, golden = field96
     st = H.HTStream(ys[0].shape[1:], 1e-4, 48, 32, 640)
-    for k, y in enumerate(ys):
-        yd = dev(y)
+    for k, yd in enumerate(ys):
         info = st.push(yd)
         row = golden["batches"][k]
         assert st.ranks()[0] == row["ranks"], k
@@ -264,8 +277,7 @@ def test_field96_full_size_ranks_and_error_bound(field96):
 
 def test_field96_first_batches_elementwise(field96):
     """Element-wise parity on the full-size batches the oracle finishes quickly (init + 2 updates)."""
-    ys, _ = field96
-    sub = ys[:3]
+    _, sub, _ = field96
     gst, ginfo, granks = run_gpu(sub, 1e-4, rank_cap=48, n_cap=96)
     ost, oinfo = run_oracle(sub, 1e-4)
     assert granks == [i.ranks for i in oinfo]
