@@ -71,7 +71,18 @@ typedef enum {
  *            rows and their residual Grams on FP32 matrix cores with FP64 partial
  *            sums, FP32 level tensors, and the skip test summed from the explicit
  *            residual energy of each contraction; the first batch (ht_init_batch)
- *            and ht_project run as HT_FP64.
+ *            and ht_project run as HT_FP64.  Every decision taken from FP32 data is
+ *            certified against an error bound of the FP32 steps (u = 2^-24: a residual
+ *            formed in FP32 errs by 2 u sqrt(r+1) ||Y||, each FP32 contraction before
+ *            it adds 0.75 u sqrt(r+1) ||Y|| in quadrature, and the rounding of a Gram
+ *            product moves its tail sums by 4 u trace(G)): the skip test must hold with that margin
+ *            around eps ||Y||, and each rank decision on both sides of eps_nw^2.  A
+ *            rank decision that fails is taken again from an FP64 residual Gram; a
+ *            skip test that fails, or a decision that fails again, runs the whole
+ *            call in FP64.  When eps_rel / sqrt(2d-2) is below twice the residual
+ *            error the model allows with every node at rank_cap in one chain (the
+ *            precision gate, ht_update_precision), the updates run in FP64 from the
+ *            start.  ht_update_info.prec_used and .recomputed report what ran.
  *   HT_BF16X3 is rejected (HT_EINVAL): a split-BF16 product carries ~2^-16
  *            relative error, which swamps eps_nw^2 when residuals are formed. */
 typedef enum { HT_FP64 = 0, HT_FP32 = 1, HT_BF16X3 = 2 } ht_precision;
@@ -101,11 +112,22 @@ typedef struct {
   float device_ms;        /* device time of the call, from HIP events on hip_stream       */
   int32_t status;         /* ht_status of this handle's update (HT_OK, or why it was
                              rolled back; ht_rise_update_many reports one per handle)   */
+  int32_t prec_used;      /* ht_precision of the contractions and Gram products that
+                             produced the committed result (HT_FP64 when an HT_FP32
+                             handle's call ran in FP64, see ht_precision)               */
+  int32_t recomputed;     /* HT_FP32: decisions taken again in FP64 because the FP32
+                             result could not be certified (a node's Gram, or the whole
+                             call, which counts one); 0 otherwise                       */
 } ht_update_info;
 
 /* Bytes of device workspace a handle with this configuration needs.  Host only.
  * Returns HT_EINVAL for an invalid configuration. */
 ht_status ht_workspace_bytes(const ht_config* cfg, size_t* bytes);
+
+/* Precision in which the HT-RISE updates of a handle with this configuration run:
+ * cfg->prec, except HT_FP64 for an HT_FP32 configuration whose eps_rel the precision
+ * gate (see ht_precision) rules out for FP32.  Host only. */
+ht_status ht_update_precision(const ht_config* cfg, int32_t* prec);
 
 /* BHT-l2r (Sec. 3.1, Algorithm 1) on the first batch Y (N samples).
  * Creates *out, whose device state lives in ws (ws_bytes >= ht_workspace_bytes,

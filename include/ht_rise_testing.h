@@ -84,6 +84,15 @@ ht_status ht_test_eig_method(const double* G, int32_t k, int32_t rmin, int32_t r
 ht_status ht_test_orth_expand(const double* U_old, int64_t alpha, int32_t r_old, double* V, int32_t rR, double* core,
                               void* hip_stream);
 
+/* Host-only: the mixed form's certificate of one rank decision.  The rule chose rank
+ * r in [rmin, room] with discarded energy t_r and smallest kept eigenvalue lam_r on a
+ * Gram whose tail sums may be off by 2 sqrt(t) dR + dR^2 + gerr; returns 1 when every
+ * Gram within that error leads to the same decision (within thr on the kept side,
+ * above it one rank lower; a decision cut short by the capacity, r == room with
+ * t_r > thr, must stay above thr), else 0. */
+int32_t ht_test_decision_certified(int32_t r, int32_t rmin, int32_t room, double t_r, double lam_r, double thr,
+                                   double dR, double gerr);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,6 +29,7 @@
 
 #include "ht_internal.h"
 #include "ht_rise.h"
+#include "ht_rise_testing.h"
 
 using ht::Elem;
 using ht::ModeView;
@@ -183,7 +184,8 @@ struct ht_state {
   int rank_cap = 0;
   int64_t max_batch = 0, n_cap = 0;
   Elem in_t = Elem::F32;
-  bool mixed = false;  // HT_FP32 form
+  bool mixed = false;     // HT_FP32 requested
+  bool mixed_ok = false;  // and the FP32 error floor lies well inside eps_nw (precision gate)
   Tree tree;
   // per-node capacities: rows of the basis matrix (alpha) and rank bound
   std::vector<int64_t> alpha_cap;
@@ -211,14 +213,17 @@ struct ht_state {
   double* orthsc = nullptr;
   double* padtmp = nullptr;
   double* tails = nullptr;
+  double* aux = nullptr;  // two per node: trace(G), lambda_r (the mixed form's certificates)
   int* ranks_dev = nullptr;
   // host staging for small read-backs: h_scal (kScalars doubles), h_tails and
-  // h_ranks (one per node), in a page-locked block when one was available
+  // h_ranks (one per node), h_aux (two per node), in a page-locked block when one
+  // was available
   void* pin = nullptr;
   std::vector<double> pin_fallback;
   double* h_scal = nullptr;
   double* h_tails = nullptr;
   int* h_ranks = nullptr;
+  double* h_aux = nullptr;
   hipStream_t last_stream = nullptr;
   ht_state() = default;
   ht_state(const ht_state&) = delete;
@@ -234,7 +239,7 @@ struct Layout {
   std::vector<size_t> core, gram, vecs, evals, eigsc;
   size_t core_backup = 0, core_backup_elems = 0, root = 0, bufA = 0, bufB = 0, buf_elems = 0, resid = 0, bufZ = 0,
          resid_elems = 0, gpart = 0, scal = 0, sspart = 0, nrmpart = 0, respart = 0, ssnode = 0, orthsc = 0, padtmp = 0,
-         tails = 0,
+         tails = 0, aux = 0,
          ranks_dev = 0;
 };
 
@@ -359,8 +364,61 @@ Layout make_layout(const ht_config* c, const Tree& tree, std::vector<int64_t>& a
   L.orthsc = take(L, ht::orth_scratch_doubles(64) * sizeof(double));
   L.padtmp = take(L, max_core * sizeof(double));
   L.tails = take(L, (size_t)nn * sizeof(double));
+  L.aux = take(L, 2 * (size_t)nn * sizeof(double));
   L.ranks_dev = take(L, (size_t)nn * sizeof(int));
   return L;
+}
+
+// ---- the mixed form's error model ----------------------------------------------
+// u = 2^-24.  Forming a residual X - U (U^T X) on FP32 matrix cores (r columns in U)
+// errs by at most kResidK u sqrt(r + 1) ||X|| in the Frobenius norm (measured on the
+// part against FP64 residuals of the test streams: at most 0.5 u sqrt(r + 1) ||X||);
+// an FP32 contraction U^T X stored as an FP32 level tensor errs by at most
+// kChainK u sqrt(r + 1) ||X|| (measured over whole contraction chains: at most
+// 0.23 u sqrt(sum (r + 1)) ||Y||); independent steps add in quadrature.  The rounding
+// of the Gram product R R^T moves its tail sums by at most kGramK u trace(G)
+// (measured: at most 1.0 u trace(G)).  ||X|| <= ||Y|| for every level tensor of a
+// batch.
+constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24
+constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
+constexpr double kResidK = 2.0;
+constexpr double kChainK = 0.75;
+constexpr double kGramK = 4.0;
+
+// Frobenius error bound of a residual formed (own = rank + 1 when formed in FP32, else
+// 0) from a level tensor with the FP32 history chain = sum (rank + 1).
+double resid_err(double ny, double own, double chain) {
+  return kU32 * ny * std::sqrt(kResidK * kResidK * own + kChainK * kChainK * chain);
+}
+
+// Precision gate: the mixed form runs only when the largest residual error the model
+// allows (every node at its rank capacity, all in one chain) stays below half of
+// eps_nw / ||Y|| = eps / sqrt(2d - 2); otherwise no FP32 decision could be certified
+// and the updates run in FP64 from the start.
+bool fp32_gate(double eps, int d, const std::vector<int>& rc) {
+  double c = 0.0;
+  for (size_t i = 1; i < rc.size(); ++i) c += rc[i] + 1.0;
+  return kResidK * kU32 * std::sqrt(c) <= 0.5 * eps / std::sqrt(2.0 * d - 2.0);
+}
+
+// Certificate of one rank decision taken on a Gram whose tail sums t(j) may differ
+// from the exact ones by at most Delta(t) = 2 sqrt(t) dR + dR^2 + gerr: sqrt(t(j)) is
+// the distance of the residual to the matrices of rank j, which moves by at most the
+// residual's error dR, and gerr bounds the Gram product's rounding.  The rule chose
+// rank r in [rmin, room] with tail t_r and smallest kept eigenvalue lam_r (so the tail
+// one rank lower is t_r + lam_r).  Certified when every Gram within that error leads
+// to the same decision: the kept side stays within thr, the side one rank lower stays
+// above it, and a rank that the capacity cut short (r == room, t_r > thr) needs more
+// under every such Gram.
+bool decision_certified(int r, int rmin, int room, double t_r, double lam_r, double thr, double dR, double gerr) {
+  auto delta = [&](double t) { return 2.0 * std::sqrt(std::max(t, 0.0)) * dR + dR * dR + gerr; };
+  if (r == room && t_r > thr) return t_r - delta(t_r) > thr;
+  if (t_r + delta(t_r) > thr) return false;
+  if (r > rmin) {
+    const double t_prev = t_r + lam_r;
+    if (t_prev - delta(t_prev) <= thr) return false;
+  }
+  return true;
 }
 
 int64_t prod(const std::vector<int64_t>& v, size_t lo, size_t hi) {
@@ -550,10 +608,33 @@ void restore_cores(ht_state* h, hipStream_t s) {
 struct LayerJobs {
   std::vector<ht::EigJob> jobs;
   std::vector<int> node, rold;
+  std::vector<char> f32;  // the job's Gram has FP32 products (mixed form)
+  std::vector<ModeView> view;
 };
 
 // Gram launches of layer ell and the eigen jobs they feed.
-void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initial, hipStream_t s, LayerJobs& L) {
+// The Gram of node's unfolding (view v of cur): of the data (r_old = 0) or of the
+// explicit residual R = M - U_old U_old^T M (Eq. compute_residual); FP32 products when
+// f32 (modes of at most 128 rows).
+void node_gram(ht_state* h, int node, const Level& cur, const ModeView& v, int r_old, bool f32, hipStream_t s) {
+  if (r_old == 0) {
+    ht::gram(cur.ptr, cur.t, v, h->gpart, h->gram[node], s);
+  } else if (v.m <= ht::kResidGramMaxM) {
+    // formed in registers or tile by tile in LDS, never written out
+    if (f32)
+      ht::resid_gram_f32(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], s);
+    else
+      ht::resid_gram(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], s);
+  } else {
+    double* z = h->bufZ;  // U_old^T M: as large as the level tensor when alpha == r_old
+    ht::ttm_contract(cur.ptr, cur.t, v, h->core[node], r_old, z, s);
+    ht::ttm_expand(z, v.P, r_old, v.S, h->core[node], v.m, cur.ptr, cur.t, h->resid, Elem::F64, s);
+    ht::gram(h->resid, Elem::F64, v, h->gpart, h->gram[node], s);
+  }
+}
+
+void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initial, bool mixed, hipStream_t s,
+                 LayerJobs& L) {
   const std::vector<int> f = h->tree.frontier(ell);
   for (size_t k = 0; k < f.size(); ++k) {
     const int node = f[k];
@@ -564,20 +645,10 @@ void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initia
     if (alpha - r_old <= 0) continue;  // the basis already spans the whole mode
     // at the rank cap the decision still runs (rmax = 0) to detect a needed growth
     const int room = std::max(0, std::min(alpha, h->rank_cap) - r_old);
-    if (r_old == 0) {
-      ht::gram(cur.ptr, cur.t, v, h->gpart, h->gram[node], s);
-    } else if (v.m <= ht::kResidGramMaxM) {
-      // Gram of R = M - U_old U_old^T M, formed tile by tile in LDS (Eq. compute_residual)
-      if (h->mixed)
-        ht::resid_gram_f32(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], s);
-      else
-        ht::resid_gram(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], s);
-    } else {
-      double* z = h->bufZ;  // U_old^T M: as large as the level tensor when alpha == r_old
-      ht::ttm_contract(cur.ptr, cur.t, v, h->core[node], r_old, z, s);
-      ht::ttm_expand(z, v.P, r_old, v.S, h->core[node], v.m, cur.ptr, cur.t, h->resid, Elem::F64, s);
-      ht::gram(h->resid, Elem::F64, v, h->gpart, h->gram[node], s);
-    }
+    const bool f32 = mixed && r_old > 0 && v.m <= ht::kResidGramMaxM;
+    node_gram(h, node, cur, v, r_old, f32, s);
+    L.f32.push_back(f32 ? 1 : 0);
+    L.view.push_back(v);
     ht::EigJob j;
     j.G = h->gram[node];
     j.scratch = h->eigsc[node];
@@ -603,10 +674,11 @@ void launch_eig(const std::vector<ht::EigJob>& jobs, hipStream_t s) {
 
 // Ranks and discarded energies of the layer (device -> host staging, not yet
 // synchronised), and after the wait their copies.
-ht_status layer_readback(ht_state* h, hipStream_t s) {
+ht_status layer_readback(ht_state* h, hipStream_t s, bool with_aux = false) {
   const int nn = (int)h->tree.nodes.size();
   HT_HIP(hipMemcpyAsync(h->h_ranks, h->ranks_dev, nn * sizeof(int), hipMemcpyDeviceToHost, s));
   HT_HIP(hipMemcpyAsync(h->h_tails, h->tails, nn * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (with_aux) HT_HIP(hipMemcpyAsync(h->h_aux, h->aux, 2 * nn * sizeof(double), hipMemcpyDeviceToHost, s));
   return HT_OK;
 }
 
@@ -667,7 +739,7 @@ ht_status layer_finish(ht_state* h, double thr, bool initial, hipStream_t s, con
 ht_status decide_layer(ht_state* h, int ell, const Level& cur, double thr, bool initial, hipStream_t s,
                        int* growth) {
   LayerJobs L;
-  layer_grams(h, ell, cur, thr, initial, s, L);
+  layer_grams(h, ell, cur, thr, initial, false, s, L);
   launch_eig(L.jobs, s);
   HT_HIP(hipGetLastError());
   ht_status st = layer_readback(h, s);
@@ -696,6 +768,7 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   h->mixed = cfg->prec == HT_FP32;
   h->tree.build(cfg->d);
   Layout L = make_layout(cfg, h->tree, h->alpha_cap, h->rc);
+  h->mixed_ok = h->mixed && fp32_gate(h->eps, h->d, h->rc);
   if (ws_bytes < L.total) {
     delete h;
     return fail(HT_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes, " + std::to_string(L.total) +
@@ -733,16 +806,18 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   h->orthsc = reinterpret_cast<double*>(base + L.orthsc);
   h->padtmp = reinterpret_cast<double*>(base + L.padtmp);
   h->tails = reinterpret_cast<double*>(base + L.tails);
+  h->aux = reinterpret_cast<double*>(base + L.aux);
   h->ranks_dev = reinterpret_cast<int*>(base + L.ranks_dev);
   h->rank.assign(nn, 0);
   {
-    const size_t nd = kScalars(nn) + 2 * (size_t)nn;  // the ranks take at most nn doubles
+    const size_t nd = kScalars(nn) + 4 * (size_t)nn;  // the ranks take at most nn doubles
     if (nd * sizeof(double) <= kPinnedBytes) h->pin = pinned_take();
     if (h->pin == nullptr) h->pin_fallback.assign(nd, 0.0);
     double* b = h->pin ? static_cast<double*>(h->pin) : h->pin_fallback.data();
     h->h_scal = b;
     h->h_tails = b + kScalars(nn);
     h->h_ranks = reinterpret_cast<int*>(b + kScalars(nn) + nn);
+    h->h_aux = b + kScalars(nn) + 2 * nn;
   }
   *out = h;
   return HT_OK;
@@ -768,7 +843,10 @@ struct Upd {
   std::vector<int> saved;
   double ny = 0, eps_des = 0, eps_proj = 0, thr = 0;
   bool skip = false, busy = false;
+  bool mixed = false;  // this pass runs the FP32 kernels
+  bool redo = false;   // an FP32 decision could not be certified: the call runs again in FP64
   int growth = 0;
+  int recomputed = 0;  // decisions taken again in FP64
   ht_status st = HT_OK;
   std::string err;
   LayerJobs L;
@@ -776,22 +854,80 @@ struct Upd {
   std::vector<double> tl;
 };
 
-ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* Ns, int count, hipStream_t s,
-                    ht_update_info* infos) {
-  std::vector<Upd> U(count);
-  for (int i = 0; i < count; ++i) {
-    Upd& u = U[i];
-    u.h = hs[i];
-    u.Y = Ys[i];
-    u.N = Ns[i];
-    if (u.h == nullptr) return fail(HT_EINVAL, "handle " + std::to_string(i) + " is NULL");
-    if (u.Y == nullptr) return fail(HT_EINVAL, "Y of handle " + std::to_string(i) + " is NULL");
-    if (u.N < 1) return fail(HT_EINVAL, "N of handle " + std::to_string(i) + " must be >= 1");
-    if (u.N > u.h->max_batch) return fail(HT_ESHAPE, "N of handle " + std::to_string(i) + " exceeds max_batch");
-    if (u.h->n_acc + u.N > u.h->n_cap)
-      return fail(HT_ESHAPE, "accumulation of handle " + std::to_string(i) + " would exceed n_cap");
+// Sum of rank + 1 over the FP32 contractions that produced the level tensor entering
+// layer ell: every node of a deeper layer whose mode has at most 128 rows.
+double fp32_chain(const ht_state* h, int ell) {
+  double c = 0.0;
+  for (size_t i = 1; i < h->tree.nodes.size(); ++i)
+    if (h->tree.nodes[i].layer > ell && alpha_now(h, (int)i) <= ht::kResidGramMaxM) c += h->rank[i] + 1.0;
+  return c;
+}
+
+// Mixed-form skip test certificate: the telescoped residual energies carry, per
+// contraction j, the error of the model on a residual of energy e_j (its own FP32
+// step and those before it), and the FP32 block sums a relative kGramK u.  True
+// when the decision eps_proj <= eps_des holds under every such error.
+bool skip_certified(const Upd& u, double lost) {
+  const ht_state* h = u.h;
+  double chain = 0.0, delta = kGramK * kU32 * std::fabs(lost);
+  for (int ell = h->tree.depth; ell >= 1; --ell)
+    for (int node : h->tree.frontier(ell)) {
+      if (h->tree.nodes[node].layer != ell) continue;
+      const double* e = h->h_scal + 8 + 2 * node;
+      const bool ex = u.expl[node] != 0;
+      const double ej = ex ? e[0] : e[0] - e[1];
+      const double own = ex ? h->rank[node] + 1.0 : 0.0;
+      const double dj = resid_err(u.ny, own, chain);
+      delta += 2.0 * std::sqrt(std::max(ej, 0.0)) * dj + dj * dj + (ex ? 0.0 : 4.0 * kU64 * e[0]);
+      chain += own;
+    }
+  return std::fabs(lost - u.eps_des * u.eps_des) > delta;
+}
+
+// Certificates of a mixed layer's decisions (after the read-back of ranks, tails and
+// the aux pairs).  A decision from an FP32 Gram that fails is listed in *redo_jobs for
+// an FP64 Gram; one that fails with an FP64 Gram (its level tensor's FP32 history
+// alone is too coarse) marks the whole update for an FP64 run.
+void certify_layer(Upd& u, int ell, bool fp64_pass, std::vector<int>* redo_jobs) {
+  const ht_state* h = u.h;
+  const double chain = fp32_chain(h, ell);
+  for (size_t q = 0; q < u.L.jobs.size(); ++q) {
+    if (fp64_pass && std::find(redo_jobs->begin(), redo_jobs->end(), (int)q) == redo_jobs->end()) continue;
+    const int node = u.L.node[q];
+    const bool f32 = !fp64_pass && u.L.f32[q];
+    const double own = f32 ? u.L.rold[q] + 1.0 : 0.0;
+    const double dR = resid_err(u.ny, own, chain);
+    const double tr = h->h_aux[2 * node];
+    const double gerr = kGramK * (f32 ? kU32 : kU64) * tr;
+    const bool ok = decision_certified(u.rk[node], u.L.jobs[q].rmin, u.L.jobs[q].rmax, u.tl[node],
+                                       h->h_aux[2 * node + 1], u.thr, dR, gerr);
+    if (ok) continue;
+    if (f32)
+      redo_jobs->push_back((int)q);
+    else
+      u.redo = true;
   }
-  Timer timer(s);
+}
+
+void aux_jobs(const Upd& u, const std::vector<int>* only, std::vector<ht::AuxJob>& out) {
+  for (size_t q = 0; q < u.L.jobs.size(); ++q) {
+    if (only && std::find(only->begin(), only->end(), (int)q) == only->end()) continue;
+    const ht::EigJob& j = u.L.jobs[q];
+    out.push_back(ht::AuxJob{j.G, j.rank, j.evals, u.h->aux + 2 * u.L.node[q], j.k});
+  }
+}
+
+// Rolls a handle back to its state before the call (cores from the backup, the ranks).
+void roll_back(Upd& u, hipStream_t s) {
+  restore_cores(u.h, s);
+  u.h->rank = u.saved;
+  u.busy = false;
+}
+
+// One pass of HT-RISE over the handles in act (each with u.mixed set): Step 1 and
+// the skip tests, then the layers in lock step, then the root appends.  Handles
+// whose FP32 decisions cannot be certified come out with u.redo set and unchanged.
+ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
   // ---- Step 1 for every handle: projection onto the existing cores; the first
   //      contraction also returns ||Y||^2 (mixed form: and the residual energies)
   //      The final sums of every handle's reductions run as one launch.
@@ -799,11 +935,12 @@ ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* N
     std::vector<ht::SumJob> sums;
     {
       const DeferSums defer(&sums);
-      for (Upd& u : U) {
+      for (Upd* up : act) {
+        Upd& u = *up;
         ht_state* h = u.h;
         h->last_stream = s;
         const int nn = (int)h->tree.nodes.size();
-        if (h->mixed) {
+        if (u.mixed) {
           u.expl.assign(nn, 0);
           u.c1 = project_all(h, u.Y, u.N, s, h->scal, true, h->scal + 8, &u.expl);
         } else {
@@ -814,19 +951,20 @@ ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* N
     }
     ht::reduce_batch(sums, s);
   }
-  for (Upd& u : U) {
-    ht_state* h = u.h;
-    const size_t ns = h->mixed ? kScalars((int)h->tree.nodes.size()) : 2;
+  for (Upd* up : act) {
+    ht_state* h = up->h;
+    const size_t ns = up->mixed ? kScalars((int)h->tree.nodes.size()) : 2;
     HT_HIP(hipMemcpyAsync(h->h_scal, h->scal, ns * sizeof(double), hipMemcpyDeviceToHost, s));
   }
   HT_HIP(hipGetLastError());
   HT_HIP(wait_stream(s));
   // ---- skip tests (Eq. relative_error_threshold)
-  for (Upd& u : U) {
+  for (Upd* up : act) {
+    Upd& u = *up;
     ht_state* h = u.h;
     const double ny2 = h->h_scal[0];
     double lost = 0.0;
-    if (h->mixed) {
+    if (u.mixed) {
       for (int ell = h->tree.depth; ell >= 1; --ell)
         for (int node : h->tree.frontier(ell))
           if (h->tree.nodes[node].layer == ell)
@@ -842,6 +980,10 @@ ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* N
     u.ny = std::sqrt(ny2);
     u.eps_des = h->eps * u.ny;
     u.eps_proj = std::sqrt(std::max(0.0, lost));
+    if (u.mixed && !skip_certified(u, lost)) {
+      u.redo = true;
+      continue;
+    }
     u.skip = u.eps_proj <= u.eps_des;
     if (u.skip) {
       const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
@@ -858,57 +1000,139 @@ ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* N
   // ---- Step 2, layer by layer from the leaves (trees of different depths aligned
   //      at their leaves)
   int max_depth = 0;
-  for (const Upd& u : U)
-    if (u.busy) max_depth = std::max(max_depth, u.h->tree.depth);
+  for (const Upd* up : act)
+    if (up->busy) max_depth = std::max(max_depth, up->h->tree.depth);
   for (int t = 0; t < max_depth; ++t) {
+    auto layer_of = [&](const Upd& u) { return u.busy ? u.h->tree.depth - t : 0; };
     std::vector<ht::EigJob> all;
-    for (Upd& u : U) {
-      const int ell = u.busy ? u.h->tree.depth - t : 0;
+    std::vector<ht::AuxJob> aux;
+    for (Upd* up : act) {
+      Upd& u = *up;
+      const int ell = layer_of(u);
       u.L = LayerJobs();
       if (ell < 1) continue;
-      layer_grams(u.h, ell, u.cur, u.thr, false, s, u.L);
+      layer_grams(u.h, ell, u.cur, u.thr, false, u.mixed, s, u.L);
       all.insert(all.end(), u.L.jobs.begin(), u.L.jobs.end());
+      if (u.mixed) aux_jobs(u, nullptr, aux);
     }
     launch_eig(all, s);
+    if (!aux.empty()) ht::decision_aux(aux.data(), (int)aux.size(), s);
     HT_HIP(hipGetLastError());
-    for (Upd& u : U) {
-      if (!u.busy || u.h->tree.depth - t < 1) continue;
-      const ht_status st = layer_readback(u.h, s);
+    for (Upd* up : act) {
+      if (layer_of(*up) < 1) continue;
+      const ht_status st = layer_readback(up->h, s, up->mixed);
       if (st != HT_OK) return st;
     }
     HT_HIP(wait_stream(s));
-    for (Upd& u : U)
-      if (u.busy && u.h->tree.depth - t >= 1) layer_collect(u.h, u.rk, u.tl);
+    for (Upd* up : act)
+      if (layer_of(*up) >= 1) layer_collect(up->h, up->rk, up->tl);
+    // ---- certificates of the mixed decisions; FP64 Grams for the uncertified ones
+    {
+      std::vector<std::vector<int>> fix(act.size());
+      std::vector<ht::EigJob> again;
+      std::vector<ht::AuxJob> again_aux;
+      for (size_t a = 0; a < act.size(); ++a) {
+        Upd& u = *act[a];
+        const int ell = layer_of(u);
+        if (ell < 1 || !u.mixed) continue;
+        certify_layer(u, ell, false, &fix[a]);
+        if (u.redo) continue;
+        for (int q : fix[a]) {
+          node_gram(u.h, u.L.node[q], u.cur, u.L.view[q], u.L.rold[q], false, s);
+          again.push_back(u.L.jobs[q]);
+          u.recomputed += 1;
+        }
+        if (!fix[a].empty()) aux_jobs(u, &fix[a], again_aux);
+      }
+      if (!again.empty()) {
+        launch_eig(again, s);
+        ht::decision_aux(again_aux.data(), (int)again_aux.size(), s);
+        HT_HIP(hipGetLastError());
+        for (size_t a = 0; a < act.size(); ++a) {
+          if (fix[a].empty() || act[a]->redo) continue;
+          const ht_status st = layer_readback(act[a]->h, s, true);
+          if (st != HT_OK) return st;
+        }
+        HT_HIP(wait_stream(s));
+        for (size_t a = 0; a < act.size(); ++a) {
+          Upd& u = *act[a];
+          if (fix[a].empty() || u.redo) continue;
+          layer_collect(u.h, u.rk, u.tl);
+          certify_layer(u, layer_of(u), true, &fix[a]);
+        }
+      }
+      for (Upd* up : act)
+        if (up->redo && up->busy) roll_back(*up, s);
+    }
     std::vector<ht::OrthJob> orth;
-    for (Upd& u : U) {
-      const int ell = u.busy ? u.h->tree.depth - t : 0;
+    for (Upd* up : act) {
+      Upd& u = *up;
+      const int ell = layer_of(u);
       if (ell < 1) continue;
       ht_status st = layer_finish(u.h, u.thr, false, s, u.L, u.rk, u.tl, &u.growth, &orth);
       if (st != HT_OK) {
-        // roll this handle back: cores from the backup, ranks from before the call
-        // (a failing handle has queued no expansion)
+        // roll this handle back (a failing handle has queued no expansion)
         u.st = st;
         u.err = g_last_error;
-        restore_cores(u.h, s);
-        u.h->rank = u.saved;
-        u.busy = false;
+        roll_back(u, s);
         continue;
       }
     }
     if (!orth.empty()) ht::orth_expand_batch(orth.data(), (int)orth.size(), s);
-    for (Upd& u : U) {
-      const int ell = u.busy ? u.h->tree.depth - t : 0;
+    for (Upd* up : act) {
+      Upd& u = *up;
+      const int ell = layer_of(u);
       if (ell < 1) continue;
-      u.cur = project_layer(u.h, ell, u.cur, s, nullptr, u.h->mixed);
+      u.cur = project_layer(u.h, ell, u.cur, s, nullptr, u.mixed);
     }
   }
-  for (Upd& u : U) {
+  for (Upd* up : act) {
+    Upd& u = *up;
     if (!u.busy) continue;
     ht_state* h = u.h;
     const int q11 = h->rank[h->tree.nodes[0].child[0]], q12 = h->rank[h->tree.nodes[0].child[1]];
     ht::root_append(u.cur.ptr, u.cur.t, u.N, q11, q12, h->root, h->n_acc, h->rank_cap, s);
   }
   HT_HIP(hipGetLastError());
+  return HT_OK;
+}
+
+ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* Ns, int count, hipStream_t s,
+                    ht_update_info* infos) {
+  std::vector<Upd> U(count);
+  for (int i = 0; i < count; ++i) {
+    Upd& u = U[i];
+    u.h = hs[i];
+    u.Y = Ys[i];
+    u.N = Ns[i];
+    if (u.h == nullptr) return fail(HT_EINVAL, "handle " + std::to_string(i) + " is NULL");
+    if (u.Y == nullptr) return fail(HT_EINVAL, "Y of handle " + std::to_string(i) + " is NULL");
+    if (u.N < 1) return fail(HT_EINVAL, "N of handle " + std::to_string(i) + " must be >= 1");
+    if (u.N > u.h->max_batch) return fail(HT_ESHAPE, "N of handle " + std::to_string(i) + " exceeds max_batch");
+    if (u.h->n_acc + u.N > u.h->n_cap)
+      return fail(HT_ESHAPE, "accumulation of handle " + std::to_string(i) + " would exceed n_cap");
+    u.mixed = u.h->mixed_ok;
+  }
+  Timer timer(s);
+  std::vector<Upd*> act;
+  for (Upd& u : U) act.push_back(&u);
+  ht_status st = rise_pass(act, s);
+  if (st != HT_OK) return st;
+  // ---- handles whose FP32 decisions were not certified: the whole call in FP64
+  act.clear();
+  for (Upd& u : U)
+    if (u.redo && u.st == HT_OK) {
+      u.mixed = false;
+      u.redo = false;
+      u.skip = u.busy = false;
+      u.growth = 0;
+      u.recomputed += 1;
+      act.push_back(&u);
+    }
+  if (!act.empty()) {
+    st = rise_pass(act, s);
+    if (st != HT_OK) return st;
+  }
   const float ms = timer.stop();
   ht_status first = HT_OK;
   std::string first_err;
@@ -928,6 +1152,8 @@ ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* N
       in.eps_proj = u.eps_proj;
       in.device_ms = ms;
       in.status = u.st;
+      in.prec_used = u.mixed ? HT_FP32 : HT_FP64;
+      in.recomputed = u.recomputed;
     }
   }
   if (first != HT_OK) return fail(first, first_err);
@@ -966,6 +1192,24 @@ ht_status ht_workspace_bytes(const ht_config* cfg, size_t* bytes) {
   std::vector<int> rc;
   *bytes = make_layout(cfg, t, ac, rc).total;
   return HT_OK;
+}
+
+ht_status ht_update_precision(const ht_config* cfg, int32_t* prec) {
+  std::string why;
+  if (prec == nullptr) return fail(HT_EINVAL, "prec is NULL");
+  if (!valid_config(cfg, why)) return fail(HT_EINVAL, why);
+  Tree t;
+  t.build(cfg->d);
+  std::vector<int64_t> ac;
+  std::vector<int> rc;
+  capacities(t, std::vector<int64_t>(cfg->n, cfg->n + cfg->d), cfg->rank_cap, ac, rc);
+  *prec = (cfg->prec == HT_FP32 && fp32_gate(cfg->eps_rel, cfg->d, rc)) ? HT_FP32 : HT_FP64;
+  return HT_OK;
+}
+
+int32_t ht_test_decision_certified(int32_t r, int32_t rmin, int32_t room, double t_r, double lam_r, double thr,
+                                   double dR, double gerr) {
+  return decision_certified(r, rmin, room, t_r, lam_r, thr, dR, gerr) ? 1 : 0;
 }
 
 ht_status ht_init_batch(const ht_config* cfg, void* ws, size_t ws_bytes, const void* Y, int64_t N, void* hip_stream,
@@ -1036,6 +1280,9 @@ ht_status ht_init_batch(const ht_config* cfg, void* ws, size_t ws_bytes, const v
     info->eps_des = h->eps * ny;
     info->eps_proj = std::sqrt(std::max(0.0, ny2 - h->h_scal[1]));
     info->device_ms = timer.stop();
+    info->status = HT_OK;
+    info->prec_used = HT_FP64;
+    info->recomputed = 0;
   }
   *out = h;
   return HT_OK;

@@ -1756,6 +1756,41 @@ __global__ __launch_bounds__(ET) void eig_trunc_kernel(EigBatch batch) {
 
 }  // namespace
 
+namespace {
+
+struct AuxBatch {
+  AuxJob j[kMaxEigJobs];
+};
+
+// trace(G) in a fixed order (strided partial sums, DPP-free wave tree, then the
+// four waves in order) and the smallest kept eigenvalue of one decision.
+__global__ __launch_bounds__(256) void decision_aux_kernel(AuxBatch b) {
+  const AuxJob J = b.j[blockIdx.x];
+  __shared__ double red[4];
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < J.k; i += 256) tr += J.G[(int64_t)i * J.k + i];
+  for (int off = 32; off > 0; off >>= 1) tr += __shfl_down(tr, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tr;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int r = *J.rank;
+    J.out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+    J.out[1] = r >= 1 ? J.evals[r - 1] : 0.0;
+  }
+}
+
+}  // namespace
+
+void decision_aux(const AuxJob* jobs, int count, hipStream_t s) {
+  for (int b0 = 0; b0 < count; b0 += kMaxEigJobs) {
+    const int n = std::min(kMaxEigJobs, count - b0);
+    AuxBatch b;
+    for (int i = 0; i < n; ++i) b.j[i] = jobs[b0 + i];
+    ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+    decision_aux_kernel<<<n, 256, 0, s>>>(b);
+  }
+}
+
 size_t eig_scratch_doubles(int k, int rmax) {
   const size_t K = (size_t)k;
   return K * (K + 1) / 2 + K * K + 6 * K + K + K + (K + 1) + 4 * K * (size_t)std::max(rmax, 1) + 64;

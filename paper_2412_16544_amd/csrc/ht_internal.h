@@ -107,6 +107,18 @@ size_t eig_scratch_doubles(int k, int rmax);
 // Runs up to kMaxEigJobs independent problems in one launch (one workgroup each).
 void eig_trunc(const EigJob* jobs, int count, hipStream_t s);
 
+// Inputs of the mixed form's decision certificate, gathered after an eigen launch:
+// out[0] = trace(G), out[1] = the smallest kept eigenvalue lambda_r (0 when the rule
+// kept nothing), so that the discarded energy one rank lower is tail + lambda_r.
+struct AuxJob {
+  const double* G;
+  const int* rank;
+  const double* evals;
+  double* out;
+  int k;
+};
+void decision_aux(const AuxJob* jobs, int count, hipStream_t s);
+
 // ---- basis expansion (FP64) -----------------------------------------------------
 // Orthogonalises the rR columns of V (alpha x rR) against U_old (alpha x r_old) twice
 // (classical Gram-Schmidt), orthonormalises them by CholeskyQR twice, normalises signs

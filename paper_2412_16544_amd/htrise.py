@@ -34,7 +34,7 @@ class ht_config(ctypes.Structure):
 class ht_update_info(ctypes.Structure):
     _fields_ = [("skipped", ctypes.c_int32), ("rank_growth", ctypes.c_int32), ("norm_y", ctypes.c_double),
                 ("eps_proj", ctypes.c_double), ("eps_des", ctypes.c_double), ("device_ms", ctypes.c_float),
-                ("status", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("prec_used", ctypes.c_int32), ("recomputed", ctypes.c_int32)]
 
 
 class HTError(RuntimeError):
@@ -54,6 +54,7 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
         L.ht_workspace_bytes.argtypes = [ctypes.POINTER(ht_config), ctypes.POINTER(sz)]
+        L.ht_update_precision.argtypes = [ctypes.POINTER(ht_config), ctypes.POINTER(i32)]
         L.ht_init_batch.argtypes = [ctypes.POINTER(ht_config), vp, sz, vp, i64, vp, ctypes.POINTER(vp),
                                     ctypes.POINTER(ht_update_info)]
         L.ht_rise_update.argtypes = [vp, vp, i64, vp, ctypes.POINTER(ht_update_info)]
@@ -69,7 +70,8 @@ def lib() -> ctypes.CDLL:
         L.ht_status_str.restype = ctypes.c_char_p
         L.ht_last_error.argtypes = []
         L.ht_last_error.restype = ctypes.c_char_p
-        for name in ("ht_workspace_bytes", "ht_init_batch", "ht_rise_update", "ht_rise_update_many", "ht_project",
+        for name in ("ht_workspace_bytes", "ht_update_precision", "ht_init_batch", "ht_rise_update",
+                     "ht_rise_update_many", "ht_project",
                      "ht_reconstruct", "ht_query_ranks", "ht_export_cores"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -104,6 +106,12 @@ def _stream(stream) -> int:
 def ht_workspace_bytes(cfg: ht_config) -> int:
     out = ctypes.c_size_t(0)
     _check(lib().ht_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)), "ht_workspace_bytes")
+    return int(out.value)
+
+
+def ht_update_precision(cfg: ht_config) -> int:
+    out = ctypes.c_int32(0)
+    _check(lib().ht_update_precision(ctypes.byref(cfg), ctypes.byref(out)), "ht_update_precision")
     return int(out.value)
 
 
@@ -184,11 +192,14 @@ class UpdateInfo:
     eps_des: float
     device_ms: float
     status: int = HT_OK
+    prec_used: int = HT_FP64
+    recomputed: int = 0
 
     @staticmethod
     def of(i: ht_update_info) -> "UpdateInfo":
         return UpdateInfo(bool(i.skipped), int(i.rank_growth), float(i.norm_y), float(i.eps_proj),
-                          float(i.eps_des), float(i.device_ms), int(i.status))
+                          float(i.eps_des), float(i.device_ms), int(i.status), int(i.prec_used),
+                          int(i.recomputed))
 
 
 class HTStream:
@@ -288,6 +299,8 @@ def _tlib():
         L.ht_test_eig.argtypes = [vp, i32, i32, i32, dbl, vp, vp, vp, vp, vp, vp]
         L.ht_test_eig_method.argtypes = [vp, i32, i32, i32, dbl, i32, vp, vp, vp, vp, vp, vp]
         L.ht_test_orth_expand.argtypes = [vp, i64, i32, vp, i32, vp, vp]
+        L.ht_test_decision_certified.argtypes = [i32, i32, i32, dbl, dbl, dbl, dbl, dbl]
+        L.ht_test_decision_certified.restype = i32
         for name in ("ht_test_sumsq", "ht_test_gram", "ht_test_resid_gram", "ht_test_resid_gram_f32",
                      "ht_test_ttm_contract", "ht_test_ttm_contract_f32", "ht_test_ttm_expand", "ht_test_eig",
                      "ht_test_eig_method", "ht_test_orth_expand"):
@@ -414,6 +427,12 @@ def ht_test_orth_expand(U_old, V, stream=None):
     _check(_tlib().ht_test_orth_expand(_ptr(core), alpha, r_old, _ptr(Vcm), rR, _ptr(core), _stream(stream)),
            "ht_test_orth_expand")
     return core.t()
+
+
+def ht_test_decision_certified(r: int, rmin: int, room: int, t_r: float, lam_r: float, thr: float, dR: float,
+                               gerr: float) -> bool:
+    """Host-only certificate of one mixed-form rank decision (ht_rise_testing.h)."""
+    return bool(_tlib().ht_test_decision_certified(r, rmin, room, t_r, lam_r, thr, dR, gerr))
 
 
 # ---- optional per-kernel timing (include/ht_rise_profile.h) --------------------------------------

@@ -3,6 +3,7 @@ entry point, sizes workspaces and rejects invalid arguments before touching a
 device.  No compute call is made here."""
 
 import ctypes
+import math
 import os
 import re
 import subprocess
@@ -27,7 +28,8 @@ def declared_functions():
     for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
         if hdr.endswith(".h"):
             text = open(os.path.join(ROOT, "include", hdr)).read()
-            names += re.findall(r"^\s*(?:ht_status|void|const char\s*\*)\s*(ht_\w+)\s*\(", text, re.M)
+            names += re.findall(r"^\s*(?:ht_status|void|const char\s*\*|int32_t|size_t)\s*(ht_\w+)\s*\(", text,
+                                re.M)
     return sorted(set(names))
 
 
@@ -124,3 +126,46 @@ def test_binding_refuses_missing_library(monkeypatch):
     monkeypatch.setattr(H, "LIB_PATH", "/nonexistent/libhtrise.so")
     with pytest.raises(RuntimeError):
         H.lib()
+
+
+# ---- precision gate and decision certificate of the mixed form (host logic) -------------------
+def _prec(n, eps, rank_cap, prec=H.HT_FP32):
+    cfg, keep = H.make_config(n, eps, rank_cap, 8, 64, prec)
+    return H.ht_update_precision(cfg)
+
+
+def test_precision_gate():
+    # 16^4 with rank capacity 64: node capacities 16, 16, 16, 16, 64, 64 -> sum(r + 1) = 198
+    assert _prec((16, 16, 16, 16), 1e-4, 64) == H.HT_FP32
+    assert _prec((16, 16, 16, 16), 1e-3, 64) == H.HT_FP32
+    assert _prec((16, 16, 16, 16), 1e-6, 64) == H.HT_FP64
+    assert _prec((16, 16, 16, 16), 1e-3, 64, H.HT_FP64) == H.HT_FP64
+    # the gate: 2 u sqrt(198) <= 0.5 eps / sqrt(6), u = 2^-24
+    edge = 4.0 * 2.0 ** -24 * math.sqrt(198) * math.sqrt(6)
+    assert _prec((16, 16, 16, 16), edge * 1.001, 64) == H.HT_FP32
+    assert _prec((16, 16, 16, 16), edge * 0.999, 64) == H.HT_FP64
+    # a larger capacity raises the floor
+    assert _prec((96, 96, 96, 3), 1e-4, 48) == H.HT_FP32
+    assert _prec((48, 48, 48, 48, 4), 1e-4, 64) == H.HT_FP32
+
+
+def test_decision_certificate():
+    cert = H.ht_test_decision_certified
+    thr = 1.0
+    # exact arithmetic: every decision of the rule certifies
+    assert cert(3, 0, 10, 0.999, 0.002, thr, 0.0, 0.0)
+    assert cert(0, 0, 10, 0.5, 0.0, thr, 0.0, 0.0)
+    # kept side within the error of the budget: tail 0.99 thr, Delta = 2 sqrt(.99) 0.01 + 1e-4 > 0.01
+    assert not cert(3, 0, 10, 0.99, 0.5, thr, 0.01, 0.0)
+    assert cert(3, 0, 10, 0.97, 0.5, thr, 0.01, 0.0)
+    # one rank lower within the error: t_r + lam_r = 1.01 thr
+    assert not cert(3, 0, 10, 0.5, 0.51, thr, 0.01, 0.0)
+    assert cert(3, 0, 10, 0.5, 0.53, thr, 0.01, 0.0)
+    # the rank floor: no lower side to check
+    assert cert(1, 1, 10, 0.5, 0.51, thr, 0.01, 0.0)
+    # the Gram rounding term alone
+    assert not cert(0, 0, 10, 0.95, 0.0, thr, 0.0, 0.06)
+    assert cert(0, 0, 10, 0.95, 0.0, thr, 0.0, 0.04)
+    # a decision cut short by the capacity (r == room, tail above thr) must stay above
+    assert cert(2, 0, 2, 2.0, 0.5, thr, 0.01, 0.0)
+    assert not cert(2, 0, 2, 1.01, 0.5, thr, 0.01, 0.0)

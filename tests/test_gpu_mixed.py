@@ -5,12 +5,15 @@ and their residual Grams on FP32 matrix cores (FP64 partial sums), stores level
 tensors in FP32 and takes the skip test from the explicit residual energy of each
 contraction; BHT-l2r, eigen solves, decisions and expansion stay FP64.
 
+Every decision taken from FP32 data carries a certificate (an error bound of the
+FP32 steps around the threshold); one that fails is taken again in FP64, and the
+call reports it (prec_used, recomputed).
+
 The bar:
-* ranks and skip decisions identical to the oracle's at every batch.  An FP32
-  residual entry is off by |delta| <~ sqrt(m) 2^-24 |x| ~ 1e-6 |x|, so a residual
-  energy moves by <= 2 ||R|| ||delta|| ~ 2e-6 ||R|| ||Y||; next to a decision
-  threshold (||R|| ~ eps ||Y||) that is ~2e-2 eps^2 ||Y||^2 / (2d - 2) at most, and
-  no decision in these streams lies within 10 % of its threshold;
+* ranks and skip decisions identical to the oracle's at every batch, including
+  decisions placed within the FP32 error of their threshold (which the
+  certificate must send to FP64) and eps = 1e-6, which the precision gate runs in
+  FP64;
 * reconstructions within MIXED_TOL = 5e-6 ||Y|| of the oracle's: the latent slices
   come out of two FP32 contraction levels, each with relative error
   <~ sqrt(m) 2^-24 ~ 6e-7 (m <= 128) in the Frobenius norm, against 1e-10 for the
@@ -19,6 +22,7 @@ The bar:
 """
 
 import json
+import math
 import os
 
 import numpy as np
@@ -52,8 +56,14 @@ def run_mixed(ys, eps, rank_cap=64):
     return st, infos, ranks
 
 
-def check_mixed(ys, eps, rank_cap=64):
+def check_mixed(ys, eps, rank_cap=64, prec=None):
+    """prec: the precision every update must report (None: any, as the certificates decide)."""
     gst, ginfo, granks = run_mixed(ys, eps, rank_cap)
+    print("updates (prec_used, recomputed):", [(i.prec_used, i.recomputed) for i in ginfo[1:]])
+    if prec is not None:
+        assert all(i.prec_used == prec for i in ginfo[1:]), [(i.prec_used, i.recomputed) for i in ginfo]
+        if prec == H.HT_FP32:
+            assert all(i.recomputed == 0 for i in ginfo[1:])
     ost = ho.BHT(ys[0].shape[1:], eps)
     oinfo = [ost.init_batch(ys[0])] + [ost.update(y) for y in ys[1:]]
     assert granks == [i.ranks for i in oinfo], (granks, [i.ranks for i in oinfo])
@@ -79,12 +89,12 @@ def check_mixed(ys, eps, rank_cap=64):
 
 def test_mixed_tiny_stream():
     ys = datagen.tiny_stream()
-    gst, _, _ = check_mixed(ys, 1e-4)
+    gst, _, _ = check_mixed(ys, 1e-4, prec=H.HT_FP32)
     assert gst.ranks() == ([8] * 6, 40)
 
 
 def test_mixed_tiny_stream_eps_1e3():
-    check_mixed(datagen.tiny_stream(), 1e-3)
+    check_mixed(datagen.tiny_stream(), 1e-3, prec=H.HT_FP32)
 
 
 @pytest.mark.parametrize("n,rank,N", [((17, 33, 5), 3, 7), ((40, 24), 5, 3), ((9, 8, 7, 6, 5, 4), 2, 4),
@@ -98,7 +108,7 @@ def test_mixed_other_orders_and_ragged_shapes(n, rank, N):
 def test_mixed_small_field_stream():
     spec = datagen.FieldSpec(grid=(24, 24, 24), channels=3, terms=6, N=8, n_batches=8, drift=2e-3, seed=9,
                              batch_seed0=900, nu=0.0, w_lo=0.2, w_hi=0.5)
-    check_mixed(list(datagen.separable_field_stream(spec)), 1e-4)
+    check_mixed(list(datagen.exact_field_stream(spec)), 1e-4)
 
 
 def test_mixed_rank_cap_rolls_back():
@@ -115,24 +125,71 @@ def test_mixed_rank_cap_rolls_back():
     np.testing.assert_array_equal(st.reconstruct().cpu().numpy(), before_rec)
 
 
-def test_mixed_eps_1e6_at_the_fp32_floor():
+def test_mixed_eps_1e6_runs_in_fp64():
     """eps = 1e-6 on the tiny model with noise 1e-9 (the configured 1e-6 noise would
-    push the transfer ranks to 256, past any rank cap): eps sits at the FP32 floor of
-    the latent slices, so rank parity is reported rather than required and the
-    error is held to the bound plus that floor."""
-    ys = datagen.tiny_stream(nu=1e-9)
-    st, infos, ranks = run_mixed(ys, 1e-6)
-    ost = ho.BHT(ys[0].shape[1:], 1e-6)
-    oinfo = [ost.init_batch(ys[0])] + [ost.update(y) for y in ys[1:]]
-    print("mixed ranks", ranks, "oracle ranks", [i.ranks for i in oinfo])
-    rec = st.reconstruct().cpu().numpy()
-    off = 0
-    for y in ys:
-        yy = y.astype(np.float64)
-        rel = np.linalg.norm(rec[off:off + y.shape[0]] - yy) / np.linalg.norm(yy)
-        print("batch error / ||Y||: %.3e" % rel)
-        assert rel <= 1e-6 + MIXED_TOL, rel
-        off += y.shape[0]
+    push the transfer ranks to 256, past any rank cap).  eps_nw / ||Y|| = 4e-7 lies
+    below the FP32 error floor, so the precision gate runs the updates in FP64: ranks
+    and skips equal the oracle's, every batch meets eps (1 + 1e-3) ||Y||."""
+    cfg, keep = H.make_config((16, 16, 16, 16), 1e-6, 64, 8, 40, H.HT_FP32)
+    assert H.ht_update_precision(cfg) == H.HT_FP64
+    check_mixed(datagen.tiny_stream(nu=1e-9), 1e-6, prec=H.HT_FP64)
+
+
+def _direction_stream(rel, eps, n1=40, n2=36, N=64, seed=41):
+    """d = 2: batch 0 is s = (1, 0.3) on orthonormal directions a_i x b_i; batch 1 adds
+    directions a_i x b_i (i = 2, 3, ...) of energies x_i^2 = rel[i-2] eps^2 ||Y_1||^2
+    (solved for x, since ||Y_1||^2 = 1.09 + sum x_i^2).  Their residual at either leaf
+    is exactly these directions, so the skip test compares sum x_i^2 with
+    eps^2 ||Y_1||^2, and a leaf keeps direction i when the energy of the directions
+    after it exceeds eps^2 ||Y_1||^2 / 2."""
+    g = np.random.default_rng(seed)
+    k = 2 + len(rel)
+    a = np.linalg.qr(g.standard_normal((n1, k)))[0]
+    b = np.linalg.qr(g.standard_normal((n2, k)))[0]
+    c = [eps * eps * r for r in rel]
+    total = 1.09 / (1.0 - sum(c))
+    ys = []
+    for s in ((1.0, 0.3), (1.0, 0.3) + tuple(math.sqrt(ci * total) for ci in c)):
+        w = np.linalg.qr(g.standard_normal((N, len(s))))[0]
+        y = np.zeros((N, n1, n2))
+        for i, si in enumerate(s):
+            y += si * np.einsum("n,x,y->nxy", w[:, i], a[:, i], b[:, i])
+        ys.append(y.astype(np.float32))
+    return ys
+
+
+@pytest.mark.parametrize("last_rel,ranks", [(1.002, [4, 4]), (0.998, [3, 3])])
+def test_mixed_certificate_retakes_near_threshold_decisions(last_rel, ranks):
+    """Two new directions: one of energy 2 eps^2 ||Y||^2 (no skip, kept), one 0.2 % from
+    the leaf threshold eps_nw^2 = eps^2 ||Y||^2 / 2 (the FP32 band there is ~0.6 %): both
+    leaves' Grams are taken again in FP64, the call stays in the mixed form, and the
+    ranks are the oracle's."""
+    eps = 1e-4
+    ys = _direction_stream((2.0, 0.5 * last_rel), eps)
+    gst, ginfo, granks = run_mixed(ys, eps)
+    ost = ho.BHT(ys[0].shape[1:], eps)
+    oinfo = [ost.init_batch(ys[0]), ost.update(ys[1])]
+    assert oinfo[1].ranks == ranks
+    assert granks == [i.ranks for i in oinfo]
+    assert not ginfo[1].skipped and not oinfo[1].skipped
+    assert ginfo[1].prec_used == H.HT_FP32
+    assert ginfo[1].recomputed == 2, ginfo[1]
+
+
+@pytest.mark.parametrize("x2_rel,skips", [(1.002, False), (0.998, True)])
+def test_mixed_certificate_runs_a_near_threshold_skip_test_in_fp64(x2_rel, skips):
+    """A skip test 0.2 % from its threshold (FP32 band ~0.4 %): the call runs in FP64
+    and the skip decision and ranks are the oracle's."""
+    eps = 1e-4
+    ys = _direction_stream((x2_rel,), eps)
+    gst, ginfo, granks = run_mixed(ys, eps)
+    ost = ho.BHT(ys[0].shape[1:], eps)
+    oinfo = [ost.init_batch(ys[0]), ost.update(ys[1])]
+    assert oinfo[1].skipped is skips
+    assert ginfo[1].skipped is skips
+    assert granks == [i.ranks for i in oinfo]
+    assert ginfo[1].prec_used == H.HT_FP64
+    assert ginfo[1].recomputed >= 1
 
 
 def test_mixed_field96_full_size():
@@ -141,9 +198,12 @@ def test_mixed_field96_full_size():
     spec = datagen.field_96_spec()
     golden = json.load(open(os.path.join(HERE, "golden", "field96_trace.json")))
     st = H.HTStream(spec.n, 1e-4, 48, 32, 640, prec=H.HT_FP32)
-    for k, y in enumerate(datagen.separable_field_stream(spec)):
-        yd = dev(y)
+    from datagen import gpu as G
+    for k in range(spec.n_batches):
+        yd = G.field_batch(spec, k)
         info = st.push(yd)
+        if k > 0:
+            print("batch", k, "prec_used", info.prec_used, "recomputed", info.recomputed)
         row = golden["batches"][k]
         assert st.ranks()[0] == row["ranks"], k
         if k > 0:
