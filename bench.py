@@ -1,32 +1,31 @@
 #!/usr/bin/env python3
 """HT-RISE ingest throughput on one MI355X: mixed precision form vs plain FP64.
 
-Workload: the 96x96x96x3 drifting separable-field stream, N = 32 samples per
-batch, 20 batches, eps = 1e-4, rank capacity 48 (84,934,656 elements per
-batch).  One step compresses the whole stream from scratch: BHT-l2r on batch 0
-and HT-RISE on batches 1..19, every batch already resident in HBM as float32.
-Both forms run on the same staged data:
+Headline workload: the 48x48x48x48x4 drifting separable-field stream (d = 5), N = 16
+samples per batch, 100 batches, eps = 1e-4, rank capacity 64 (339,738,624 elements
+per batch, 136 GB of float32 staged in HBM before timing by datagen's device
+generator).  One step compresses the whole stream from scratch: BHT-l2r on batch 0
+and HT-RISE on batches 1..99.  Both forms run on the same staged data:
 
   fp64   every contraction and Gram product on FP64 matrix cores;
   mixed  HT-RISE contractions and residual Grams on FP32 matrix cores with FP64
-         sums, skip test from explicit residual energies; BHT-l2r, eigen solves,
-         decisions and expansion in FP64.
+         sums and certified decisions (an uncertified one is taken again in FP64);
+         BHT-l2r, eigen solves, decisions and expansion in FP64.
 
-`value` is the mixed form's elements ingested per second over the timed steps;
-the plain form's rate and the ratio are reported beside it, together with the
-HT-RISE-only rates (update calls only, as the paper times updates).  Each run is
-checked after timing against the oracle's stored rank / skip trace and the
-per-batch error bound.  Also reported: the roofline position of the mixed form's
-dominant kernel class (HIP-event timing inside the library, on the launch
-stream), and the FP64 NumPy oracle timed on this host on a bounded sample.
+`value` is the mixed form's elements ingested per second over the timed steps; the
+plain form's rate and the ratio are reported beside it, together with the
+HT-RISE-only rates (update calls only, as the paper times updates) and per-call
+device times of the uninstrumented steps.  After timing, an untimed pass is checked
+batch by batch against the oracle's stored rank / skip trace, and sampled batches
+against the per-batch error bound.  Also reported: the roofline position of the mixed
+form's dominant kernel class (HIP-event timing inside the library on the launch
+stream, last timed step), the 96x96x96x3 stream (N = 32, 20 batches) the same way,
+the many-streams form, and the FP64 NumPy oracle timed on this host on a bounded
+sample of the headline stream.
 
-Beside it, the many-streams form: 64 independent exact-rank streams of uneven
-shapes (3-4 modes of 16..128, 4-32 samples, at most 2^20 elements per batch),
-10 HT-RISE updates each, timed one stream at a time (ht_rise_update) and in lock
-step (ht_rise_update_many), in both precision forms.
-
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--form both|mixed|fp64] [--no-many]
-    python bench.py --copy-probe      # a plain 256 MiB device copy (counter calibration)
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--form both|mixed|fp64]
+                    [--workload field48|field96] [--only] [--no-many] [--cpu-sample B]
+    python bench.py --copy-probe      # a plain 2 GiB device copy (counter calibration)
     python bench.py --ingest-counters FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB
 """
 
@@ -43,7 +42,6 @@ if ROOT not in sys.path:
 
 METRIC = "HT-RISE ingest elements/s at rel. err ≤1e-4, mixed-prec batched vs FP64 plain"
 EPS = 1e-4
-RANK_CAP = 48
 BOUND_SLACK = 1e-3
 # MI355X datasheet peaks (dense)
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
@@ -101,33 +99,65 @@ def roofline(kind: str, d: dict) -> dict:
     return r
 
 
-def cpu_baseline(spec, n_sample: int):
-    """The oracle as it stands, on the first n_sample batches of the same stream (host cores)."""
-    import datagen
-    from oracle import ht_oracle as ho
+def cpu_info() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_threads() -> int:
     try:
         from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count() or 1])
+        return int(max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count() or 1]))
     except Exception:  # pragma: no cover
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    ys = list(datagen.separable_field_stream(spec, batches=range(n_sample)))
-    st = ho.BHT(ys[0].shape[1:], EPS)
-    t0 = time.perf_counter()
-    st.init_batch(ys[0])
-    for y in ys[1:]:
-        st.update(y)
-    dt = time.perf_counter() - t0
-    elems = n_sample * spec.elements_per_batch
-    return {"value": elems / dt, "unit": "elements/s", "cores": int(threads), "kind": "oracle",
-            "sample": "first %d of %d batches (BHT-l2r + %d HT-RISE updates), FP64 NumPy, %.1f s"
-                      % (n_sample, spec.n_batches, n_sample - 1, dt),
-            "ranks_after_sample": st.ranks}
+        return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_baseline(spec, n_batches: int, n_samples: int):
+    """The oracle as it stands on a bounded sample of the same stream: the first n_batches
+    batches (BHT-l2r + updates), each cut to its first n_samples samples (the generator
+    draws them first, so they are the full batches' first samples), on the host cores;
+    then the same on one thread."""
+    import dataclasses
+    import datagen
+    from oracle import ht_oracle as ho
+    sub = dataclasses.replace(spec, N=n_samples, n_batches=n_batches)
+    ys = [datagen.exact_field_batch(sub, k) for k in range(n_batches)]
+
+    def timed():
+        st = ho.BHT(ys[0].shape[1:], EPS)
+        t0 = time.perf_counter()
+        st.init_batch(ys[0])
+        for y in ys[1:]:
+            st.update(y)
+        return time.perf_counter() - t0, st
+
+    dt, st = timed()
+    elems = n_batches * sub.elements_per_batch
+    out = {"value": elems / dt, "unit": "elements/s", "cores": _oracle_threads(), "kind": "oracle",
+           "sample": "first %d batches (BHT-l2r + %d HT-RISE updates) of the stream, first %d of %d samples each, "
+                     "FP64 NumPy, %.1f s" % (n_batches, n_batches - 1, n_samples, spec.N, dt),
+           "cpu_model": cpu_info(), "ranks_after_sample": st.ranks}
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(1):
+            dt1, _ = timed()
+        out["value_1_thread"] = elems / dt1
+    except Exception as e:  # pragma: no cover
+        out["value_1_thread"] = None
+        out["one_thread_error"] = str(e)
+    return out
 
 
 def copy_probe():
-    """A plain device copy of 256 MiB: the reference for the HBM byte counters."""
+    """A plain device copy of 2 GiB (well above the 256 MB last-level cache): the reference
+    for the HBM byte counters."""
     import torch
-    n = 1 << 25  # doubles
+    n = 1 << 28  # doubles
     src = torch.ones(n, dtype=torch.float64, device="cuda:0")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -136,12 +166,15 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}), flush=True)
 
 
-def run_form(form, spec, ys, golden, steps, warmup):
+def run_form(form, spec, ys, golden, steps, warmup, rank_cap):
+    """Times `steps` passes over the staged stream (BHT-l2r on batch 0, HT-RISE on the
+    rest) in one precision form, then checks an untimed pass batch by batch against
+    the oracle's stored trace and the per-batch error bound."""
     import torch
     from paper_2412_16544_amd import htrise as H
-    nb = spec.n_batches
+    nb = len(ys)
     prec = H.HT_FP32 if form == "mixed" else H.HT_FP64
-    st = H.HTStream(spec.n, EPS, RANK_CAP, spec.N, spec.N * nb, "float32", prec=prec)
+    st = H.HTStream(spec.n, EPS, rank_cap, spec.N, spec.N * nb, "float32", prec=prec)
 
     def one_pass():
         st.reset()
@@ -152,47 +185,100 @@ def run_form(form, spec, ys, golden, steps, warmup):
         log("%s: warmup %d done" % (form, w))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    passes = []
     for s in range(steps):
-        # per-kernel HIP events (two records around every launch, a few microseconds of
-        # host time each) on the last timed step only; their cost stays inside the timing
+        # per-kernel HIP events (two records around every launch) on the last timed
+        # step only; their cost stays inside the timing
         H.ht_profile_enable(s == steps - 1)
-        infos = one_pass()
+        passes.append(one_pass())
+        log("%s: timed step %d done" % (form, s))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = H.ht_profile_read_all()
     H.ht_profile_enable(False)
     log("%s: timed %d steps in %.3f s" % (form, steps, elapsed))
 
-    # correctness of the last timed pass, outside the timed region
-    ranks, nacc = st.ranks()
-    ok = ranks == golden["batches"][-1]["ranks"] and nacc == spec.N * nb
-    ok = ok and all(i.skipped == g["skipped"] for i, g in zip(infos[1:], golden["batches"][1:]))
+    # ---- untimed checks: ranks and skips after every batch against the oracle's trace,
+    #      the skips of every timed pass, and the error bound on sampled batches
+    st.reset()
+    mismatch = []
+    for k, y in enumerate(ys):
+        info = st.push(y)
+        row = golden["batches"][k]
+        if st.ranks()[0] != row["ranks"] or (k > 0 and bool(info.skipped) != row["skipped"]):
+            mismatch.append(k)
+    for p in passes:
+        for k, info in enumerate(p[1:], 1):
+            if bool(info.skipped) != golden["batches"][k]["skipped"]:
+                mismatch.append(k)
     worst = 0.0
-    for k in (0, 1, nb // 2, nb - 1):
+    for k in sorted({0, 1, nb // 2, nb - 1}):
         rec = st.reconstruct(spec.N * k, spec.N)
         yk = ys[k].double()
         worst = max(worst, (torch.linalg.vector_norm(rec - yk) / torch.linalg.vector_norm(yk)).item())
-    ok = ok and worst <= EPS * (1 + BOUND_SLACK)
-    log("%s: ranks/skips vs oracle trace and error bound: %s (worst sampled relative error %.3e)" % (form, ok, worst))
+        del rec, yk
+    ok = not mismatch and worst <= EPS * (1 + BOUND_SLACK)
+    log("%s: ranks/skips at every batch vs oracle trace and error bound: %s (mismatches %s, worst sampled "
+        "relative error %.3e)" % (form, ok, sorted(set(mismatch))[:10], worst))
     E = spec.elements_per_batch
-    upd = infos[1:]
-    upd_ms = sum(i.device_ms for i in upd)
+    # per-call device times from the uninstrumented passes
+    plain = passes[:-1] or passes
+    upd = [i for p in plain for i in p[1:] if not i.skipped]
+    skp = [i for p in plain for i in p[1:] if i.skipped]
+    upd_ms = sum(i.device_ms for p in plain for i in p[1:]) / len(plain)
     kinds = {k: v for k, v in prof.items() if v["launches"] > 0}
     cand = [k for k in KIND_TYPE if k in kinds]
     dom = max(cand, key=lambda k: kinds[k]["ms"])
+    last = plain[-1]
     st.close()
+    del st
+    torch.cuda.empty_cache()
     return {
         "value": nb * E * steps / elapsed,
         "ms_per_step": elapsed * 1e3 / steps,
         "rise_update_elements_per_s": (nb - 1) * E / (upd_ms * 1e-3) if upd_ms > 0 else None,
-        "init_batch_ms": infos[0].device_ms,
-        "update_batch_ms": sum(i.device_ms for i in upd if not i.skipped) / max(1, sum(not i.skipped for i in upd)),
-        "skip_batch_ms": sum(i.device_ms for i in upd if i.skipped) / max(1, sum(i.skipped for i in upd)),
-        "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in kinds.items()},
+        "init_batch_ms": sum(p[0].device_ms for p in plain) / len(plain),
+        "update_batch_ms": sum(i.device_ms for i in upd) / max(1, len(upd)),
+        "skip_batch_ms": sum(i.device_ms for i in skp) / max(1, len(skp)),
+        "updates_per_pass": sum(not i.skipped for i in last[1:]),
+        "skips_per_pass": sum(bool(i.skipped) for i in last[1:]),
+        "fp64_recomputed_decisions_per_pass": sum(i.recomputed for i in last[1:]),
+        "updates_run_in_fp64_per_pass": sum(i.prec_used == H.HT_FP64 for i in last[1:] if not i.skipped)
+        if form == "mixed" else None,
+        "kernel_ms_last_step": {k: round(v["ms"], 3) for k, v in kinds.items()},
         "roofline": roofline(dom, kinds[dom]),
         "parity_vs_oracle_trace": bool(ok),
         "worst_sampled_rel_error": worst,
     }
+
+
+def stage(spec):
+    """Every batch of the stream generated straight into HBM (datagen's device generator,
+    bit for bit its host generator, which the oracle's trace was computed from)."""
+    import torch
+    from datagen import gpu as G
+    t0 = time.perf_counter()
+    ys = []
+    for k in range(spec.n_batches):
+        y = torch.empty((spec.N,) + spec.n, dtype=torch.float32, device="cuda:0")
+        G.field_batch_into(spec, k, y)
+        ys.append(y)
+        if k % 25 == 24:
+            log("staged %d of %d batches" % (k + 1, spec.n_batches))
+    torch.cuda.synchronize()
+    log("staged %d batches of %d elements in HBM (%.1f s)" % (spec.n_batches, spec.elements_per_batch,
+                                                              time.perf_counter() - t0))
+    return ys
+
+
+def run_workload(name, spec, rank_cap, forms, steps, warmup):
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", name + "_trace.json")))
+    ys = stage(spec)
+    res = {f: run_form(f, spec, ys, golden, steps, warmup, rank_cap) for f in forms}
+    del ys
+    import torch
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_many(count=64, cap=1 << 20):
@@ -279,7 +365,7 @@ def ingest_counters(fetch_db, write_db, copy_fetch_db, copy_write_db, out_path):
         q = "select kernel_name, value from counters_collection where counter_name = ?"
         return list(con.execute(q, (counter,)))
 
-    copy_bytes = (1 << 25) * 8
+    copy_bytes = (1 << 28) * 8
     cf = [v for n, v in rows(copy_fetch_db, "FETCH_SIZE") if "copyBuffer" in n and v * 1024 > copy_bytes / 4]
     cw = [v for n, v in rows(copy_write_db, "WRITE_SIZE") if "copyBuffer" in n and v * 1024 > copy_bytes / 4]
     f_fetch = copy_bytes / (sum(cf) / len(cf) * 1024)
@@ -302,13 +388,24 @@ def ingest_counters(fetch_db, write_db, copy_fetch_db, copy_write_db, out_path):
     print(json.dumps(out, indent=1))
 
 
+WORKLOADS = {
+    "field48": ("48x48x48x48x4 drifting separable field (d=5, 16 terms switching on, oscillating drift), N=16 per "
+                "batch, 100 batches, eps=1e-4, rank_cap 64; step = BHT-l2r on batch 0 + HT-RISE on batches 1-99", 64),
+    "field96": ("96x96x96x3 drifting separable field, N=32 per batch, 20 batches, eps=1e-4, rank_cap 48; "
+                "step = BHT-l2r on batch 0 + HT-RISE on batches 1-19", 48),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", choices=("both", "mixed", "fp64"), default="both")
-    ap.add_argument("--cpu-sample", type=int, default=10, help="batches of the oracle baseline (0 = skip)")
+    ap.add_argument("--workload", choices=("field48", "field96"), default="field48",
+                    help="the headline stream (the other one is measured beside it unless --only)")
+    ap.add_argument("--only", action="store_true", help="measure the headline stream only")
+    ap.add_argument("--cpu-sample", type=int, default=2, help="batches of the oracle baseline (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-many", action="store_true", help="skip the many-streams measurement")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
@@ -325,20 +422,14 @@ def main():
         ingest_counters(*args.ingest_counters, os.path.join(ROOT, "profiles", "traffic.json"))
         return
 
-    import torch
     import datagen
 
-    spec = datagen.field_96_spec()
-    E = spec.elements_per_batch
-    nb = spec.n_batches
-    t0 = time.perf_counter()
-    ys = [torch.from_numpy(y).to("cuda:0") for y in datagen.separable_field_stream(spec)]
-    torch.cuda.synchronize()
-    log("staged %d batches of %d elements in HBM (%.1f s)" % (nb, E, time.perf_counter() - t0))
-    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "field96_trace.json")))
-
+    specs = {"field48": datagen.field_48_spec(), "field96": datagen.field_96_spec()}
     forms = ["mixed", "fp64"] if args.form == "both" else [args.form]
-    res = {f: run_form(f, spec, ys, golden, args.steps, args.warmup) for f in forms}
+    head_name = args.workload
+    spec = specs[head_name]
+    desc, rank_cap = WORKLOADS[head_name]
+    res = run_workload(head_name, spec, rank_cap, forms, args.steps, args.warmup)
     head = res[forms[0]]
     line = {
         "metric": METRIC,
@@ -353,9 +444,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if forms[0] == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "96x96x96x3 drifting separable field, N=32 per batch, 20 batches, eps=1e-4, "
-                               "rank_cap 48; step = BHT-l2r on batch 0 + HT-RISE on batches 1-19",
-                   "form": forms[0], "elements_per_batch": E, "batches": nb},
+        "config": {"workload": desc, "form": forms[0], "elements_per_batch": spec.elements_per_batch,
+                   "batches": spec.n_batches},
         "roofline": head["roofline"],
         "forms": res,
     }
@@ -364,11 +454,19 @@ def main():
         r1, r2 = res["mixed"]["rise_update_elements_per_s"], res["fp64"]["rise_update_elements_per_s"]
         line["mixed_over_fp64_rise_updates"] = r1 / r2 if r1 and r2 else None
     line["parity_vs_oracle_trace"] = all(r["parity_vs_oracle_trace"] for r in res.values())
+    if not args.only:
+        other = "field96" if head_name == "field48" else "field48"
+        ores = run_workload(other, specs[other], WORKLOADS[other][1], forms, args.steps, args.warmup)
+        line["also"] = {other: {"workload": WORKLOADS[other][0], "forms": ores}}
+        if len(forms) == 2:
+            line["also"][other]["mixed_over_fp64"] = ores["mixed"]["value"] / ores["fp64"]["value"]
+        line["parity_vs_oracle_trace"] = line["parity_vs_oracle_trace"] and all(
+            r["parity_vs_oracle_trace"] for r in ores.values())
     if not args.no_many and args.form == "both":
         line["many_streams"] = run_many()
     if args.cpu_sample > 0:
-        log("timing the oracle on %d batches of the same stream..." % args.cpu_sample)
-        line["cpu_baseline"] = cpu_baseline(spec, args.cpu_sample)
+        log("timing the oracle on a sample of the same stream...")
+        line["cpu_baseline"] = cpu_baseline(spec, args.cpu_sample, 1)
     print(json.dumps(line), flush=True)
 
 
