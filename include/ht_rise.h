@@ -167,6 +167,18 @@ ht_status ht_rise_update_many(ht_handle* hs, const void* const* Ys, const int64_
  * latent is a device buffer of N * r_{1,1} * r_{1,2} float64, C-order [N][r11][r12]. */
 ht_status ht_project(ht_handle h, const void* Y, int64_t N, void* latent, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops): ht_project without the handle's workspace buffers.  The
+ * intermediate level tensors of the projection chain live in a static device array
+ * of 256 MiB that the library holds on every GPU it runs on until the process ends;
+ * the batch is projected in chunks of as many samples as fit.  No device memory is
+ * allocated or freed.  Returns HT_ESHAPE, before any work, when one sample's chain
+ * (its two largest alternating intermediates, FP64) needs more than 256 MiB.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (different
+ * streams or threads) race and must be serialised by the caller.  Same arguments,
+ * layout and result as ht_project. */
+ht_status ht_project_static(ht_handle h, const void* Y, int64_t N, void* latent, void* hip_stream);
+
 /* Reconstruction of accumulated samples [first, first+count) into the device
  * buffer out (count * prod(n) elements of type dtype, C-order [count][n_1]...[n_d]). */
 ht_status ht_reconstruct(ht_handle h, int64_t first, int64_t count, void* out, int32_t dtype,

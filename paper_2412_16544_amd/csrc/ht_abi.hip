@@ -467,13 +467,15 @@ double* other(const ht_state* h, const void* p) { return p == h->bufA ? h->bufB 
 // energy it discards: FP32 ones the explicit sum into energy[2 node] (explicit[node]
 // set), FP64 ones ||in||^2 and ||out||^2 into energy[2 node] and [2 node + 1].
 Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, double* norm_out = nullptr,
-                    bool mixed = false, double* energy = nullptr, std::vector<char>* expl = nullptr) {
+                    bool mixed = false, double* energy = nullptr, std::vector<char>* expl = nullptr,
+                    double* const* pp = nullptr) {
   const std::vector<int> f = h->tree.frontier(ell);
   Level cur = in;
   for (size_t k = 0; k < f.size(); ++k) {
     const int node = f[k];
     if (h->tree.nodes[node].layer != ell) continue;
-    double* dst = other(h, cur.ptr);
+    // intermediates alternate between the handle's two level buffers, or the pair pp
+    double* dst = pp ? (cur.ptr == pp[0] ? pp[1] : pp[0]) : other(h, cur.ptr);
     const ModeView v = view_of(cur, k);
     if (mixed && v.m <= ht::kResidGramMaxM) {
       ht::ttm_contract_f32(cur.ptr, cur.t, v, h->core[node], h->rank[node], reinterpret_cast<float*>(dst),
@@ -820,6 +822,33 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
     h->h_aux = b + kScalars(nn) + 2 * nn;
   }
   *out = h;
+  return HT_OK;
+}
+
+// ---- the static scratch of ht_project_static: one copy per GPU, in the code object,
+//      so that the call allocates nothing.  Host code must never pass the array's
+//      name to a kernel (in host code it is a stand-in, not a device address): the
+//      device address comes from hipGetSymbolAddress, taken once per device with that
+//      device current, and only that pointer is used.
+constexpr size_t kStaticScratchDoubles = (size_t)1 << 25;  // 256 MiB
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+ht_status static_scratch(double** out) {
+  int dev = -1;
+  HT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HT_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    HT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr) return fail(HT_EDEVICE, "hipGetSymbolAddress returned NULL");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
   return HT_OK;
 }
 
@@ -1317,6 +1346,53 @@ ht_status ht_project(ht_handle h, const void* Y, int64_t N, void* latent, void* 
   h->last_stream = s;
   Level c1 = project_all(h, Y, N, s);
   ht::copy_f64(static_cast<const double*>(c1.ptr), static_cast<double*>(latent), (int64_t)c1.elems(), s);
+  HT_HIP(hipGetLastError());
+  HT_HIP(wait_stream(s));
+  return HT_OK;
+}
+
+ht_status ht_project_static(ht_handle h, const void* Y, int64_t N, void* latent, void* hip_stream) {
+  g_last_error.clear();
+  if (h == nullptr || Y == nullptr || latent == nullptr) return fail(HT_EINVAL, "NULL argument");
+  if (N < 1) return fail(HT_EINVAL, "N must be >= 1");
+  double* base = nullptr;
+  ht_status st = static_scratch(&base);
+  if (st != HT_OK) return st;
+  // per-sample sizes of the chain's intermediates, which alternate between two halves
+  size_t half[2] = {0, 0};
+  {
+    int flip = 0;
+    for (int ell = h->tree.depth; ell >= 1; --ell) {
+      const std::vector<int> f = h->tree.frontier(ell);
+      std::vector<int64_t> sz = frontier_sizes(h, ell);
+      for (size_t k = 0; k < f.size(); ++k) {
+        if (h->tree.nodes[f[k]].layer != ell) continue;
+        sz[k] = h->rank[f[k]];
+        half[flip] = std::max(half[flip], (size_t)prod(sz, 0, sz.size()));
+        flip ^= 1;
+      }
+    }
+  }
+  // the second half starts at a 256-byte boundary: 32 doubles of slack
+  const size_t per = half[0] + half[1];
+  const int64_t chunk = std::min<int64_t>(N, (int64_t)((kStaticScratchDoubles - 32) / per));
+  if (chunk < 1)
+    return fail(HT_ESHAPE, "one sample's projection needs " + std::to_string(per * sizeof(double)) +
+                               " bytes of scratch, more than the static " +
+                               std::to_string(kStaticScratchDoubles * sizeof(double)));
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  h->last_stream = s;
+  double* pp[2] = {base, base + align256(half[0] * chunk * sizeof(double)) / sizeof(double)};
+  const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
+  const size_t esz = h->in_t == Elem::F32 ? 4 : 8;
+  const int64_t sample = prod(h->n, 0, h->n.size());
+  for (int64_t n0 = 0; n0 < N; n0 += chunk) {
+    const int64_t cn = std::min<int64_t>(chunk, N - n0);
+    Level cur{static_cast<const char*>(Y) + (size_t)n0 * sample * esz, h->in_t, cn, h->n};
+    for (int ell = h->tree.depth; ell >= 1; --ell) cur = project_layer(h, ell, cur, s, nullptr, false, nullptr, nullptr, pp);
+    ht::copy_f64(static_cast<const double*>(cur.ptr), static_cast<double*>(latent) + (size_t)n0 * r11 * r12,
+                 cn * r11 * r12, s);
+  }
   HT_HIP(hipGetLastError());
   HT_HIP(wait_stream(s));
   return HT_OK;

@@ -61,6 +61,7 @@ def lib() -> ctypes.CDLL:
         L.ht_rise_update_many.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64), i32, vp,
                                           ctypes.POINTER(ht_update_info)]
         L.ht_project.argtypes = [vp, vp, i64, vp, vp]
+        L.ht_project_static.argtypes = [vp, vp, i64, vp, vp]
         L.ht_reconstruct.argtypes = [vp, i64, i64, vp, i32, vp]
         L.ht_query_ranks.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.ht_export_cores.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz, ctypes.POINTER(sz)]
@@ -71,7 +72,7 @@ def lib() -> ctypes.CDLL:
         L.ht_last_error.argtypes = []
         L.ht_last_error.restype = ctypes.c_char_p
         for name in ("ht_workspace_bytes", "ht_update_precision", "ht_init_batch", "ht_rise_update",
-                     "ht_rise_update_many", "ht_project",
+                     "ht_rise_update_many", "ht_project", "ht_project_static",
                      "ht_reconstruct", "ht_query_ranks", "ht_export_cores"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -149,6 +150,10 @@ def ht_rise_update_many(handles: Sequence[int], Ys, stream=None):
 
 def ht_project(h: int, Y, latent, stream=None) -> None:
     _check(lib().ht_project(h, _ptr(Y), Y.shape[0], _ptr(latent), _stream(stream)), "ht_project")
+
+
+def ht_project_static(h: int, Y, latent, stream=None) -> None:
+    _check(lib().ht_project_static(h, _ptr(Y), Y.shape[0], _ptr(latent), _stream(stream)), "ht_project_static")
 
 
 def ht_reconstruct(h: int, first: int, count: int, out, dtype: int, stream=None) -> None:
