@@ -200,16 +200,21 @@ def run_form(form, spec, ys, golden, steps, warmup, rank_cap):
 
     # ---- untimed checks: ranks and skips after every batch against the oracle's trace,
     #      the skips of every timed pass, and the error bound on sampled batches
+    from datagen import gpu as G
     st.reset()
-    mismatch = []
+    rows = golden["batches"]
+    mismatch = [] if len(rows) == nb else ["trace has %d batches" % len(rows)]
+    mismatch += ["data %d" % k for k in range(min(nb, len(rows)))
+                 if G.checksum(ys[k]) != rows[k].get("data_checksum")]
     for k, y in enumerate(ys):
         info = st.push(y)
-        row = golden["batches"][k]
-        if st.ranks()[0] != row["ranks"] or (k > 0 and bool(info.skipped) != row["skipped"]):
+        if k >= len(rows):
+            continue
+        if st.ranks()[0] != rows[k]["ranks"] or (k > 0 and bool(info.skipped) != rows[k]["skipped"]):
             mismatch.append(k)
     for p in passes:
-        for k, info in enumerate(p[1:], 1):
-            if bool(info.skipped) != golden["batches"][k]["skipped"]:
+        for k, info in enumerate(p[1:len(rows)], 1):
+            if bool(info.skipped) != rows[k]["skipped"]:
                 mismatch.append(k)
     worst = 0.0
     for k in sorted({0, 1, nb // 2, nb - 1}):
@@ -217,9 +222,29 @@ def run_form(form, spec, ys, golden, steps, warmup, rank_cap):
         yk = ys[k].double()
         worst = max(worst, (torch.linalg.vector_norm(rec - yk) / torch.linalg.vector_norm(yk)).item())
         del rec, yk
+    # held-out batches after the stream: relative test error (Sec. 4.1), against the
+    # oracle's stored values when the trace has them
+    rte = None
+    ref = golden.get("rte_heldout")
+    if ref is not None:
+        import dataclasses
+        ext = dataclasses.replace(spec, n_batches=spec.n_batches + len(ref["batches"]))
+        yk = torch.empty_like(ys[0])
+        vals, diff = [], 0.0
+        for k, cs, errs in zip(ref["batches"], ref["data_checksum"], ref["rel_err"]):
+            G.field_batch_into(ext, k, yk)
+            if G.checksum(yk) != cs:
+                mismatch.append("held-out data %d" % k)
+            e = st.rte(yk)
+            vals += e
+            diff = max(diff, max(abs(a - b) for a, b in zip(e, errs)))
+        rte = {"batches": ref["batches"], "mean": sum(vals) / len(vals), "max": max(vals),
+               "oracle_mean": sum(sum(x) for x in ref["rel_err"]) / sum(len(x) for x in ref["rel_err"]),
+               "max_abs_diff_vs_oracle": diff}
+        del yk
     ok = not mismatch and worst <= EPS * (1 + BOUND_SLACK)
     log("%s: ranks/skips at every batch vs oracle trace and error bound: %s (mismatches %s, worst sampled "
-        "relative error %.3e)" % (form, ok, sorted(set(mismatch))[:10], worst))
+        "relative error %.3e)" % (form, ok, sorted(set(map(str, mismatch)))[:10], worst))
     E = spec.elements_per_batch
     # per-call device times from the uninstrumented passes
     plain = passes[:-1] or passes
@@ -249,6 +274,7 @@ def run_form(form, spec, ys, golden, steps, warmup, rank_cap):
         "roofline": roofline(dom, kinds[dom]),
         "parity_vs_oracle_trace": bool(ok),
         "worst_sampled_rel_error": worst,
+        "rte_heldout": rte,
     }
 
 

@@ -536,31 +536,36 @@ def exact_field_factors(spec: FieldSpec, k: int) -> FieldFactors:
 
 
 def exact_field_batch(spec: FieldSpec, k: int, chunk: int = 1 << 22, workers: int = 4) -> np.ndarray:
-    """Batch k of the exactly reproducible field as float32 (N, *grid, channels), on the host."""
+    """Batch k of the exactly reproducible field as float32 (N, *grid, channels), on the host.
+
+    The signal is one BLAS product (exact, so its blocking is immaterial); only the
+    noise and the rounding run in worker threads, which call no BLAS (concurrent
+    BLAS calls from several threads are not safe in every BLAS build)."""
     ff = exact_field_factors(spec, k)
     T, N, P1 = ff.A.shape
     P2 = ff.B.shape[1]
+    sig = (ff.A.reshape(T, N * P1).T @ ff.B).reshape(-1)      # exact in any order
     out = np.empty(N * P1 * P2, dtype=np.float32)
-    per = P1 * P2
 
-    def one(s):
-        sig = (ff.A[:, s, :].T @ ff.B).reshape(-1)           # exact in any order
-        for c0 in range(0, per, chunk):
-            c1 = min(per, c0 + chunk)
-            if ff.scale != 0.0:
-                y = sig[c0:c1] + ff.scale * noise_unit(ff.key, s * per + c0, c1 - c0)
-            else:
-                y = sig[c0:c1]
-            out[s * per + c0:s * per + c1] = y.astype(np.float32)
+    def one(c0):
+        c1 = min(sig.size, c0 + chunk)
+        y = sig[c0:c1] + ff.scale * noise_unit(ff.key, c0, c1 - c0) if ff.scale != 0.0 else sig[c0:c1]
+        out[c0:c1] = y.astype(np.float32)
 
-    if N * per >= (1 << 24) and workers > 1:
+    starts = range(0, sig.size, chunk)
+    if workers > 1 and sig.size > chunk:
         from concurrent.futures import ThreadPoolExecutor
         with ThreadPoolExecutor(max_workers=workers) as ex:
-            list(ex.map(one, range(N)))
+            list(ex.map(one, starts))
     else:
-        for s in range(N):
-            one(s)
+        for c0 in starts:
+            one(c0)
     return out.reshape(ff.shape)
+
+
+def checksum(y: np.ndarray) -> int:
+    """Exact checksum of a float32 array: the sum of its bit patterns as integers."""
+    return int(np.sum(np.ascontiguousarray(y, dtype=np.float32).view(np.uint32), dtype=np.uint64))
 
 
 def exact_field_stream(spec: FieldSpec, batches: Sequence[int] | None = None) -> Iterator[np.ndarray]:

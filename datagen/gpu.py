@@ -50,3 +50,9 @@ def field_batch(spec: FieldSpec, k: int, device: str = "cuda:0"):
     out = torch.empty((spec.N,) + spec.n, dtype=torch.float32, device=device)
     field_batch_into(spec, k, out)
     return out
+
+
+def checksum(t) -> int:
+    """datagen.checksum of a float32 CUDA tensor (the sum of its bit patterns), on the device."""
+    import torch
+    return int((t.contiguous().view(torch.int32).to(torch.int64) & 0xFFFFFFFF).sum().item())

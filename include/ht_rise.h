@@ -184,6 +184,22 @@ ht_status ht_project_static(ht_handle h, const void* Y, int64_t N, void* latent,
 ht_status ht_reconstruct(ht_handle h, int64_t first, int64_t count, void* out, int32_t dtype,
                          void* hip_stream);
 
+/* The decoder of Problem 1: the tensors of N latent codes (device, float64, C-order
+ * [N][r_{1,1}][r_{1,2}], as ht_project writes them) contracted root-to-leaves with
+ * the current cores (Eq. htucker_reconstruction) into the device buffer out
+ * (N * prod(n) elements of type dtype, C-order [N][n_1]...[n_d]). */
+ht_status ht_decode(ht_handle h, const double* latent, int64_t N, void* out, int32_t dtype, void* hip_stream);
+
+/* Relative test error of N samples Y (device, cfg->in_dtype, not accumulated): for
+ * each sample i, rel_err[i] (host) = ||Y_i - decode(encode(Y_i))||_F / ||Y_i||_F, the
+ * summand of the relative test error (Sec. 4.1, Eq. generalization_performance; the
+ * RTE is their mean).  The reconstruction is the orthogonal projection of Y_i onto
+ * the span of the HT bases, so the error is taken as sqrt(||Y_i||^2 - ||C_i||^2)
+ * from the FP64 per-sample norms of the sample and of its latent code C_i, without
+ * materialising the reconstruction (the subtraction leaves an absolute error of
+ * about 1e-15 / rel_err[i] in rel_err[i]).  Synchronises. */
+ht_status ht_rte(ht_handle h, const void* Y, int64_t N, double* rel_err, void* hip_stream);
+
 /* Copies the rank vector R (2d-2 entries, order as above) into ranks[0..cap-1],
  * the entry count into *n_ranks and N_acc into *n_accum (each pointer may be NULL).
  * Host memory; synchronises the handle's last stream.  cap < 2d-2 is HT_EINVAL

@@ -336,6 +336,15 @@ class BHT:
                     c = contract_mode(c, 1 + k, self.core[nd.idx])
         return c.reshape((n_b,) + self.n)
 
+    def relative_test_errors(self, y: np.ndarray) -> np.ndarray:
+        """Per-sample ||Y_i - decode(project(Y_i))|| / ||Y_i|| of held-out samples: the
+        summands of the relative test error (Sec. 4.1, Eq. generalization_performance)."""
+        y = np.asarray(y, dtype=np.float64)
+        rec = self.decode(self.project(y))
+        d = (y - rec).reshape(y.shape[0], -1)
+        n = y.reshape(y.shape[0], -1)
+        return np.sqrt(np.sum(d * d, axis=1)) / np.sqrt(np.sum(n * n, axis=1))
+
     def reconstruct(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         if count is None:
             count = self.n_accum - first

@@ -203,6 +203,7 @@ struct ht_state {
   double* bufA = nullptr;
   double* bufB = nullptr;
   double* resid = nullptr;
+  size_t resid_elems = 0;
   double* bufZ = nullptr;
   double* gpart = nullptr;
   double* scal = nullptr;
@@ -460,7 +461,28 @@ std::vector<int64_t> frontier_sizes(const ht_state* h, int ell) {
 
 double* other(const ht_state* h, const void* p) { return p == h->bufA ? h->bufB : h->bufA; }
 
-// Contract every node of layer ell (left to right) with U^T, then merge siblings.
+// Order in which the nodes of layer ell contract the level tensor (frontier positions).
+// The contractions of one layer act on different modes and commute (every node of a
+// layer projects the same tensor), so the order only changes the cost: contracting
+// mode k (m rows onto r) costs ~2 r T flops on a tensor of T elements and leaves
+// T r / m, and the order that minimises the sum takes the modes by ascending
+// r / (1 - r / m) (an exchange argument on two adjacent steps); modes that do not
+// shrink come last, ties keep the frontier order.
+std::vector<int> contraction_order(const ht_state* h, int ell, const std::vector<int64_t>& modes) {
+  const std::vector<int> f = h->tree.frontier(ell);
+  std::vector<int> ks;
+  std::vector<double> key(f.size(), 0.0);
+  for (size_t k = 0; k < f.size(); ++k) {
+    if (h->tree.nodes[f[k]].layer != ell) continue;
+    const double r = h->rank[f[k]], m = (double)modes[k];
+    key[k] = r < m ? r / (1.0 - r / m) : HUGE_VAL;
+    ks.push_back((int)k);
+  }
+  std::stable_sort(ks.begin(), ks.end(), [&](int a, int b) { return key[a] < key[b]; });
+  return ks;
+}
+
+// Contract every node of layer ell with U^T (in contraction_order), then merge siblings.
 // With norm_out the first contraction also writes the squared norm of the input.
 // mixed: contractions of modes with at most 128 rows on FP32 matrix cores (FP32
 // level tensor out); with energy, every contraction also writes the residual
@@ -471,9 +493,8 @@ Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, 
                     double* const* pp = nullptr) {
   const std::vector<int> f = h->tree.frontier(ell);
   Level cur = in;
-  for (size_t k = 0; k < f.size(); ++k) {
+  for (const int k : contraction_order(h, ell, in.modes)) {
     const int node = f[k];
-    if (h->tree.nodes[node].layer != ell) continue;
     // intermediates alternate between the handle's two level buffers, or the pair pp
     double* dst = pp ? (cur.ptr == pp[0] ? pp[1] : pp[0]) : other(h, cur.ptr);
     const ModeView v = view_of(cur, k);
@@ -529,6 +550,40 @@ Level project_all(const ht_state* h, const void* Y, int64_t N, hipStream_t s, do
     norm_out = nullptr;
   }
   return cur;
+}
+
+// Root-to-leaves expansion (Eq. htucker_reconstruction) of N latent slices
+// [N][r11][r12] (FP64, at lat, which may be a caller's buffer) into out (C-order
+// [N][n_1]...[n_d] of type ot).  Each layer expands its nodes in the reverse of
+// contraction_order (the transposed chain, so it costs what the projection costs);
+// intermediates alternate between the handle's two level buffers.
+void expand_all(const ht_state* h, const double* lat, int64_t N, void* out, Elem ot, hipStream_t s) {
+  const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
+  Level cur{lat, Elem::F64, N, {r11, r12}};
+  for (int ell = 1; ell <= h->tree.depth; ++ell) {
+    const std::vector<int> f = h->tree.frontier(ell);
+    // split merged modes: sizes of frontier(ell) after its layer is processed
+    std::vector<int64_t> sz(f.size());
+    for (size_t k = 0; k < f.size(); ++k) {
+      const TNode& t = h->tree.nodes[f[k]];
+      sz[k] = (t.layer == ell) ? h->rank[f[k]] : h->n[t.lo];
+    }
+    cur.modes = sz;
+    std::vector<int> order = contraction_order(h, ell, frontier_sizes(h, ell));
+    std::reverse(order.begin(), order.end());
+    for (size_t q = 0; q < order.size(); ++q) {
+      const int k = order[q];
+      const int node = f[k];
+      const int64_t alpha = alpha_now(h, node);
+      const ModeView v = view_of(cur, (size_t)k);
+      const bool final_step = (ell == h->tree.depth) && (q + 1 == order.size());
+      void* dst = final_step ? out : static_cast<void*>(other(h, cur.ptr));
+      ht::ttm_expand(static_cast<const double*>(cur.ptr), v.P, h->rank[node], v.S, h->core[node], alpha, nullptr,
+                     Elem::F64, dst, final_step ? ot : Elem::F64, s);
+      cur.ptr = dst;
+      cur.modes[k] = alpha;
+    }
+  }
 }
 
 ht_status sync_read(ht_state* h, hipStream_t s, const double* dev, size_t count, double* host) {
@@ -798,6 +853,7 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   h->bufA = reinterpret_cast<double*>(base + L.bufA);
   h->bufB = reinterpret_cast<double*>(base + L.bufB);
   h->resid = reinterpret_cast<double*>(base + L.resid);
+  h->resid_elems = L.resid_elems;
   h->bufZ = reinterpret_cast<double*>(base + L.bufZ);
   h->gpart = reinterpret_cast<double*>(base + L.gpart);
   h->scal = reinterpret_cast<double*>(base + L.scal);
@@ -899,9 +955,10 @@ double fp32_chain(const ht_state* h, int ell) {
 bool skip_certified(const Upd& u, double lost) {
   const ht_state* h = u.h;
   double chain = 0.0, delta = kGramK * kU32 * std::fabs(lost);
-  for (int ell = h->tree.depth; ell >= 1; --ell)
-    for (int node : h->tree.frontier(ell)) {
-      if (h->tree.nodes[node].layer != ell) continue;
+  for (int ell = h->tree.depth; ell >= 1; --ell) {
+    const std::vector<int> f = h->tree.frontier(ell);
+    for (const int k : contraction_order(h, ell, frontier_sizes(h, ell))) {
+      const int node = f[k];
       const double* e = h->h_scal + 8 + 2 * node;
       const bool ex = u.expl[node] != 0;
       const double ej = ex ? e[0] : e[0] - e[1];
@@ -910,6 +967,7 @@ bool skip_certified(const Upd& u, double lost) {
       delta += 2.0 * std::sqrt(std::max(ej, 0.0)) * dj + dj * dj + (ex ? 0.0 : 4.0 * kU64 * e[0]);
       chain += own;
     }
+  }
   return std::fabs(lost - u.eps_des * u.eps_des) > delta;
 }
 
@@ -1365,8 +1423,7 @@ ht_status ht_project_static(ht_handle h, const void* Y, int64_t N, void* latent,
     for (int ell = h->tree.depth; ell >= 1; --ell) {
       const std::vector<int> f = h->tree.frontier(ell);
       std::vector<int64_t> sz = frontier_sizes(h, ell);
-      for (size_t k = 0; k < f.size(); ++k) {
-        if (h->tree.nodes[f[k]].layer != ell) continue;
+      for (const int k : contraction_order(h, ell, frontier_sizes(h, ell))) {
         sz[k] = h->rank[f[k]];
         half[flip] = std::max(half[flip], (size_t)prod(sz, 0, sz.size()));
         flip ^= 1;
@@ -1413,55 +1470,63 @@ ht_status ht_reconstruct(ht_handle h, int64_t first, int64_t count, void* out, i
   for (int64_t c0 = 0; c0 < count; c0 += h->max_batch) {
     const int64_t cn = std::min<int64_t>(h->max_batch, count - c0);
     ht::root_extract(h->root, first + c0, cn, r11, r12, h->rank_cap, h->bufA, s);
-    Level cur{h->bufA, Elem::F64, cn, {r11, r12}};
-    char* dst_final = static_cast<char*>(out) + (size_t)c0 * per * esz;
-    for (int ell = 1; ell <= h->tree.depth; ++ell) {
-      const std::vector<int> f = h->tree.frontier(ell);
-      // split merged modes: sizes of frontier(ell) after its layer is processed
-      std::vector<int64_t> sz(f.size());
-      for (size_t k = 0; k < f.size(); ++k) {
-        const TNode& t = h->tree.nodes[f[k]];
-        sz[k] = (t.layer == ell) ? h->rank[f[k]] : h->n[t.lo];
-      }
-      cur.modes = sz;
-      // expand right to left (the reverse of the projection order)
-      int last_k = -1;
-      for (size_t k = 0; k < f.size(); ++k)
-        if (h->tree.nodes[f[k]].layer == ell) last_k = (int)k;
-      for (int k = (int)f.size() - 1; k >= 0; --k) {
-        const int node = f[k];
-        if (h->tree.nodes[node].layer != ell) continue;
-        int64_t first_k = -1;
-        for (size_t q = 0; q < f.size(); ++q)
-          if (h->tree.nodes[f[q]].layer == ell) {
-            first_k = (int64_t)q;
-            break;
-          }
-        const int64_t alpha = alpha_now(h, node);
-        const ModeView v = view_of(cur, (size_t)k);
-        const bool final_step = (ell == h->tree.depth) && (k == first_k);
-        void* dst = final_step ? static_cast<void*>(dst_final) : static_cast<void*>(other(h, cur.ptr));
-        ht::ttm_expand(static_cast<const double*>(cur.ptr), v.P, h->rank[node], v.S, h->core[node], alpha, nullptr,
-                       Elem::F64, dst, final_step ? ot : Elem::F64, s);
-        cur.ptr = dst;
-        cur.modes[k] = alpha;
-      }
-      (void)last_k;
-      if (ell < h->tree.depth) {
-        // alpha of a transfer node splits into its successors' ranks: frontier(ell+1) sizes
-        std::vector<int> f2 = h->tree.frontier(ell + 1);
-        std::vector<int64_t> s2(f2.size());
-        for (size_t k = 0; k < f2.size(); ++k) {
-          const TNode& t = h->tree.nodes[f2[k]];
-          s2[k] = (t.layer == ell + 1) ? h->rank[f2[k]] : h->n[t.lo];
-        }
-        cur.modes = s2;
-      }
-    }
-    if (h->tree.depth == 0) return fail(HT_EINVAL, "degenerate tree");
+    expand_all(h, h->bufA, cn, static_cast<char*>(out) + (size_t)c0 * per * esz, ot, s);
   }
   HT_HIP(hipGetLastError());
   HT_HIP(wait_stream(s));
+  return HT_OK;
+}
+
+ht_status ht_decode(ht_handle h, const double* latent, int64_t N, void* out, int32_t dtype, void* hip_stream) {
+  g_last_error.clear();
+  if (h == nullptr || latent == nullptr || out == nullptr) return fail(HT_EINVAL, "NULL argument");
+  if (dtype != HT_F32 && dtype != HT_F64) return fail(HT_EINVAL, "dtype must be HT_F32 or HT_F64");
+  if (N < 0) return fail(HT_EINVAL, "N must be >= 0");
+  if (N == 0) return HT_OK;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  h->last_stream = s;
+  const Elem ot = dtype == HT_F32 ? Elem::F32 : Elem::F64;
+  const size_t esz = dtype == HT_F32 ? 4 : 8;
+  const int64_t per = prod(h->n, 0, h->n.size());
+  const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
+  for (int64_t c0 = 0; c0 < N; c0 += h->max_batch) {
+    const int64_t cn = std::min<int64_t>(h->max_batch, N - c0);
+    expand_all(h, latent + (size_t)c0 * r11 * r12, cn, static_cast<char*>(out) + (size_t)c0 * per * esz, ot, s);
+  }
+  HT_HIP(hipGetLastError());
+  HT_HIP(wait_stream(s));
+  return HT_OK;
+}
+
+ht_status ht_rte(ht_handle h, const void* Y, int64_t N, double* rel_err, void* hip_stream) {
+  g_last_error.clear();
+  if (h == nullptr || Y == nullptr || rel_err == nullptr) return fail(HT_EINVAL, "NULL argument");
+  if (N < 1) return fail(HT_EINVAL, "N must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  h->last_stream = s;
+  const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
+  const size_t esz = h->in_t == Elem::F32 ? 4 : 8;
+  const int64_t per = prod(h->n, 0, h->n.size());
+  // the residual buffer is idle outside updates: per-sample norms and their partials
+  const int64_t cap = std::min<int64_t>(h->max_batch, (int64_t)(h->resid_elems / (2 + 2 * ht::kSegBlocks)));
+  if (cap < 1) return fail(HT_ENOMEM, "workspace too small for the per-sample norms");
+  double* y2 = h->resid;
+  double* c2 = y2 + cap;
+  double* part = c2 + cap;
+  std::vector<double> hy(2 * cap);
+  for (int64_t c0 = 0; c0 < N; c0 += cap) {
+    const int64_t cn = std::min<int64_t>(cap, N - c0);
+    const void* yc = static_cast<const char*>(Y) + (size_t)c0 * per * esz;
+    Level c1 = project_all(h, yc, cn, s);
+    ht::sumsq_segments(yc, h->in_t, cn, per, part, y2, s);
+    ht::sumsq_segments(c1.ptr, c1.t, cn, (int64_t)r11 * r12, part + cap * ht::kSegBlocks, c2, s);
+    HT_HIP(hipMemcpyAsync(hy.data(), y2, 2 * cap * sizeof(double), hipMemcpyDeviceToHost, s));
+    HT_HIP(wait_stream(s));
+    for (int64_t i = 0; i < cn; ++i) {
+      const double a = hy[i], b = hy[cap + i];
+      rel_err[c0 + i] = a > 0.0 ? std::sqrt(std::max(0.0, a - b) / a) : 0.0;
+    }
+  }
   return HT_OK;
 }
 

@@ -26,6 +26,11 @@ enum class Elem : int { F32 = 0, F64 = 1 };
 // partials must hold kSumsqBlocks doubles.
 constexpr int kSumsqBlocks = 1024;
 void sumsq(const void* x, Elem t, int64_t n, double* partials, double* out, hipStream_t s);
+// Sum of squares of each of nseg consecutive segments of len elements into out[g];
+// partials must hold nseg * kSegBlocks doubles.  nseg < 65536.
+constexpr int kSegBlocks = 64;
+void sumsq_segments(const void* x, Elem t, int64_t nseg, int64_t len, double* partials, double* out,
+                    hipStream_t s);
 
 // The second level of every split reduction (workgroup partials -> one FP64 sum,
 // in a fixed order).  Between sums_defer_begin and sums_defer_end the launchers of

@@ -1855,6 +1855,43 @@ void sumsq(const void* x, Elem t, int64_t n, double* partials, double* out, hipS
   finish_sum(partials, kSumsqBlocks, out, s);
 }
 
+// Per-segment sums of squares: segment g is x[g * len, (g + 1) * len).  Grid
+// (blocks, segments) of partials, then one workgroup per segment sums its partials
+// in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_seg_kernel(const T* __restrict__ x, int64_t len,
+                                                        double* __restrict__ part) {
+  const T* xs = x + (int64_t)blockIdx.y * len;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
+    const double v = ld(xs, i);
+    acc = fma(v, v, acc);
+  }
+  __shared__ double red[4];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void reduce_seg_kernel(const double* __restrict__ part, int n,
+                                                         double* __restrict__ out) {
+  reduce_body(part + (int64_t)blockIdx.x * n, n, out + blockIdx.x);
+}
+
+void sumsq_segments(const void* x, Elem t, int64_t nseg, int64_t len, double* partials, double* out,
+                    hipStream_t s) {
+  if (nseg <= 0 || len <= 0) return;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kSegBlocks, len / 4096));
+  ProfScope prof(KKind::Sumsq, s, 2.0 * nseg * len, (double)nseg * len * (t == Elem::F32 ? 4 : 8));
+  const dim3 grid((unsigned)blocks, (unsigned)nseg);
+  if (t == Elem::F32)
+    sumsq_seg_kernel<float><<<grid, 256, 0, s>>>(static_cast<const float*>(x), len, partials);
+  else
+    sumsq_seg_kernel<double><<<grid, 256, 0, s>>>(static_cast<const double*>(x), len, partials);
+  reduce_seg_kernel<<<(unsigned)nseg, 256, 0, s>>>(partials, blocks, out);
+}
+
 size_t panel_lds_bytes(bool resid, int R, size_t esz) {
   const int RP = (R + 15) & ~15;
   size_t n = (size_t)GBK * GLD;

@@ -63,6 +63,8 @@ def lib() -> ctypes.CDLL:
         L.ht_project.argtypes = [vp, vp, i64, vp, vp]
         L.ht_project_static.argtypes = [vp, vp, i64, vp, vp]
         L.ht_reconstruct.argtypes = [vp, i64, i64, vp, i32, vp]
+        L.ht_decode.argtypes = [vp, vp, i64, vp, i32, vp]
+        L.ht_rte.argtypes = [vp, vp, i64, ctypes.POINTER(ctypes.c_double), vp]
         L.ht_query_ranks.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.ht_export_cores.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz, ctypes.POINTER(sz)]
         L.ht_destroy.argtypes = [vp]
@@ -72,7 +74,7 @@ def lib() -> ctypes.CDLL:
         L.ht_last_error.argtypes = []
         L.ht_last_error.restype = ctypes.c_char_p
         for name in ("ht_workspace_bytes", "ht_update_precision", "ht_init_batch", "ht_rise_update",
-                     "ht_rise_update_many", "ht_project", "ht_project_static",
+                     "ht_rise_update_many", "ht_project", "ht_project_static", "ht_decode", "ht_rte",
                      "ht_reconstruct", "ht_query_ranks", "ht_export_cores"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -158,6 +160,17 @@ def ht_project_static(h: int, Y, latent, stream=None) -> None:
 
 def ht_reconstruct(h: int, first: int, count: int, out, dtype: int, stream=None) -> None:
     _check(lib().ht_reconstruct(h, first, count, _ptr(out), dtype, _stream(stream)), "ht_reconstruct")
+
+
+def ht_decode(h: int, latent, out, dtype: int, stream=None) -> None:
+    _check(lib().ht_decode(h, _ptr(latent), latent.shape[0], _ptr(out), dtype, _stream(stream)), "ht_decode")
+
+
+def ht_rte(h: int, Y, stream=None) -> List[float]:
+    n = int(Y.shape[0])
+    buf = (ctypes.c_double * n)()
+    _check(lib().ht_rte(h, _ptr(Y), n, buf, _stream(stream)), "ht_rte")
+    return [float(buf[i]) for i in range(n)]
 
 
 def ht_query_ranks(h: int) -> Tuple[List[int], int]:
@@ -259,6 +272,18 @@ class HTStream:
         out = torch.empty((count,) + self.n, dtype=td, device=self.device)
         ht_reconstruct(self.h, first, count, out, HT_F64 if dtype == "float64" else HT_F32, stream)
         return out
+
+    def decode(self, latent, dtype: str = "float64", stream=None):
+        """Tensors of latent codes [N][r11][r12] (float64 CUDA tensor), root-to-leaves."""
+        import torch
+        td = torch.float64 if dtype == "float64" else torch.float32
+        out = torch.empty((latent.shape[0],) + self.n, dtype=td, device=self.device)
+        ht_decode(self.h, latent.contiguous(), out, HT_F64 if dtype == "float64" else HT_F32, stream)
+        return out
+
+    def rte(self, Y, stream=None) -> List[float]:
+        """Per-sample relative errors of encode -> decode on held-out samples."""
+        return ht_rte(self.h, Y, stream)
 
     def export(self):
         """Cores (rank-vector order, rows x r) and root (N_acc, r11, r12) as float64 NumPy arrays."""

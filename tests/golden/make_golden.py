@@ -3,11 +3,17 @@
     python tests/golden/make_golden.py [field96|field48|all]
 
 field96_trace.json: per batch of the 96x96x96x3, N=32, 20-batch drifting-field
-stream at eps = 1e-4 - the oracle's skip flags, HT rank vectors, relative
+stream at eps = 1e-4 - an exact checksum of the batch's float32 values (the sum of
+their bit patterns, so a GPU run can prove it saw the same data), the oracle's skip
+flags, HT rank vectors, relative
 projection errors, the smallest relative distance of any rank decision from its
 threshold (on either side: the kept tail and the tail one rank lower) and whether
 any decision sat within 1e-6 eps_nw^2 of its threshold.  GPU tests compare the
 HIP library's full-size run with it.
+
+Both also hold the oracle's per-sample relative test errors (Sec. 4.1) of the two
+batches that follow the stream, encoded and decoded with the final cores
+("rte_heldout"; for field48 written from the trace's final checkpoint).
 
 field48_trace.json: the same for all 100 batches of the 48^4 x 4, N=16 stream
 (d = 5, a three-level tree), the large-stream workload, plus the oracle's
@@ -19,9 +25,7 @@ point of the stream).
 import json
 import math
 import os
-import queue
 import sys
-import threading
 
 import numpy as np
 
@@ -54,34 +58,55 @@ def sample_positions(shape, seed=7):
     return np.sort(g.choice(per * shape[0], size=SAMPLE_POSITIONS, replace=False))
 
 
-def prefetch(spec):
-    """Generates the batches in a background thread, one ahead of the oracle."""
-    q = queue.Queue(maxsize=1)
-
-    def work():
-        for k in range(spec.n_batches):
-            q.put(datagen.exact_field_batch(spec, k))
-        q.put(None)
-
-    threading.Thread(target=work, daemon=True).start()
-    while True:
-        y = q.get()
-        if y is None:
-            return
-        yield y
+def _gen(args):
+    spec, k = args
+    return datagen.exact_field_batch(spec, k)
 
 
-def trace(spec, eps, label, sampled=()):
-    st = None
+def prefetch(spec, first=0):
+    """Generates the batches from `first` on in a separate process, one ahead of the
+    oracle (a process, not a thread: the oracle's BLAS calls must not run concurrently
+    with the generator's in one process)."""
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(1) as pool:
+        for y in pool.imap(_gen, [(spec, k) for k in range(first, spec.n_batches)]):
+            yield y
+
+
+def save_state(path, st, rows, samples):
+    """Checkpoint of a long trace: the oracle's cores and root and the rows so far."""
+    arrays = {"root": st.root}
+    for idx, u in st.core.items():
+        arrays["core_%d" % idx] = u
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, meta=np.frombuffer(json.dumps({"rows": rows, "samples": samples}).encode(), dtype=np.uint8),
+             **arrays)
+    os.replace(tmp, path)
+
+
+def load_state(path, st):
+    with np.load(path) as z:
+        meta = json.loads(bytes(z["meta"]).decode())
+        st.root = z["root"]
+        st.core = {int(k[5:]): z[k] for k in z.files if k.startswith("core_")}
+    return meta["rows"], meta["samples"]
+
+
+def trace(spec, eps, label, sampled=(), checkpoint=None, state=None):
+    st = state if state is not None else ho.BHT(spec.n, eps)
     rows = []
     samples = {}
-    for k, y in enumerate(prefetch(spec)):
+    if checkpoint and os.path.exists(checkpoint):
+        rows, samples = load_state(checkpoint, st)
+        print("resuming after batch %d" % (len(rows) - 1), flush=True)
+    first = len(rows)
+    for k, y in enumerate(prefetch(spec, first), first):
         if k == 0:
-            st = ho.BHT(y.shape[1:], eps)
             info = st.init_batch(y)
         else:
             info = st.update(y)
-        rows.append({"batch": k, "skipped": bool(info.skipped), "ranks": info.ranks,
+        rows.append({"batch": k, "data_checksum": datagen.checksum(y), "skipped": bool(info.skipped),
+                     "ranks": info.ranks,
                      "eps_proj_rel": info.eps_proj / info.norm_y,
                      "near_tie_1e-6": bool(info.any_near_tie(1e-6)),
                      "min_decision_margin_rel": decision_margin(info)})
@@ -93,6 +118,8 @@ def trace(spec, eps, label, sampled=()):
                                "error_rel": err / info.norm_y}
             del rec
         print(rows[-1], flush=True)
+        if checkpoint and (k % 5 == 4 or k == spec.n_batches - 1):
+            save_state(checkpoint, st, rows, samples)
     out = {"stream": label, "eps": eps, "source": "oracle/ht_oracle.py via tests/golden/make_golden.py",
            "batches": rows}
     if sampled:
@@ -100,25 +127,65 @@ def trace(spec, eps, label, sampled=()):
     return out
 
 
+HELDOUT = 2  # held-out batches after the stream (the next batches of the same generator)
+
+
+def heldout_rte(st, spec):
+    """The oracle's per-sample relative test errors on the HELDOUT batches that follow
+    the stream (Sec. 4.1, Eq. generalization_performance)."""
+    import dataclasses
+    ext = dataclasses.replace(spec, n_batches=spec.n_batches + HELDOUT)
+    out = {"batches": [], "data_checksum": [], "rel_err": []}
+    for k in range(spec.n_batches, spec.n_batches + HELDOUT):
+        y = datagen.exact_field_batch(ext, k)
+        out["batches"].append(k)
+        out["data_checksum"].append(datagen.checksum(y))
+        out["rel_err"].append([float(e) for e in st.relative_test_errors(y)])
+    return out
+
+
 def field96_trace(eps=1e-4):
-    return trace(datagen.field_96_spec(), eps,
-                 "field_96 (96x96x96x3, N=32, 20 batches, drift 3e-4, widths [0.2,0.5], exact generator)")
+    spec = datagen.field_96_spec()
+    st = ho.BHT(spec.n, eps)
+    data = trace(spec, eps, "field_96 (96x96x96x3, N=32, 20 batches, drift 3e-4, widths [0.2,0.5], exact generator)",
+                 state=st)
+    data["rte_heldout"] = heldout_rte(st, spec)
+    return data
 
 
-def field48_trace(eps=1e-4):
+def field48_rte(checkpoint, eps=1e-4):
+    """Adds the held-out relative test errors to field48_trace.json from the final
+    checkpoint of the field48 trace."""
+    spec = datagen.field_48_spec()
+    st = ho.BHT(spec.n, eps)
+    rows, _ = load_state(checkpoint, st)
+    assert len(rows) == spec.n_batches, "the checkpoint is not the end of the stream"
+    path = os.path.join(HERE, "field48_trace.json")
+    data = json.load(open(path))
+    data["rte_heldout"] = heldout_rte(st, spec)
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1)
+
+
+def field48_trace(eps=1e-4, checkpoint=None):
     return trace(datagen.field_48_spec(), eps,
                  "field_48 (48x48x48x48x4, N=16, 100 batches, 16 terms switching on from 6 every 9 batches, "
                  "oscillating drift 1e-3 period 25, widths [0.2,0.5], noise 1e-6, exact generator)",
-                 sampled=SAMPLED_BATCHES)
+                 sampled=SAMPLED_BATCHES, checkpoint=checkpoint)
 
 
 if __name__ == "__main__":
+    # optional second argument: a checkpoint file for the long field48 trace (written
+    # every five batches; a rerun with the same file resumes from it)
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
+    ckpt = sys.argv[2] if len(sys.argv) > 2 else None
     if which in ("field96", "all"):
         data = field96_trace()
         with open(os.path.join(HERE, "field96_trace.json"), "w") as f:
             json.dump(data, f, indent=1)
     if which in ("field48", "all"):
-        data = field48_trace()
+        data = field48_trace(checkpoint=ckpt)
         with open(os.path.join(HERE, "field48_trace.json"), "w") as f:
             json.dump(data, f, indent=1)
+    if which in ("field48rte", "all") and ckpt:
+        field48_rte(ckpt)

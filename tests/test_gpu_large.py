@@ -35,8 +35,9 @@ def golden():
     return json.load(open(os.path.join(HERE, "golden", "field48_trace.json")))
 
 
-@pytest.mark.parametrize("prec,tol,slack,rec_tol", [(H.HT_FP64, 1e-9, 0.0, 1e-10), (H.HT_FP32, 1e-5, 1e-3, 5e-6)])
-def test_field48_full_size(golden, prec, tol, slack, rec_tol):
+@pytest.mark.parametrize("prec,tol,slack,rec_tol,rte_tol", [(H.HT_FP64, 1e-9, 0.0, 1e-10, 1e-9),
+                                                             (H.HT_FP32, 1e-5, 1e-3, 5e-6, 1e-6)])
+def test_field48_full_size(golden, prec, tol, slack, rec_tol, rte_tol):
     from datagen import gpu as G
     spec = datagen.field_48_spec()
     nb = len(golden["batches"])
@@ -49,8 +50,9 @@ def test_field48_full_size(golden, prec, tol, slack, rec_tol):
     try:
         for k in range(nb):
             G.field_batch_into(spec, k, y)
-            info = st.push(y)
             row = golden["batches"][k]
+            assert G.checksum(y) == row["data_checksum"], k   # the oracle's trace is of these values
+            info = st.push(y)
             ranks = st.ranks()[0]
             print("batch %d ranks %s skipped %s eps_proj/|Y| %.3e (oracle %.3e) prec_used %d recomputed %d"
                   % (k, ranks, info.skipped, info.eps_proj / info.norm_y, row["eps_proj_rel"], info.prec_used,
@@ -75,5 +77,18 @@ def test_field48_full_size(golden, prec, tol, slack, rec_tol):
             print("batch %d sampled max |gpu - oracle| / |Y| = %.2e" % (k, diff / norms[k]), flush=True)
             assert diff <= rec_tol * norms[k], (k, diff / norms[k])
             del rec
+        # held-out batches after the stream: per-sample relative test errors (Sec. 4.1)
+        if "rte_heldout" in golden:
+            import dataclasses
+            ref = golden["rte_heldout"]
+            ext = dataclasses.replace(spec, n_batches=spec.n_batches + len(ref["batches"]))
+            for k, cs, errs in zip(ref["batches"], ref["data_checksum"], ref["rel_err"]):
+                G.field_batch_into(ext, k, y)
+                assert G.checksum(y) == cs
+                rte = st.rte(y)
+                diff = max(abs(a - b) for a, b in zip(rte, errs))
+                print("held-out batch %d: RTE %.4e (oracle %.4e), max diff %.2e"
+                      % (k, sum(rte) / len(rte), sum(errs) / len(errs), diff), flush=True)
+                assert diff <= rte_tol, (k, diff)
     finally:
         st.close()

@@ -261,11 +261,13 @@ def field96():
 def test_field96_full_size_ranks_and_error_bound(field96):
     """The 96^3 x 3, N = 32, 20-batch stream at eps = 1e-4: ranks and skips equal the
     oracle's stored trace, and every batch meets ||Y - Y_hat|| <= eps ||Y||."""
+    from datagen import gpu as G
     ys, _, golden = field96
     st = H.HTStream(ys[0].shape[1:], 1e-4, 48, 32, 640)
     for k, yd in enumerate(ys):
-        info = st.push(yd)
         row = golden["batches"][k]
+        assert G.checksum(yd) == row["data_checksum"], k
+        info = st.push(yd)
         assert st.ranks()[0] == row["ranks"], k
         if k > 0:
             assert info.skipped == row["skipped"], k
@@ -286,3 +288,57 @@ def test_field96_first_batches_elementwise(field96):
         rec_g = gst.reconstruct(32 * k, 32).cpu().numpy()
         rec_o = ost.reconstruct(32 * k, 32)
         assert np.linalg.norm(rec_g - rec_o) <= RECON_TOL * np.linalg.norm(sub[k].astype(np.float64))
+
+
+# --------------------------------------------------------------------------- #
+# encoder / decoder on held-out samples (Problem 1; Sec. 4.1 relative test error)
+# --------------------------------------------------------------------------- #
+
+
+def test_heldout_rte_and_decode_tiny_stream():
+    """After the five batches, a sixth of the same model (not accumulated): the
+    per-sample relative test errors equal the oracle's, decode(project(Y)) equals the
+    oracle's decode element-wise, and decoding the root's own slices reproduces
+    ht_reconstruct."""
+    ys = datagen.tiny_stream(6)
+    gst, _, _ = run_gpu(ys[:5], 1e-4)
+    ost, _ = run_oracle(ys[:5], 1e-4)
+    test = ys[5]
+    rte_g = np.array(gst.rte(dev(test)))
+    rte_o = ost.relative_test_errors(test)
+    assert np.max(np.abs(rte_g - rte_o)) <= 1e-9, (rte_g, rte_o)
+    lat = gst.project(dev(test))
+    rec_g = gst.decode(lat).cpu().numpy()
+    rec_o = ost.decode(ost.project(test))
+    ny = np.linalg.norm(test.astype(np.float64))
+    assert np.linalg.norm(rec_g - rec_o) <= RECON_TOL * ny
+    # explicit errors of the decoded tensors match ht_rte's identity-based ones; the
+    # identity subtracts two FP64 energies, so its error in e is ~1e-15 / e (e ~ 1e-6
+    # here: noise-level test errors)
+    d = (rec_g - test.astype(np.float64)).reshape(test.shape[0], -1)
+    explicit = np.linalg.norm(d, axis=1) / np.linalg.norm(test.reshape(test.shape[0], -1).astype(np.float64), axis=1)
+    np.testing.assert_allclose(rte_g, explicit, rtol=0, atol=1e-9)
+    # the decoder on the root's stored slices is the reconstruction
+    _, root = split_export(gst, ost)
+    root_t = torch.from_numpy(np.ascontiguousarray(root[8:16])).to("cuda:0")
+    assert torch.equal(gst.decode(root_t), gst.reconstruct(8, 8))
+
+
+def test_field96_heldout_rte(field96):
+    """The two batches after the 96^3 x 3 stream, encoded and decoded with the final
+    cores: per-sample relative test errors equal the oracle's stored ones."""
+    import dataclasses
+    from datagen import gpu as G
+    ys, _, golden = field96
+    spec = datagen.field_96_spec()
+    st = H.HTStream(spec.n, 1e-4, 48, 32, 640)
+    for yd in ys:
+        st.push(yd)
+    ref = golden["rte_heldout"]
+    ext = dataclasses.replace(spec, n_batches=spec.n_batches + len(ref["batches"]))
+    for k, cs, errs in zip(ref["batches"], ref["data_checksum"], ref["rel_err"]):
+        y = G.field_batch(ext, k)
+        assert G.checksum(y) == cs
+        rte = np.array(st.rte(y))
+        print("held-out batch %d: RTE %.4e (oracle %.4e)" % (k, rte.mean(), np.mean(errs)))
+        assert np.max(np.abs(rte - np.array(errs))) <= 1e-9

@@ -420,3 +420,24 @@ def test_first_layer_decisions_use_the_raw_batch():
         m = np.moveaxis(y, 1 + dim, 0).reshape(16, -1)
         lam = np.sort(np.linalg.eigvalsh(m @ m.T))[::-1]
         np.testing.assert_allclose(info.decisions[idx].sigma[:4] ** 2, lam[:4], rtol=1e-10)
+
+
+def test_relative_test_errors_closed_form():
+    """Relative test error (Sec. 4.1, Eq. generalization_performance): a held-out sample
+    y_n = sum_i s_i w_ni a_i b_i^T whose third direction lies outside the trained span
+    {a_0, a_1} x {b_0, b_1} has error |s_2 w_n2| / sqrt(sum_i s_i^2 w_ni^2); a sample
+    inside the span has none."""
+    ys, _, _ = _diag_stream([((1.0, 0.3), _diag_pairs(2)), ((1.0, 0.3, 0.2), _diag_pairs(3)),
+                             ((0.7, 0.4), _diag_pairs(2))])
+    st = ho.BHT(ys[0].shape[1:], 1e-6)
+    st.init_batch(ys[0])
+    assert st.ranks == [2, 2]
+    # the weights w of batch 1 are recovered from the data: w_ni = <y_n, a_i b_i^T> / s_i
+    g = np.random.default_rng(31)
+    a = np.linalg.qr(g.standard_normal((9, 3)))[0]
+    b = np.linalg.qr(g.standard_normal((8, 3)))[0]
+    s = np.array([1.0, 0.3, 0.2])
+    w = np.array([[np.sum(yn * np.outer(a[:, i], b[:, i])) / s[i] for i in range(3)] for yn in ys[1]])
+    expect = np.abs(s[2] * w[:, 2]) / np.sqrt(np.sum((s[None, :] * w) ** 2, axis=1))
+    np.testing.assert_allclose(st.relative_test_errors(ys[1]), expect, rtol=1e-10)
+    assert np.max(st.relative_test_errors(ys[2])) < 1e-13
