@@ -99,8 +99,20 @@ typedef struct {
   int64_t n_cap;          /* capacity: largest accumulated sample count N_acc, >= 1      */
   int32_t prec;           /* ht_precision                                                */
   int32_t in_dtype;       /* ht_dtype of Y                                               */
-  uint64_t flags;         /* reserved, must be 0                                         */
+  uint64_t flags;         /* bitwise or of ht_flags (0: none)                            */
 } ht_config;
+
+/* Option bits of ht_config.flags.
+ *   HT_ADAPTIVE_BUDGET  App. C's alternative error bound: after each layer (of BHT-l2r
+ *                       and of every HT-RISE update) the nodewise tolerance of the
+ *                       layers above becomes eps_nw = sqrt(eps_abs^2 - eps_l^2) /
+ *                       sqrt(svd_rem), with eps_l^2 = ||Y||^2 - ||C_l||^2 the energy
+ *                       the approximation has lost so far (HT_FP32: the energies the
+ *                       contractions of the second projection discarded, summed, and
+ *                       their error bound taken into the decision certificates),
+ *                       eps_abs = eps_rel ||Y|| and svd_rem the non-root nodes of the
+ *                       layers still to come.  One extra read-back per layer. */
+typedef enum { HT_ADAPTIVE_BUDGET = 1 } ht_flags;
 
 typedef struct {
   int32_t skipped;        /* 1 when the batch was represented well enough (Alg. 2 skip) */

@@ -30,6 +30,9 @@ the design notes of the repository):
   and at most alpha - r_old;
 * budget: eps_nw = eps * ||Y|| / sqrt(2d-2) (Alg. 1, Alg. 2 and the BHT-l2r
   corollary in App. A; the sqrt(2d-3) of the plain-HT theorem does not apply);
+  with ``adaptive`` (App. C) it is recomputed after every layer from the error
+  incurred so far and the number of SVDs left (every non-root node of the layers
+  still to come);
 * eps_des uses the norm of the *new* batch;
 * skip test with <=, radicand clamped at 0;
 * C-order reshapes; a merged sibling index is i_a * r_b + i_b, so a transfer
@@ -264,13 +267,16 @@ class BHT:
     (r_{1,1}, r_{1,2}, N_acc).
     """
 
-    def __init__(self, n: Sequence[int], eps: float, tree: Optional[DimTree] = None):
+    def __init__(self, n: Sequence[int], eps: float, tree: Optional[DimTree] = None, adaptive: bool = False):
         self.n = tuple(int(x) for x in n)
         self.d = len(self.n)
         self.tree = tree if tree is not None else DimTree(self.d)
         if not (0.0 < eps < 1.0):
             raise ValueError("eps must lie in (0, 1)")
         self.eps = float(eps)
+        # App. C: after each layer the nodewise tolerance is recomputed from the error
+        # actually incurred so far, eps_nw = sqrt(eps_abs^2 - eps_l^2) / sqrt(svd_rem)
+        self.adaptive = bool(adaptive)
         self.core: Dict[int, np.ndarray] = {}
         self.root: Optional[np.ndarray] = None
         self.history: List[BatchInfo] = []
@@ -351,6 +357,15 @@ class BHT:
         lat = np.moveaxis(self.root[:, :, first:first + count], 2, 0)
         return self.decode(lat)
 
+    def _adapted_eps_nw(self, eps_abs: float, ny2: float, c: np.ndarray, ell: int) -> float:
+        """App. C: the nodewise tolerance for the layers above ell, from the error of
+        the approximation so far, eps_l^2 = ||Y||^2 - ||C_l||^2, the remaining budget
+        eps_rem^2 = eps_abs^2 - eps_l^2 and the number of SVDs still to come."""
+        eps_l2 = ny2 - fro2(c)
+        rem2 = max(0.0, eps_abs * eps_abs - eps_l2)
+        svd_rem = sum(1 for nd in self.tree.non_root if nd.layer < ell)
+        return math.sqrt(rem2 / svd_rem)
+
     # ---- BHT-l2r (Algorithm 1) -----------------------------------------------
     def init_batch(self, y: np.ndarray) -> BatchInfo:
         y = np.asarray(y, dtype=np.float64)
@@ -375,6 +390,8 @@ class BHT:
                 self.core[nd.idx] = bases[nd.idx]
                 c = contract_mode_t(c, 1 + k, bases[nd.idx])
             c = self._merge_to(c, ell)
+            if self.adaptive and ell > 1:
+                eps_nw = self._adapted_eps_nw(self.eps * ny, ny * ny, c, ell)
         self.root = np.ascontiguousarray(np.moveaxis(c, 0, 2))
         c2 = fro2(c)
         info = BatchInfo(False, ny, self.eps * ny, math.sqrt(max(0.0, ny * ny - c2)), self.ranks, decisions)
@@ -424,6 +441,8 @@ class BHT:
             for k, nd in here:
                 c = contract_mode_t(c, 1 + k, self.core[nd.idx])
             c = self._merge_to(c, ell)
+            if self.adaptive and ell > 1:
+                eps_nw = self._adapted_eps_nw(eps_des, ny2, c, ell)
         self._append_root(c)
         info = BatchInfo(False, ny, eps_des, eps_proj, self.ranks, decisions)
         self.history.append(info)

@@ -186,6 +186,7 @@ struct ht_state {
   Elem in_t = Elem::F32;
   bool mixed = false;     // HT_FP32 requested
   bool mixed_ok = false;  // and the FP32 error floor lies well inside eps_nw (precision gate)
+  bool adaptive = false;  // HT_ADAPTIVE_BUDGET: nodewise tolerance recomputed after every layer
   Tree tree;
   // per-node capacities: rows of the basis matrix (alpha) and rank bound
   std::vector<int64_t> alpha_cap;
@@ -320,7 +321,7 @@ bool valid_config(const ht_config* c, std::string& why) {
   if (c->n_cap < 1) return why = "n_cap must be >= 1", false;
   if (c->prec != HT_FP64 && c->prec != HT_FP32) return why = "prec must be HT_FP64 or HT_FP32", false;
   if (c->in_dtype != HT_F32 && c->in_dtype != HT_F64) return why = "in_dtype must be HT_F32 or HT_F64", false;
-  if (c->flags != 0) return why = "flags must be 0", false;
+  if ((c->flags & ~(uint64_t)HT_ADAPTIVE_BUDGET) != 0) return why = "unknown bits in flags", false;
   return true;
 }
 
@@ -826,6 +827,7 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   h->tree.build(cfg->d);
   Layout L = make_layout(cfg, h->tree, h->alpha_cap, h->rc);
   h->mixed_ok = h->mixed && fp32_gate(h->eps, h->d, h->rc);
+  h->adaptive = (cfg->flags & HT_ADAPTIVE_BUDGET) != 0;
   if (ws_bytes < L.total) {
     delete h;
     return fail(HT_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes, " + std::to_string(L.total) +
@@ -927,6 +929,7 @@ struct Upd {
   std::vector<char> expl;
   std::vector<int> saved;
   double ny = 0, eps_des = 0, eps_proj = 0, thr = 0;
+  double lost2 = 0, lost_err = 0, thr_err = 0;  // adaptive budget: error so far and its FP32 bound
   bool skip = false, busy = false;
   bool mixed = false;  // this pass runs the FP32 kernels
   bool redo = false;   // an FP32 decision could not be certified: the call runs again in FP64
@@ -946,6 +949,22 @@ double fp32_chain(const ht_state* h, int ell) {
   for (size_t i = 1; i < h->tree.nodes.size(); ++i)
     if (h->tree.nodes[i].layer > ell && alpha_now(h, (int)i) <= ht::kResidGramMaxM) c += h->rank[i] + 1.0;
   return c;
+}
+
+// App. C: number of truncated SVDs still to come after layer ell (every non-root node
+// of the layers above it).
+int svd_remaining(const ht_state* h, int ell) {
+  int c = 0;
+  for (size_t i = 1; i < h->tree.nodes.size(); ++i)
+    if (h->tree.nodes[i].layer < ell) ++c;
+  return c;
+}
+
+// App. C: the nodewise threshold eps_nw^2 = (eps_abs^2 - eps_l^2) / svd_rem for the
+// layers above ell, where eps_l^2 = lost2 is the energy the approximation has lost so
+// far (clamped at 0).
+double adapted_thr(double eps_abs, double lost2, const ht_state* h, int ell) {
+  return std::max(0.0, eps_abs * eps_abs - lost2) / svd_remaining(h, ell);
 }
 
 // Mixed-form skip test certificate: the telescoped residual energies carry, per
@@ -985,7 +1004,7 @@ void certify_layer(Upd& u, int ell, bool fp64_pass, std::vector<int>* redo_jobs)
     const double own = f32 ? u.L.rold[q] + 1.0 : 0.0;
     const double dR = resid_err(u.ny, own, chain);
     const double tr = h->h_aux[2 * node];
-    const double gerr = kGramK * (f32 ? kU32 : kU64) * tr;
+    const double gerr = kGramK * (f32 ? kU32 : kU64) * tr + u.thr_err;
     const bool ok = decision_certified(u.rk[node], u.L.jobs[q].rmin, u.L.jobs[q].rmax, u.tl[node],
                                        h->h_aux[2 * node + 1], u.thr, dR, gerr);
     if (ok) continue;
@@ -1081,6 +1100,7 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
       backup_cores(h, s);
       const double eps_nw = u.eps_des / std::sqrt(2.0 * h->d - 2.0);
       u.thr = eps_nw * eps_nw;
+      u.lost2 = u.lost_err = u.thr_err = 0.0;
       u.cur = Level{u.Y, h->in_t, u.N, h->n};
     }
   }
@@ -1166,11 +1186,59 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
       }
     }
     if (!orth.empty()) ht::orth_expand_batch(orth.data(), (int)orth.size(), s);
+    bool adapt = false;
     for (Upd* up : act) {
       Upd& u = *up;
       const int ell = layer_of(u);
       if (ell < 1) continue;
-      u.cur = project_layer(u.h, ell, u.cur, s, nullptr, u.mixed);
+      ht_state* h = u.h;
+      const bool ad = h->adaptive && ell > 1;
+      if (ad && u.mixed) {
+        // App. C in the mixed form: the energy each pass-2 contraction discards, summed
+        // (a difference of FP32-accurate norms would not resolve eps_des^2)
+        u.expl.assign(h->tree.nodes.size(), 0);
+        u.cur = project_layer(h, ell, u.cur, s, nullptr, true, h->scal + 8, &u.expl);
+      } else {
+        u.cur = project_layer(h, ell, u.cur, s, nullptr, u.mixed);
+        if (ad) ht::sumsq(u.cur.ptr, u.cur.t, (int64_t)u.cur.elems(), h->sspart, h->scal + 1, s);
+      }
+      if (ad) {
+        HT_HIP(hipMemcpyAsync(h->h_scal, h->scal, kScalars((int)h->tree.nodes.size()) * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+        adapt = true;
+      }
+    }
+    if (adapt) {
+      HT_HIP(wait_stream(s));
+      for (Upd* up : act) {
+        Upd& u = *up;
+        const int ell = layer_of(u);
+        if (ell <= 1 || !u.h->adaptive) continue;
+        const ht_state* h = u.h;
+        if (u.mixed) {
+          // this layer's discarded energies and their error bound (as in the skip test)
+          double chain = fp32_chain(h, ell);
+          const std::vector<int> f = h->tree.frontier(ell);
+          for (const int k : contraction_order(h, ell, frontier_sizes(h, ell))) {
+            const int node = f[k];
+            const double* e = h->h_scal + 8 + 2 * node;
+            const bool ex = u.expl[node] != 0;
+            const double ej = ex ? e[0] : e[0] - e[1];
+            const double own = ex ? h->rank[node] + 1.0 : 0.0;
+            const double dj = resid_err(u.ny, own, chain);
+            u.lost2 += ej;
+            u.lost_err += 2.0 * std::sqrt(std::max(ej, 0.0)) * dj + dj * dj + kGramK * kU32 * std::fabs(ej) +
+                          (ex ? 0.0 : 4.0 * kU64 * e[0]);
+            chain += own;
+          }
+        } else {
+          u.lost2 = u.ny * u.ny - h->h_scal[1];
+          u.lost_err = 4.0 * kU64 * u.ny * u.ny;
+        }
+        const int rem = svd_remaining(h, ell);
+        u.thr = adapted_thr(u.eps_des, u.lost2, h, ell);
+        u.thr_err = u.lost_err / rem;
+      }
     }
   }
   for (Upd* up : act) {
@@ -1336,15 +1404,26 @@ ht_status ht_init_batch(const ht_config* cfg, void* ws, size_t ws_bytes, const v
   }
   const double ny = std::sqrt(ny2);
   const double eps_nw = h->eps * ny / std::sqrt(2.0 * h->d - 2.0);
+  double thr = eps_nw * eps_nw;
   Level cur{Y, h->in_t, N, h->n};
   int growth = 0;
   for (int ell = h->tree.depth; ell >= 1; --ell) {
-    st = decide_layer(h, ell, cur, eps_nw * eps_nw, true, s, &growth);
+    st = decide_layer(h, ell, cur, thr, true, s, &growth);
     if (st != HT_OK) {
       delete h;
       return st;
     }
     cur = project_layer(h, ell, cur, s);
+    if (h->adaptive && ell > 1) {
+      // App. C: the energy lost so far sets the tolerance of the layers above
+      ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), h->sspart, h->scal + 1, s);
+      st = sync_read(h, s, h->scal + 1, 1, h->h_scal + 1);
+      if (st != HT_OK) {
+        delete h;
+        return st;
+      }
+      thr = adapted_thr(h->eps * ny, ny2 - h->h_scal[1], h, ell);
+    }
   }
   const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
   ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), h->sspart, h->scal + 1, s);

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libhtrise.so")
 HT_OK, HT_EINVAL, HT_ESHAPE, HT_ENOMEM, HT_ERANKCAP, HT_EDEVICE, HT_ENUMERIC = range(7)
 HT_FP64, HT_FP32, HT_BF16X3 = 0, 1, 2
 HT_F32, HT_F64 = 0, 1
+HT_ADAPTIVE_BUDGET = 1
 
 STATUS_NAMES = {0: "HT_OK", 1: "HT_EINVAL", 2: "HT_ESHAPE", 3: "HT_ENOMEM", 4: "HT_ERANKCAP",
                 5: "HT_EDEVICE", 6: "HT_ENUMERIC"}
@@ -224,13 +225,13 @@ class HTStream:
     """One tensor stream in batch-HT form: the workspace tensor plus the library handle."""
 
     def __init__(self, n: Sequence[int], eps: float, rank_cap: int, max_batch: int, n_cap: int,
-                 in_dtype: str = "float32", prec: int = HT_FP64, device: str = "cuda:0"):
+                 in_dtype: str = "float32", prec: int = HT_FP64, device: str = "cuda:0", flags: int = 0):
         import torch
         self.n = tuple(int(x) for x in n)
         self.d = len(self.n)
         self.device = torch.device(device)
         self._cfg, self._keep = make_config(self.n, eps, rank_cap, max_batch, n_cap, prec,
-                                            HT_F32 if in_dtype == "float32" else HT_F64)
+                                            HT_F32 if in_dtype == "float32" else HT_F64, flags)
         self.ws_bytes = ht_workspace_bytes(self._cfg)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.h = 0

@@ -73,7 +73,7 @@ def test_mixed_form_is_a_valid_config():
 
 @pytest.mark.parametrize("kw", [dict(n=(16,)), dict(eps=0.0), dict(eps=1.0), dict(n=(16, 0, 3)),
                                 dict(rank_cap=0), dict(rank_cap=65), dict(max_batch=0), dict(n_cap=0),
-                                dict(prec=7), dict(prec=2), dict(in_dtype=5), dict(flags=1)])
+                                dict(prec=7), dict(prec=2), dict(in_dtype=5), dict(flags=2)])
 def test_invalid_configs_rejected(kw):
     with pytest.raises(H.HTError) as e:
         _ws(**kw)
@@ -169,3 +169,7 @@ def test_decision_certificate():
     # a decision cut short by the capacity (r == room, tail above thr) must stay above
     assert cert(2, 0, 2, 2.0, 0.5, thr, 0.01, 0.0)
     assert not cert(2, 0, 2, 1.01, 0.5, thr, 0.01, 0.0)
+
+
+def test_adaptive_budget_flag_is_accepted():
+    assert _ws(flags=H.HT_ADAPTIVE_BUDGET) == _ws()

@@ -441,3 +441,95 @@ def test_relative_test_errors_closed_form():
     expect = np.abs(s[2] * w[:, 2]) / np.sqrt(np.sum((s[None, :] * w) ** 2, axis=1))
     np.testing.assert_allclose(st.relative_test_errors(ys[1]), expect, rtol=1e-10)
     assert np.max(st.relative_test_errors(ys[2])) < 1e-13
+
+
+# --------------------------------------------------------------------------- #
+# Adaptive error budget (App. C)
+# --------------------------------------------------------------------------- #
+
+
+def _triple_batches(terms_list, n=(9, 8, 7), N=6, seed=5):
+    """d = 3 batches y = sum_t s_t w_t (x) a_{i_t} (x) b_{j_t} (x) c_{k_t} with orthonormal
+    a, b, c sets and orthonormal sample weights w (one per term).  Tree {1,2},{3}:
+    the leaves see the a-, b- and c-directions, the (1,2) transfer node the pairs
+    a_i (x) b_j."""
+    g = np.random.default_rng(seed)
+    a = np.linalg.qr(g.standard_normal((n[0], 4)))[0]
+    b = np.linalg.qr(g.standard_normal((n[1], 4)))[0]
+    c = np.linalg.qr(g.standard_normal((n[2], 4)))[0]
+    out = []
+    for terms in terms_list:
+        w = np.linalg.qr(g.standard_normal((N, len(terms))))[0]
+        y = np.zeros((N,) + n)
+        for t, (st, i, j, k) in enumerate(terms):
+            y += st * np.einsum("n,x,y,z->nxyz", w[:, t], a[:, i], b[:, j], c[:, k])
+        out.append(y)
+    return out
+
+
+def _x_for(frac, eps, base2):
+    """x with x^2 = frac * eps^2 * (base2 + x^2)."""
+    c = frac * eps * eps
+    return math.sqrt(c * base2 / (1.0 - c))
+
+
+def test_adaptive_budget_bht_l2r_closed_form():
+    """The pair a_0 (x) b_1 carries x^2 = 0.35 eps^2 ||Y||^2 at the (1,2) node only: the
+    leaves lose nothing, so App. C's tolerance for layer 1 is eps_abs^2 / 2 (two SVDs
+    left) instead of eps_abs^2 / 4: the fixed budget keeps the pair (rank 3), the
+    adaptive one drops it (rank 2), and the error is exactly x."""
+    eps = 1e-3
+    x = _x_for(0.35, eps, 1.25)
+    (y,) = _triple_batches([[(1.0, 0, 0, 0), (0.5, 1, 1, 1), (x, 0, 1, 0)]])
+    fixed = ho.BHT(y.shape[1:], eps)
+    fixed.init_batch(y)
+    adapt = ho.BHT(y.shape[1:], eps, adaptive=True)
+    adapt.init_batch(y)
+    assert fixed.ranks == [3, 2, 2, 2]
+    assert adapt.ranks == [2, 2, 2, 2]
+    err = math.sqrt(ho.fro2(adapt.reconstruct() - y))
+    assert err == pytest.approx(x, rel=1e-8)
+    assert err <= eps * math.sqrt(ho.fro2(y))
+    # d = 2 has a single layer: nothing to adapt
+    ys, _, _ = _diag_stream([((1.0, 0.3, 0.05, 4e-5, 1e-6), _diag_pairs(5))])
+    for e in (1e-4, 5e-5):
+        f2, a2 = ho.BHT(ys[0].shape[1:], e), ho.BHT(ys[0].shape[1:], e, adaptive=True)
+        f2.init_batch(ys[0])
+        a2.init_batch(ys[0])
+        assert f2.ranks == a2.ranks
+
+
+def test_adaptive_budget_ht_rise_closed_form():
+    """HT-RISE: a new leaf direction a_2 (x) b_0 of energy 10 eps^2 ||Y||^2 forces an
+    update that the leaves absorb exactly; the pair a_0 (x) b_1 of energy
+    0.35 eps_des^2 is kept at the (1,2) node by the fixed budget (eps_des^2 / 4) and
+    dropped by the adaptive one (eps_des^2 / 2)."""
+    eps = 1e-3
+    base = [(1.0, 0, 0, 0), (0.5, 1, 1, 1)]
+    y10 = _x_for(10.0 / 1.35, eps, 1.25)  # rough size; the exact fractions follow from the norms
+    x = _x_for(0.35, eps, 1.25 + y10 ** 2)
+    y0, y1 = _triple_batches([base, base + [(y10, 2, 0, 0), (x, 0, 1, 0)]])
+    ny2 = ho.fro2(y1)
+    assert x * x == pytest.approx(0.35 * eps * eps * ny2, rel=1e-9)
+    fixed = ho.BHT(y0.shape[1:], eps)
+    adapt = ho.BHT(y0.shape[1:], eps, adaptive=True)
+    for st in (fixed, adapt):
+        st.init_batch(y0)
+        assert st.ranks == [2, 2, 2, 2]
+        info = st.update(y1)
+        assert not info.skipped
+    assert fixed.ranks == [4, 2, 3, 2]
+    assert adapt.ranks == [3, 2, 3, 2]
+    err = math.sqrt(ho.fro2(adapt.reconstruct(6, 6) - y1))
+    assert err == pytest.approx(x, rel=1e-6)
+    assert err <= eps * math.sqrt(ny2)
+
+
+def test_adaptive_budget_meets_the_bound_on_the_tiny_stream():
+    ys = datagen.tiny_stream()
+    st = ho.BHT(ys[0].shape[1:], 1e-4, adaptive=True)
+    for k, y in enumerate(ys):
+        (st.init_batch if k == 0 else st.update)(y)
+    for k, y in enumerate(ys):
+        yy = y.astype(np.float64)
+        assert math.sqrt(ho.fro2(st.reconstruct(8 * k, 8) - yy)) <= 1e-4 * math.sqrt(ho.fro2(yy))
