@@ -111,8 +111,17 @@ typedef struct {
  *                       contractions of the second projection discarded, summed, and
  *                       their error bound taken into the decision certificates),
  *                       eps_abs = eps_rel ||Y|| and svd_rem the non-root nodes of the
- *                       layers still to come.  One extra read-back per layer. */
-typedef enum { HT_ADAPTIVE_BUDGET = 1 } ht_flags;
+ *                       layers still to come.  One extra read-back per layer.
+ *   HT_PLAIN_HT_BUDGET  the nodewise tolerance eps_rel ||Y|| / sqrt(2d-3) of the
+ *                       leaves-to-root hierarchical Tucker algorithm (Sec. 2.3.1,
+ *                       Thm. ht_nodewise_error) instead of sqrt(2d-2).  With N = 1 and
+ *                       a batch mode among the modes (cfg->n = (N_samples, n_1..n_d)),
+ *                       ht_init_batch then computes the plain HT decomposition with the
+ *                       batch as a node of the tree: the two successors of the root
+ *                       decide on the same matrix C_1 (one truncated SVD, Eq.
+ *                       ht_last_svd), their cores are its left and right singular
+ *                       vectors and the root is diag(Sigma_1) up to signs. */
+typedef enum { HT_ADAPTIVE_BUDGET = 1, HT_PLAIN_HT_BUDGET = 2 } ht_flags;
 
 typedef struct {
   int32_t skipped;        /* 1 when the batch was represented well enough (Alg. 2 skip) */

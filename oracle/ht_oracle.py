@@ -484,6 +484,90 @@ class BHT:
         return self.core[idx].reshape(self.rank(a), self.rank(b), self.rank(idx))
 
 
+class PlainHT:
+    """Leaves-to-root error truncated hierarchical Tucker decomposition of ONE d-way
+    tensor (Sec. 2.3.1, the algorithm the paper takes from Grasedyck's leaves-to-root
+    method), the baseline the batch format is compared with (App. D.1).
+
+    Layers p..2: an error truncated SVD of every node's unfolding of the same level
+    tensor (Eq. ht_leaf_svd, HOSVD within a layer), contraction with the kept left
+    singular vectors (Eq. ht_leaf_contraction) and the reshape to the next frontier
+    (Eq. ht_index_set_construction); transfer cores are the reshaped vectors (Eq.
+    ht_tucker_core_reshape).  Layer 1: one truncated SVD of the matrix C_1 (Eq.
+    ht_last_svd): U_1 and V_1 become the cores of the root's two successors and the
+    kept singular values the (diagonal) root.  Every truncation uses
+    eps_nw = eps ||Y|| / sqrt(2d - 3) (Thm. ht_nodewise_error).
+    """
+
+    def __init__(self, y: np.ndarray, eps: float, tree: Optional[DimTree] = None):
+        y = np.asarray(y, dtype=np.float64)
+        self.n = tuple(y.shape)
+        self.d = y.ndim
+        if self.d < 2:
+            raise ValueError("a dimension tree needs d >= 2")
+        self.tree = tree if tree is not None else DimTree(self.d)
+        self.eps = float(eps)
+        ny = math.sqrt(fro2(y))
+        eps_nw = self.eps * ny / math.sqrt(2 * self.d - 3)
+        self.core: Dict[int, np.ndarray] = {}
+        self.decisions: Dict[int, Truncation] = {}
+        c = y
+        for ell in range(self.tree.depth, 1, -1):
+            front = self.tree.frontier(ell)
+            here = [(k, nd) for k, nd in enumerate(front) if nd.layer == ell]
+            bases = {}
+            for k, nd in here:          # every node of the layer sees the same tensor
+                u, t = truncated_svd(unfold(c, k), eps_nw, rmin=1)
+                bases[nd.idx] = u
+                self.decisions[nd.idx] = t
+            for k, nd in here:
+                self.core[nd.idx] = bases[nd.idx]
+                c = contract_mode_t(c, k, bases[nd.idx])
+            c = c.reshape(tuple(self._size(nd) for nd in self.tree.frontier(ell - 1)))
+        # layer 1: the final SVD of C_1 (alpha_11 x alpha_12)
+        root = self.tree.nodes[0]
+        a, b = root.children
+        c1 = c.reshape(self._size(self.tree.nodes[a]), self._size(self.tree.nodes[b]))
+        u, sv, vt = np.linalg.svd(c1, full_matrices=False)
+        tail = np.concatenate([np.cumsum((sv ** 2)[::-1])[::-1], [0.0]])
+        r0 = next(r for r in range(1, len(sv) + 1) if tail[r] <= eps_nw * eps_nw)
+        self.core[a] = u[:, :r0]
+        self.core[b] = vt[:r0].T
+        self.root = np.diag(sv[:r0])
+        self.decisions[a] = Truncation(rank=r0, sigma=sv, tail2=float(tail[r0]), eps_nw=eps_nw,
+                                       tail2_prev=float(tail[r0 - 1]) if r0 > 1 else math.inf, rmin=1,
+                                       rmax=len(sv))
+
+    def _size(self, nd: Node) -> int:
+        """Size of nd's mode in the level tensor entering its layer."""
+        if nd.is_leaf:
+            return self.n[nd.dim]
+        ca, cb = nd.children
+        return self.core[ca].shape[1] * self.core[cb].shape[1]
+
+    @property
+    def ranks(self) -> List[int]:
+        return [int(self.core[nd.idx].shape[1]) for nd in self.tree.non_root]
+
+    def _frame(self, idx: int) -> np.ndarray:
+        """The node's basis over its modes: (prod of its mode sizes) x r, C order."""
+        nd = self.tree.nodes[idx]
+        if nd.is_leaf:
+            return self.core[idx]
+        ca, cb = nd.children
+        fa, fb = self._frame(ca), self._frame(cb)
+        g = self.core[idx].reshape(fa.shape[1], fb.shape[1], -1)
+        return np.einsum("ia,jb,abr->ijr", fa, fb, g).reshape(fa.shape[0] * fb.shape[0], -1)
+
+    def reconstruct(self) -> np.ndarray:
+        a, b = self.tree.nodes[0].children
+        return (self._frame(a) @ self.root @ self._frame(b).T).reshape(self.n)
+
+    def num_elements(self) -> int:
+        """Entries of all cores and the root (the denominator of the compression ratio)."""
+        return int(sum(u.size for u in self.core.values()) + self.root.size)
+
+
 def compress_stream(batches, eps: float, tree: Optional[DimTree] = None) -> BHT:
     """BHT-l2r on the first batch, HT-RISE on every later one."""
     it = iter(batches)

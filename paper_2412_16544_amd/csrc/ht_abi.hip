@@ -187,6 +187,7 @@ struct ht_state {
   bool mixed = false;     // HT_FP32 requested
   bool mixed_ok = false;  // and the FP32 error floor lies well inside eps_nw (precision gate)
   bool adaptive = false;  // HT_ADAPTIVE_BUDGET: nodewise tolerance recomputed after every layer
+  int shares = 0;         // truncations the budget is split over: 2d - 2, or 2d - 3 (HT_PLAIN_HT_BUDGET)
   Tree tree;
   // per-node capacities: rows of the basis matrix (alpha) and rank bound
   std::vector<int64_t> alpha_cap;
@@ -321,7 +322,8 @@ bool valid_config(const ht_config* c, std::string& why) {
   if (c->n_cap < 1) return why = "n_cap must be >= 1", false;
   if (c->prec != HT_FP64 && c->prec != HT_FP32) return why = "prec must be HT_FP64 or HT_FP32", false;
   if (c->in_dtype != HT_F32 && c->in_dtype != HT_F64) return why = "in_dtype must be HT_F32 or HT_F64", false;
-  if ((c->flags & ~(uint64_t)HT_ADAPTIVE_BUDGET) != 0) return why = "unknown bits in flags", false;
+  if ((c->flags & ~(uint64_t)(HT_ADAPTIVE_BUDGET | HT_PLAIN_HT_BUDGET)) != 0)
+    return why = "unknown bits in flags", false;
   return true;
 }
 
@@ -828,6 +830,7 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   Layout L = make_layout(cfg, h->tree, h->alpha_cap, h->rc);
   h->mixed_ok = h->mixed && fp32_gate(h->eps, h->d, h->rc);
   h->adaptive = (cfg->flags & HT_ADAPTIVE_BUDGET) != 0;
+  h->shares = (cfg->flags & HT_PLAIN_HT_BUDGET) ? 2 * cfg->d - 3 : 2 * cfg->d - 2;
   if (ws_bytes < L.total) {
     delete h;
     return fail(HT_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes, " + std::to_string(L.total) +
@@ -957,7 +960,8 @@ int svd_remaining(const ht_state* h, int ell) {
   int c = 0;
   for (size_t i = 1; i < h->tree.nodes.size(); ++i)
     if (h->tree.nodes[i].layer < ell) ++c;
-  return c;
+  // under the plain-HT budget the root's two successors share one SVD
+  return h->shares == 2 * h->d - 3 ? c - 1 : c;
 }
 
 // App. C: the nodewise threshold eps_nw^2 = (eps_abs^2 - eps_l^2) / svd_rem for the
@@ -1098,7 +1102,7 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
       u.busy = true;
       u.saved = h->rank;
       backup_cores(h, s);
-      const double eps_nw = u.eps_des / std::sqrt(2.0 * h->d - 2.0);
+      const double eps_nw = u.eps_des / std::sqrt((double)h->shares);
       u.thr = eps_nw * eps_nw;
       u.lost2 = u.lost_err = u.thr_err = 0.0;
       u.cur = Level{u.Y, h->in_t, u.N, h->n};
@@ -1403,7 +1407,7 @@ ht_status ht_init_batch(const ht_config* cfg, void* ws, size_t ws_bytes, const v
     return fail(HT_EINVAL, "the initial batch is all zeros");
   }
   const double ny = std::sqrt(ny2);
-  const double eps_nw = h->eps * ny / std::sqrt(2.0 * h->d - 2.0);
+  const double eps_nw = h->eps * ny / std::sqrt((double)h->shares);
   double thr = eps_nw * eps_nw;
   Level cur{Y, h->in_t, N, h->n};
   int growth = 0;

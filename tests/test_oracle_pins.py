@@ -533,3 +533,60 @@ def test_adaptive_budget_meets_the_bound_on_the_tiny_stream():
     for k, y in enumerate(ys):
         yy = y.astype(np.float64)
         assert math.sqrt(ho.fro2(st.reconstruct(8 * k, 8) - yy)) <= 1e-4 * math.sqrt(ho.fro2(yy))
+
+
+# --------------------------------------------------------------------------- #
+# Plain leaves-to-root HT (Sec. 2.3.1), the baseline of the format comparison
+# --------------------------------------------------------------------------- #
+
+
+def test_plain_ht_of_a_matrix_is_the_truncated_svd():
+    """d = 2: one SVD with eps_nw = eps ||Y|| / sqrt(2*2-3) = eps ||Y||: the rank is the
+    smallest r whose tail of squared singular values is <= eps^2 ||Y||^2, the root holds
+    the kept singular values and the error is the tail."""
+    g = np.random.default_rng(3)
+    s = np.array([1.0, 0.5, 0.1, 0.03, 0.009, 0.001])
+    u = np.linalg.qr(g.standard_normal((9, 6)))[0]
+    v = np.linalg.qr(g.standard_normal((7, 6)))[0]
+    y = (u * s) @ v.T
+    for eps, r in ((0.05, 3), (0.02, 4), (0.005, 5)):
+        ht = ho.PlainHT(y, eps)
+        tail = np.sum(s[r:] ** 2)
+        assert tail <= (eps * np.linalg.norm(s)) ** 2 < np.sum(s[r - 1:] ** 2)
+        assert ht.ranks == [r, r]
+        np.testing.assert_allclose(np.diag(ht.root), s[:r], rtol=1e-12)
+        assert math.sqrt(ho.fro2(ht.reconstruct() - y)) == pytest.approx(math.sqrt(tail), rel=1e-8)
+
+
+def test_plain_ht_budget_is_2d_minus_3():
+    """d = 3 diagonal tensor s_t a_t (x) b_t (x) c_t with x^2 = 0.3 eps^2 ||Y||^2 on its last
+    term: the plain-HT tolerance eps^2 ||Y||^2 / 3 drops it at the leaves (rank 2), the
+    batch format's eps^2 ||Y||^2 / 4 would keep it (rank 3); the error is exactly x."""
+    g = np.random.default_rng(8)
+    a, b, c = (np.linalg.qr(g.standard_normal((n, 3)))[0] for n in (8, 7, 6))
+    eps = 1e-3
+    x = _x_for(0.3, eps, 1.09)
+    s = (1.0, 0.3, x)
+    y = sum(st * np.einsum("i,j,k->ijk", a[:, t], b[:, t], c[:, t]) for t, st in enumerate(s))
+    ht = ho.PlainHT(y, eps)
+    assert ht.ranks == [2, 2, 2, 2]
+    assert math.sqrt(ho.fro2(ht.reconstruct() - y)) == pytest.approx(x, rel=1e-6)
+    bht = ho.BHT(y.shape, eps)
+    bht.init_batch(y[None])
+    assert bht.ranks[2:] == [3, 3]
+
+
+@pytest.mark.parametrize("shape,rank", [((8, 9, 10, 7), 3), ((6, 5, 7, 4, 8), 2), ((12, 10, 9), 4)])
+def test_plain_ht_bound_orthonormal_cores_and_diagonal_root(shape, rank):
+    """Thm. ht_nodewise_error: ||Y - Y_hat|| <= eps ||Y||; every core orthonormal; the
+    root is diagonal and non-increasing; exact low-rank data is recovered."""
+    spec = datagen.HTModelSpec(n=shape[1:], rank=rank, N=shape[0], n_batches=1, seed=21, batch_seed0=2100,
+                               nu=1e-3)
+    y = next(datagen.ht_model_stream(spec)).astype(np.float64)
+    for eps in (1e-2, 1e-4):
+        ht = ho.PlainHT(y, eps)
+        assert math.sqrt(ho.fro2(ht.reconstruct() - y)) <= eps * math.sqrt(ho.fro2(y))
+        for u in ht.core.values():
+            np.testing.assert_allclose(u.T @ u, np.eye(u.shape[1]), atol=1e-12)
+        sv = np.diag(ht.root)
+        assert np.all(np.diff(sv) <= 0) and np.allclose(ht.root, np.diag(sv))
