@@ -120,8 +120,13 @@ typedef struct {
  *                       batch as a node of the tree: the two successors of the root
  *                       decide on the same matrix C_1 (one truncated SVD, Eq.
  *                       ht_last_svd), their cores are its left and right singular
- *                       vectors and the root is diag(Sigma_1) up to signs. */
-typedef enum { HT_ADAPTIVE_BUDGET = 1, HT_PLAIN_HT_BUDGET = 2 } ht_flags;
+ *                       vectors and the root is diag(Sigma_1) up to signs.
+ *   HT_ST_HOSVD         the variant of the footnote of Sec. 2.3.1: the nodes of a layer
+ *                       are truncated one after the other, left to right, each on the
+ *                       level tensor its predecessors in the layer have already
+ *                       contracted (sequentially truncated HOSVD), in BHT-l2r and in
+ *                       each HT-RISE update; one eigen launch and read-back per node. */
+typedef enum { HT_ADAPTIVE_BUDGET = 1, HT_PLAIN_HT_BUDGET = 2, HT_ST_HOSVD = 4 } ht_flags;
 
 typedef struct {
   int32_t skipped;        /* 1 when the batch was represented well enough (Alg. 2 skip) */

@@ -42,7 +42,9 @@ the design notes of the repository):
 * "unfold(C, l)" in Alg. 2's inner loop is read as the unfolding along the mode
   of node j;
 * leaves on layer p-1 are processed on the partially projected tensor;
-* within a layer every node sees the same tensor (HOSVD, not ST-HOSVD);
+* within a layer every node sees the same tensor (HOSVD, not ST-HOSVD); with
+  ``st_hosvd`` (the variant of the footnote in Sec. 2.3.1) the nodes of a layer are
+  truncated left to right, each on the tensor its predecessors contracted;
 * the new residual directions get one classical Gram-Schmidt pass against the
   old basis and a QR (a no-op in exact arithmetic, where they are orthogonal
   already);
@@ -267,7 +269,8 @@ class BHT:
     (r_{1,1}, r_{1,2}, N_acc).
     """
 
-    def __init__(self, n: Sequence[int], eps: float, tree: Optional[DimTree] = None, adaptive: bool = False):
+    def __init__(self, n: Sequence[int], eps: float, tree: Optional[DimTree] = None, adaptive: bool = False,
+                 st_hosvd: bool = False):
         self.n = tuple(int(x) for x in n)
         self.d = len(self.n)
         self.tree = tree if tree is not None else DimTree(self.d)
@@ -277,6 +280,10 @@ class BHT:
         # App. C: after each layer the nodewise tolerance is recomputed from the error
         # actually incurred so far, eps_nw = sqrt(eps_abs^2 - eps_l^2) / sqrt(svd_rem)
         self.adaptive = bool(adaptive)
+        # the footnote of Sec. 2.3.1: the nodes of a layer may instead be truncated one
+        # after the other (ST-HOSVD), each on the tensor its predecessors in the layer
+        # (left to right) have already contracted
+        self.st_hosvd = bool(st_hosvd)
         self.core: Dict[int, np.ndarray] = {}
         self.root: Optional[np.ndarray] = None
         self.history: List[BatchInfo] = []
@@ -381,14 +388,21 @@ class BHT:
         for ell in range(self.tree.depth, 0, -1):
             front = self.tree.frontier(ell)
             here = [(k, nd) for k, nd in enumerate(front) if nd.layer == ell]
-            bases = {}
-            for k, nd in here:  # every node of the layer sees the same tensor
-                u, t = truncated_svd(unfold(c, 1 + k), eps_nw, rmin=1)
-                bases[nd.idx] = u
-                decisions[nd.idx] = t
-            for k, nd in here:
-                self.core[nd.idx] = bases[nd.idx]
-                c = contract_mode_t(c, 1 + k, bases[nd.idx])
+            if self.st_hosvd:
+                for k, nd in here:  # each node on the tensor its predecessors contracted
+                    u, t = truncated_svd(unfold(c, 1 + k), eps_nw, rmin=1)
+                    decisions[nd.idx] = t
+                    self.core[nd.idx] = u
+                    c = contract_mode_t(c, 1 + k, u)
+            else:
+                bases = {}
+                for k, nd in here:  # every node of the layer sees the same tensor
+                    u, t = truncated_svd(unfold(c, 1 + k), eps_nw, rmin=1)
+                    bases[nd.idx] = u
+                    decisions[nd.idx] = t
+                for k, nd in here:
+                    self.core[nd.idx] = bases[nd.idx]
+                    c = contract_mode_t(c, 1 + k, bases[nd.idx])
             c = self._merge_to(c, ell)
             if self.adaptive and ell > 1:
                 eps_nw = self._adapted_eps_nw(self.eps * ny, ny * ny, c, ell)
@@ -434,12 +448,17 @@ class BHT:
                     q, rr = np.linalg.qr(u_r)
                     u_r = sign_normalise(q)
                 grown[nd.idx] = np.concatenate([u_old, u_r], axis=1)
-            for k, nd in here:
-                r_new = grown[nd.idx].shape[1] - self.rank(nd.idx)
-                self._pad_parent(nd, r_new)
-                self.core[nd.idx] = grown[nd.idx]
-            for k, nd in here:
-                c = contract_mode_t(c, 1 + k, self.core[nd.idx])
+                if self.st_hosvd:   # this node's expansion, then its contraction, before the next
+                    self._pad_parent(nd, grown[nd.idx].shape[1] - r_old)
+                    self.core[nd.idx] = grown[nd.idx]
+                    c = contract_mode_t(c, 1 + k, grown[nd.idx])
+            if not self.st_hosvd:
+                for k, nd in here:
+                    r_new = grown[nd.idx].shape[1] - self.rank(nd.idx)
+                    self._pad_parent(nd, r_new)
+                    self.core[nd.idx] = grown[nd.idx]
+                for k, nd in here:
+                    c = contract_mode_t(c, 1 + k, self.core[nd.idx])
             c = self._merge_to(c, ell)
             if self.adaptive and ell > 1:
                 eps_nw = self._adapted_eps_nw(eps_des, ny2, c, ell)

@@ -188,6 +188,7 @@ struct ht_state {
   bool mixed_ok = false;  // and the FP32 error floor lies well inside eps_nw (precision gate)
   bool adaptive = false;  // HT_ADAPTIVE_BUDGET: nodewise tolerance recomputed after every layer
   int shares = 0;         // truncations the budget is split over: 2d - 2, or 2d - 3 (HT_PLAIN_HT_BUDGET)
+  bool st_hosvd = false;  // HT_ST_HOSVD: the nodes of a layer truncated one after the other
   Tree tree;
   // per-node capacities: rows of the basis matrix (alpha) and rank bound
   std::vector<int64_t> alpha_cap;
@@ -322,7 +323,7 @@ bool valid_config(const ht_config* c, std::string& why) {
   if (c->n_cap < 1) return why = "n_cap must be >= 1", false;
   if (c->prec != HT_FP64 && c->prec != HT_FP32) return why = "prec must be HT_FP64 or HT_FP32", false;
   if (c->in_dtype != HT_F32 && c->in_dtype != HT_F64) return why = "in_dtype must be HT_F32 or HT_F64", false;
-  if ((c->flags & ~(uint64_t)(HT_ADAPTIVE_BUDGET | HT_PLAIN_HT_BUDGET)) != 0)
+  if ((c->flags & ~(uint64_t)(HT_ADAPTIVE_BUDGET | HT_PLAIN_HT_BUDGET | HT_ST_HOSVD)) != 0)
     return why = "unknown bits in flags", false;
   return true;
 }
@@ -491,12 +492,16 @@ std::vector<int> contraction_order(const ht_state* h, int ell, const std::vector
 // level tensor out); with energy, every contraction also writes the residual
 // energy it discards: FP32 ones the explicit sum into energy[2 node] (explicit[node]
 // set), FP64 ones ||in||^2 and ||out||^2 into energy[2 node] and [2 node + 1].
+// With only (frontier positions) just those nodes are contracted, in that order, and
+// the tensor is not merged (the ST-HOSVD steps of a layer); merge_level finishes it.
+Level merge_level(const ht_state* h, int ell, const Level& cur);
+
 Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, double* norm_out = nullptr,
                     bool mixed = false, double* energy = nullptr, std::vector<char>* expl = nullptr,
-                    double* const* pp = nullptr) {
+                    double* const* pp = nullptr, const std::vector<int>* only = nullptr) {
   const std::vector<int> f = h->tree.frontier(ell);
   Level cur = in;
-  for (const int k : contraction_order(h, ell, in.modes)) {
+  for (const int k : only ? *only : contraction_order(h, ell, in.modes)) {
     const int node = f[k];
     // intermediates alternate between the handle's two level buffers, or the pair pp
     double* dst = pp ? (cur.ptr == pp[0] ? pp[1] : pp[0]) : other(h, cur.ptr);
@@ -535,7 +540,11 @@ Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, 
     norm_out = nullptr;
     cur.modes[k] = h->rank[node];
   }
-  // merge to the frontier of layer ell - 1 (a reshape: adjacent siblings fuse)
+  return only ? cur : merge_level(h, ell, cur);
+}
+
+// Merge to the frontier of layer ell - 1 (a reshape: adjacent siblings fuse).
+Level merge_level(const ht_state* h, int ell, const Level& cur) {
   Level out = cur;
   if (ell >= 1) out.modes = frontier_sizes(h, ell - 1 >= 1 ? ell - 1 : 1);
   if (ell == 1) {
@@ -694,11 +703,12 @@ void node_gram(ht_state* h, int node, const Level& cur, const ModeView& v, int r
 }
 
 void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initial, bool mixed, hipStream_t s,
-                 LayerJobs& L) {
+                 LayerJobs& L, int only_k = -1) {
   const std::vector<int> f = h->tree.frontier(ell);
   for (size_t k = 0; k < f.size(); ++k) {
     const int node = f[k];
     if (h->tree.nodes[node].layer != ell) continue;
+    if (only_k >= 0 && (int)k != only_k) continue;
     const ModeView v = view_of(cur, k);
     const int alpha = (int)v.m;
     const int r_old = initial ? 0 : h->rank[node];
@@ -797,9 +807,9 @@ ht_status layer_finish(ht_state* h, double thr, bool initial, hipStream_t s, con
 }
 
 ht_status decide_layer(ht_state* h, int ell, const Level& cur, double thr, bool initial, hipStream_t s,
-                       int* growth) {
+                       int* growth, int only_k = -1) {
   LayerJobs L;
-  layer_grams(h, ell, cur, thr, initial, false, s, L);
+  layer_grams(h, ell, cur, thr, initial, false, s, L, only_k);
   launch_eig(L.jobs, s);
   HT_HIP(hipGetLastError());
   ht_status st = layer_readback(h, s);
@@ -831,6 +841,7 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   h->mixed_ok = h->mixed && fp32_gate(h->eps, h->d, h->rc);
   h->adaptive = (cfg->flags & HT_ADAPTIVE_BUDGET) != 0;
   h->shares = (cfg->flags & HT_PLAIN_HT_BUDGET) ? 2 * cfg->d - 3 : 2 * cfg->d - 2;
+  h->st_hosvd = (cfg->flags & HT_ST_HOSVD) != 0;
   if (ws_bytes < L.total) {
     delete h;
     return fail(HT_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes, " + std::to_string(L.total) +
@@ -933,6 +944,7 @@ struct Upd {
   std::vector<int> saved;
   double ny = 0, eps_des = 0, eps_proj = 0, thr = 0;
   double lost2 = 0, lost_err = 0, thr_err = 0;  // adaptive budget: error so far and its FP32 bound
+  double chain_extra = 0;  // ST-HOSVD: FP32 contractions of this layer before the current node
   bool skip = false, busy = false;
   bool mixed = false;  // this pass runs the FP32 kernels
   bool redo = false;   // an FP32 decision could not be certified: the call runs again in FP64
@@ -1000,7 +1012,7 @@ bool skip_certified(const Upd& u, double lost) {
 // alone is too coarse) marks the whole update for an FP64 run.
 void certify_layer(Upd& u, int ell, bool fp64_pass, std::vector<int>* redo_jobs) {
   const ht_state* h = u.h;
-  const double chain = fp32_chain(h, ell);
+  const double chain = fp32_chain(h, ell) + u.chain_extra;
   for (size_t q = 0; q < u.L.jobs.size(); ++q) {
     if (fp64_pass && std::find(redo_jobs->begin(), redo_jobs->end(), (int)q) == redo_jobs->end()) continue;
     const int node = u.L.node[q];
@@ -1009,8 +1021,17 @@ void certify_layer(Upd& u, int ell, bool fp64_pass, std::vector<int>* redo_jobs)
     const double dR = resid_err(u.ny, own, chain);
     const double tr = h->h_aux[2 * node];
     const double gerr = kGramK * (f32 ? kU32 : kU64) * tr + u.thr_err;
-    const bool ok = decision_certified(u.rk[node], u.L.jobs[q].rmin, u.L.jobs[q].rmax, u.tl[node],
-                                       h->h_aux[2 * node + 1], u.thr, dR, gerr);
+    bool ok = decision_certified(u.rk[node], u.L.jobs[q].rmin, u.L.jobs[q].rmax, u.tl[node],
+                                 h->h_aux[2 * node + 1], u.thr, dR, gerr);
+    // The kept vectors must be accurate too, not only their number: a Gram error E
+    // turns a kept direction by ~|E| / gap, and the part of its energy left behind
+    // reappears in later batches' residuals (measured on the 48^4 x 4 stream: with
+    // FP32 vectors the projection errors of later batches drift up to 3.5x the
+    // oracle's and a rank differs after 80 batches).  E is the product rounding plus
+    // the residual's own error against the residual, 2 sqrt(trace) dR; near the
+    // threshold the gap may be as small as thr, so a growing node whose E exceeds 1 %
+    // of thr takes its Gram again in FP64.
+    if (ok && f32 && u.rk[node] > 0 && gerr + 2.0 * std::sqrt(std::max(tr, 0.0)) * dR > 0.01 * u.thr) ok = false;
     if (ok) continue;
     if (f32)
       redo_jobs->push_back((int)q);
@@ -1115,102 +1136,136 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
     if (up->busy) max_depth = std::max(max_depth, up->h->tree.depth);
   for (int t = 0; t < max_depth; ++t) {
     auto layer_of = [&](const Upd& u) { return u.busy ? u.h->tree.depth - t : 0; };
-    std::vector<ht::EigJob> all;
-    std::vector<ht::AuxJob> aux;
-    for (Upd* up : act) {
-      Upd& u = *up;
+    // the nodes each handle truncates per step of this layer: all of them at once
+    // (HOSVD: every node sees the same tensor), or one after the other in frontier
+    // order (HT_ST_HOSVD: each on the tensor its predecessors have contracted)
+    std::vector<std::vector<std::vector<int>>> steps(act.size());
+    size_t nsteps = 0;
+    for (size_t a = 0; a < act.size(); ++a) {
+      Upd& u = *act[a];
       const int ell = layer_of(u);
-      u.L = LayerJobs();
+      u.chain_extra = 0.0;
       if (ell < 1) continue;
-      layer_grams(u.h, ell, u.cur, u.thr, false, u.mixed, s, u.L);
-      all.insert(all.end(), u.L.jobs.begin(), u.L.jobs.end());
-      if (u.mixed) aux_jobs(u, nullptr, aux);
+      if (u.h->st_hosvd) {
+        const std::vector<int> f = u.h->tree.frontier(ell);
+        for (size_t k = 0; k < f.size(); ++k)
+          if (u.h->tree.nodes[f[k]].layer == ell) steps[a].push_back({(int)k});
+      } else {
+        steps[a].push_back({});
+      }
+      nsteps = std::max(nsteps, steps[a].size());
+      if (u.h->adaptive && u.mixed) u.expl.assign(u.h->tree.nodes.size(), 0);
     }
-    launch_eig(all, s);
-    if (!aux.empty()) ht::decision_aux(aux.data(), (int)aux.size(), s);
-    HT_HIP(hipGetLastError());
-    for (Upd* up : act) {
-      if (layer_of(*up) < 1) continue;
-      const ht_status st = layer_readback(up->h, s, up->mixed);
-      if (st != HT_OK) return st;
-    }
-    HT_HIP(wait_stream(s));
-    for (Upd* up : act)
-      if (layer_of(*up) >= 1) layer_collect(up->h, up->rk, up->tl);
-    // ---- certificates of the mixed decisions; FP64 Grams for the uncertified ones
-    {
-      std::vector<std::vector<int>> fix(act.size());
-      std::vector<ht::EigJob> again;
-      std::vector<ht::AuxJob> again_aux;
+    for (size_t sub = 0; sub < nsteps; ++sub) {
+      auto active = [&](size_t a) { return layer_of(*act[a]) >= 1 && sub < steps[a].size(); };
+      auto only_of = [&](size_t a) -> const std::vector<int>* {
+        return steps[a][sub].empty() ? nullptr : &steps[a][sub];
+      };
+      std::vector<ht::EigJob> all;
+      std::vector<ht::AuxJob> aux;
       for (size_t a = 0; a < act.size(); ++a) {
         Upd& u = *act[a];
-        const int ell = layer_of(u);
-        if (ell < 1 || !u.mixed) continue;
-        certify_layer(u, ell, false, &fix[a]);
-        if (u.redo) continue;
-        for (int q : fix[a]) {
-          node_gram(u.h, u.L.node[q], u.cur, u.L.view[q], u.L.rold[q], false, s);
-          again.push_back(u.L.jobs[q]);
-          u.recomputed += 1;
-        }
-        if (!fix[a].empty()) aux_jobs(u, &fix[a], again_aux);
+        u.L = LayerJobs();
+        if (!active(a)) continue;
+        const std::vector<int>* only = only_of(a);
+        layer_grams(u.h, layer_of(u), u.cur, u.thr, false, u.mixed, s, u.L, only ? (*only)[0] : -1);
+        all.insert(all.end(), u.L.jobs.begin(), u.L.jobs.end());
+        if (u.mixed) aux_jobs(u, nullptr, aux);
       }
-      if (!again.empty()) {
-        launch_eig(again, s);
-        ht::decision_aux(again_aux.data(), (int)again_aux.size(), s);
-        HT_HIP(hipGetLastError());
-        for (size_t a = 0; a < act.size(); ++a) {
-          if (fix[a].empty() || act[a]->redo) continue;
-          const ht_status st = layer_readback(act[a]->h, s, true);
-          if (st != HT_OK) return st;
-        }
-        HT_HIP(wait_stream(s));
+      launch_eig(all, s);
+      if (!aux.empty()) ht::decision_aux(aux.data(), (int)aux.size(), s);
+      HT_HIP(hipGetLastError());
+      for (size_t a = 0; a < act.size(); ++a) {
+        if (!active(a)) continue;
+        const ht_status st = layer_readback(act[a]->h, s, act[a]->mixed);
+        if (st != HT_OK) return st;
+      }
+      HT_HIP(wait_stream(s));
+      for (size_t a = 0; a < act.size(); ++a)
+        if (active(a)) layer_collect(act[a]->h, act[a]->rk, act[a]->tl);
+      // ---- certificates of the mixed decisions; FP64 Grams for the uncertified ones
+      {
+        std::vector<std::vector<int>> fix(act.size());
+        std::vector<ht::EigJob> again;
+        std::vector<ht::AuxJob> again_aux;
         for (size_t a = 0; a < act.size(); ++a) {
           Upd& u = *act[a];
-          if (fix[a].empty() || u.redo) continue;
-          layer_collect(u.h, u.rk, u.tl);
-          certify_layer(u, layer_of(u), true, &fix[a]);
+          if (!active(a) || !u.mixed) continue;
+          certify_layer(u, layer_of(u), false, &fix[a]);
+          if (u.redo) continue;
+          for (int q : fix[a]) {
+            node_gram(u.h, u.L.node[q], u.cur, u.L.view[q], u.L.rold[q], false, s);
+            again.push_back(u.L.jobs[q]);
+            u.recomputed += 1;
+          }
+          if (!fix[a].empty()) aux_jobs(u, &fix[a], again_aux);
+        }
+        if (!again.empty()) {
+          launch_eig(again, s);
+          ht::decision_aux(again_aux.data(), (int)again_aux.size(), s);
+          HT_HIP(hipGetLastError());
+          for (size_t a = 0; a < act.size(); ++a) {
+            if (fix[a].empty() || act[a]->redo) continue;
+            const ht_status st = layer_readback(act[a]->h, s, true);
+            if (st != HT_OK) return st;
+          }
+          HT_HIP(wait_stream(s));
+          for (size_t a = 0; a < act.size(); ++a) {
+            Upd& u = *act[a];
+            if (fix[a].empty() || u.redo) continue;
+            layer_collect(u.h, u.rk, u.tl);
+            certify_layer(u, layer_of(u), true, &fix[a]);
+          }
+        }
+        for (Upd* up : act)
+          if (up->redo && up->busy) roll_back(*up, s);
+      }
+      std::vector<ht::OrthJob> orth;
+      for (size_t a = 0; a < act.size(); ++a) {
+        Upd& u = *act[a];
+        if (!active(a)) continue;
+        ht_status st = layer_finish(u.h, u.thr, false, s, u.L, u.rk, u.tl, &u.growth, &orth);
+        if (st != HT_OK) {
+          // roll this handle back (a failing handle has queued no expansion)
+          u.st = st;
+          u.err = g_last_error;
+          roll_back(u, s);
+          continue;
         }
       }
-      for (Upd* up : act)
-        if (up->redo && up->busy) roll_back(*up, s);
-    }
-    std::vector<ht::OrthJob> orth;
-    for (Upd* up : act) {
-      Upd& u = *up;
-      const int ell = layer_of(u);
-      if (ell < 1) continue;
-      ht_status st = layer_finish(u.h, u.thr, false, s, u.L, u.rk, u.tl, &u.growth, &orth);
-      if (st != HT_OK) {
-        // roll this handle back (a failing handle has queued no expansion)
-        u.st = st;
-        u.err = g_last_error;
-        roll_back(u, s);
-        continue;
+      if (!orth.empty()) ht::orth_expand_batch(orth.data(), (int)orth.size(), s);
+      // ---- the projection of this step (merged into the next frontier after the last)
+      for (size_t a = 0; a < act.size(); ++a) {
+        Upd& u = *act[a];
+        if (!active(a)) continue;
+        ht_state* h = u.h;
+        const int ell = layer_of(u);
+        const std::vector<int>* only = only_of(a);
+        if (only) {
+          const int k = (*only)[0];
+          if (u.mixed && u.cur.modes[k] <= ht::kResidGramMaxM) u.chain_extra += h->rank[h->tree.frontier(ell)[k]] + 1.0;
+        }
+        if (h->adaptive && ell > 1 && u.mixed) {
+          // App. C in the mixed form: the energy each second-pass contraction discards,
+          // summed (a difference of FP32-accurate norms would not resolve eps_des^2)
+          u.cur = project_layer(h, ell, u.cur, s, nullptr, true, h->scal + 8, &u.expl, nullptr, only);
+        } else {
+          u.cur = project_layer(h, ell, u.cur, s, nullptr, u.mixed, nullptr, nullptr, nullptr, only);
+        }
+        if (only && sub + 1 == steps[a].size()) u.cur = merge_level(h, ell, u.cur);
       }
     }
-    if (!orth.empty()) ht::orth_expand_batch(orth.data(), (int)orth.size(), s);
+    // ---- App. C: the tolerance of the layers above from the energy lost so far
     bool adapt = false;
     for (Upd* up : act) {
       Upd& u = *up;
       const int ell = layer_of(u);
-      if (ell < 1) continue;
+      if (ell <= 1 || !u.h->adaptive) continue;
       ht_state* h = u.h;
-      const bool ad = h->adaptive && ell > 1;
-      if (ad && u.mixed) {
-        // App. C in the mixed form: the energy each pass-2 contraction discards, summed
-        // (a difference of FP32-accurate norms would not resolve eps_des^2)
-        u.expl.assign(h->tree.nodes.size(), 0);
-        u.cur = project_layer(h, ell, u.cur, s, nullptr, true, h->scal + 8, &u.expl);
-      } else {
-        u.cur = project_layer(h, ell, u.cur, s, nullptr, u.mixed);
-        if (ad) ht::sumsq(u.cur.ptr, u.cur.t, (int64_t)u.cur.elems(), h->sspart, h->scal + 1, s);
-      }
-      if (ad) {
-        HT_HIP(hipMemcpyAsync(h->h_scal, h->scal, kScalars((int)h->tree.nodes.size()) * sizeof(double),
-                              hipMemcpyDeviceToHost, s));
-        adapt = true;
-      }
+      if (!u.mixed) ht::sumsq(u.cur.ptr, u.cur.t, (int64_t)u.cur.elems(), h->sspart, h->scal + 1, s);
+      HT_HIP(hipMemcpyAsync(h->h_scal, h->scal, kScalars((int)h->tree.nodes.size()) * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+      adapt = true;
     }
     if (adapt) {
       HT_HIP(wait_stream(s));
@@ -1223,8 +1278,9 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
           // this layer's discarded energies and their error bound (as in the skip test)
           double chain = fp32_chain(h, ell);
           const std::vector<int> f = h->tree.frontier(ell);
-          for (const int k : contraction_order(h, ell, frontier_sizes(h, ell))) {
+          for (size_t k = 0; k < f.size(); ++k) {
             const int node = f[k];
+            if (h->tree.nodes[node].layer != ell) continue;
             const double* e = h->h_scal + 8 + 2 * node;
             const bool ex = u.expl[node] != 0;
             const double ej = ex ? e[0] : e[0] - e[1];
@@ -1412,12 +1468,29 @@ ht_status ht_init_batch(const ht_config* cfg, void* ws, size_t ws_bytes, const v
   Level cur{Y, h->in_t, N, h->n};
   int growth = 0;
   for (int ell = h->tree.depth; ell >= 1; --ell) {
-    st = decide_layer(h, ell, cur, thr, true, s, &growth);
-    if (st != HT_OK) {
-      delete h;
-      return st;
+    if (h->st_hosvd) {
+      // ST-HOSVD: the nodes of the layer one after the other, left to right, each on
+      // the tensor its predecessors have contracted
+      const std::vector<int> f = h->tree.frontier(ell);
+      for (size_t k = 0; k < f.size(); ++k) {
+        if (h->tree.nodes[f[k]].layer != ell) continue;
+        st = decide_layer(h, ell, cur, thr, true, s, &growth, (int)k);
+        if (st != HT_OK) {
+          delete h;
+          return st;
+        }
+        const std::vector<int> one{(int)k};
+        cur = project_layer(h, ell, cur, s, nullptr, false, nullptr, nullptr, nullptr, &one);
+      }
+      cur = merge_level(h, ell, cur);
+    } else {
+      st = decide_layer(h, ell, cur, thr, true, s, &growth);
+      if (st != HT_OK) {
+        delete h;
+        return st;
+      }
+      cur = project_layer(h, ell, cur, s);
     }
-    cur = project_layer(h, ell, cur, s);
     if (h->adaptive && ell > 1) {
       // App. C: the energy lost so far sets the tolerance of the layers above
       ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), h->sspart, h->scal + 1, s);

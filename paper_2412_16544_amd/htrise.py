@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libhtrise.so")
 HT_OK, HT_EINVAL, HT_ESHAPE, HT_ENOMEM, HT_ERANKCAP, HT_EDEVICE, HT_ENUMERIC = range(7)
 HT_FP64, HT_FP32, HT_BF16X3 = 0, 1, 2
 HT_F32, HT_F64 = 0, 1
-HT_ADAPTIVE_BUDGET, HT_PLAIN_HT_BUDGET = 1, 2
+HT_ADAPTIVE_BUDGET, HT_PLAIN_HT_BUDGET, HT_ST_HOSVD = 1, 2, 4
 
 STATUS_NAMES = {0: "HT_OK", 1: "HT_EINVAL", 2: "HT_ESHAPE", 3: "HT_ENOMEM", 4: "HT_ERANKCAP",
                 5: "HT_EDEVICE", 6: "HT_ENUMERIC"}

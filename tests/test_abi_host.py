@@ -73,7 +73,7 @@ def test_mixed_form_is_a_valid_config():
 
 @pytest.mark.parametrize("kw", [dict(n=(16,)), dict(eps=0.0), dict(eps=1.0), dict(n=(16, 0, 3)),
                                 dict(rank_cap=0), dict(rank_cap=65), dict(max_batch=0), dict(n_cap=0),
-                                dict(prec=7), dict(prec=2), dict(in_dtype=5), dict(flags=4)])
+                                dict(prec=7), dict(prec=2), dict(in_dtype=5), dict(flags=8)])
 def test_invalid_configs_rejected(kw):
     with pytest.raises(H.HTError) as e:
         _ws(**kw)

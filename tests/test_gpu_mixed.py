@@ -63,7 +63,9 @@ def check_mixed(ys, eps, rank_cap=64, prec=None):
     if prec is not None:
         assert all(i.prec_used == prec for i in ginfo[1:]), [(i.prec_used, i.recomputed) for i in ginfo]
         if prec == H.HT_FP32:
-            assert all(i.recomputed == 0 for i in ginfo[1:])
+            # skips and non-growing decisions stay FP32; a growing node's Gram is taken
+            # again in FP64 for accurate kept vectors
+            assert all(i.recomputed <= i.rank_growth for i in ginfo[1:])
     ost = ho.BHT(ys[0].shape[1:], eps)
     oinfo = [ost.init_batch(ys[0])] + [ost.update(y) for y in ys[1:]]
     assert granks == [i.ranks for i in oinfo], (granks, [i.ranks for i in oinfo])

@@ -590,3 +590,51 @@ def test_plain_ht_bound_orthonormal_cores_and_diagonal_root(shape, rank):
             np.testing.assert_allclose(u.T @ u, np.eye(u.shape[1]), atol=1e-12)
         sv = np.diag(ht.root)
         assert np.all(np.diff(sv) <= 0) and np.allclose(ht.root, np.diag(sv))
+
+
+# --------------------------------------------------------------------------- #
+# ST-HOSVD within a layer (the footnote of Sec. 2.3.1)
+# --------------------------------------------------------------------------- #
+
+
+def test_st_hosvd_bht_l2r_closed_form():
+    """The spectrum of the HOSVD pin: with ST-HOSVD leaf 2 sees the tensor leaf 1 has
+    contracted, (1, .3, .05, 7e-5) at tail 0.90 thr, and keeps 3."""
+    ys, _, _ = _diag_stream([((1.0, 0.3, 0.05, 7e-5, 5.2e-5), _diag_pairs(5))])
+    st = ho.BHT(ys[0].shape[1:], 1e-4, st_hosvd=True)
+    st.init_batch(ys[0])
+    assert st.ranks == [4, 3]
+    assert math.sqrt(ho.fro2(st.reconstruct() - ys[0])) <= 1e-4 * math.sqrt(ho.fro2(ys[0]))
+
+
+def test_st_hosvd_ht_rise_closed_form():
+    """A residual spectrum (x, z, w) with z^2 = 0.9 thr, w^2 = 0.5 thr (thr = eps_des^2 / 2):
+    leaf 1 keeps x and z (dropping z too would leave 1.4 thr); with HOSVD leaf 2 sees the
+    same and keeps 2, with ST-HOSVD it sees the tensor leaf 1 contracted, where w is
+    gone, and keeps only x."""
+    eps = 1e-4
+    fr = {"x": 10.0, "z": 0.9, "w": 0.5}
+    c = {k: eps * eps * v / 2.0 for k, v in fr.items()}
+    total = 1.09 / (1.0 - sum(c.values()))
+    x, z, w = (math.sqrt(c[k] * total) for k in ("x", "z", "w"))
+    ys, _, _ = _diag_stream([((1.0, 0.3), _diag_pairs(2)), ((1.0, 0.3, x, z, w), _diag_pairs(5))])
+    hosvd, st = ho.BHT(ys[0].shape[1:], eps), ho.BHT(ys[0].shape[1:], eps, st_hosvd=True)
+    for s in (hosvd, st):
+        s.init_batch(ys[0])
+        assert not s.update(ys[1]).skipped
+    assert hosvd.ranks == [4, 4]
+    assert st.ranks == [4, 3]
+    err = math.sqrt(ho.fro2(st.reconstruct(6, 6) - ys[1]))
+    assert err == pytest.approx(math.sqrt(z * z + w * w), rel=1e-6)
+    assert err <= eps * math.sqrt(ho.fro2(ys[1]))
+
+
+def test_st_hosvd_meets_the_bound_on_the_tiny_stream():
+    ys = datagen.tiny_stream()
+    st = ho.BHT(ys[0].shape[1:], 1e-4, st_hosvd=True)
+    for k, y in enumerate(ys):
+        (st.init_batch if k == 0 else st.update)(y)
+    assert st.ranks == [8] * 6
+    for k, y in enumerate(ys):
+        yy = y.astype(np.float64)
+        assert math.sqrt(ho.fro2(st.reconstruct(8 * k, 8) - yy)) <= 1e-4 * math.sqrt(ho.fro2(yy))
