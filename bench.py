@@ -297,6 +297,85 @@ def stage(spec):
     return ys
 
 
+def run_variants(steps, warmup):
+    """The method's variants beside the headline: the adaptive error budget (App. C) and
+    ST-HOSVD within a layer on the 96^3 x 3 stream (both forms, timed like the
+    headline, ranks and skips checked at every batch against the oracle's variant
+    traces), and the plain leaves-to-root HT (Sec. 2.3.1) against BHT-l2r on the first
+    batch of both field streams (the format comparison of App. D.1): device time of the
+    one-shot decomposition, ranks against the oracle's, compression ratios."""
+    import torch
+    import datagen
+    from paper_2412_16544_amd import htrise as H
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "variants_trace.json")))
+    spec = datagen.field_96_spec()
+    ys = stage(spec)
+    E = spec.elements_per_batch
+    out = {"workload": WORKLOADS["field96"][0]}
+    for name, flags in (("adaptive_budget", H.HT_ADAPTIVE_BUDGET), ("st_hosvd", H.HT_ST_HOSVD)):
+        rows = gold["field96_" + ("adaptive" if name == "adaptive_budget" else name)]
+        out[name] = {}
+        for form, prec in (("mixed", H.HT_FP32), ("fp64", H.HT_FP64)):
+            st = H.HTStream(spec.n, EPS, 48, spec.N, spec.N * len(ys), prec=prec, flags=flags)
+            for _ in range(warmup):
+                st.reset()
+                for y in ys:
+                    st.push(y)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                st.reset()
+                for y in ys:
+                    st.push(y)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            st.reset()
+            ok = True
+            for k, y in enumerate(ys):
+                info = st.push(y)
+                ok = ok and st.ranks()[0] == rows[k]["ranks"] and (k == 0 or bool(info.skipped) == rows[k]["skipped"])
+            cr = len(ys) * E / len(st.export())
+            out[name][form] = {"value": len(ys) * E / dt, "ms_per_step": dt * 1e3, "final_ranks": st.ranks()[0],
+                               "compression_ratio": cr, "parity_vs_oracle_trace": bool(ok)}
+            log("variant %s %s: %.3e elements/s, ranks %s, parity %s" % (name, form, len(ys) * E / dt,
+                                                                         st.ranks()[0], ok))
+            st.close()
+            del st
+    del ys
+    torch.cuda.empty_cache()
+    # plain HT (batch as a mode, one tensor) against BHT-l2r on the first batch
+    out["bht_vs_plain_ht"] = {}
+    for wname, sp, rc in (("field96", spec, 48), ("field48", datagen.field_48_spec(), 64)):
+        from datagen import gpu as G
+        y = G.field_batch(sp, 0)
+        ref = gold[wname + "_batch0_plain_ht"]
+        res = {}
+        for fmt in ("bht_l2r", "plain_ht"):
+            times = []
+            for _ in range(3):
+                if fmt == "bht_l2r":
+                    st = H.HTStream(sp.n, EPS, rc, sp.N, sp.N)
+                    info = st.push(y)
+                else:
+                    st = H.HTStream((sp.N,) + sp.n, EPS, 64, 1, 1, flags=H.HT_PLAIN_HT_BUDGET)
+                    info = st.push(y.view((1, sp.N) + sp.n))
+                times.append(info.device_ms)
+                ranks = st.ranks()[0]
+                size = len(st.export())
+                st.close()
+                del st
+            res[fmt] = {"device_ms": sorted(times)[1], "ranks": ranks, "compression_ratio": sp.elements_per_batch / size}
+        res["plain_ht_ranks_match_oracle"] = res["plain_ht"]["ranks"] == ref["ranks"]
+        res["plain_ht_over_bht_time"] = res["plain_ht"]["device_ms"] / res["bht_l2r"]["device_ms"]
+        out["bht_vs_plain_ht"][wname] = res
+        log("%s batch 0: BHT-l2r %.2f ms (CR %.1f), plain HT %.2f ms (CR %.1f), HT ranks match oracle %s"
+            % (wname, res["bht_l2r"]["device_ms"], res["bht_l2r"]["compression_ratio"], res["plain_ht"]["device_ms"],
+               res["plain_ht"]["compression_ratio"], res["plain_ht_ranks_match_oracle"]))
+        del y
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_workload(name, spec, rank_cap, forms, steps, warmup):
     golden = json.load(open(os.path.join(ROOT, "tests", "golden", name + "_trace.json")))
     ys = stage(spec)
@@ -490,6 +569,8 @@ def main():
             r["parity_vs_oracle_trace"] for r in ores.values())
     if not args.no_many and args.form == "both":
         line["many_streams"] = run_many()
+    if not args.only and args.form == "both":
+        line["variants"] = run_variants(max(1, args.steps // 4), min(args.warmup, 1))
     if args.cpu_sample > 0:
         log("timing the oracle on a sample of the same stream...")
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_sample, 1)

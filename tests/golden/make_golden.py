@@ -15,6 +15,10 @@ Both also hold the oracle's per-sample relative test errors (Sec. 4.1) of the tw
 batches that follow the stream, encoded and decoded with the final cores
 ("rte_heldout"; for field48 written from the trace's final checkpoint).
 
+variants_trace.json: the adaptive-budget (App. C) and ST-HOSVD variants on the
+96^3 x 3 stream, and the plain leaves-to-root HT (Sec. 2.3.1) of the first batch of
+both field streams as one tensor with the batch as a mode.
+
 field48_trace.json: the same for all 100 batches of the 48^4 x 4, N=16 stream
 (d = 5, a three-level tree), the large-stream workload, plus the oracle's
 reconstruction of the first batches at fixed sampled element positions (the
@@ -174,6 +178,36 @@ def field48_trace(eps=1e-4, checkpoint=None):
                  sampled=SAMPLED_BATCHES, checkpoint=checkpoint)
 
 
+def variants():
+    """The method's variants on the 96^3 x 3 stream (adaptive budget, ST-HOSVD: per batch
+    ranks, skips and projection errors) and the plain leaves-to-root HT of the first
+    batch of both field streams, taken as one tensor with the batch as its first mode
+    (ranks and core element counts)."""
+    out = {"source": "oracle/ht_oracle.py via tests/golden/make_golden.py"}
+    spec = datagen.field_96_spec()
+    ys = [datagen.exact_field_batch(spec, k) for k in range(spec.n_batches)]
+    for name, kw in (("field96_adaptive", dict(adaptive=True)), ("field96_st_hosvd", dict(st_hosvd=True))):
+        st = ho.BHT(spec.n, 1e-4, **kw)
+        rows = []
+        for k, y in enumerate(ys):
+            info = st.init_batch(y) if k == 0 else st.update(y)
+            rows.append({"batch": k, "skipped": bool(info.skipped), "ranks": info.ranks,
+                         "eps_proj_rel": info.eps_proj / info.norm_y,
+                         "min_decision_margin_rel": decision_margin(info)})
+            print(name, rows[-1], flush=True)
+        out[name] = rows
+    del ys
+    for name, sp in (("field96_batch0_plain_ht", spec), ("field48_batch0_plain_ht", datagen.field_48_spec())):
+        y = datagen.exact_field_batch(sp, 0)
+        ht = ho.PlainHT(y, 1e-4)
+        out[name] = {"shape": list(y.shape), "ranks": ht.ranks, "core_elements": ht.num_elements(),
+                     "error_rel": math.sqrt(ho.fro2(ht.reconstruct() - y) / ho.fro2(y))}
+        print(name, out[name], flush=True)
+        del y, ht
+    with open(os.path.join(HERE, "variants_trace.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
     # optional second argument: a checkpoint file for the long field48 trace (written
     # every five batches; a rerun with the same file resumes from it)
@@ -189,3 +223,5 @@ if __name__ == "__main__":
             json.dump(data, f, indent=1)
     if which in ("field48rte", "all") and ckpt:
         field48_rte(ckpt)
+    if which in ("variants", "all"):
+        variants()
