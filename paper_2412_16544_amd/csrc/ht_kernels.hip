@@ -1146,16 +1146,25 @@ __global__ __launch_bounds__(256) void gram_reg_kernel(const float* __restrict__
 // --------------------------------------------------------------------------
 constexpr int kGram64Ld = 17;  // row stride (doubles) of a wave's residual half in LDS
 
-// Owner wave of the upper tiles in row i of a TI x TI tile grid: whole rows, paired
-// so the waves get near-equal tile counts (8 rows: i with 7 - i, 9 tiles each; 6
-// rows: 6 | 5 + 1 | 4 + 2 | 3), and a wave reads each operand row once per k step.
-__host__ __device__ constexpr int gram64_owner(int TI, int i) {
+// Owner wave of upper tile (i, j) of a TI x TI tile grid.  Up to four tile rows the
+// tiles go round robin in row-major order (TI = 3: two tiles for waves 0-1, one for
+// waves 2-3, against three for wave 0 with whole rows); for 6 and 8 rows whole rows,
+// paired so the waves get near-equal tile counts (8 rows: i with 7 - i, 9 tiles
+// each; 6 rows: 6 | 5 + 1 | 4 + 2 | 3) and a wave reads each operand row once per
+// k step.
+__host__ __device__ constexpr int gram64_owner(int TI, int i, int j) {
+  if (TI <= 4) {
+    int q = j - i;
+    for (int a = 0; a < i; ++a) q += TI - a;
+    return q % 4;
+  }
   return TI == 8 ? (i < 7 - i ? i : 7 - i) : (i < 4 ? i : TI - i);
 }
 __host__ __device__ constexpr int gram64_tiles(int TI, int W) {
   int n = 0;
   for (int i = 0; i < TI; ++i)
-    if (gram64_owner(TI, i) == W) n += TI - i;
+    for (int j = i; j < TI; ++j)
+      if (gram64_owner(TI, i, j) == W) ++n;
   return n;
 }
 __host__ __device__ constexpr int gram64_max_tiles(int TI) {
@@ -1163,13 +1172,16 @@ __host__ __device__ constexpr int gram64_max_tiles(int TI) {
   for (int w = 0; w < 4; ++w) n = gram64_tiles(TI, w) > n ? gram64_tiles(TI, w) : n;
   return n;
 }
+// true when wave W owns a tile in tile row or tile column i (it needs operand row i)
+__host__ __device__ constexpr bool gram64_uses(int TI, int W, int i) {
+  for (int k = 0; k < TI; ++k)
+    if (gram64_owner(TI, k < i ? k : i, k < i ? i : k) == W) return true;
+  return false;
+}
 
 // wave W's tiles, accumulated over the four waves' residual halves in LDS
 template <int TI, int W, int NA>
 __device__ __forceinline__ void gram64_accumulate(const double* sRw, int wreg, int c16, int g4, d4 (&acc)[NA]) {
-  int lo = TI;
-  for (int i = TI - 1; i >= 0; --i)
-    if (gram64_owner(TI, i) == W) lo = i;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
     const double* rw = sRw + w * wreg;
@@ -1177,13 +1189,14 @@ __device__ __forceinline__ void gram64_accumulate(const double* sRw, int wreg, i
     for (int k4 = 0; k4 < 4; ++k4) {
       double op[TI];
 #pragma unroll
-      for (int i = 0; i < TI; ++i) op[i] = i >= lo ? rw[(16 * i + c16) * kGram64Ld + 4 * k4 + g4] : 0.0;
+      for (int i = 0; i < TI; ++i)
+        op[i] = gram64_uses(TI, W, i) ? rw[(16 * i + c16) * kGram64Ld + 4 * k4 + g4] : 0.0;
       int q = 0;
 #pragma unroll
       for (int i = 0; i < TI; ++i) {
-        if (gram64_owner(TI, i) == W) {
 #pragma unroll
-          for (int j = i; j < TI; ++j) {
+        for (int j = i; j < TI; ++j) {
+          if (gram64_owner(TI, i, j) == W) {
             acc[q] = mfma16(op[i], op[j], acc[q]);
             ++q;
           }
@@ -1198,9 +1211,9 @@ __device__ __forceinline__ void gram64_store(const d4 (&acc)[NA], int m, int c16
   int q = 0;
 #pragma unroll
   for (int i = 0; i < TI; ++i) {
-    if (gram64_owner(TI, i) == W) {
 #pragma unroll
-      for (int j = i; j < TI; ++j) {
+    for (int j = i; j < TI; ++j) {
+      if (gram64_owner(TI, i, j) == W) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = 16 * i + g4 + 4 * v, col = 16 * j + c16;
@@ -1968,6 +1981,8 @@ int reg_mode(Elem t, const ModeView& v, int R) {
 
 #define HT_REG_CASES(X)                                                                                \
   X(2, 1, 0) X(2, 2, 0) X(2, 3, 0) X(2, 4, 0) X(4, 1, 0) X(4, 2, 0) X(4, 3, 0) X(4, 4, 0)                 \
+  X(3, 1, 0) X(3, 2, 0) X(3, 3, 0) X(3, 4, 0) X(3, 1, 1) X(3, 2, 1) X(3, 1, 2) X(3, 2, 2)                 \
+  X(3, 1, 3) X(3, 2, 3) X(3, 1, 4) X(3, 2, 4)                                                             \
   X(6, 1, 0) X(6, 2, 0) X(6, 3, 0) X(6, 4, 0) X(8, 1, 0) X(8, 2, 0) X(8, 3, 0) X(8, 4, 0)                 \
   X(4, 1, 1) X(4, 2, 1) X(6, 1, 1) X(6, 2, 1) X(4, 1, 2) X(4, 2, 2) X(6, 1, 2) X(6, 2, 2)                 \
   X(4, 1, 3) X(4, 2, 3) X(6, 1, 3) X(6, 2, 3) X(4, 1, 4) X(4, 2, 4) X(6, 1, 4) X(6, 2, 4)
@@ -1975,9 +1990,19 @@ int reg_mode(Elem t, const ModeView& v, int R) {
 // the FP64 Gram's cases: without 128 rows and more than 32 basis columns
 #define HT_REG64_CASES(X)                                                                              \
   X(2, 1, 0) X(2, 2, 0) X(2, 3, 0) X(2, 4, 0) X(4, 1, 0) X(4, 2, 0) X(4, 3, 0) X(4, 4, 0)                 \
+  X(3, 1, 0) X(3, 2, 0) X(3, 3, 0) X(3, 4, 0) X(3, 1, 1) X(3, 2, 1) X(3, 1, 2) X(3, 2, 2)                 \
+  X(3, 1, 3) X(3, 2, 3) X(3, 1, 4) X(3, 2, 4)                                                             \
   X(6, 1, 0) X(6, 2, 0) X(6, 3, 0) X(6, 4, 0) X(8, 1, 0) X(8, 2, 0)                                       \
   X(4, 1, 1) X(4, 2, 1) X(6, 1, 1) X(6, 2, 1) X(4, 1, 2) X(4, 2, 2) X(6, 1, 2) X(6, 2, 2)                 \
   X(4, 1, 3) X(4, 2, 3) X(6, 1, 3) X(6, 2, 3) X(4, 1, 4) X(4, 2, 4) X(6, 1, 4) X(6, 2, 4)
+
+// row tiles of 16 of a register-direct kernel for an m-row mode: 2, 3, 4, 6 or 8 (an
+// odd count other than 3 is rounded up; three tiles cover the 33-48 row modes without
+// a padding tile)
+int reg_tiles(int64_t m) {
+  const int t = (int)((m + 15) / 16);
+  return t == 3 ? 3 : (t + 1) & ~1;
+}
 
 int64_t reg_blocks(const ModeView& v, int mode) { return mode == 0 ? v.P * v.S / 32 : (v.P + 15) / 16; }
 
@@ -1985,7 +2010,7 @@ int64_t reg_blocks(const ModeView& v, int mode) { return mode == 0 ? v.P * v.S /
 // bound the partial buffer is sized for
 void gram_reg(const float* x, const ModeView& v, int mode, const double* U, int R, double* part, double* G,
               hipStream_t s) {
-  const int ti = ((int)((v.m + 15) / 16) + 1) & ~1;
+  const int ti = reg_tiles(v.m);
   const int rt = (R + 15) / 16;
   const int64_t nblk = reg_blocks(v, mode);
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(512, (nblk + 3) / 4));
@@ -2027,7 +2052,7 @@ void gram_reg(const float* x, const ModeView& v, int mode, const double* U, int 
 // projection.
 void gram_reg64(const float* x, const ModeView& v, int mode, const double* U, int R, double* part, double* G,
                 hipStream_t s) {
-  const int ti = ((int)((v.m + 15) / 16) + 1) & ~1;
+  const int ti = reg_tiles(v.m);
   const int rt = R > 0 ? (R + 15) / 16 : 1;
   const int64_t nblk = reg_blocks(v, mode);
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(512, (nblk + 3) / 4));
@@ -2230,7 +2255,7 @@ bool ttm_reg64_applies(Elem t, const ModeView& v, int R) {
 template <typename T, bool NN>
 void launch_ttm_reg64(const T* x, const ModeView& v, const double* U, int R, double* Z, double* norm_part,
                       double* norm_out, double fl, double by, hipStream_t s) {
-  const int ti = ((int)((v.m + 15) / 16) + 1) & ~1;  // 2, 4, 6 or 8 row tiles
+  const int ti = reg_tiles(v.m);
   const int nrt = (R + 15) / 16;
   const int64_t nblk = v.P * v.S / 32;
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kTtmMaxBlocks, (nblk + 3) / 4));
@@ -2239,6 +2264,7 @@ void launch_ttm_reg64(const T* x, const ModeView& v, const double* U, int R, dou
     ProfScope prof(KKind::TtmContractReg64, s, fl, by);
     switch (ti) {
       case 2: ttm_reg64_kernel<T, 2, NN><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part); break;
+      case 3: ttm_reg64_kernel<T, 3, NN><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part); break;
       case 4: ttm_reg64_kernel<T, 4, NN><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part); break;
       case 6: ttm_reg64_kernel<T, 6, NN><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part); break;
       default: ttm_reg64_kernel<T, 8, NN><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, U, R, Z, norm_part); break;
@@ -2324,7 +2350,7 @@ template <bool NN, bool RR>
 void launch_ttm_reg(const float* x, const ModeView& v, int mode, const double* U, int R, float* Z,
                     double* norm_part, double* norm_out, double* res_part, double* res_out, double fl, double by,
                     hipStream_t s) {
-  const int ti = ((int)((v.m + 15) / 16) + 1) & ~1;  // 2, 4, 6 or 8 row tiles
+  const int ti = reg_tiles(v.m);
   const int rt = (R + 15) / 16;
   const int64_t nblk = reg_blocks(v, mode);
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kRegMaxBlocks, (nblk + 3) / 4));

@@ -46,7 +46,10 @@ def test_gram(P, m, S, dtype):
 @pytest.mark.parametrize("P,m,S,R", [(3, 96, 1000, 12), (5, 9, 7, 3), (100, 16, 1, 5), (2, 128, 33, 64), (7, 17, 5, 1),
                                      (4, 64, 300, 16), (50, 40, 2, 20), (1, 96, 31, 47),
                                      (3, 96, 1024, 12), (2, 128, 64, 64), (5, 40, 96, 20), (2, 96, 288, 47),
-                                     (100, 96, 3, 14), (37, 64, 1, 5), (50, 48, 2, 20), (19, 96, 4, 32)])
+                                     (100, 96, 3, 14), (37, 64, 1, 5), (50, 48, 2, 20), (19, 96, 4, 32),
+                                     # three row tiles (33-48 rows): per-tile wave ownership of the FP64 Gram
+                                     (4, 48, 2048, 18), (3, 44, 64, 40), (2, 48, 96, 47), (37, 48, 1, 5),
+                                     (21, 36, 3, 17), (19, 48, 4, 30)])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_resid_gram(P, m, S, R, dtype):
     g = rng(P * 7 + m + S + R)
@@ -63,11 +66,14 @@ def test_resid_gram(P, m, S, R, dtype):
                                      (1, 130, 40, 17), (7, 17, 5, 1), (4, 64, 300, 16), (50, 9, 1, 9),
                                      # column runs in whole blocks of 32, m % 4 == 0: register-direct FP64
                                      (3, 96, 1024, 12), (2, 128, 64, 64), (5, 40, 96, 20), (2, 96, 288, 47),
-                                     (64, 8, 16384, 3), (3, 4, 32, 1),
+                                     (64, 8, 16384, 3), (3, 4, 32, 1), (4, 48, 2048, 18), (3, 44, 64, 40),
                                      # modes of more than 128 rows: U staged once, or in chunks (m = 600)
                                      (16, 182, 42, 40), (3, 600, 50, 40), (2, 131, 1, 64),
-                                     # small modes: one column per thread
-                                     (5824, 42, 1, 30), (1000, 3, 1, 3), (3, 47, 9, 47)])
+                                     # LDS-panel kernel (42 and 47 rows, runs not in blocks of 32)
+                                     (5824, 42, 1, 30), (3, 47, 9, 47),
+                                     # modes of at most 8 rows: one column per thread (S > 1 with
+                                     # 33 columns, outside the register kernel's blocks of 32)
+                                     (1000, 3, 1, 3), (7, 5, 33, 4)])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_ttm_contract(P, m, S, R, dtype):
     g = rng(P + m + S + R)
@@ -92,8 +98,12 @@ MIXED_SHAPES = [(3, 96, 1000, 12), (5, 9, 7, 3), (100, 16, 1, 5), (2, 128, 33, 6
                 (64, 8, 16384, 3),
                 # runs of 1-4 columns: 16 slabs per register block (partial last block, several per wave)
                 (100, 96, 3, 14), (37, 64, 1, 5), (50, 48, 2, 20), (19, 96, 4, 32), (300000, 40, 1, 3),
-                # modes of at most 48 rows outside the register kernels: one column per thread
-                (5824, 42, 1, 30), (220000, 3, 1, 3), (33, 47, 5, 47), (3000, 1, 2, 1)]
+                # three row tiles (33-48 rows), runs in blocks of 32 and short runs
+                (4, 48, 2048, 18), (3, 44, 64, 40), (2, 48, 96, 47), (37, 48, 1, 5), (21, 36, 3, 17),
+                (19, 48, 4, 30),
+                # outside the register kernels: the LDS-panel kernel (42 and 47 rows) and one
+                # column per thread (modes of at most 8 rows)
+                (5824, 42, 1, 30), (33, 47, 5, 47), (220000, 3, 1, 3), (3000, 1, 2, 1)]
 
 
 def near_subspace(P, m, S, R, seed, dtype=np.float32):
