@@ -422,21 +422,32 @@ def run_many(count=64, cap=1 << 20):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         ranks = [st.ranks() for st in sts]
+        # untimed: every batch of every stream within its error bound (HT-RISE theorem)
+        worst = 0.0
+        for st, ys, sp in zip(sts, data, specs):
+            rec = st.reconstruct()
+            for k in range(nb):
+                yk = ys[k].double()
+                e = (torch.linalg.vector_norm(rec[k * sp.N:(k + 1) * sp.N] - yk) / torch.linalg.vector_norm(yk)).item()
+                worst = max(worst, e)
+            del rec
         for st in sts:
             st.close()
-        return upd_elems / dt, dt, ranks
+        return upd_elems / dt, dt, ranks, worst
 
     one(H.HT_FP64, False)  # warm-up: first launches of every kernel shape
     res = {}
     for name, prec, batched in (("fp64_one_by_one", H.HT_FP64, False), ("fp64_batched", H.HT_FP64, True),
                                 ("mixed_one_by_one", H.HT_FP32, False), ("mixed_batched", H.HT_FP32, True)):
-        v, dt, ranks = one(prec, batched)
-        res[name] = {"elements_per_s": v, "seconds": dt, "ranks": ranks}
-        log("many streams %s: %.3e elements/s (%.3f s)" % (name, v, dt))
+        v, dt, ranks, worst = one(prec, batched)
+        res[name] = {"elements_per_s": v, "seconds": dt, "ranks": ranks, "worst": worst}
+        log("many streams %s: %.3e elements/s (%.3f s), worst batch error %.3e" % (name, v, dt, worst))
     same = all(res[k]["ranks"] == res["fp64_one_by_one"]["ranks"] for k in res)
+    worst = max(r["worst"] for r in res.values())
     out = {"workload": "%d exact-rank streams (d 3-4, n_i 16-128, N 4-32, <= %d elements per batch), "
                        "10 HT-RISE updates each, eps=1e-4" % (count, cap),
-           "update_elements": upd_elems, "ranks_agree_across_runs": bool(same)}
+           "update_elements": upd_elems, "ranks_agree_across_runs": bool(same),
+           "worst_batch_rel_error": worst, "error_bound_holds": bool(worst <= EPS * (1 + BOUND_SLACK))}
     for k, v in res.items():
         out[k] = v["elements_per_s"]
     out["mixed_batched_over_fp64_one_by_one"] = res["mixed_batched"]["elements_per_s"] / res["fp64_one_by_one"][

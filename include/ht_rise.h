@@ -21,7 +21,8 @@
  *   first, which the paper allows (Sec. 3.1 footnote on the batch position).
  *   Element type is cfg->in_dtype (float32 or float64).
  * Dimension tree.  Balanced binary tree, depth ceil(log2 d), the first half of a
- *   node's modes (ceil(q/2) of them) going to its first successor (Sec. 2.3).
+ *   node's modes (ceil(q/2) of them) going to its first successor (Sec. 2.3), unless
+ *   cfg->tree_parent gives another binary tree over runs of consecutive modes.
  *   Nodes are numbered layer by layer from the root, left to right; the HT rank
  *   vector R = [r_{1,1}, r_{1,2}, r_{2,1}, ...] (Sec. 2.3) lists the 2d-2 non-root
  *   nodes in that order.
@@ -39,8 +40,10 @@
  * Errors.  Every entry point returns an ht_status.  Argument errors are detected
  *   before any work is enqueued and leave the handle unchanged.  A device-side
  *   failure inside an update (rank capacity exceeded, a non-finite norm) rolls
- *   the handle back to its state before the call.  ht_last_error() returns a
- *   human-readable message for the calling thread's last failure.
+ *   the handle back to its state before the call; so does a HIP runtime error
+ *   met during an update (HT_EDEVICE), as far as the device still executes the
+ *   restoring copies.  ht_last_error() returns a human-readable message for the
+ *   calling thread's last failure.
  */
 #ifndef HT_RISE_H
 #define HT_RISE_H
@@ -100,6 +103,15 @@ typedef struct {
   int32_t prec;           /* ht_precision                                                */
   int32_t in_dtype;       /* ht_dtype of Y                                               */
   uint64_t flags;         /* bitwise or of ht_flags (0: none)                            */
+  const int32_t* tree_parent; /* NULL: the balanced tree below; else the dimension tree
+                             (Sec. 2.3) as 2d-1 parent indices (copied at init):
+                             tree_parent[0] = -1 is the root, every other node's parent
+                             precedes it, every inner node has two successors (the
+                             lower index first), and the nodes are numbered layer by
+                             layer, left to right; the leaves, read left to right, are
+                             modes 0..d-1, so every node holds a run of consecutive
+                             modes.  Any other array is HT_EINVAL.  The rank vector
+                             follows this numbering.                                   */
 } ht_config;
 
 /* Option bits of ht_config.flags.
@@ -185,7 +197,8 @@ ht_status ht_rise_update(ht_handle h, const void* Y, int64_t N, void* hip_stream
  * whole call.  Argument errors are returned before any work, leaving every handle
  * unchanged.  A handle whose update fails (HT_ERANKCAP, HT_ENUMERIC) is rolled
  * back alone, its infos[i].status says why, the others commit, and the call
- * returns the first failing handle's status.  A handle may appear once. */
+ * returns the first failing handle's status.  A HIP runtime error during the call
+ * rolls every handle back and returns HT_EDEVICE.  A handle may appear once. */
 ht_status ht_rise_update_many(ht_handle* hs, const void* const* Ys, const int64_t* Ns, int32_t count,
                               void* hip_stream, ht_update_info* infos);
 

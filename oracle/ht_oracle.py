@@ -10,7 +10,8 @@ notation:
 
 * dimension tree: balanced binary tree, depth ceil(log2 d), leaves on the last
   two layers (Sec. 2.3, "Hierarchical Tucker Format"); the first half of a node's
-  modes gets ceil(q/2) of them;
+  modes gets ceil(q/2) of them; or any binary tree over runs of consecutive modes
+  given by its parent array;
 * BHT-l2r: Algorithm 1 (Sec. 3.1) - HOSVD layer by layer from the leaves, the
   batch mode kept intact and absorbed into the root;
 * HT-RISE: Algorithm 2 (Sec. 3.2) - Step 1 projection and the skip test
@@ -92,15 +93,19 @@ class Node:
 
 
 class DimTree:
-    """Balanced binary dimension tree over d modes.
+    """Binary dimension tree over d modes (Sec. 2.3).
 
-    A node over q > 1 modes has two successors: the first ceil(q/2) modes and the
-    rest.  Successor order follows position within the layer.  Nodes are numbered
-    layer by layer from the root, left to right, so ``nodes[1:]`` is the order of
-    the HT rank vector R = [r_{1,1}, r_{1,2}, r_{2,1}, ...].
+    By default balanced: a node over q > 1 modes has two successors, the first
+    ceil(q/2) modes and the rest.  Any other binary tree whose nodes hold runs of
+    consecutive modes can be given as ``parent`` (2d - 1 entries, -1 for the root):
+    a node's successors are the nodes naming it as parent, the lower index first,
+    and the leaves, read left to right, are modes 0 .. d-1.  Either way nodes are
+    numbered layer by layer from the root, left to right (``parent`` must already be
+    in that order), so ``nodes[1:]`` is the order of the HT rank vector
+    R = [r_{1,1}, r_{1,2}, r_{2,1}, ...].
     """
 
-    def __init__(self, d: int):
+    def __init__(self, d: int, parent: Optional[Sequence[int]] = None):
         if d < 2:
             raise ValueError("a dimension tree needs d >= 2")
         self.d = d
@@ -114,7 +119,10 @@ class DimTree:
                 build(lo, mid, layer + 1, me, 0)
                 build(mid, hi, layer + 1, me, 1)
 
-        build(0, d, 0, -1, -1)
+        if parent is None:
+            build(0, d, 0, -1, -1)
+        else:
+            raw = self._from_parent(d, [int(p) for p in parent])
         order = sorted(range(len(raw)), key=lambda i: (raw[i][0], raw[i][1]))
         new_of = {old: new for new, old in enumerate(order)}
         self.nodes: List[Node] = []
@@ -129,6 +137,45 @@ class DimTree:
             ch.sort(key=lambda i: self.nodes[i].lo)
             self.nodes[p_idx].children = tuple(ch)
         self.depth = max(nd.layer for nd in self.nodes)
+
+    @staticmethod
+    def _from_parent(d: int, parent: List[int]) -> List[Tuple[int, int, int, int, int]]:
+        """(layer, lo, hi, parent, pos) per node of a tree given by its parent array."""
+        if len(parent) != 2 * d - 1 or parent[0] != -1:
+            raise ValueError("a tree over d modes has 2d - 1 nodes, node 0 the root (parent -1)")
+        kids: List[List[int]] = [[] for _ in parent]
+        for i in range(1, len(parent)):
+            if not 0 <= parent[i] < i:
+                raise ValueError("every node's parent must precede it")
+            kids[parent[i]].append(i)
+        if any(len(k) not in (0, 2) for k in kids):
+            raise ValueError("every inner node needs exactly two successors")
+        lo = [0] * len(parent)
+        hi = [0] * len(parent)
+        layer = [0] * len(parent)
+        nxt = [0]
+
+        def walk(i):
+            if not kids[i]:
+                lo[i], hi[i] = nxt[0], nxt[0] + 1
+                nxt[0] += 1
+                return
+            for c in kids[i]:
+                layer[c] = layer[i] + 1
+                walk(c)
+            lo[i], hi[i] = lo[kids[i][0]], hi[kids[i][1]]
+
+        walk(0)
+        if nxt[0] != d:
+            raise ValueError("the tree must have d leaves")
+        key = [(layer[i], lo[i]) for i in range(len(parent))]
+        if key != sorted(key):
+            raise ValueError("nodes must be numbered layer by layer, left to right")
+        pos = [-1] + [kids[parent[i]].index(i) for i in range(1, len(parent))]
+        return [(layer[i], lo[i], hi[i], parent[i], pos[i]) for i in range(len(parent))]
+
+    def parents(self) -> List[int]:
+        return [nd.parent for nd in self.nodes]
 
     def layer(self, ell: int) -> List[Node]:
         return [nd for nd in self.nodes if nd.layer == ell]

@@ -51,8 +51,9 @@ ht_status fail(ht_status st, const std::string& msg) {
   } while (0)
 
 // --------------------------------------------------------------------------
-// Dimension tree: balanced, first half of a node's modes to its first successor
-// (Sec. 2.3); nodes numbered layer by layer, left to right.
+// Dimension tree (Sec. 2.3): balanced, the first half of a node's modes to its first
+// successor, or any binary tree over runs of consecutive modes given by a parent
+// array; nodes numbered layer by layer, left to right.
 // --------------------------------------------------------------------------
 struct TNode {
   int layer = 0, lo = 0, hi = 0, parent = -1, child[2] = {-1, -1}, child_pos = -1;
@@ -104,6 +105,64 @@ struct Tree {
       const int p = nodes[i].parent;
       if (p >= 0) nodes[p].child[nodes[i].child_pos] = (int)i;
     }
+  }
+
+  // The tree of a parent array (2d - 1 entries, parent[0] = -1, numbered layer by layer
+  // from the root, left to right): a node's successors are the nodes naming it, the
+  // lower index first; the leaves, read left to right, are modes 0 .. d-1.
+  bool from_parent(int d_, const int32_t* parent, std::string& why) {
+    d = d_;
+    const int nn = 2 * d - 1;
+    if (parent[0] != -1) return why = "tree_parent[0] must be -1 (the root)", false;
+    nodes.assign(nn, TNode());
+    for (int i = 1; i < nn; ++i) {
+      const int p = parent[i];
+      if (p < 0 || p >= i) return why = "tree_parent: every node's parent must precede it", false;
+      TNode& q = nodes[p];
+      if (q.child[1] >= 0) return why = "tree_parent: a node has more than two successors", false;
+      q.child[q.child[0] < 0 ? 0 : 1] = i;
+      nodes[i].parent = p;
+      nodes[i].child_pos = q.child[1] == i ? 1 : 0;
+    }
+    for (int i = 0; i < nn; ++i)
+      if (nodes[i].child[0] >= 0 && nodes[i].child[1] < 0)
+        return why = "tree_parent: an inner node has a single successor", false;
+    // layers and mode runs by a walk from the root, leaves numbered left to right
+    int next = 0;
+    std::vector<int> stack{0};
+    std::vector<int> order;
+    while (!stack.empty()) {
+      const int i = stack.back();
+      stack.pop_back();
+      order.push_back(i);
+      if (!nodes[i].leaf()) {
+        for (int c : {nodes[i].child[1], nodes[i].child[0]}) {
+          nodes[c].layer = nodes[i].layer + 1;
+          stack.push_back(c);
+        }
+      }
+    }
+    for (int i : order)
+      if (nodes[i].leaf()) {
+        nodes[i].lo = next;
+        nodes[i].hi = ++next;
+      }
+    if (next != d) return why = "tree_parent must describe a tree with d leaves", false;
+    for (auto it = order.rbegin(); it != order.rend(); ++it) {
+      TNode& t = nodes[*it];
+      if (!t.leaf()) {
+        t.lo = nodes[t.child[0]].lo;
+        t.hi = nodes[t.child[1]].hi;
+      }
+    }
+    depth = 0;
+    for (int i = 0; i < nn; ++i) {
+      depth = std::max(depth, nodes[i].layer);
+      if (i > 0 && (nodes[i].layer < nodes[i - 1].layer ||
+                    (nodes[i].layer == nodes[i - 1].layer && nodes[i].lo < nodes[i - 1].lo)))
+        return why = "tree_parent must number the nodes layer by layer, left to right", false;
+    }
+    return true;
   }
 
   // modes of the level tensor entering layer ell, in mode order
@@ -325,7 +384,20 @@ bool valid_config(const ht_config* c, std::string& why) {
   if (c->in_dtype != HT_F32 && c->in_dtype != HT_F64) return why = "in_dtype must be HT_F32 or HT_F64", false;
   if ((c->flags & ~(uint64_t)(HT_ADAPTIVE_BUDGET | HT_PLAIN_HT_BUDGET | HT_ST_HOSVD)) != 0)
     return why = "unknown bits in flags", false;
+  if (c->tree_parent != nullptr) {
+    Tree t;
+    if (!t.from_parent(c->d, c->tree_parent, why)) return false;
+  }
   return true;
+}
+
+// the configuration's dimension tree (balanced without tree_parent)
+bool make_tree(const ht_config* c, Tree& t, std::string& why) {
+  if (c->tree_parent == nullptr) {
+    t.build(c->d);
+    return true;
+  }
+  return t.from_parent(c->d, c->tree_parent, why);
 }
 
 Layout make_layout(const ht_config* c, const Tree& tree, std::vector<int64_t>& alpha_cap, std::vector<int>& rc) {
@@ -836,7 +908,7 @@ ht_status setup_handle(const ht_config* cfg, void* ws, size_t ws_bytes, ht_state
   h->n_cap = cfg->n_cap;
   h->in_t = cfg->in_dtype == HT_F32 ? Elem::F32 : Elem::F64;
   h->mixed = cfg->prec == HT_FP32;
-  h->tree.build(cfg->d);
+  make_tree(cfg, h->tree, why);
   Layout L = make_layout(cfg, h->tree, h->alpha_cap, h->rc);
   h->mixed_ok = h->mixed && fp32_gate(h->eps, h->d, h->rc);
   h->adaptive = (cfg->flags & HT_ADAPTIVE_BUDGET) != 0;
@@ -946,6 +1018,7 @@ struct Upd {
   double lost2 = 0, lost_err = 0, thr_err = 0;  // adaptive budget: error so far and its FP32 bound
   double chain_extra = 0;  // ST-HOSVD: FP32 contractions of this layer before the current node
   bool skip = false, busy = false;
+  bool began = false;  // started an update in this call (its cores were backed up)
   bool mixed = false;  // this pass runs the FP32 kernels
   bool redo = false;   // an FP32 decision could not be certified: the call runs again in FP64
   int growth = 0;
@@ -1121,6 +1194,7 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
       ht::root_append(u.c1.ptr, u.c1.t, u.N, r11, r12, h->root, h->n_acc, h->rank_cap, s);
     } else {
       u.busy = true;
+      u.began = true;
       u.saved = h->rank;
       backup_cores(h, s);
       const double eps_nw = u.eps_des / std::sqrt((double)h->shares);
@@ -1312,6 +1386,22 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
   return HT_OK;
 }
 
+// A failure inside a pass (a HIP error, a failed read-back): every handle that began an
+// update in this call gets its cores and ranks back (the root slices past n_acc are not
+// part of it yet), so the call leaves every handle as it was and returns the failure.
+ht_status abandon_call(std::vector<Upd>& U, hipStream_t s, ht_status st) {
+  const std::string err = g_last_error;
+  for (Upd& u : U)
+    if (u.began) {
+      restore_cores(u.h, s);
+      u.h->rank = u.saved;
+      u.busy = false;
+    }
+  (void)hipStreamSynchronize(s);
+  g_last_error = err;
+  return st;
+}
+
 ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* Ns, int count, hipStream_t s,
                     ht_update_info* infos) {
   std::vector<Upd> U(count);
@@ -1332,7 +1422,7 @@ ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* N
   std::vector<Upd*> act;
   for (Upd& u : U) act.push_back(&u);
   ht_status st = rise_pass(act, s);
-  if (st != HT_OK) return st;
+  if (st != HT_OK) return abandon_call(U, s, st);
   // ---- handles whose FP32 decisions were not certified: the whole call in FP64
   act.clear();
   for (Upd& u : U)
@@ -1346,7 +1436,7 @@ ht_status rise_many(ht_state* const* hs, const void* const* Ys, const int64_t* N
     }
   if (!act.empty()) {
     st = rise_pass(act, s);
-    if (st != HT_OK) return st;
+    if (st != HT_OK) return abandon_call(U, s, st);
   }
   const float ms = timer.stop();
   ht_status first = HT_OK;
@@ -1402,7 +1492,7 @@ ht_status ht_workspace_bytes(const ht_config* cfg, size_t* bytes) {
   if (bytes == nullptr) return fail(HT_EINVAL, "bytes is NULL");
   if (!valid_config(cfg, why)) return fail(HT_EINVAL, why);
   Tree t;
-  t.build(cfg->d);
+  make_tree(cfg, t, why);
   std::vector<int64_t> ac;
   std::vector<int> rc;
   *bytes = make_layout(cfg, t, ac, rc).total;
@@ -1414,7 +1504,7 @@ ht_status ht_update_precision(const ht_config* cfg, int32_t* prec) {
   if (prec == nullptr) return fail(HT_EINVAL, "prec is NULL");
   if (!valid_config(cfg, why)) return fail(HT_EINVAL, why);
   Tree t;
-  t.build(cfg->d);
+  make_tree(cfg, t, why);
   std::vector<int64_t> ac;
   std::vector<int> rc;
   capacities(t, std::vector<int64_t>(cfg->n, cfg->n + cfg->d), cfg->rank_cap, ac, rc);

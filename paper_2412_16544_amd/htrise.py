@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "HT_OK", 1: "HT_EINVAL", 2: "HT_ESHAPE", 3: "HT_ENOMEM", 4: "
 class ht_config(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("n", ctypes.POINTER(ctypes.c_int64)), ("eps_rel", ctypes.c_double),
                 ("rank_cap", ctypes.c_int32), ("max_batch", ctypes.c_int64), ("n_cap", ctypes.c_int64),
-                ("prec", ctypes.c_int32), ("in_dtype", ctypes.c_int32), ("flags", ctypes.c_uint64)]
+                ("prec", ctypes.c_int32), ("in_dtype", ctypes.c_int32), ("flags", ctypes.c_uint64),
+                ("tree_parent", ctypes.POINTER(ctypes.c_int32))]
 
 
 class ht_update_info(ctypes.Structure):
@@ -88,11 +89,14 @@ def _check(st: int, where: str) -> None:
 
 
 def make_config(n: Sequence[int], eps: float, rank_cap: int, max_batch: int, n_cap: int,
-                prec: int = HT_FP64, in_dtype: int = HT_F32, flags: int = 0) -> Tuple[ht_config, object]:
+                prec: int = HT_FP64, in_dtype: int = HT_F32, flags: int = 0,
+                tree_parent: Optional[Sequence[int]] = None) -> Tuple[ht_config, object]:
     arr = (ctypes.c_int64 * len(n))(*[int(x) for x in n])
+    par = None if tree_parent is None else (ctypes.c_int32 * len(tree_parent))(*[int(x) for x in tree_parent])
     cfg = ht_config(len(n), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int64)), float(eps), int(rank_cap),
-                    int(max_batch), int(n_cap), int(prec), int(in_dtype), int(flags))
-    return cfg, arr  # keep arr alive with cfg
+                    int(max_batch), int(n_cap), int(prec), int(in_dtype), int(flags),
+                    None if par is None else ctypes.cast(par, ctypes.POINTER(ctypes.c_int32)))
+    return cfg, (arr, par)  # keep the arrays alive with cfg
 
 
 def _ptr(t) -> int:
@@ -225,13 +229,14 @@ class HTStream:
     """One tensor stream in batch-HT form: the workspace tensor plus the library handle."""
 
     def __init__(self, n: Sequence[int], eps: float, rank_cap: int, max_batch: int, n_cap: int,
-                 in_dtype: str = "float32", prec: int = HT_FP64, device: str = "cuda:0", flags: int = 0):
+                 in_dtype: str = "float32", prec: int = HT_FP64, device: str = "cuda:0", flags: int = 0,
+                 tree_parent: Optional[Sequence[int]] = None):
         import torch
         self.n = tuple(int(x) for x in n)
         self.d = len(self.n)
         self.device = torch.device(device)
         self._cfg, self._keep = make_config(self.n, eps, rank_cap, max_batch, n_cap, prec,
-                                            HT_F32 if in_dtype == "float32" else HT_F64, flags)
+                                            HT_F32 if in_dtype == "float32" else HT_F64, flags, tree_parent)
         self.ws_bytes = ht_workspace_bytes(self._cfg)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.h = 0

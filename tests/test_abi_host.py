@@ -81,6 +81,35 @@ def test_invalid_configs_rejected(kw):
     assert H.lib().ht_last_error().decode()
 
 
+def _ws_tree(n, parent):
+    cfg, keep = H.make_config(n, 1e-4, 16, 4, 16, tree_parent=parent)
+    return H.ht_workspace_bytes(cfg)
+
+
+@pytest.mark.parametrize("n,parent", [((8, 8, 8, 8), [-1, 0, 0, 1, 1, 3, 3]), ((8, 8, 8, 8), [-1, 0, 0, 2, 2, 4, 4]),
+                                      ((6, 6, 6, 6, 6), [-1, 0, 0, 2, 2, 3, 3, 4, 4]), ((5, 7), [-1, 0, 0])])
+def test_tree_parent_accepted(n, parent):
+    assert _ws_tree(n, parent) > 0
+
+
+def test_tree_parent_of_the_balanced_tree_sizes_like_the_default():
+    # the balanced tree written out: same capacities, same workspace
+    assert _ws_tree((8, 9, 10, 11, 12), [-1, 0, 0, 1, 1, 2, 2, 3, 3]) == _ws_tree((8, 9, 10, 11, 12), None)
+
+
+@pytest.mark.parametrize("parent", [[-1, 0, 0, 0, 1, 1, 2],      # three successors of the root
+                                    [-1, 0, 0, 1, 1, 1, 1],      # four successors of node 1
+                                    [-1, 0, 0, 2, 2, 1, 1],      # not layer by layer, left to right
+                                    [0, 0, 0, 1, 1, 2, 2],       # no root
+                                    [-1, 0, 0, 3, 3, 4, 4],      # a parent after its successor
+                                    [-1, 0, 2, 1, 1, 2, 2]])     # a node naming a later parent
+def test_invalid_tree_parent_rejected(parent):
+    with pytest.raises(H.HTError) as e:
+        _ws_tree((8, 8, 8, 8), parent)
+    assert e.value.status == H.HT_EINVAL
+    assert "tree_parent" in H.lib().ht_last_error().decode()
+
+
 def test_null_arguments_rejected_before_device_work():
     L = H.lib()
     cfg, keep = H.make_config((4, 4), 1e-3, 4, 2, 4)

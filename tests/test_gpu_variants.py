@@ -1,5 +1,6 @@
 """GPU (MI355X) parity of the method's variants with the oracle's: ST-HOSVD within a
-layer (HT_ST_HOSVD, the footnote of Sec. 2.3.1).  Ranks and skips equal the oracle's
+layer (HT_ST_HOSVD, the footnote of Sec. 2.3.1) and dimension trees other than the
+balanced one (ht_config.tree_parent, Sec. 2.3).  Ranks and skips equal the oracle's
 at every batch, reconstructions match (FP64 1e-10, mixed 5e-6 of ||Y||), every batch
 meets its error bound; the closed forms of the oracle pins (a node that keeps fewer
 directions on its predecessors' contracted tensor) hold in both forms."""
@@ -29,9 +30,12 @@ def dev(y):
     return torch.from_numpy(np.ascontiguousarray(y)).to("cuda:0")
 
 
-def check(ys, eps, prec, tol, slack, flags, oracle_kw, tree=None):
+def check(ys, eps, prec, tol, slack, flags, oracle_kw, tree_parent=None):
     N = max(y.shape[0] for y in ys)
-    st = H.HTStream(ys[0].shape[1:], eps, 64, N, sum(y.shape[0] for y in ys), prec=prec, flags=flags)
+    st = H.HTStream(ys[0].shape[1:], eps, 64, N, sum(y.shape[0] for y in ys), prec=prec, flags=flags,
+                    tree_parent=tree_parent)
+    d = ys[0].ndim - 1
+    tree = None if tree_parent is None else ho.DimTree(d, parent=tree_parent)
     ost = ho.BHT(ys[0].shape[1:], eps, tree=tree, **oracle_kw)
     for k, y in enumerate(ys):
         info = st.push(dev(y))
@@ -86,3 +90,34 @@ def test_st_hosvd_with_adaptive_budget_d5(prec, tol, slack):
                                grow_at=(2,), grow_by=1, grow_scale=0.1)
     check(list(datagen.ht_model_stream(spec)), 1e-4, prec, tol, slack,
           flags=H.HT_ST_HOSVD | H.HT_ADAPTIVE_BUDGET, oracle_kw=dict(st_hosvd=True, adaptive=True))
+
+
+# unbalanced trees over runs of consecutive modes (numbered layer by layer, left to right)
+TREES4 = [[-1, 0, 0, 1, 1, 3, 3], [-1, 0, 0, 2, 2, 4, 4]]
+TREE5 = [-1, 0, 0, 2, 2, 3, 3, 4, 4]
+PLAIN = dict(flags=0, oracle_kw={})
+
+
+@pytest.mark.parametrize("prec,tol,slack", FORMS)
+@pytest.mark.parametrize("parent", TREES4)
+def test_other_trees_tiny_stream(prec, tol, slack, parent):
+    st, _ = check(datagen.tiny_stream(), 1e-4, prec, tol, slack, tree_parent=parent, **PLAIN)
+    assert st.ranks()[0] != [8] * 6   # not the generating (balanced) tree's ranks
+
+
+@pytest.mark.parametrize("prec,tol,slack", FORMS)
+@pytest.mark.parametrize("parent", TREES4)
+def test_other_trees_small_field_stream(prec, tol, slack, parent):
+    spec = datagen.FieldSpec(grid=(24, 24, 24), channels=3, terms=6, N=8, n_batches=8, drift=2e-3, seed=9,
+                             batch_seed0=900, nu=0.0, w_lo=0.2, w_hi=0.5)
+    check(list(datagen.exact_field_stream(spec)), 1e-4, prec, tol, slack, tree_parent=parent, **PLAIN)
+
+
+@pytest.mark.parametrize("prec,tol,slack", FORMS)
+def test_other_tree_d5_with_variants(prec, tol, slack):
+    spec = datagen.HTModelSpec(n=(8, 9, 8, 7, 8), rank=3, N=4, n_batches=6, seed=77, batch_seed0=7700, nu=1e-6,
+                               grow_at=(3, 4), grow_by=2, grow_scale=0.1)
+    ys = list(datagen.ht_model_stream(spec))
+    check(ys, 1e-4, prec, tol, slack, tree_parent=TREE5, **PLAIN)
+    check(ys, 1e-4, prec, tol, slack, tree_parent=TREE5, flags=H.HT_ST_HOSVD | H.HT_ADAPTIVE_BUDGET,
+          oracle_kw=dict(st_hosvd=True, adaptive=True))

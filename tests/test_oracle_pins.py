@@ -50,6 +50,57 @@ def test_tree_d5_and_d3_groupings():
     assert [(nd.layer, nd.lo + 1, nd.hi) for nd in t3.nodes] == [(0, 1, 3), (1, 1, 2), (1, 3, 3), (2, 1, 1), (2, 2, 2)]
 
 
+# Trees given by a parent array: unbalanced shapes hold the same runs of modes as the
+# definition, and every node's rank on exact data is the rank of its unfolding (the
+# node's modes against the batch and all other modes), computed here directly.
+OTHER_TREES = {
+    4: [[-1, 0, 0, 1, 1, 3, 3],            # {1,2,3},{4} -> {1,2},{3} -> {1},{2}
+        [-1, 0, 0, 2, 2, 4, 4]],           # {1},{2,3,4} -> {2},{3,4} -> {3},{4}
+    5: [[-1, 0, 0, 2, 2, 3, 3, 4, 4]],     # {1},{2,3,4,5} -> {2,3},{4,5} -> leaves
+}
+
+
+def test_tree_from_parent_array():
+    t = ho.DimTree(4, parent=OTHER_TREES[4][1])
+    assert [(nd.layer, nd.lo + 1, nd.hi, nd.children) for nd in t.nodes] == [
+        (0, 1, 4, (1, 2)), (1, 1, 1, ()), (1, 2, 4, (3, 4)), (2, 2, 2, ()), (2, 3, 4, (5, 6)), (3, 3, 3, ()),
+        (3, 4, 4, ())]
+    for d in (2, 3, 4, 5, 6):
+        b = ho.DimTree(d)
+        assert ho.DimTree(d, parent=b.parents()).nodes == b.nodes
+    for bad in ([-1, 0, 0, 0, 1, 1, 2], [-1, 0, 0, 1, 1, 1, 1], [-1, 0, 0, 2, 2, 1, 1], [0, 0, 0, 1, 1, 2, 2],
+                [-1, 0, 0, 3, 3, 4, 4]):
+        with pytest.raises(ValueError):
+            ho.DimTree(4, parent=bad)
+
+
+def _unfolding_rank(y, nd):
+    """Rank of the batch's unfolding with the node's modes as rows (sample modes start at axis 1)."""
+    axes = list(range(1 + nd.lo, 1 + nd.hi))
+    rest = [a for a in range(y.ndim) if a not in axes]
+    m = np.transpose(y, axes + rest).reshape(int(np.prod([y.shape[a] for a in axes])), -1)
+    sv = np.linalg.svd(m.astype(np.float64), compute_uv=False)
+    return int(np.sum(sv > 1e-5 * sv[0]))
+
+
+@pytest.mark.parametrize("d,k", [(4, 0), (4, 1), (5, 0)])
+def test_other_trees_rank_is_the_unfolding_rank(d, k):
+    spec = datagen.HTModelSpec(n=(9, 8, 7, 6) if d == 4 else (5, 6, 5, 4, 5), rank=3, N=6, n_batches=1, seed=11 + d,
+                               batch_seed0=1100 + d, nu=0.0)
+    y = next(iter(datagen.ht_model_stream(spec)))
+    tree = ho.DimTree(d, parent=OTHER_TREES[d][k])
+    o = ho.BHT(y.shape[1:], 1e-6, tree=tree)
+    o.init_batch(y)
+    assert o.ranks == [_unfolding_rank(y, nd) for nd in tree.non_root]
+    # the balanced tree of the generating model gives its own ranks, not these
+    ob = ho.BHT(y.shape[1:], 1e-6)
+    ob.init_batch(y)
+    assert ob.ranks == [_unfolding_rank(y, nd) for nd in ob.tree.non_root]
+    assert ob.ranks != o.ranks
+    rec = o.reconstruct()
+    assert np.linalg.norm(rec - y) <= 1e-6 * np.linalg.norm(y)
+
+
 # --------------------------------------------------------------------------- #
 # Closed-form d = 2 case: BHT-l2r is a truncated HOSVD of the two sample modes
 # (Sec. 2.2 Tucker format; Eq. ht_leaf_svd) with the batch mode untouched.
