@@ -153,9 +153,11 @@ typedef struct {
   int32_t prec_used;      /* ht_precision of the contractions and Gram products that
                              produced the committed result (HT_FP64 when an HT_FP32
                              handle's call ran in FP64, see ht_precision)               */
-  int32_t recomputed;     /* HT_FP32: decisions taken again in FP64 because the FP32
-                             result could not be certified (a node's Gram, or the whole
-                             call, which counts one); 0 otherwise                       */
+  int32_t recomputed;     /* HT_FP32: decisions taken from FP64 residual Grams because
+                             an FP32 result could not be certified or its kept vectors
+                             would not be accurate enough (a node's Gram, taken in FP64
+                             directly when the skip test's energies already show it, or
+                             again; the whole call in FP64 counts one); 0 otherwise     */
 } ht_update_info;
 
 /* Bytes of device workspace a handle with this configuration needs.  Host only.

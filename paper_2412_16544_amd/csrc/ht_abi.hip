@@ -568,49 +568,71 @@ std::vector<int> contraction_order(const ht_state* h, int ell, const std::vector
 // the tensor is not merged (the ST-HOSVD steps of a layer); merge_level finishes it.
 Level merge_level(const ht_state* h, int ell, const Level& cur);
 
+// One contraction of a projection chain: frontier position k (node) of the level
+// tensor cur, into dst.  Mixed form (modes of at most 128 rows): FP32 products and an
+// FP32 result, with energy the explicit residual energy of the contraction; else FP64,
+// with energy the energies before and after it.  norm_out also takes ||X||^2.  With
+// group, a contraction that qualifies is added to it instead of being launched.
+void contract_one(const ht_state* h, Level& cur, int k, int node, double* dst, hipStream_t s, double* norm_out,
+                  bool mixed, double* energy, std::vector<char>* expl, std::vector<ht::TtmJob>* group = nullptr) {
+  const ModeView v = view_of(cur, k);
+  const bool grouped = group != nullptr && ht::ttm_groupable(v, h->rank[node]) &&
+                       (mixed ? v.m <= ht::kResidGramMaxM : energy == nullptr);
+  if (mixed && v.m <= ht::kResidGramMaxM) {
+    double* np = norm_out ? h->nrmpart : nullptr;
+    double* rp = energy ? h->respart + (size_t)node * res_stride() : nullptr;
+    double* ro = energy ? energy + 2 * node : nullptr;
+    if (grouped)
+      group->push_back(ht::TtmJob{cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, Elem::F32, np, norm_out, rp,
+                                  ro});
+    else
+      ht::ttm_contract_f32(cur.ptr, cur.t, v, h->core[node], h->rank[node], reinterpret_cast<float*>(dst), np,
+                           norm_out, rp, ro, s);
+    if (expl) (*expl)[node] = 1;
+    cur.ptr = dst;
+    cur.t = Elem::F32;
+  } else if (grouped) {
+    group->push_back(ht::TtmJob{cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, Elem::F64,
+                                norm_out ? h->nrmpart : nullptr, norm_out, nullptr, nullptr});
+    if (expl) (*expl)[node] = 0;
+    cur.ptr = dst;
+    cur.t = Elem::F64;
+  } else {
+    double* ssp = h->ssnode + (size_t)node * 2 * ht::kSumsqBlocks;
+    if (expl) (*expl)[node] = 0;
+    // the energies before and after the contraction, from the contraction itself
+    // where it can, else by two sums of squares
+    const bool fused = energy != nullptr && norm_out == nullptr &&
+                       ht::ttm_contract_sq(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, ssp,
+                                           energy + 2 * node, ssp + ht::kSumsqBlocks, energy + 2 * node + 1,
+                                           ht::kSumsqBlocks, s);
+    if (!fused) {
+      if (energy) ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), ssp, energy + 2 * node, s);
+      if (norm_out != nullptr)
+        ht::ttm_contract_norm(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, h->nrmpart, norm_out, s);
+      else
+        ht::ttm_contract(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, s);
+    }
+    cur.ptr = dst;
+    cur.t = Elem::F64;
+    if (energy && !fused) {
+      cur.modes[k] = h->rank[node];
+      ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), ssp + ht::kSumsqBlocks, energy + 2 * node + 1, s);
+    }
+  }
+  cur.modes[k] = h->rank[node];
+}
+
 Level project_layer(const ht_state* h, int ell, const Level& in, hipStream_t s, double* norm_out = nullptr,
                     bool mixed = false, double* energy = nullptr, std::vector<char>* expl = nullptr,
                     double* const* pp = nullptr, const std::vector<int>* only = nullptr) {
   const std::vector<int> f = h->tree.frontier(ell);
   Level cur = in;
   for (const int k : only ? *only : contraction_order(h, ell, in.modes)) {
-    const int node = f[k];
     // intermediates alternate between the handle's two level buffers, or the pair pp
     double* dst = pp ? (cur.ptr == pp[0] ? pp[1] : pp[0]) : other(h, cur.ptr);
-    const ModeView v = view_of(cur, k);
-    if (mixed && v.m <= ht::kResidGramMaxM) {
-      ht::ttm_contract_f32(cur.ptr, cur.t, v, h->core[node], h->rank[node], reinterpret_cast<float*>(dst),
-                           norm_out ? h->nrmpart : nullptr, norm_out,
-                           energy ? h->respart + (size_t)node * res_stride() : nullptr,
-                           energy ? energy + 2 * node : nullptr, s);
-      if (expl) (*expl)[node] = 1;
-      cur.ptr = dst;
-      cur.t = Elem::F32;
-    } else {
-      double* ssp = h->ssnode + (size_t)node * 2 * ht::kSumsqBlocks;
-      if (expl) (*expl)[node] = 0;
-      // the energies before and after the contraction, from the contraction itself
-      // where it can, else by two sums of squares
-      const bool fused = energy != nullptr && norm_out == nullptr &&
-                         ht::ttm_contract_sq(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, ssp,
-                                             energy + 2 * node, ssp + ht::kSumsqBlocks, energy + 2 * node + 1,
-                                             ht::kSumsqBlocks, s);
-      if (!fused) {
-        if (energy) ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), ssp, energy + 2 * node, s);
-        if (norm_out != nullptr)
-          ht::ttm_contract_norm(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, h->nrmpart, norm_out, s);
-        else
-          ht::ttm_contract(cur.ptr, cur.t, v, h->core[node], h->rank[node], dst, s);
-      }
-      cur.ptr = dst;
-      cur.t = Elem::F64;
-      if (energy && !fused) {
-        cur.modes[k] = h->rank[node];
-        ht::sumsq(cur.ptr, cur.t, (int64_t)cur.elems(), ssp + ht::kSumsqBlocks, energy + 2 * node + 1, s);
-      }
-    }
+    contract_one(h, cur, k, f[k], dst, s, norm_out, mixed, energy, expl);
     norm_out = nullptr;
-    cur.modes[k] = h->rank[node];
   }
   return only ? cur : merge_level(h, ell, cur);
 }
@@ -775,7 +797,7 @@ void node_gram(ht_state* h, int node, const Level& cur, const ModeView& v, int r
 }
 
 void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initial, bool mixed, hipStream_t s,
-                 LayerJobs& L, int only_k = -1) {
+                 LayerJobs& L, int only_k = -1, const std::vector<char>* fp64 = nullptr) {
   const std::vector<int> f = h->tree.frontier(ell);
   for (size_t k = 0; k < f.size(); ++k) {
     const int node = f[k];
@@ -787,7 +809,7 @@ void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initia
     if (alpha - r_old <= 0) continue;  // the basis already spans the whole mode
     // at the rank cap the decision still runs (rmax = 0) to detect a needed growth
     const int room = std::max(0, std::min(alpha, h->rank_cap) - r_old);
-    const bool f32 = mixed && r_old > 0 && v.m <= ht::kResidGramMaxM;
+    const bool f32 = mixed && r_old > 0 && v.m <= ht::kResidGramMaxM && !(fp64 && (*fp64)[node]);
     node_gram(h, node, cur, v, r_old, f32, s);
     L.f32.push_back(f32 ? 1 : 0);
     L.view.push_back(v);
@@ -1022,7 +1044,8 @@ struct Upd {
   bool mixed = false;  // this pass runs the FP32 kernels
   bool redo = false;   // an FP32 decision could not be certified: the call runs again in FP64
   int growth = 0;
-  int recomputed = 0;  // decisions taken again in FP64
+  int recomputed = 0;  // decisions taken from FP64 residual Grams (directly or again)
+  std::vector<double> e1;  // mixed form: each node's residual energy in the skip test
   ht_status st = HT_OK;
   std::string err;
   LayerJobs L;
@@ -1131,26 +1154,83 @@ void roll_back(Upd& u, hipStream_t s) {
 // One pass of HT-RISE over the handles in act (each with u.mixed set): Step 1 and
 // the skip tests, then the layers in lock step, then the root appends.  Handles
 // whose FP32 decisions cannot be certified come out with u.redo set and unchanged.
+// Mixed form: the nodes of layer ell whose residual Gram goes straight to FP64.  The
+// skip test's residual energy e of a node's contraction bounds the trace of its
+// residual Gram from below (it was taken on a tensor with less energy: the other
+// contractions of the layer before it and the old bases of the layers below, whose
+// coordinates the updated level tensor contains).  With e above twice the threshold
+// the node grows, and with 2 sqrt(e) dR above a hundredth of it the kept vectors of
+// an FP32 Gram would fail the accuracy criterion of certify_layer: its FP32 Gram would
+// only be taken again in FP64, which costs a second eigen launch and read-back.
+void fp64_nodes(const Upd& u, int ell, std::vector<char>& out) {
+  const ht_state* h = u.h;
+  out.assign(h->tree.nodes.size(), 0);
+  if (!u.mixed || u.e1.empty() || h->st_hosvd) return;  // (ST-HOSVD: no such bound)
+  const double chain = fp32_chain(h, ell) + u.chain_extra;
+  for (size_t node = 1; node < h->tree.nodes.size(); ++node) {
+    if (h->tree.nodes[node].layer != ell || h->rank[node] == 0) continue;
+    if (alpha_now(h, (int)node) > ht::kResidGramMaxM) continue;  // an FP64 Gram anyway
+    const double e = u.e1[node];
+    const double dR = resid_err(u.ny, h->rank[node] + 1.0, chain);
+    if (e > 2.0 * u.thr && 2.0 * std::sqrt(e) * dR > 0.01 * u.thr) out[node] = 1;
+  }
+}
+
 ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
   // ---- Step 1 for every handle: projection onto the existing cores; the first
   //      contraction also returns ||Y||^2 (mixed form: and the residual energies)
   //      The final sums of every handle's reductions run as one launch.
+  //      The chains advance in lock step, one contraction of every handle per step,
+  //      and the small contractions of a step go out as one grouped launch.
   {
     std::vector<ht::SumJob> sums;
     {
       const DeferSums defer(&sums);
+      struct Chain {
+        Upd* u;
+        Level cur;
+        int ell;
+        std::vector<int> order;
+        size_t pos;
+        double* norm_out;
+      };
+      std::vector<Chain> ch;
       for (Upd* up : act) {
         Upd& u = *up;
         ht_state* h = u.h;
         h->last_stream = s;
-        const int nn = (int)h->tree.nodes.size();
-        if (u.mixed) {
-          u.expl.assign(nn, 0);
-          u.c1 = project_all(h, u.Y, u.N, s, h->scal, true, h->scal + 8, &u.expl);
-        } else {
-          u.c1 = project_all(h, u.Y, u.N, s, h->scal);
-          ht::sumsq(u.c1.ptr, u.c1.t, (int64_t)u.c1.elems(), h->sspart, h->scal + 1, s);
+        if (u.mixed) u.expl.assign(h->tree.nodes.size(), 0);
+        Level cur{u.Y, h->in_t, u.N, h->n};
+        ch.push_back(Chain{&u, cur, h->tree.depth, contraction_order(h, h->tree.depth, cur.modes), 0, h->scal});
+      }
+      std::vector<ht::TtmJob> group;
+      for (bool more = true; more;) {
+        more = false;
+        group.clear();
+        for (Chain& c : ch) {
+          ht_state* h = c.u->h;
+          while (c.ell >= 1 && c.pos == c.order.size()) {  // layer done: merge, next layer
+            c.cur = merge_level(h, c.ell, c.cur);
+            if (--c.ell >= 1) {
+              c.order = contraction_order(h, c.ell, c.cur.modes);
+              c.pos = 0;
+            }
+          }
+          if (c.ell < 1) continue;
+          const int k = c.order[c.pos++];
+          const int node = h->tree.frontier(c.ell)[k];
+          Upd& u = *c.u;
+          contract_one(h, c.cur, k, node, other(h, c.cur.ptr), s, c.norm_out, u.mixed,
+                       u.mixed ? h->scal + 8 : nullptr, u.mixed ? &u.expl : nullptr, &group);
+          c.norm_out = nullptr;
+          more = true;
         }
+        if (!group.empty()) ht::ttm_group(group, s);
+      }
+      for (Chain& c : ch) {
+        Upd& u = *c.u;
+        u.c1 = c.cur;
+        if (!u.mixed) ht::sumsq(u.c1.ptr, u.c1.t, (int64_t)u.c1.elems(), u.h->sspart, u.h->scal + 1, s);
       }
     }
     ht::reduce_batch(sums, s);
@@ -1169,10 +1249,14 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
     const double ny2 = h->h_scal[0];
     double lost = 0.0;
     if (u.mixed) {
+      u.e1.assign(h->tree.nodes.size(), 0.0);
       for (int ell = h->tree.depth; ell >= 1; --ell)
         for (int node : h->tree.frontier(ell))
-          if (h->tree.nodes[node].layer == ell)
-            lost += u.expl[node] ? h->h_scal[8 + 2 * node] : h->h_scal[8 + 2 * node] - h->h_scal[8 + 2 * node + 1];
+          if (h->tree.nodes[node].layer == ell) {
+            u.e1[node] =
+                u.expl[node] ? h->h_scal[8 + 2 * node] : h->h_scal[8 + 2 * node] - h->h_scal[8 + 2 * node + 1];
+            lost += u.e1[node];
+          }
     } else {
       lost = ny2 - h->h_scal[1];
     }
@@ -1242,7 +1326,11 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
         u.L = LayerJobs();
         if (!active(a)) continue;
         const std::vector<int>* only = only_of(a);
-        layer_grams(u.h, layer_of(u), u.cur, u.thr, false, u.mixed, s, u.L, only ? (*only)[0] : -1);
+        std::vector<char> f64;
+        fp64_nodes(u, layer_of(u), f64);
+        layer_grams(u.h, layer_of(u), u.cur, u.thr, false, u.mixed, s, u.L, only ? (*only)[0] : -1, &f64);
+        for (size_t q = 0; q < u.L.node.size(); ++q)
+          if (u.mixed && !u.L.f32[q] && f64[u.L.node[q]]) u.recomputed += 1;
         all.insert(all.end(), u.L.jobs.begin(), u.L.jobs.end());
         if (u.mixed) aux_jobs(u, nullptr, aux);
       }

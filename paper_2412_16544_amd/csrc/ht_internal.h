@@ -79,6 +79,33 @@ bool ttm_contract_sq(const void* x, Elem t, const ModeView& v, const double* U, 
 // arrays hold ttm_norm_partials() doubles each.
 void ttm_contract_f32(const void* x, Elem t, const ModeView& v, const double* U, int R, float* Z, double* norm_part,
                       double* norm_out, double* res_part, double* res_out, hipStream_t s);
+
+// ---- grouped contractions -----------------------------------------------------
+// Independent contractions Z = U^T X of small level tensors (one step of the
+// projection chains of many streams) through the LDS-panel kernel, one launch per
+// input / output type combination for up to 24 jobs.  A job computes what the panel
+// kernel computes for it alone, so the result does not depend on the group: an FP32
+// output (zt) takes FP32 products, with res_part (ttm_norm_partials() doubles) the
+// explicit residual energy ||X - U Z||^2 as well (into res_out); with norm_part the
+// sum of squares of X (into norm_out).  The final sums go through the deferred-sum
+// mechanism when it is active.  ttm_groupable says which contractions qualify: modes
+// of at most 128 rows, 1 <= R <= 64, at most kGroupMaxElems input elements.
+constexpr int64_t kGroupMaxElems = int64_t(1) << 20;
+struct TtmJob {
+  const void* x;
+  Elem t;
+  ModeView v;
+  const double* U;
+  int R;
+  void* Z;
+  Elem zt;
+  double* norm_part;
+  double* norm_out;
+  double* res_part;
+  double* res_out;
+};
+bool ttm_groupable(const ModeView& v, int R);
+void ttm_group(const std::vector<TtmJob>& jobs, hipStream_t s);
 // Gram of the explicit residual with the products on FP32 matrix cores and the
 // workgroup partials summed in FP64.
 void resid_gram_f32(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "ht_internal.h"
 
@@ -153,6 +154,32 @@ constexpr int GB = 128;
 constexpr int GBK = 32;
 constexpr int GLD = GB + 1;  // odd stride in doubles: conflict-free column writes
 constexpr int GMAXT = 16;
+
+// A basis U (column-major, m rows, R columns, FP64) staged transposed into LDS:
+// dst[a * ld + r] = U[a0 + a, r] for a < na, r < nr, zero where a >= na_valid or
+// r >= R.  The workgroup walks the entries column by column (consecutive threads read
+// consecutive rows of one column) and keeps eight loads in flight per thread before
+// the LDS stores, so the staging costs a few cache round trips, not one per entry.
+template <typename CT>
+__device__ __forceinline__ void stage_ut(const double* __restrict__ U, int64_t m, int R, int64_t a0, int na,
+                                         int nr, int na_valid, CT* dst, int ld) {
+  const int tot = na * nr;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 256 * 8) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + 256 * q;
+      const int r = e / na, a = e - (e / na) * na;
+      v[q] = (e < tot && a < na_valid && r < R) ? U[(a0 + a) + (int64_t)r * m] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + 256 * q;
+      const int r = e / na, a = e - (e / na) * na;
+      if (e < tot) dst[a * ld + r] = static_cast<CT>(v[q]);
+    }
+  }
+}
 
 __device__ __forceinline__ void tile_of(int t, bool diag, int tI, int tJ, int& ti, int& tj) {
   if (!diag) {
@@ -466,12 +493,7 @@ __global__ __launch_bounds__(256) void gram_panel_kernel(const T* __restrict__ X
 
   // zero the panel once: entries never written by a tile stay zero
   for (int e = threadIdx.x; e < GBK * GLD; e += 256) sM[e] = CT(0);
-  if (RESID) {
-    for (int e = threadIdx.x; e < GB * ULD; e += 256) {
-      const int a = e / ULD, t = e - (e / ULD) * ULD;
-      sU[e] = (a < mi && t < R) ? static_cast<CT>(U[a + (int64_t)t * m]) : CT(0);
-    }
-  }
+  if (RESID) stage_ut(U, m, R, 0, GB, ULD, mi, sU, ULD);
   PanelLoader<T> L;
   L.init(m, S, tw);
   const int64_t K = P * S;
@@ -661,12 +683,14 @@ GramPlan gram_plan(const ModeView& v) {
 // tile in registers and sums its squares (the energy one contraction discards,
 // Eq. compute_residual).  Both sums are FP64.
 // --------------------------------------------------------------------------
+// The work of workgroup bid of one panel contraction (the kernel below, and one job of
+// the grouped launch).
 template <typename T, typename CT, bool NORM, bool RESE>
-__global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
-                                                        int64_t ktiles, int64_t kt_per_split, int tw,
-                                                        const double* __restrict__ U, int R, CT* __restrict__ Z,
-                                                        double* __restrict__ norm_part,
-                                                        double* __restrict__ res_part) {
+__device__ __forceinline__ void ttm_panel_body(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
+                                               int64_t ktiles, int64_t kt_per_split, int tw,
+                                               const double* __restrict__ U, int R, CT* __restrict__ Z,
+                                               double* __restrict__ norm_part, double* __restrict__ res_part,
+                                               int bid) {
   typedef typename MA<CT>::acc AT;
   extern __shared__ double dsm[];
   CT* sM = reinterpret_cast<CT*>(dsm);  // [GBK][GLD]
@@ -679,14 +703,11 @@ __global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X,
   const int mi = (int)m;
   const int tI = (mi + 15) >> 4;
   for (int e = threadIdx.x; e < GBK * GLD; e += 256) sM[e] = CT(0);
-  for (int e = threadIdx.x; e < GB * ULD; e += 256) {
-    const int a = e / ULD, t = e - (e / ULD) * ULD;
-    sU[e] = (a < mi && t < R) ? static_cast<CT>(U[a + (int64_t)t * m]) : CT(0);
-  }
+  stage_ut(U, m, R, 0, GB, ULD, mi, sU, ULD);
   PanelLoader<T> L;
   L.init(m, S, tw);
   const int64_t K = P * S;
-  const int64_t kt0 = (int64_t)blockIdx.x * kt_per_split;
+  const int64_t kt0 = (int64_t)bid * kt_per_split;
   const int64_t kt1 = min(ktiles, kt0 + kt_per_split);
   T rg[PER_PANEL];
   if (kt0 < kt1) L.load(X, P, m, S, K, kt0, tw, rg);
@@ -776,10 +797,53 @@ __global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X,
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      if (NORM) norm_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-      if (RESE) res_part[blockIdx.x] = (red[4] + red[5]) + (red[6] + red[7]);
+      if (NORM) norm_part[bid] = (red[0] + red[1]) + (red[2] + red[3]);
+      if (RESE) res_part[bid] = (red[4] + red[5]) + (red[6] + red[7]);
     }
   }
+}
+
+template <typename T, typename CT, bool NORM, bool RESE>
+__global__ __launch_bounds__(256) void ttm_panel_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
+                                                        int64_t ktiles, int64_t kt_per_split, int tw,
+                                                        const double* __restrict__ U, int R, CT* __restrict__ Z,
+                                                        double* __restrict__ norm_part,
+                                                        double* __restrict__ res_part) {
+  ttm_panel_body<T, CT, NORM, RESE>(X, P, m, S, ktiles, kt_per_split, tw, U, R, Z, norm_part, res_part,
+                                    (int)blockIdx.x);
+}
+
+// Many independent panel contractions of one input and output type in one launch
+// (the same step of the projection chains of many streams): job q owns workgroups
+// [blk0_q, blk0_{q+1}); whether a job also sums the squares of its input (NORM) is
+// per job.  Each job computes exactly what its own ttm_panel_kernel launch would.
+struct PanelJob {
+  const void* X;
+  int64_t P, m, S, ktiles, kt_per_split;
+  const double* U;
+  void* Z;
+  double* norm_part;  // NULL: no sum of squares of the input
+  double* res_part;
+  int tw, R, blk0;
+};
+constexpr int kMaxPanelJobs = 24;
+struct PanelBatch {
+  PanelJob j[kMaxPanelJobs];
+  int n;
+};
+
+template <typename T, typename CT, bool RESE>
+__global__ __launch_bounds__(256) void ttm_panel_group_kernel(PanelBatch b) {
+  int q = 0;
+  while (q + 1 < b.n && (int)blockIdx.x >= b.j[q + 1].blk0) ++q;
+  const PanelJob& J = b.j[q];
+  const int bid = (int)blockIdx.x - J.blk0;
+  if (J.norm_part != nullptr)
+    ttm_panel_body<T, CT, true, RESE>(static_cast<const T*>(J.X), J.P, J.m, J.S, J.ktiles, J.kt_per_split, J.tw,
+                                      J.U, J.R, static_cast<CT*>(J.Z), J.norm_part, J.res_part, bid);
+  else
+    ttm_panel_body<T, CT, false, RESE>(static_cast<const T*>(J.X), J.P, J.m, J.S, J.ktiles, J.kt_per_split, J.tw,
+                                       J.U, J.R, static_cast<CT*>(J.Z), nullptr, J.res_part, bid);
 }
 
 // --------------------------------------------------------------------------
@@ -888,10 +952,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SL == 0 && 
   extern __shared__ float sUr[];  // sUr[a * ULD + r]: U in FP32, zero outside m x R
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g4 = lane >> 4, c16 = lane & 15;
-  for (int e = threadIdx.x; e < 16 * TI * ULD; e += 256) {
-    const int a = e / ULD, r = e - (e / ULD) * ULD;
-    sUr[e] = (a < m && r < R) ? static_cast<float>(U[a + (int64_t)r * m]) : 0.f;
-  }
+  stage_ut(U, m, R, 0, 16 * TI, ULD, m, sUr, ULD);
   __syncthreads();
   const int nblk = (int)RegBlock<SL>::blocks(P, S);
   const int pr = 4 * (c16 & 3) + (c16 >> 2);  // permuted row of U read by this lane
@@ -1022,10 +1083,7 @@ __global__ __launch_bounds__(256) void gram_reg_kernel(const float* __restrict__
   float* sT = sgr + 16 * TI * ULD;   // 4 transpose buffers, later the tile sums
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g4 = lane >> 4, c16 = lane & 15;
-  for (int e = threadIdx.x; e < 16 * TI * ULD; e += 256) {
-    const int a = e / ULD, r = e - (e / ULD) * ULD;
-    sUr[e] = (a < m && r < R) ? static_cast<float>(U[a + (int64_t)r * m]) : 0.f;
-  }
+  stage_ut(U, m, R, 0, 16 * TI, ULD, m, sUr, ULD);
   __syncthreads();
   float* myT = sT + wave * WREG;
   const int nblk = (int)RegBlock<SL>::blocks(P, S);
@@ -1238,12 +1296,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SL == 0 && 
   double* sRw = sg64 + (RESID ? 16 * TI * ULD : 0);    // four residual halves
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g4 = lane >> 4, c16 = lane & 15;
-  if (RESID) {
-    for (int e = threadIdx.x; e < 16 * TI * ULD; e += 256) {
-      const int a = e / ULD, r = e - (e / ULD) * ULD;
-      sUd[e] = (a < m && r < R) ? U[a + (int64_t)r * m] : 0.0;
-    }
-  }
+  if (RESID) stage_ut(U, m, R, 0, 16 * TI, ULD, m, sUd, ULD);
   constexpr int NA = gram64_max_tiles(TI);
   d4 acc[NA];
 #pragma unroll
@@ -1341,10 +1394,7 @@ __global__ __launch_bounds__(256) void ttm_reg64_kernel(const T* __restrict__ X,
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g4 = lane >> 4, c16 = lane & 15;
   const int nrt = (R + 15) >> 4, uld = 16 * nrt + 1;
-  for (int e = threadIdx.x; e < 16 * TI * uld; e += 256) {
-    const int a = e / uld, r = e - (e / uld) * uld;
-    sUd[e] = (a < m && r < R) ? U[a + (int64_t)r * m] : 0.0;
-  }
+  stage_ut(U, m, R, 0, 16 * TI, uld, m, sUd, uld);
   __syncthreads();
   constexpr int esz = (int)sizeof(T);
   const int lane_off = (2 * c16 + g4 * (int)S) * esz;
@@ -1453,9 +1503,7 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
     const int ac = (int)min<int64_t>(chunk, m - a0);
     const int ac4 = (ac + 3) & ~3;
     __syncthreads();
-    for (int r = wave; r < RP; r += 4)
-      for (int a = lane; a < ac4; a += 64)
-        sU[a * ULD + r] = (a < ac && r < R) ? U[(a0 + a) + (int64_t)r * m] : 0.0;
+    stage_ut(U, m, R, a0, ac4, RP, ac, sU, ULD);
     __syncthreads();
     const int nst = ac4 >> 2;
     const T* xp = X + base + a0 * S;
@@ -2244,6 +2292,86 @@ void launch_ttm_panel(const void* x, const ModeView& v, const double* U, int R, 
   ProfScope prof(KKind::Layout, s, 0.0, 0.0);
   if (NORM) finish_sum(norm_part, blocks, norm_out, s);
   if (RESE) finish_sum(res_part, blocks, res_out, s);
+}
+
+bool ttm_groupable(const ModeView& v, int R) {
+  return v.m <= GB && R >= 1 && R <= 64 && v.P * v.m * v.S <= kGroupMaxElems;
+}
+
+// one launch of up to kMaxPanelJobs jobs of one type combination
+template <typename T, typename CT, bool RESE>
+void launch_panel_group(const TtmJob* jobs, int n, hipStream_t s) {
+  PanelBatch b;
+  b.n = n;
+  int blocks = 0, rpmax = 16;
+  double fl = 0.0, by = 0.0;
+  for (int q = 0; q < n; ++q) {
+    const TtmJob& J = jobs[q];
+    const int64_t K = J.v.P * J.v.S;
+    PanelJob& P = b.j[q];
+    P.X = J.x;
+    P.P = J.v.P;
+    P.m = J.v.m;
+    P.S = J.v.S;
+    P.tw = J.v.S >= GBK ? GBK : (int)(J.v.S * (GBK / J.v.S));
+    P.ktiles = (K + P.tw - 1) / P.tw;
+    const int64_t want = std::min<int64_t>(kTtmMaxBlocks, std::max<int64_t>(1, P.ktiles));
+    P.kt_per_split = (P.ktiles + want - 1) / want;
+    const int nb = (int)((P.ktiles + P.kt_per_split - 1) / P.kt_per_split);
+    P.U = J.U;
+    P.R = J.R;
+    P.Z = J.Z;
+    P.norm_part = J.norm_part;
+    P.res_part = J.res_part;
+    P.blk0 = blocks;
+    blocks += nb;
+    rpmax = std::max(rpmax, (J.R + 15) & ~15);
+    fl += (RESE ? 4.0 : 2.0) * J.R * J.v.m * (double)K;
+    by += (double)J.v.m * K * sizeof(T) + (double)J.R * K * sizeof(CT) + (double)J.v.m * J.R * 8;
+  }
+  const size_t lds = ((size_t)GBK * GLD + (size_t)GB * (rpmax + 1) + (RESE ? (size_t)rpmax * ZLD : 0)) * sizeof(CT);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_panel_group_kernel<T, CT, RESE>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    attr = true;
+  }
+  {
+    ProfScope prof(std::is_same<CT, float>::value ? KKind::TtmContract32 : KKind::TtmContract, s, fl, by);
+    ttm_panel_group_kernel<T, CT, RESE><<<blocks, 256, lds, s>>>(b);
+  }
+  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+  for (int q = 0; q < n; ++q) {
+    const PanelJob& P = b.j[q];
+    const int nb = (q + 1 < n ? b.j[q + 1].blk0 : blocks) - P.blk0;
+    if (P.norm_part != nullptr) finish_sum(P.norm_part, nb, jobs[q].norm_out, s);
+    if (RESE) finish_sum(P.res_part, nb, jobs[q].res_out, s);
+  }
+}
+
+void ttm_group(const std::vector<TtmJob>& jobs, hipStream_t s) {
+  // the jobs of each type combination, in list order, up to kMaxPanelJobs per launch
+  for (int combo = 0; combo < 8; ++combo) {
+    std::vector<TtmJob> sel;
+    for (const TtmJob& J : jobs) {
+      const int c = (J.t == Elem::F64 ? 4 : 0) + (J.zt == Elem::F64 ? 2 : 0) + (J.res_part != nullptr ? 1 : 0);
+      if (c == combo) sel.push_back(J);
+    }
+    for (size_t b0 = 0; b0 < sel.size(); b0 += kMaxPanelJobs) {
+      const int n = (int)std::min<size_t>(kMaxPanelJobs, sel.size() - b0);
+      const TtmJob* js = sel.data() + b0;
+      switch (combo) {
+        case 0: launch_panel_group<float, float, false>(js, n, s); break;
+        case 1: launch_panel_group<float, float, true>(js, n, s); break;
+        case 2: launch_panel_group<float, double, false>(js, n, s); break;
+        case 3: launch_panel_group<float, double, true>(js, n, s); break;
+        case 4: launch_panel_group<double, float, false>(js, n, s); break;
+        case 5: launch_panel_group<double, float, true>(js, n, s); break;
+        case 6: launch_panel_group<double, double, false>(js, n, s); break;
+        default: launch_panel_group<double, double, true>(js, n, s); break;
+      }
+    }
+  }
 }
 
 bool ttm_reg64_applies(Elem t, const ModeView& v, int R) {
