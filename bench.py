@@ -388,51 +388,67 @@ def run_workload(name, spec, rank_cap, forms, steps, warmup):
     return res
 
 
-def run_many(count=64, cap=1 << 20):
-    """The many-streams workload: updates timed one by one and in lock step, both forms."""
+def run_many(count=64, cap=1 << 20, d_choices=(3, 4), rank_hi=12, on_device=False):
+    """The many-streams workload: updates timed one by one and in lock step, both forms.
+
+    With on_device the streams' batches are built on the device round by round
+    (datagen.gpu.model_batches), outside the timed calls; else they are generated on
+    the host once and kept resident."""
     import torch
     import datagen
+    from datagen import gpu as G
     from paper_2412_16544_amd import htrise as H
-    # 16^5 N >= 4.2M exceeds the cap: 3- and 4-mode streams at this size
-    specs = datagen.multi_stream_specs(count=count, max_elements=cap, d_choices=(3, 4))
-    t0 = time.perf_counter()
-    data = []
-    for i, sp in enumerate(specs):
-        data.append([torch.from_numpy(y).to("cuda:0") for y in datagen.ht_model_stream(sp)])
-        if i % 16 == 15:
-            log("many streams: generated %d of %d (%.1f s)" % (i + 1, count, time.perf_counter() - t0))
-    torch.cuda.synchronize()
-    nb = len(data[0])
+    specs = datagen.multi_stream_specs(count=count, max_elements=cap, d_choices=d_choices, rank_hi=rank_hi)
+    nb = specs[0].n_batches
     upd_elems = sum(sp.elements_per_batch for sp in specs) * (nb - 1)
-    log("many streams: %d streams staged (%.1f s), %d update elements" % (count, time.perf_counter() - t0, upd_elems))
+    data = None
+    if not on_device:
+        t0 = time.perf_counter()
+        data = [[torch.from_numpy(y).to("cuda:0") for y in datagen.ht_model_stream(sp)] for sp in specs]
+        torch.cuda.synchronize()
+        log("many streams: %d streams staged (%.1f s), %d update elements" % (count, time.perf_counter() - t0,
+                                                                             upd_elems))
+
+    def rounds():
+        """round k -> the k-th batch of every stream (device tensors)"""
+        if data is not None:
+            for k in range(nb):
+                yield [ys[k] for ys in data]
+            return
+        gens = [G.model_batches(sp) for sp in specs]
+        for _ in range(nb):
+            yield [next(g) for g in gens]
 
     def one(prec, batched):
         sts = [H.HTStream(sp.n, EPS, 32, sp.N, sp.N * nb, prec=prec) for sp in specs]
-        for st, ys in zip(sts, data):
-            st.push(ys[0])
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for k in range(1, nb):
+        dt = 0.0
+        for k, ys in enumerate(rounds()):
+            if k == 0:
+                for st, y in zip(sts, ys):
+                    st.push(y)
+                continue
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
             if batched:
-                code, _ = H.HTStream.update_many(sts, [ys[k] for ys in data])
+                code, _ = H.HTStream.update_many(sts, ys)
                 assert code == H.HT_OK
             else:
-                for st, ys in zip(sts, data):
-                    st.update(ys[k])
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
+                for st, y in zip(sts, ys):
+                    st.update(y)
+            torch.cuda.synchronize()
+            dt += time.perf_counter() - t1
         ranks = [st.ranks() for st in sts]
         # untimed: every batch of every stream within its error bound (HT-RISE theorem)
         worst = 0.0
-        for st, ys, sp in zip(sts, data, specs):
-            rec = st.reconstruct()
-            for k in range(nb):
-                yk = ys[k].double()
-                e = (torch.linalg.vector_norm(rec[k * sp.N:(k + 1) * sp.N] - yk) / torch.linalg.vector_norm(yk)).item()
-                worst = max(worst, e)
-            del rec
+        for k, ys in enumerate(rounds()):
+            for st, y, sp in zip(sts, ys, specs):
+                rec = st.reconstruct(k * sp.N, sp.N)
+                yk = y.double()
+                worst = max(worst, (torch.linalg.vector_norm(rec - yk) / torch.linalg.vector_norm(yk)).item())
+                del rec, yk
         for st in sts:
             st.close()
+        torch.cuda.empty_cache()
         return upd_elems / dt, dt, ranks, worst
 
     one(H.HT_FP64, False)  # warm-up: first launches of every kernel shape
@@ -441,16 +457,20 @@ def run_many(count=64, cap=1 << 20):
                                 ("mixed_one_by_one", H.HT_FP32, False), ("mixed_batched", H.HT_FP32, True)):
         v, dt, ranks, worst = one(prec, batched)
         res[name] = {"elements_per_s": v, "seconds": dt, "ranks": ranks, "worst": worst}
-        log("many streams %s: %.3e elements/s (%.3f s), worst batch error %.3e" % (name, v, dt, worst))
+        log("many streams (<= %d): %s: %.3e elements/s (%.3f s), worst batch error %.3e" % (cap, name, v, dt, worst))
     same = all(res[k]["ranks"] == res["fp64_one_by_one"]["ranks"] for k in res)
     worst = max(r["worst"] for r in res.values())
-    out = {"workload": "%d exact-rank streams (d 3-4, n_i 16-128, N 4-32, <= %d elements per batch), "
-                       "10 HT-RISE updates each, eps=1e-4" % (count, cap),
+    out = {"workload": "%d exact-rank streams (d %s, n_i 16-128, N 4-32, rank 2-%d + 2 directions at batches 4 "
+                       "and 8, <= %d elements per batch), 10 HT-RISE updates each, eps=1e-4, rank_cap 32%s"
+                       % (count, "-".join(map(str, (min(d_choices), max(d_choices)))), rank_hi, cap,
+                          "; batches built on the device per round, outside the timing" if on_device else ""),
            "update_elements": upd_elems, "ranks_agree_across_runs": bool(same),
            "worst_batch_rel_error": worst, "error_bound_holds": bool(worst <= EPS * (1 + BOUND_SLACK))}
     for k, v in res.items():
         out[k] = v["elements_per_s"]
     out["mixed_batched_over_fp64_one_by_one"] = res["mixed_batched"]["elements_per_s"] / res["fp64_one_by_one"][
+        "elements_per_s"]
+    out["mixed_batched_over_fp64_batched"] = res["mixed_batched"]["elements_per_s"] / res["fp64_batched"][
         "elements_per_s"]
     return out
 
@@ -581,7 +601,10 @@ def main():
         line["parity_vs_oracle_trace"] = line["parity_vs_oracle_trace"] and all(
             r["parity_vs_oracle_trace"] for r in ores.values())
     if not args.no_many and args.form == "both":
+        # small streams (launch-bound), then the configured sizes (up to 2^25 elements
+        # per batch, 3-5 modes, generating ranks 2-16)
         line["many_streams"] = run_many()
+        line["many_streams_configured"] = run_many(cap=1 << 25, d_choices=(3, 4, 5), rank_hi=16, on_device=True)
     if not args.only and args.form == "both":
         line["variants"] = run_variants(max(1, args.steps // 4), min(args.warmup, 1))
     if args.cpu_sample > 0:

@@ -195,14 +195,14 @@ def _build_frames(g: np.random.Generator, n: Sequence[int], ranks: dict, previou
     return f
 
 
-def ht_model_stream(spec: HTModelSpec) -> Iterator[np.ndarray]:
-    """Yield ``spec.n_batches`` float32 batches of shape (N, *n).
+def ht_model_parts(spec: HTModelSpec) -> Iterator[Tuple[List[Tuple[np.ndarray, np.ndarray, np.ndarray]],
+                                                            np.random.Generator]]:
+    """Per batch k: the terms (F_L, S, F_R) of its signal, sum_terms F_L S_n F_R^T per
+    sample n, and the batch's generator, positioned for the noise draw.
 
-    Batch k is sum over the direction sets introduced so far of
-    F_L S_k F_R^T (per sample), where F_L, F_R are the frames of the root's two
-    children and S_k holds fresh Gaussian root slices, plus relative noise of
-    standard deviation ``nu * rms(signal)``.
-    """
+    F_L, F_R are the frames of the root's two children of each direction set
+    introduced so far and S (N x r_L x r_R) holds fresh Gaussian root slices scaled
+    by the set's scale."""
     n = tuple(spec.n)
     d = len(n)
     if d < 2:
@@ -218,13 +218,26 @@ def ht_model_stream(spec: HTModelSpec) -> Iterator[np.ndarray]:
             sets.append(_build_frames(g, n, grow, sets))
             scales.append(spec.grow_scale)
         gb = rng(spec.batch_seed0 + k)
-        nl = int(np.prod(n[left[0]:left[1]]))
-        nr = int(np.prod(n[right[0]:right[1]]))
-        y = np.zeros((spec.N, nl, nr))
+        terms = []
         for fr, sc in zip(sets, scales):
             fl = fr.frame(*left)
             fright = fr.frame(*right)
-            s = sc * gb.standard_normal((spec.N, fl.shape[1], fright.shape[1]))
+            terms.append((fl, sc * gb.standard_normal((spec.N, fl.shape[1], fright.shape[1])), fright))
+        yield terms, gb
+
+
+def ht_model_stream(spec: HTModelSpec) -> Iterator[np.ndarray]:
+    """Yield ``spec.n_batches`` float32 batches of shape (N, *n).
+
+    Batch k is sum over the direction sets introduced so far of
+    F_L S_k F_R^T (per sample), where F_L, F_R are the frames of the root's two
+    children and S_k holds fresh Gaussian root slices, plus relative noise of
+    standard deviation ``nu * rms(signal)``.
+    """
+    n = tuple(spec.n)
+    for terms, gb in ht_model_parts(spec):
+        y = np.zeros((spec.N, terms[0][0].shape[0], terms[0][2].shape[0]))
+        for fl, s, fright in terms:
             y += np.einsum("xi,nij,yj->nxy", fl, s, fright, optimize=True)
         if spec.nu > 0:
             rms = math.sqrt(float(np.mean(y * y)))
@@ -406,7 +419,7 @@ def field_48_stream(n_batches: int = 100, N: int = 16, nu: float = 1e-6) -> Iter
 
 def multi_stream_specs(count: int = 64, seed0: int = 4000, n_batches: int = 11,
                        max_elements: int = 1 << 25, nu: float = 1e-5,
-                       d_choices: Sequence[int] = (3, 4, 5)) -> List[HTModelSpec]:
+                       d_choices: Sequence[int] = (3, 4, 5), rank_hi: int = 12) -> List[HTModelSpec]:
     """``count`` exact-rank streams: d from ``d_choices``, n_i in [16,128], N in [4,32].
 
     Mode sizes are drawn uniformly; while N * prod(n) exceeds ``max_elements`` the
@@ -414,7 +427,7 @@ def multi_stream_specs(count: int = 64, seed0: int = 4000, n_batches: int = 11,
     ends quickly even for d = 5 (plain redrawing of all modes almost never meets
     the cap there).  A cap below N * 16^d cannot be met; smaller caps therefore
     come with fewer modes in ``d_choices``.  The generating rank r0 is drawn from
-    [2,12] and capped by what the modes allow; batches 4 and 8 add 2 fresh
+    [2, rank_hi] and capped by what the modes allow; batches 4 and 8 add 2 fresh
     directions at every node.  ``n_batches`` counts the initial batch, so 11 means
     10 updates.
     """
@@ -429,7 +442,7 @@ def multi_stream_specs(count: int = 64, seed0: int = 4000, n_batches: int = 11,
             if n[i] <= 16:
                 break
             n[i] = int(g.integers(16, n[i]))
-        r0 = int(g.integers(2, 13))
+        r0 = int(g.integers(2, rank_hi + 1))
         r0 = min(r0, min(n) - 4)
         specs.append(HTModelSpec(n=tuple(n), rank=r0, N=N, n_batches=n_batches, seed=seed0 + s,
                                  batch_seed0=(seed0 + s) * 100, nu=nu, grow_at=(4, 8),

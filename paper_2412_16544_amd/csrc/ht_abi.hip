@@ -1396,7 +1396,15 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
         }
       }
       if (!orth.empty()) ht::orth_expand_batch(orth.data(), (int)orth.size(), s);
-      // ---- the projection of this step (merged into the next frontier after the last)
+      // ---- the projection of this step (merged into the next frontier after the last):
+      //      the handles' contraction chains advance in lock step, the small
+      //      contractions of a step in one grouped launch
+      struct PChain {
+        size_t a;
+        std::vector<int> order, f;
+        size_t pos;
+      };
+      std::vector<PChain> pc;
       for (size_t a = 0; a < act.size(); ++a) {
         Upd& u = *act[a];
         if (!active(a)) continue;
@@ -1411,10 +1419,27 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
           // App. C in the mixed form: the energy each second-pass contraction discards,
           // summed (a difference of FP32-accurate norms would not resolve eps_des^2)
           u.cur = project_layer(h, ell, u.cur, s, nullptr, true, h->scal + 8, &u.expl, nullptr, only);
-        } else {
-          u.cur = project_layer(h, ell, u.cur, s, nullptr, u.mixed, nullptr, nullptr, nullptr, only);
+          if (only && sub + 1 == steps[a].size()) u.cur = merge_level(h, ell, u.cur);
+          continue;
         }
-        if (only && sub + 1 == steps[a].size()) u.cur = merge_level(h, ell, u.cur);
+        pc.push_back(PChain{a, only ? *only : contraction_order(h, ell, u.cur.modes), h->tree.frontier(ell), 0});
+      }
+      std::vector<ht::TtmJob> group;
+      for (bool more = true; more;) {
+        more = false;
+        group.clear();
+        for (PChain& c : pc) {
+          if (c.pos == c.order.size()) continue;
+          Upd& u = *act[c.a];
+          const int k = c.order[c.pos++];
+          contract_one(u.h, u.cur, k, c.f[k], other(u.h, u.cur.ptr), s, nullptr, u.mixed, nullptr, nullptr, &group);
+          more = true;
+        }
+        if (!group.empty()) ht::ttm_group(group, s);
+      }
+      for (const PChain& c : pc) {
+        Upd& u = *act[c.a];
+        if (only_of(c.a) == nullptr || sub + 1 == steps[c.a].size()) u.cur = merge_level(u.h, layer_of(u), u.cur);
       }
     }
     // ---- App. C: the tolerance of the layers above from the energy lost so far

@@ -123,3 +123,35 @@ def test_many_rolls_back_only_the_failing_stream(six_streams):
     np.testing.assert_array_equal(sts[0].reconstruct().cpu().numpy(), before_rec0)
     for s, b, sp in zip(sts[1:], before[1:], specs[1:4]):
         assert s.ranks()[1] == b[1] + sp.N   # committed
+
+
+@pytest.mark.parametrize("prec", [H.HT_FP64, H.HT_FP32])
+def test_device_built_streams_match_oracle(prec):
+    """Streams of the configured shapes' kind (3-5 modes, generating ranks up to 16),
+    their batches built on the device (datagen.gpu.model_batches) and copied to the
+    host for the oracle: ranks and skips after every batch and every batch's error bound."""
+    from datagen import gpu as G
+    specs = datagen.multi_stream_specs(count=3, seed0=4100, n_batches=11, max_elements=1 << 17,
+                                       d_choices=(3, 4, 5), rank_hi=16)
+    data = [list(G.model_batches(sp)) for sp in specs]
+    host = [[y.cpu().numpy() for y in ys] for ys in data]
+    sts = []
+    ors = []
+    for sp, ys, hs in zip(specs, data, host):
+        st = H.HTStream(sp.n, 1e-4, 32, sp.N, sp.N * len(ys), prec=prec)
+        st.push(ys[0])
+        sts.append(st)
+        o = ho.BHT(hs[0].shape[1:], 1e-4)
+        o.init_batch(hs[0])
+        ors.append(o)
+    for k in range(1, len(data[0])):
+        code, infos = H.HTStream.update_many(sts, [ys[k] for ys in data])
+        assert code == H.HT_OK
+        oinfo = [o.update(hs[k]) for o, hs in zip(ors, host)]
+        assert [i.skipped for i in infos] == [i.skipped for i in oinfo], k
+        assert [s.ranks()[0] for s in sts] == [i.ranks for i in oinfo], k
+    for s, hs, sp in zip(sts, host, specs):
+        rec = s.reconstruct().cpu().numpy()
+        for k, y in enumerate(hs):
+            yy = y.astype(np.float64)
+            assert np.linalg.norm(rec[k * sp.N:(k + 1) * sp.N] - yy) <= 1e-4 * (1 + 1e-3) * np.linalg.norm(yy), k
