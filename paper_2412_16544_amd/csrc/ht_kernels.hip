@@ -1297,7 +1297,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SL == 0 && 
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g4 = lane >> 4, c16 = lane & 15;
   if (RESID) stage_ut(U, m, R, 0, 16 * TI, ULD, m, sUd, ULD);
-  constexpr int NA = gram64_max_tiles(TI);
+  // Up to four row tiles every wave accumulates every upper tile over its own blocks
+  // (the accumulators fit), so the waves never wait for each other; the four sets are
+  // added in wave order at the end.  Larger modes share the tiles out as above.
+  constexpr bool ALL = TI <= 4;
+  constexpr int NA = ALL ? TI * (TI + 1) / 2 : gram64_max_tiles(TI);
   d4 acc[NA];
 #pragma unroll
   for (int u = 0; u < NA; ++u) acc[u] = d4{0, 0, 0, 0};
@@ -1359,22 +1363,72 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SL == 0 && 
         for (int v = 0; v < 4; ++v)
           myR[(16 * it + 4 * v + g4) * kGram64Ld + c16] = (double)x[4 * it + v][h] - y[v];
       }
-      __syncthreads();
-      switch (wave) {
-        case 0: gram64_accumulate<TI, 0>(sRw, WREG, c16, g4, acc); break;
-        case 1: gram64_accumulate<TI, 1>(sRw, WREG, c16, g4, acc); break;
-        case 2: gram64_accumulate<TI, 2>(sRw, WREG, c16, g4, acc); break;
-        default: gram64_accumulate<TI, 3>(sRw, WREG, c16, g4, acc); break;
+      if constexpr (ALL) {
+        // the wave's own half only: it reads back its own LDS writes, no barrier
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4) {
+          double op[TI];
+#pragma unroll
+          for (int i = 0; i < TI; ++i) op[i] = myR[(16 * i + c16) * kGram64Ld + 4 * k4 + g4];
+          int q = 0;
+#pragma unroll
+          for (int i = 0; i < TI; ++i) {
+#pragma unroll
+            for (int j = i; j < TI; ++j) {
+              acc[q] = mfma16(op[i], op[j], acc[q]);
+              ++q;
+            }
+          }
+        }
+      } else {
+        __syncthreads();
+        switch (wave) {
+          case 0: gram64_accumulate<TI, 0>(sRw, WREG, c16, g4, acc); break;
+          case 1: gram64_accumulate<TI, 1>(sRw, WREG, c16, g4, acc); break;
+          case 2: gram64_accumulate<TI, 2>(sRw, WREG, c16, g4, acc); break;
+          default: gram64_accumulate<TI, 3>(sRw, WREG, c16, g4, acc); break;
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
   double* out = part + (int64_t)blockIdx.x * m * m;
-  switch (wave) {
-    case 0: gram64_store<TI, 0>(acc, m, c16, g4, out); break;
-    case 1: gram64_store<TI, 1>(acc, m, c16, g4, out); break;
-    case 2: gram64_store<TI, 2>(acc, m, c16, g4, out); break;
-    default: gram64_store<TI, 3>(acc, m, c16, g4, out); break;
+  if constexpr (ALL) {
+    // the four waves' tiles added in wave order through LDS (the residual regions,
+    // free now), then one FP64 partial: tile (i, j), register v of lane l is
+    // G[16 i + l / 16 + 4 v][16 j + l % 16]
+    __syncthreads();
+    for (int w = 0; w < 4; ++w) {
+      if (wave == w) {
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            double* d = sRw + (q * 256 + v * 64 + lane);
+            *d = (w == 0) ? acc[q][v] : *d + acc[q][v];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < NA * 256; e += 256) {
+      const int q = e >> 8, v = (e >> 6) & 3, l = e & 63;
+      int i = 0, qq = q;
+      while (qq >= TI - i) {
+        qq -= TI - i;
+        ++i;
+      }
+      const int j = i + qq;
+      const int row = 16 * i + (l >> 4) + 4 * v, col = 16 * j + (l & 15);
+      if (row < m && col < m) out[row * m + col] = sRw[e];
+    }
+  } else {
+    switch (wave) {
+      case 0: gram64_store<TI, 0>(acc, m, c16, g4, out); break;
+      case 1: gram64_store<TI, 1>(acc, m, c16, g4, out); break;
+      case 2: gram64_store<TI, 2>(acc, m, c16, g4, out); break;
+      default: gram64_store<TI, 3>(acc, m, c16, g4, out); break;
+    }
   }
 }
 
@@ -1480,6 +1534,7 @@ constexpr int TUS = 65;  // LDS row stride (doubles) of the staged U chunk of th
 // added in wave order through LDS.
 // --------------------------------------------------------------------------
 constexpr int kDirectLdsDoubles = 19968;  // U chunk: chunk x (RP + 1) doubles of dynamic LDS
+constexpr unsigned kDirectColsMinBlocks = 4096;  // column blocks from which whole blocks go to waves
 
 // SQ: also the workgroup partials of ||X||^2 (in_part) and ||Z||^2 (out_part)
 template <typename T, bool SQ>
@@ -1570,6 +1625,104 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
     if (threadIdx.x == 0) {
       in_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
       out_part[blockIdx.x] = zsq;
+    }
+  }
+}
+
+// The same contraction for many columns: each wave owns whole 16-column blocks (two
+// at a time) and runs every row of them, so no partial sum crosses waves; the
+// workgroup's eight column blocks share each staged chunk of U, and workgroups loop
+// over tiles of eight blocks.  With SQ the workgroup partials of ||X||^2 and ||Z||^2.
+template <typename T, bool SQ>
+__global__ __launch_bounds__(256) void ttm_direct_cols_kernel(const T* __restrict__ X, int64_t P, int64_t m,
+                                                              int64_t S, const double* __restrict__ U, int R,
+                                                              int chunk, double* __restrict__ Z,
+                                                              double* __restrict__ in_part,
+                                                              double* __restrict__ out_part) {
+  extern __shared__ double sU[];  // sU[a][r], chunk rows of ULD
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int RP = (R + 15) & ~15, ULD = RP + 1, rt = RP >> 4;
+  const int64_t K = P * S;
+  const int64_t ncb = (K + 15) / 16;
+  const int kr = lane >> 4;
+  double xsq = 0.0, zsq = 0.0;
+  for (int64_t cb0 = (int64_t)blockIdx.x * 8; cb0 < ncb; cb0 += (int64_t)gridDim.x * 8) {  // uniform
+    int64_t c[2], base[2];
+    bool cv[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      c[j] = (cb0 + 2 * wave + j) * 16 + (lane & 15);
+      cv[j] = c[j] < K;
+      base[j] = cv[j] ? col_base(c[j], m, S) : 0;
+    }
+    d4 acc[2][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[j][t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t a0 = 0; a0 < m; a0 += chunk) {
+      const int ac = (int)min<int64_t>(chunk, m - a0);
+      const int ac4 = (ac + 3) & ~3;
+      __syncthreads();
+      stage_ut(U, m, R, a0, ac4, RP, ac, sU, ULD);
+      __syncthreads();
+      const int nst = ac4 >> 2;
+      for (int st = 0; st < nst; st += 4) {  // four row steps of both blocks: eight loads in flight
+        double b[2][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int a = 4 * (st + q) + kr;
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            b[j][q] = (cv[j] && a < ac) ? static_cast<double>(X[base[j] + (a0 + a) * S]) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (st + q < nst) {
+            const double* ua = sU + (4 * (st + q) + kr) * ULD + (lane & 15);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              if (SQ) xsq = fma(b[j][q], b[j][q], xsq);
+#pragma unroll
+              for (int t = 0; t < 4; ++t)
+                if (t < rt) acc[j][t] = mfma16(ua[t * 16], b[j][q], acc[j][t]);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (!cv[j]) continue;
+      const int64_t p = c[j] / S, sidx = c[j] - (c[j] / S) * S;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < rt) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = t * 16 + MA<double>::row(lane, v);
+            if (r < R) {
+              const double z = acc[j][t][v];
+              Z[(p * R + r) * S + sidx] = z;
+              if (SQ) zsq = fma(z, z, zsq);
+            }
+          }
+        }
+      }
+    }
+  }
+  if (SQ) {
+    __shared__ double red[8];
+    xsq = wave_sum(xsq);
+    zsq = wave_sum(zsq);
+    if (lane == 0) {
+      red[wave] = xsq;
+      red[4 + wave] = zsq;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      in_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+      out_part[blockIdx.x] = (red[4] + red[5]) + (red[6] + red[7]);
     }
   }
 }
@@ -2220,6 +2373,40 @@ void launch_ttm_direct(const void* x, Elem t, const ModeView& v, const double* U
   }
   const unsigned blocks = (unsigned)((K + 15) / 16);
   const int RP = (R + 15) & ~15;
+  if (blocks >= kDirectColsMinBlocks) {
+    // many column blocks: whole blocks per wave, U in chunks of at most 64 KiB (two
+    // workgroups per compute unit), tiles of eight blocks spread evenly over at most
+    // 512 workgroups
+    static bool cattr = false;
+    if (!cattr) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_direct_cols_kernel<float, SQ>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 8192 * (int)sizeof(double));
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ttm_direct_cols_kernel<double, SQ>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 8192 * (int)sizeof(double));
+      cattr = true;
+    }
+    const int64_t tiles = ((int64_t)blocks + 7) / 8;
+    const int64_t per = (tiles + 511) / 512;
+    const unsigned grid = (unsigned)((tiles + per - 1) / per);
+    const int chunk = (int)std::min<int64_t>(((8192 / (RP + 1)) / 4) * 4, (v.m + 3) & ~3);
+    const size_t lds = (size_t)chunk * (RP + 1) * sizeof(double);
+    {
+      ProfScope prof(KKind::TtmContract, s, 2.0 * R * v.m * (double)K,
+                     (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8);
+      if (t == Elem::F32)
+        ttm_direct_cols_kernel<float, SQ><<<grid, 256, lds, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R,
+                                                                 chunk, Z, in_part, out_part);
+      else
+        ttm_direct_cols_kernel<double, SQ><<<grid, 256, lds, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U,
+                                                                  R, chunk, Z, in_part, out_part);
+    }
+    if (SQ) {
+      ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+      finish_sum(in_part, (int)grid, in_out, s);
+      finish_sum(out_part, (int)grid, out_out, s);
+    }
+    return;
+  }
   // few column blocks (transfer nodes): all of U in one chunk; many: at most 64 KiB,
   // two workgroups per compute unit
   const int cap = blocks >= 512 ? 8192 : kDirectLdsDoubles;
@@ -2466,7 +2653,10 @@ void ttm_contract_norm(const void* x, Elem t, const ModeView& v, const double* U
 bool ttm_contract_sq(const void* x, Elem t, const ModeView& v, const double* U, int R, double* Z, double* in_part,
                      double* in_out, double* out_part, double* out_out, int max_parts, hipStream_t s) {
   const int64_t K = v.P * v.S;
-  if (v.m <= GB || (K + 15) / 16 > max_parts) return false;
+  const int64_t blocks = (K + 15) / 16;
+  // workgroup partials: one per column block, or at most 512 with whole blocks per wave
+  const int64_t parts = blocks >= kDirectColsMinBlocks ? std::min<int64_t>(512, (blocks + 7) / 8) : blocks;
+  if (v.m <= GB || parts > max_parts) return false;
   launch_ttm_direct<true>(x, t, v, U, R, Z, in_part, in_out, out_part, out_out, s);
   return true;
 }

@@ -69,6 +69,9 @@ def test_resid_gram(P, m, S, R, dtype):
                                      (64, 8, 16384, 3), (3, 4, 32, 1), (4, 48, 2048, 18), (3, 44, 64, 40),
                                      # modes of more than 128 rows: U staged once, or in chunks (m = 600)
                                      (16, 182, 42, 40), (3, 600, 50, 40), (2, 131, 1, 64),
+                                     # ... and with 4096 column blocks or more, whole blocks per wave
+                                     # (a ragged last block; U in two chunks for m = 300)
+                                     (64, 160, 1100, 24), (5, 131, 13109, 17), (7, 300, 10000, 46),
                                      # LDS-panel kernel (42 and 47 rows, runs not in blocks of 32)
                                      (5824, 42, 1, 30), (3, 47, 9, 47),
                                      # modes of at most 8 rows: one column per thread (S > 1 with
