@@ -148,7 +148,9 @@ def test_resid_gram_f32(P, m, S, R, dtype):
 
 
 @pytest.mark.parametrize("P,R,S,m", [(3, 12, 1000, 96), (5, 3, 7, 3), (100, 5, 1, 16), (2, 64, 33, 200),
-                                     (1, 17, 40, 130), (7, 1, 5, 17)])
+                                     (1, 17, 40, 130), (7, 1, 5, 17),
+                                     # enough column groups that a workgroup runs several row blocks
+                                     (2, 17, 40000, 150), (3, 46, 25000, 306)])
 @pytest.mark.parametrize("with_m", [False, True])
 def test_ttm_expand(P, R, S, m, with_m):
     g = rng(P + m + S + R + 7)
