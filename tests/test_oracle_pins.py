@@ -689,3 +689,61 @@ def test_st_hosvd_meets_the_bound_on_the_tiny_stream():
     for k, y in enumerate(ys):
         yy = y.astype(np.float64)
         assert math.sqrt(ho.fro2(st.reconstruct(8 * k, 8) - yy)) <= 1e-4 * math.sqrt(ho.fro2(yy))
+
+
+# --------------------------------------------------------------------------- #
+# Decision bookkeeping: the near-tie flag, the residual rank cap, the stream helper
+# --------------------------------------------------------------------------- #
+
+
+def test_near_tie_flags_a_tail_at_the_threshold():
+    """d = 2 closed form (both unfoldings have singular values s): with s_3 placed so
+    that the tail of rank 2 is eps_nw^2 (1 + delta), the decision keeps 3 directions
+    and is a near tie for a band wider than delta, not for a narrower one."""
+    eps = 1e-3
+    base = np.array([1.0, 0.5])
+    for delta, band, expect in ((1e-7, 1e-5, True), (1e-7, 1e-9, False), (1e-3, 1e-5, False)):
+        # ||Y||^2 = 1.25 + s3^2 and eps_nw^2 = eps^2 ||Y||^2 / 2; s3^2 = eps_nw^2 (1 + delta)
+        c = eps * eps * (1.0 + delta) / 2.0
+        s3 = math.sqrt(c * 1.25 / (1.0 - c))
+        y, _, _, _ = _diag_batch(np.concatenate([base, [s3]]))
+        o = ho.BHT(y.shape[1:], eps)
+        info = o.init_batch(y)
+        assert o.ranks == [3, 3]
+        assert info.any_near_tie(band) is expect, (delta, band)
+        t = info.decisions[1]
+        thr = t.eps_nw ** 2
+        assert abs(t.tail2_prev - thr) == pytest.approx(delta * thr, rel=1e-3)
+
+
+def test_residual_rank_cap_is_the_complement_of_the_old_basis():
+    """At eps = 1e-17 the truncation of a residual would also keep the rounding noise
+    left along the old basis (~1e-16 of the batch, far above eps_nw); the cap
+    alpha - r_old keeps each node to its mode size, and the cores stay orthonormal."""
+    g = np.random.default_rng(5)
+    n1, n2, N = 4, 5, 12
+    a = np.linalg.qr(g.standard_normal((n1, n1)))[0]
+    b = np.linalg.qr(g.standard_normal((n2, n2)))[0]
+    y0 = np.einsum("ni,xi,yi->nxy", g.standard_normal((N, 2)), a[:, :2], b[:, :2])
+    y1 = g.standard_normal((N, n1, n2))            # full rank: every direction is new
+    o = ho.BHT((n1, n2), 1e-17)
+    o.init_batch(y0)
+    r_old = list(o.ranks)        # at this tolerance the first batch's noise is kept too
+    info = o.update(y1)
+    assert not info.skipped
+    assert o.ranks == [n1, n2]   # never beyond the mode size
+    for idx, r0 in zip((1, 2), r_old):
+        u = o.core[idx]
+        assert np.allclose(u.T @ u, np.eye(u.shape[1]), atol=1e-12)
+        assert info.decisions[idx].rmax == u.shape[0] - r0
+
+
+def test_compress_stream_is_init_then_updates():
+    ys = datagen.tiny_stream()
+    a = ho.compress_stream(ys, 1e-4)
+    b = ho.BHT(ys[0].shape[1:], 1e-4)
+    b.init_batch(ys[0])
+    for y in ys[1:]:
+        b.update(y)
+    assert a.ranks == b.ranks and a.n_accum == b.n_accum
+    assert np.array_equal(a.reconstruct(), b.reconstruct())
