@@ -49,7 +49,9 @@ def test_gram(P, m, S, dtype):
                                      (100, 96, 3, 14), (37, 64, 1, 5), (50, 48, 2, 20), (19, 96, 4, 32),
                                      # three row tiles (33-48 rows): per-tile wave ownership of the FP64 Gram
                                      (4, 48, 2048, 18), (3, 44, 64, 40), (2, 48, 96, 47), (37, 48, 1, 5),
-                                     (21, 36, 3, 17), (19, 48, 4, 30)])
+                                     (21, 36, 3, 17), (19, 48, 4, 30),
+                                     # runs not in whole blocks of 32; rows not in steps of four
+                                     (3, 76, 330, 20), (5, 40, 34, 12), (9, 103, 62, 33)])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_resid_gram(P, m, S, R, dtype):
     g = rng(P * 7 + m + S + R)
@@ -104,6 +106,9 @@ MIXED_SHAPES = [(3, 96, 1000, 12), (5, 9, 7, 3), (100, 16, 1, 5), (2, 128, 33, 6
                 # three row tiles (33-48 rows), runs in blocks of 32 and short runs
                 (4, 48, 2048, 18), (3, 44, 64, 40), (2, 48, 96, 47), (37, 48, 1, 5), (21, 36, 3, 17),
                 (19, 48, 4, 30),
+                # runs that are not whole blocks of 32 and row counts that are not
+                # multiples of four (LDS-panel kernel)
+                (3, 76, 330, 20), (5, 40, 34, 12), (2, 124, 100, 64), (9, 103, 62, 33), (4, 17, 2050, 5),
                 # outside the register kernels: the LDS-panel kernel (42 and 47 rows) and one
                 # column per thread (modes of at most 8 rows)
                 (5824, 42, 1, 30), (33, 47, 5, 47), (220000, 3, 1, 3), (3000, 1, 2, 1)]
