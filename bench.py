@@ -274,6 +274,10 @@ def run_form(form, spec, ys, golden, steps, warmup, rank_cap):
         if form == "mixed" else None,
         "kernel_ms_profiled_pass": {k: round(v["ms"], 3) for k, v in kinds.items()},
         "roofline": roofline(dom, kinds[dom]),
+        # every contraction / Gram class of the profiled pass against its own roofline
+        "rooflines": {k: {x: v for x, v in roofline(k, kinds[k]).items() if x in ("bound", "achieved", "unit", "frac",
+                                                                                  "launches", "avg_launch_ms")}
+                      for k in cand},
         "parity_vs_oracle_trace": bool(ok),
         "worst_sampled_rel_error": worst,
         "rte_heldout": rte,
