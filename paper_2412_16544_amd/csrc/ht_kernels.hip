@@ -859,6 +859,21 @@ __global__ __launch_bounds__(256) void ttm_panel_group_kernel(PanelBatch b) {
 // Loads are buffer loads with the row step as a scalar offset; lanes past the
 // last slab fall outside the buffer's extent and read zeros.
 // --------------------------------------------------------------------------
+// The register-direct kernels keep two sets of block registers: a wave's next block
+// is loaded into one set while it works on the other.  The two copies of the block
+// code must stay separate (merged, they would need a copy between the sets, which
+// waits for the loads); the marker differs per set, and as a memory clobber it also
+// keeps U^T re-read from LDS per block instead of held in registers.
+template <int SET>
+__device__ __forceinline__ void reg_set_mark() {
+  if (SET == 0)
+    asm volatile("; register set 0" ::: "memory");
+  else
+    asm volatile("; register set 1" ::: "memory");
+}
+constexpr std::integral_constant<int, 0> kSet0{};
+constexpr std::integral_constant<int, 1> kSet1{};
+
 template <int SL>
 struct RegBlock {
   static constexpr int NH = SL == 0 ? 2 : SL;
@@ -868,14 +883,16 @@ struct RegBlock {
   int s0;      // SL = 0: first s of the block
   bool live;   // the lane's columns exist
 
-  __device__ __forceinline__ void setup(const float* X, int64_t P, int m, int64_t S, int blk, int g4, int c16) {
+  // valid = false: a buffer of extent 0, whose loads read zeros without touching memory
+  __device__ __forceinline__ void setup(const float* X, int64_t P, int m, int64_t S, int blk, int g4, int c16,
+                                        bool valid = true) {
     if (SL == 0) {
       const int S32 = (int)S;
       const int c0 = blk * 32;
       p = c0 / S32;
       s0 = c0 - (int)p * S32;
       rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X) + p * m * S + s0, (short)0,
-                                             (m * S32 - s0) * 4, 0x00020000);
+                                             valid ? (m * S32 - s0) * 4 : 0, 0x00020000);
       lane_off = (2 * c16 + g4 * S32) * 4;
       step = 16 * S32;
       live = true;
@@ -885,7 +902,7 @@ struct RegBlock {
       s0 = 0;
       const int64_t left = P - p0 < 16 ? P - p0 : 16;
       rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X) + p0 * m * SL, (short)0,
-                                             (int)(left * m * SL * 4), 0x00020000);
+                                             valid ? (int)(left * m * SL * 4) : 0, 0x00020000);
       lane_off = (c16 * m * SL + g4 * SL) * 4;
       step = 16 * SL;
       live = p < P;
@@ -898,7 +915,10 @@ struct RegBlock {
     typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      if (4 * t < m) {
+      // SL = 0: rows past m lie past the extent, which ends with the block's slab, and
+      // read zeros; the loads go out unconditionally, so the compiler can count the
+      // loads in flight (a wave's next block is loaded while it works on the current)
+      if (SL == 0 || 4 * t < m) {
         if (SL == 1) {
           x[t][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, lane_off, t * step, 0));
         } else if (SL == 0 || SL == 2) {
@@ -957,12 +977,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SL == 0 && 
   const int nblk = (int)RegBlock<SL>::blocks(P, S);
   const int pr = 4 * (c16 & 3) + (c16 >> 2);  // permuted row of U read by this lane
   double nrm = 0.0, res = 0.0;
-  for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
-    asm volatile("" ::: "memory");  // U^T is re-read from LDS per block, not held in registers
-    RegBlock<SL> B;
-    B.setup(X, P, m, S, blk, g4, c16);
-    float x[NT][NH];
-    B.load(x, m);
+  // one block on loaded registers
+  auto block = [&](const RegBlock<SL>& B, float (&x)[NT][NH], auto set) {
+    reg_set_mark<decltype(set)::value>();  // U^T is re-read from LDS per block, not held in registers
     if (NORM) {
       double n0 = 0.0, n1 = 0.0;  // two chains: the sums are not latency-bound
 #pragma unroll
@@ -999,7 +1016,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SL == 0 && 
         for (int v = 0; v < 4; ++v) {
           const int r = 16 * rt + 4 * g4 + v;
           if (r < R) {
-            if (SL == 0) {
+            if constexpr (SL == 0) {
               *reinterpret_cast<float2*>(Z + B.out_index(R, S, r, 0, c16)) = make_float2(zz[rt][0][v], zz[rt][1][v]);
             } else {
 #pragma unroll
@@ -1039,6 +1056,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SL == 0 && 
         }
       }
       res += (double)e0 + (double)e1;
+    }
+  };
+  // two register sets: the loads of a wave's next block are in flight while it
+  // works on the current one (a copy between the sets would wait for them)
+  const int step = gridDim.x * 4;
+  RegBlock<SL> B0, B1;
+  float x0[NT][NH], x1[NT][NH];
+  // (past the last block the loads go to an empty buffer: no branch around them)
+  int blk = blockIdx.x * 4 + wave;
+  if (blk < nblk) {
+    B0.setup(X, P, m, S, blk, g4, c16);
+    B0.load(x0, m);
+    for (;;) {
+      const int b1 = blk + step;
+      B1.setup(X, P, m, S, b1 < nblk ? b1 : blk, g4, c16, b1 < nblk);
+      B1.load(x1, m);
+      block(B0, x0, kSet0);
+      if (b1 >= nblk) break;
+      blk = b1 + step;
+      B0.setup(X, P, m, S, blk < nblk ? blk : b1, g4, c16, blk < nblk);
+      B0.load(x0, m);
+      block(B1, x1, kSet1);
+      if (blk >= nblk) break;
     }
   }
   if (NORM || RESE) {
@@ -1091,12 +1131,9 @@ __global__ __launch_bounds__(256) void gram_reg_kernel(const float* __restrict__
   f4 acc[NTILE];
 #pragma unroll
   for (int q = 0; q < NTILE; ++q) acc[q] = f4{0, 0, 0, 0};
-  for (int blk = blockIdx.x * 4 + wave; blk < nblk; blk += gridDim.x * 4) {
-    asm volatile("" ::: "memory");
-    RegBlock<SL> B;
-    B.setup(X, P, m, S, blk, g4, c16);
-    float x[NT][NH];
-    B.load(x, m);
+  // one block on loaded registers
+  auto block = [&](float (&x)[NT][NH], auto set) {
+    reg_set_mark<decltype(set)::value>();
     {
       f4 zz[RT][NH];
 #pragma unroll
@@ -1159,6 +1196,28 @@ __global__ __launch_bounds__(256) void gram_reg_kernel(const float* __restrict__
         }
       }
     }
+  };
+  // two register sets, the next block's loads in flight during the current one.  The
+  // loop runs whole pairs of blocks with no branch between a load and its use (the
+  // compiler would sink the loads to their use); a block past the last is read from an
+  // empty buffer as zeros, which add nothing to the Gram.
+  const int step = gridDim.x * 4;
+  const int first = blockIdx.x * 4 + wave;
+  const int pairs = first < nblk ? ((nblk - 1 - first) / step + 2) / 2 : 0;
+  RegBlock<SL> B0, B1;
+  float x0[NT][NH], x1[NT][NH];
+  if (pairs > 0) {
+    B0.setup(X, P, m, S, first, g4, c16);
+    B0.load(x0, m);
+  }
+  for (int q = 0; q < pairs; ++q) {
+    const int b1 = first + (2 * q + 1) * step, b2 = b1 + step;
+    B1.setup(X, P, m, S, b1 < nblk ? b1 : first, g4, c16, b1 < nblk);
+    B1.load(x1, m);
+    block(x0, kSet0);
+    B0.setup(X, P, m, S, b2 < nblk ? b2 : first, g4, c16, b2 < nblk);
+    B0.load(x0, m);
+    block(x1, kSet1);
   }
   // the workgroup's sum in wave order, then one FP64 partial: tile (i, j), register
   // v of lane l is G[16 i + 4 (l / 16) + v][16 j + l % 16]
@@ -1308,19 +1367,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SL == 0 && 
   double* myR = sRw + wave * WREG;
   const int nblk = (int)RegBlock<SL>::blocks(P, S);
   __syncthreads();
-  for (int g0 = blockIdx.x * 4; g0 < nblk; g0 += gridDim.x * 4) {  // uniform over the workgroup
-    const int blk = g0 + wave;
-    float x[NT][NH];
-    if (blk < nblk) {
-      RegBlock<SL> B;
-      B.setup(X, P, m, S, blk, g4, c16);
-      B.load(x, m);
-    } else {
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int h = 0; h < NH; ++h) x[t][h] = 0.f;
-    }
+  // one step of the workgroup (block g0 + wave of every wave; zeros past the last)
+  auto block = [&](float (&x)[NT][NH], auto set) {
+    reg_set_mark<decltype(set)::value>();
     d4 zz[RESID ? RT : 1][NH];
     if (RESID) {
 #pragma unroll
@@ -1391,6 +1440,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SL == 0 && 
         __syncthreads();
       }
     }
+  };
+  // two register sets, the next step's loads in flight during the current one.  The
+  // loop runs whole pairs of steps with no branch between a load and its use (the
+  // compiler would sink the loads to their use); a wave past the last block reads an
+  // empty buffer as zeros (no memory access), which add nothing to the Gram.
+  const int step = gridDim.x * 4;
+  const int g0 = blockIdx.x * 4;  // uniform over the workgroup
+  const int pairs = g0 < nblk ? ((nblk - 1 - g0) / step + 2) / 2 : 0;
+  RegBlock<SL> B0, B1;
+  float x0[NT][NH], x1[NT][NH];
+  auto setup = [&](RegBlock<SL>& B, int g) {
+    const bool ok = g + wave < nblk;
+    B.setup(X, P, m, S, ok ? g + wave : 0, g4, c16, ok);
+  };
+  if (pairs > 0) {
+    setup(B0, g0);
+    B0.load(x0, m);
+  }
+  for (int q = 0; q < pairs; ++q) {
+    setup(B1, g0 + (2 * q + 1) * step);
+    B1.load(x1, m);
+    block(x0, kSet0);
+    setup(B0, g0 + (2 * q + 2) * step);
+    B0.load(x0, m);
+    block(x1, kSet1);
   }
   double* out = part + (int64_t)blockIdx.x * m * m;
   if constexpr (ALL) {
