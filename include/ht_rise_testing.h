@@ -43,6 +43,14 @@ ht_status ht_test_ttm_contract(const void* x, int32_t dtype, int64_t P, int64_t 
 ht_status ht_test_resid_gram_f32(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
                                  int32_t R, double* G, double* scratch, void* hip_stream);
 
+/* Mixed form: the residual Gram above as (I - U U^T) G (I - U U^T) from the FP64 Gram
+ * G = X_(k) X_(k)^T, no residual formed (the identity R R^T = (I - U U^T) G (I - U U^T)
+ * of Eq. compute_residual).  FP32 x in register-direct blocks only: m % 4 == 0,
+ * m <= 128 and S % 32 == 0 (or S <= 4 with 32 < m <= 96 and R <= 32); else
+ * HT_EINVAL.  Same arguments and scratch as ht_test_resid_gram. */
+ht_status ht_test_resid_gram_proj(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
+                                  int32_t R, double* G, double* scratch, void* hip_stream);
+
 /* Mixed form contraction: Z (float32, [P][R][S]) = U^T X on FP32 matrix cores, with
  * norm2[0] = ||X||^2 and resid2[0] = ||X - U U^T X||^2 (the explicit residual of
  * Eq. compute_residual, summed in FP64).  m <= 128, 1 <= R <= 64; scratch holds

@@ -462,6 +462,14 @@ constexpr double kResidK = 2.0;
 constexpr double kChainK = 0.75;
 constexpr double kGramK = 4.0;
 
+// A residual Gram taken as (I - U U^T) M M^T (I - U U^T) from the FP64 Gram of M
+// carries the rounding of M M^T, relative to ||M||^2 <= ||Y||^2 rather than to the
+// residual's trace: its tail sums move by at most kGramProjK u64 ||Y||^2 (measured on
+// the register-direct shapes of the test streams: at most 16 u64 ||M||^2).  It is used
+// where that stays below a thousandth of the threshold.
+constexpr double kGramProjK = 1024.0;
+bool gram_proj_ok(double ny, double thr) { return kGramProjK * kU64 * ny * ny <= 1e-3 * thr; }
+
 // Frobenius error bound of a residual formed (own = rank + 1 when formed in FP32, else
 // 0) from a level tensor with the FP32 history chain = sum (rank + 1).
 double resid_err(double ny, double own, double chain) {
@@ -772,16 +780,21 @@ struct LayerJobs {
   std::vector<ht::EigJob> jobs;
   std::vector<int> node, rold;
   std::vector<char> f32;  // the job's Gram has FP32 products (mixed form)
+  std::vector<char> gm;   // the job's residual Gram is the projected FP64 Gram of M (mixed form)
   std::vector<ModeView> view;
 };
 
 // Gram launches of layer ell and the eigen jobs they feed.
 // The Gram of node's unfolding (view v of cur): of the data (r_old = 0) or of the
-// explicit residual R = M - U_old U_old^T M (Eq. compute_residual); FP32 products when
-// f32 (modes of at most 128 rows).
-void node_gram(ht_state* h, int node, const Level& cur, const ModeView& v, int r_old, bool f32, hipStream_t s) {
+// residual R = M - U_old U_old^T M (Eq. compute_residual): formed explicitly, with FP32
+// products when f32 (modes of at most 128 rows), or with gm as
+// (I - U_old U_old^T) M M^T (I - U_old U_old^T) from the FP64 Gram of M.
+void node_gram(ht_state* h, int node, const Level& cur, const ModeView& v, int r_old, bool f32, hipStream_t s,
+               bool gm = false) {
   if (r_old == 0) {
     ht::gram(cur.ptr, cur.t, v, h->gpart, h->gram[node], s);
+  } else if (gm) {
+    ht::resid_gram_proj(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], s);
   } else if (v.m <= ht::kResidGramMaxM) {
     // formed in registers or tile by tile in LDS, never written out
     if (f32)
@@ -796,8 +809,9 @@ void node_gram(ht_state* h, int node, const Level& cur, const ModeView& v, int r
   }
 }
 
+// proj: the handle's error budget admits residual Grams from the Gram of M (gram_proj_ok).
 void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initial, bool mixed, hipStream_t s,
-                 LayerJobs& L, int only_k = -1, const std::vector<char>* fp64 = nullptr) {
+                 LayerJobs& L, int only_k = -1, const std::vector<char>* fp64 = nullptr, bool proj = false) {
   const std::vector<int> f = h->tree.frontier(ell);
   for (size_t k = 0; k < f.size(); ++k) {
     const int node = f[k];
@@ -809,9 +823,11 @@ void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initia
     if (alpha - r_old <= 0) continue;  // the basis already spans the whole mode
     // at the rank cap the decision still runs (rmax = 0) to detect a needed growth
     const int room = std::max(0, std::min(alpha, h->rank_cap) - r_old);
-    const bool f32 = mixed && r_old > 0 && v.m <= ht::kResidGramMaxM && !(fp64 && (*fp64)[node]);
-    node_gram(h, node, cur, v, r_old, f32, s);
+    const bool gm = mixed && proj && r_old > 0 && ht::resid_gram_proj_applies(cur.t, v, r_old);
+    const bool f32 = !gm && mixed && r_old > 0 && v.m <= ht::kResidGramMaxM && !(fp64 && (*fp64)[node]);
+    node_gram(h, node, cur, v, r_old, f32, s, gm);
     L.f32.push_back(f32 ? 1 : 0);
+    L.gm.push_back(gm ? 1 : 0);
     L.view.push_back(v);
     ht::EigJob j;
     j.G = h->gram[node];
@@ -1116,7 +1132,8 @@ void certify_layer(Upd& u, int ell, bool fp64_pass, std::vector<int>* redo_jobs)
     const double own = f32 ? u.L.rold[q] + 1.0 : 0.0;
     const double dR = resid_err(u.ny, own, chain);
     const double tr = h->h_aux[2 * node];
-    const double gerr = kGramK * (f32 ? kU32 : kU64) * tr + u.thr_err;
+    const bool gm = !fp64_pass && u.L.gm[q];
+    const double gerr = (gm ? kGramProjK * kU64 * u.ny * u.ny : kGramK * (f32 ? kU32 : kU64) * tr) + u.thr_err;
     bool ok = decision_certified(u.rk[node], u.L.jobs[q].rmin, u.L.jobs[q].rmax, u.tl[node],
                                  h->h_aux[2 * node + 1], u.thr, dR, gerr);
     // The kept vectors must be accurate too, not only their number: a Gram error E
@@ -1328,9 +1345,10 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
         const std::vector<int>* only = only_of(a);
         std::vector<char> f64;
         fp64_nodes(u, layer_of(u), f64);
-        layer_grams(u.h, layer_of(u), u.cur, u.thr, false, u.mixed, s, u.L, only ? (*only)[0] : -1, &f64);
+        layer_grams(u.h, layer_of(u), u.cur, u.thr, false, u.mixed, s, u.L, only ? (*only)[0] : -1, &f64,
+                    u.mixed && gram_proj_ok(u.ny, u.thr));
         for (size_t q = 0; q < u.L.node.size(); ++q)
-          if (u.mixed && !u.L.f32[q] && f64[u.L.node[q]]) u.recomputed += 1;
+          if (u.mixed && !u.L.f32[q] && !u.L.gm[q] && f64[u.L.node[q]]) u.recomputed += 1;
         all.insert(all.end(), u.L.jobs.begin(), u.L.jobs.end());
         if (u.mixed) aux_jobs(u, nullptr, aux);
       }

@@ -644,6 +644,60 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
   G[e] = acc;
 }
 
+// --------------------------------------------------------------------------
+// Residual Gram from the Gram of the data: for R = M - U U^T M,
+//   R R^T = (I - U U^T) G (I - U U^T),  G = M M^T,
+// for any U (I - U U^T is symmetric).  With B = U^T G, V = B U (= U^T G U) and
+// E = B - V U^T / 2 it is G - U E - E^T U^T, which is symmetric by construction
+// and written so.  G is m x m row-major and symmetric, U is m x R column-major;
+// one workgroup (m <= 128, R <= 64), E and V in LDS, the result in place.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gram_project_kernel(double* __restrict__ G, int m, const double* __restrict__ U,
+                                                           int R) {
+  extern __shared__ double gpE[];
+  double* E = gpE;          // R x m: B, then E
+  double* V = gpE + R * m;  // R x R
+  const int tid = threadIdx.x;
+  for (int e = tid; e < R * m; e += 256) {  // B = U^T G (column j of G: coalesced over j)
+    const int r = e / m, j = e - r * m;
+    const double* u = U + (int64_t)r * m;
+    double a0 = 0.0, a1 = 0.0;
+    int i = 0;
+    for (; i + 1 < m; i += 2) {
+      a0 = fma(u[i], G[(int64_t)i * m + j], a0);
+      a1 = fma(u[i + 1], G[(int64_t)(i + 1) * m + j], a1);
+    }
+    if (i < m) a0 = fma(u[i], G[(int64_t)i * m + j], a0);
+    E[e] = a0 + a1;
+  }
+  __syncthreads();
+  for (int e = tid; e < R * R; e += 256) {  // V = B U
+    const int r = e / R, q = e - r * R;
+    const double* u = U + (int64_t)q * m;
+    double acc = 0.0;
+    for (int j = 0; j < m; ++j) acc = fma(E[r * m + j], u[j], acc);
+    V[e] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < R * m; e += 256) {  // E = B - V U^T / 2
+    const int r = e / m, j = e - r * m;
+    double acc = 0.0;
+    for (int q = 0; q < R; ++q) acc = fma(V[r * R + q], U[j + (int64_t)q * m], acc);
+    E[e] -= 0.5 * acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < m * m; e += 256) {  // upper triangle: G - U E - E^T U^T, mirrored
+    const int i = e / m, j = e - i * m;
+    if (i > j) continue;
+    double acc = 0.0;
+    for (int r = 0; r < R; ++r)
+      acc = fma(U[i + (int64_t)r * m], E[r * m + j], fma(E[r * m + i], U[j + (int64_t)r * m], acc));
+    const double g = G[e] - acc;
+    G[e] = g;
+    G[(int64_t)j * m + i] = g;
+  }
+}
+
 struct GramPlan {
   int nb, npairs, nsplit, tw;
   int64_t ktiles, kt_per_split, blk;
@@ -1608,7 +1662,7 @@ constexpr int TUS = 65;  // LDS row stride (doubles) of the staged U chunk of th
 // added in wave order through LDS.
 // --------------------------------------------------------------------------
 constexpr int kDirectLdsDoubles = 19968;  // U chunk: chunk x (RP + 1) doubles of dynamic LDS
-constexpr unsigned kDirectColsMinBlocks = 4096;  // column blocks from which whole blocks go to waves
+constexpr unsigned kDirectColsMinBlocks = 1024;  // column blocks from which whole blocks go to waves
 
 // SQ: also the workgroup partials of ||X||^2 (in_part) and ||Z||^2 (out_part)
 template <typename T, bool SQ>
@@ -2240,7 +2294,9 @@ size_t gram_partial_bound(int64_t m) {
 size_t gram_partial_doubles(const ModeView& v) {
   if (v.m <= kSmallM) return (size_t)kSmallBlocks * (kSmallM * (kSmallM + 1) / 2);
   const GramPlan g = gram_plan(v);
-  return (size_t)g.nsplit * g.npairs * g.blk;
+  // (the register-direct Grams write up to 512 partials of m x m)
+  const size_t reg = v.m <= kResidGramMaxM ? (size_t)512 * v.m * v.m : 0;
+  return std::max<size_t>((size_t)g.nsplit * g.npairs * g.blk, reg);
 }
 
 // Register-direct block mode of an FP32 mode view: 0 for column runs in blocks of
@@ -2270,6 +2326,12 @@ int reg_mode(Elem t, const ModeView& v, int R) {
   X(6, 1, 0) X(6, 2, 0) X(6, 3, 0) X(6, 4, 0) X(8, 1, 0) X(8, 2, 0)                                       \
   X(4, 1, 1) X(4, 2, 1) X(6, 1, 1) X(6, 2, 1) X(4, 1, 2) X(4, 2, 2) X(6, 1, 2) X(6, 2, 2)                 \
   X(4, 1, 3) X(4, 2, 3) X(6, 1, 3) X(6, 2, 3) X(4, 1, 4) X(4, 2, 4) X(6, 1, 4) X(6, 2, 4)
+
+// the FP64 Gram of the data on register-direct blocks (no basis): one instantiation
+// per row-tile count and block mode
+#define HT_GRAM64M_CASES(X)                                                                            \
+  X(2, 0) X(3, 0) X(4, 0) X(6, 0) X(8, 0) X(3, 1) X(3, 2) X(3, 3) X(3, 4) X(4, 1) X(4, 2) X(4, 3) X(4, 4) \
+  X(6, 1) X(6, 2) X(6, 3) X(6, 4)
 
 // row tiles of 16 of a register-direct kernel for an m-row mode: 2, 3, 4, 6 or 8 (an
 // odd count other than 3 is rounded up; three tiles cover the 33-48 row modes without
@@ -2362,6 +2424,63 @@ void gram_reg64(const float* x, const ModeView& v, int mode, const double* U, in
   gram_finish(g, v, part, G, s);
 }
 
+// FP64 Gram M M^T of an FP32 unfolding on register-direct blocks (block mode from
+// reg_mode): gram_reg64_kernel without a basis, at most 512 workgroup partials
+void gram_m64(const float* x, const ModeView& v, int mode, double* part, double* G, hipStream_t s) {
+  const int ti = reg_tiles(v.m);
+  const int64_t nblk = reg_blocks(v, mode);
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(512, (nblk + 3) / 4));
+  const size_t lds = (size_t)4 * 16 * ti * kGram64Ld * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+#define HT_GMA(TI, SL)                                                                              \
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_reg64_kernel<TI, 1, false, SL>),  \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
+    HT_GRAM64M_CASES(HT_GMA)
+#undef HT_GMA
+    attr = true;
+  }
+  const double K = (double)v.P * v.S, md = (double)v.m;
+  {
+    ProfScope prof(KKind::GramReg64, s, md * md * K, md * K * 4);
+#define HT_GM(TI, SL)                                                                                     \
+  case HT_REG_KEY(TI, 1, SL):                                                                             \
+    gram_reg64_kernel<TI, 1, false, SL><<<blocks, 256, lds, s>>>(x, v.P, (int)v.m, v.S, nullptr, 0, part); \
+    break;
+    switch (HT_REG_KEY(ti, 1, mode)) {
+      HT_GRAM64M_CASES(HT_GM)
+      default: break;
+    }
+#undef HT_GM
+  }
+  GramPlan g;
+  g.nb = 1;
+  g.npairs = 1;
+  g.nsplit = blocks;
+  g.blk = v.m * v.m;
+  gram_finish(g, v, part, G, s);
+}
+
+bool gram_reg_shape(Elem t, const ModeView& v, int R) { return reg_mode(t, v, R) >= 0; }
+
+bool resid_gram_proj_applies(Elem t, const ModeView& v, int R) {
+  return reg_mode(t, v, R) >= 0 && (double)v.P * v.m * v.S >= kGramProjMinElems;
+}
+
+void resid_gram_proj(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,
+                     hipStream_t s) {
+  gram_m64(static_cast<const float*>(x), v, reg_mode(t, v, R), part, G, s);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_project_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (64 * 128 + 64 * 64) * (int)sizeof(double));
+    attr = true;
+  }
+  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+  const size_t lds = ((size_t)R * v.m + (size_t)R * R) * sizeof(double);
+  gram_project_kernel<<<1, 256, lds, s>>>(G, (int)v.m, U, R);
+}
+
 void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hipStream_t s) {
   const double K = (double)v.P * v.S, md = (double)v.m;
   if (v.m <= kSmallM) {
@@ -2375,6 +2494,11 @@ void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hip
     }
     ProfScope prof(KKind::Layout, s, 0.0, 0.0);
     gram_small_reduce_kernel<<<(unsigned)(v.m * v.m), 256, 0, s>>>(part, (int)v.m, kSmallBlocks, G);
+    return;
+  }
+  const int mode = reg_mode(t, v, 1);
+  if (mode >= 0) {  // FP32 data in register-direct blocks
+    gram_m64(static_cast<const float*>(x), v, mode, part, G, s);
     return;
   }
   const GramPlan g = gram_plan(v);

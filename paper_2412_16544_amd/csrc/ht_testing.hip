@@ -56,6 +56,15 @@ ht_status ht_test_resid_gram_f32(const void* x, int32_t dtype, int64_t P, int64_
   return hipGetLastError() == hipSuccess ? HT_OK : HT_EDEVICE;
 }
 
+ht_status ht_test_resid_gram_proj(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
+                                  int32_t R, double* G, double* scratch, void* s) {
+  if (!x || !U || !G || !scratch || P < 1 || m < 1 || S < 1 || R < 1 || R > 64 || !ok_dtype(dtype) ||
+      !ht::gram_reg_shape(elem(dtype), ht::ModeView{P, m, S}, R))
+    return HT_EINVAL;
+  ht::resid_gram_proj(x, elem(dtype), ht::ModeView{P, m, S}, U, R, scratch, G, st(s));
+  return hipGetLastError() == hipSuccess ? HT_OK : HT_EDEVICE;
+}
+
 size_t ht_test_ttm_partials_doubles(void) { return ht::ttm_norm_partials(); }
 
 ht_status ht_test_ttm_contract_f32(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,

@@ -326,6 +326,7 @@ def _tlib():
         L.ht_test_ttm_contract.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp]
         L.ht_test_resid_gram.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, vp]
         L.ht_test_resid_gram_f32.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, vp]
+        L.ht_test_resid_gram_proj.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, vp]
         L.ht_test_ttm_partials_doubles.argtypes = []
         L.ht_test_ttm_partials_doubles.restype = sz
         L.ht_test_ttm_contract_f32.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, vp, vp, vp]
@@ -338,6 +339,7 @@ def _tlib():
         L.ht_test_decision_certified.argtypes = [i32, i32, i32, dbl, dbl, dbl, dbl, dbl]
         L.ht_test_decision_certified.restype = i32
         for name in ("ht_test_sumsq", "ht_test_gram", "ht_test_resid_gram", "ht_test_resid_gram_f32",
+                     "ht_test_resid_gram_proj",
                      "ht_test_ttm_contract", "ht_test_ttm_contract_f32", "ht_test_ttm_expand", "ht_test_eig",
                      "ht_test_eig_method", "ht_test_orth_expand"):
             getattr(L, name).restype = ctypes.c_int
@@ -386,6 +388,17 @@ def ht_test_resid_gram_f32(x, P: int, m: int, S: int, U, stream=None):
     Ucm = U.t().contiguous()
     _check(L.ht_test_resid_gram_f32(_ptr(x), _dt(x), P, m, S, _ptr(Ucm), U.shape[1], _ptr(G), _ptr(sc),
                                     _stream(stream)), "ht_test_resid_gram_f32")
+    return G
+
+
+def ht_test_resid_gram_proj(x, P: int, m: int, S: int, U, stream=None):
+    import torch
+    L = _tlib()
+    sc = torch.empty(max(1, L.ht_test_gram_scratch_doubles(P, m, S)), dtype=torch.float64, device=x.device)
+    G = torch.empty((m, m), dtype=torch.float64, device=x.device)
+    Ucm = U.t().contiguous()
+    _check(L.ht_test_resid_gram_proj(_ptr(x), _dt(x), P, m, S, _ptr(Ucm), U.shape[1], _ptr(G), _ptr(sc),
+                                     _stream(stream)), "ht_test_resid_gram_proj")
     return G
 
 

@@ -30,7 +30,7 @@ GRAM_SHAPES = [(1, 1, 1), (3, 8, 1), (2, 9, 31), (6, 33, 32), (3, 96, 1000), (5,
                (4, 256, 3), (9, 40, 64), (1, 300, 2),
                # register-direct blocks (FP32 input): runs in blocks of 32, and runs of 1-4 columns
                (3, 96, 1024), (2, 128, 64), (5, 40, 96), (64, 12, 16384), (100, 96, 3), (37, 64, 1), (50, 48, 2),
-               (19, 96, 4)]
+               (19, 96, 4), (3, 120, 32), (4, 108, 64)]
 
 
 @pytest.mark.parametrize("P,m,S", GRAM_SHAPES)
@@ -64,6 +64,48 @@ def test_resid_gram(P, m, S, R, dtype):
     assert np.max(np.abs(G - ref)) <= 1e-12 * max(1.0, np.max(np.abs(M @ M.T)))
 
 
+# The residual Gram as (I - U U^T) M M^T (I - U U^T) from the FP64 Gram of M
+# (register-direct shapes; 128 rows with 64 basis columns; runs of 1-4 columns;
+# eight row tiles).  M near the span of U, as in HT-RISE, so the residual is small next
+# to M: the explicit FP64 residual Gram is exact to ~u ||R|| ||M||, and the comparison
+# sees the rounding of M M^T, relative to ||M||^2 (u = 2^-53).
+PROJ_SHAPES = [(3, 96, 1024, 12), (2, 128, 64, 64), (5, 40, 96, 20), (4, 48, 2048, 6), (64, 12, 512, 3),
+               (50, 40, 2, 20), (100, 36, 4, 12), (7, 64, 3, 30), (9, 92, 1, 32), (3, 120, 32, 40),
+               (8, 48, 65536, 6)]
+
+
+def proj_inputs(P, m, S, R, seed):
+    g = rng(seed)
+    Q, _ = np.linalg.qr(g.standard_normal((m, m)))
+    scale = np.where(np.arange(m) < R, 1.0, 1e-3)
+    M = Q @ (scale[:, None] * g.standard_normal((m, P * S)))
+    x = np.ascontiguousarray(M.reshape(m, P, S).transpose(1, 0, 2), dtype=np.float32)
+    return x, Q[:, :R].copy()
+
+
+@pytest.mark.parametrize("P,m,S,R", PROJ_SHAPES)
+def test_resid_gram_proj(P, m, S, R):
+    x, U = proj_inputs(P, m, S, R, 11 * P + m + S + R)
+    G = H.ht_test_resid_gram_proj(torch.from_numpy(x).cuda(), P, m, S, torch.from_numpy(U).cuda()).cpu().numpy()
+    M = unfold_np(x.astype(np.float64), P, m, S)
+    Rr = M - U @ (U.T @ M)
+    ref = Rr @ Rr.T
+    unit = 2.0 ** -53 * float(np.sum(M * M))
+    assert np.array_equal(G, G.T)
+    err = np.max(np.abs(G - ref)) / unit
+    # tail sums (the quantities the rank rule reads) of the two Grams
+    lg, lr = np.linalg.eigvalsh(G)[::-1], np.linalg.eigvalsh(ref)[::-1]
+    terr = np.max(np.abs(np.cumsum(lg[::-1])[::-1] - np.cumsum(lr[::-1])[::-1])) / unit
+    assert err <= 16.0 and terr <= 16.0, (err, terr)
+
+
+def test_resid_gram_proj_rejects_other_shapes():
+    x = torch.zeros(3 * 50 * 33, dtype=torch.float32).cuda()
+    U = torch.zeros((50, 4), dtype=torch.float64).cuda()
+    with pytest.raises(H.HTError):
+        H.ht_test_resid_gram_proj(x, 3, 50, 33, U)
+
+
 @pytest.mark.parametrize("P,m,S,R", [(3, 96, 1000, 12), (5, 3, 7, 3), (100, 16, 1, 5), (2, 200, 33, 64),
                                      (1, 130, 40, 17), (7, 17, 5, 1), (4, 64, 300, 16), (50, 9, 1, 9),
                                      # column runs in whole blocks of 32, m % 4 == 0: register-direct FP64
@@ -71,9 +113,11 @@ def test_resid_gram(P, m, S, R, dtype):
                                      (64, 8, 16384, 3), (3, 4, 32, 1), (4, 48, 2048, 18), (3, 44, 64, 40),
                                      # modes of more than 128 rows: U staged once, or in chunks (m = 600)
                                      (16, 182, 42, 40), (3, 600, 50, 40), (2, 131, 1, 64),
-                                     # ... and with 4096 column blocks or more, whole blocks per wave
-                                     # (a ragged last block; U in two chunks for m = 300)
+                                     # ... and with 1024 column blocks of 16 or more, whole blocks per
+                                     # wave (a ragged last block; U in two chunks for m = 300; 1024 to
+                                     # 4096 blocks, fewer tiles of eight than workgroups could run)
                                      (64, 160, 1100, 24), (5, 131, 13109, 17), (7, 300, 10000, 46),
+                                     (16, 400, 1600, 30), (3, 200, 5999, 20), (1, 144, 16384, 16),
                                      # LDS-panel kernel (42 and 47 rows, runs not in blocks of 32)
                                      (5824, 42, 1, 30), (3, 47, 9, 47),
                                      # modes of at most 8 rows: one column per thread (S > 1 with
