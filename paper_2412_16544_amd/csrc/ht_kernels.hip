@@ -650,49 +650,66 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
 // for any U (I - U U^T is symmetric).  With B = U^T G, V = B U (= U^T G U) and
 // E = B - V U^T / 2 it is G - U E - E^T U^T, which is symmetric by construction
 // and written so.  G is m x m row-major and symmetric, U is m x R column-major;
-// one workgroup (m <= 128, R <= 64), E and V in LDS, the result in place.
+// one workgroup (m <= 128, R <= 64), the result in place.  E and V sit in LDS, and
+// U and G too when STAGE (then every inner loop reads LDS only).
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gram_project_kernel(double* __restrict__ G, int m, const double* __restrict__ U,
-                                                           int R) {
-  extern __shared__ double gpE[];
-  double* E = gpE;          // R x m: B, then E
-  double* V = gpE + R * m;  // R x R
+constexpr int kProjThreads = 512;
+constexpr int kProjLdsDoubles = 19456;  // 152 KiB
+
+__host__ __device__ constexpr int proj_lds_doubles(int m, int R, bool stage) {
+  return R * m + R * R + (stage ? m * m + R * m : 0);
+}
+
+template <bool STAGE>
+__global__ __launch_bounds__(kProjThreads) void gram_project_kernel(double* __restrict__ G, int m,
+                                                                    const double* __restrict__ U, int R) {
+  extern __shared__ double gpL[];
+  double* E = gpL;               // R x m: B, then E
+  double* V = E + R * m;         // R x R
+  double* Gs = V + R * R;        // G (STAGE)
+  double* Ul = Gs + m * m;       // U, m x R column-major (STAGE)
+  const double* Gr = STAGE ? Gs : G;
+  const double* Us = STAGE ? Ul : U;
   const int tid = threadIdx.x;
-  for (int e = tid; e < R * m; e += 256) {  // B = U^T G (column j of G: coalesced over j)
+  if (STAGE) {
+    for (int e = tid; e < R * m; e += kProjThreads) Ul[e] = U[e];
+    for (int e = tid; e < m * m; e += kProjThreads) Gs[e] = G[e];
+    __syncthreads();
+  }
+  for (int e = tid; e < R * m; e += kProjThreads) {  // B = U^T G
     const int r = e / m, j = e - r * m;
-    const double* u = U + (int64_t)r * m;
+    const double* u = Us + r * m;
     double a0 = 0.0, a1 = 0.0;
     int i = 0;
     for (; i + 1 < m; i += 2) {
-      a0 = fma(u[i], G[(int64_t)i * m + j], a0);
-      a1 = fma(u[i + 1], G[(int64_t)(i + 1) * m + j], a1);
+      a0 = fma(u[i], Gr[i * m + j], a0);
+      a1 = fma(u[i + 1], Gr[(i + 1) * m + j], a1);
     }
-    if (i < m) a0 = fma(u[i], G[(int64_t)i * m + j], a0);
+    if (i < m) a0 = fma(u[i], Gr[i * m + j], a0);
     E[e] = a0 + a1;
   }
   __syncthreads();
-  for (int e = tid; e < R * R; e += 256) {  // V = B U
+  for (int e = tid; e < R * R; e += kProjThreads) {  // V = B U
     const int r = e / R, q = e - r * R;
-    const double* u = U + (int64_t)q * m;
+    const double* u = Us + q * m;
     double acc = 0.0;
     for (int j = 0; j < m; ++j) acc = fma(E[r * m + j], u[j], acc);
     V[e] = acc;
   }
   __syncthreads();
-  for (int e = tid; e < R * m; e += 256) {  // E = B - V U^T / 2
+  for (int e = tid; e < R * m; e += kProjThreads) {  // E = B - V U^T / 2 (reads V and U only)
     const int r = e / m, j = e - r * m;
     double acc = 0.0;
-    for (int q = 0; q < R; ++q) acc = fma(V[r * R + q], U[j + (int64_t)q * m], acc);
+    for (int q = 0; q < R; ++q) acc = fma(V[r * R + q], Us[j + q * m], acc);
     E[e] -= 0.5 * acc;
   }
   __syncthreads();
-  for (int e = tid; e < m * m; e += 256) {  // upper triangle: G - U E - E^T U^T, mirrored
+  for (int e = tid; e < m * m; e += kProjThreads) {  // upper triangle: G - U E - E^T U^T, mirrored
     const int i = e / m, j = e - i * m;
     if (i > j) continue;
     double acc = 0.0;
-    for (int r = 0; r < R; ++r)
-      acc = fma(U[i + (int64_t)r * m], E[r * m + j], fma(E[r * m + i], U[j + (int64_t)r * m], acc));
-    const double g = G[e] - acc;
+    for (int r = 0; r < R; ++r) acc = fma(Us[i + r * m], E[r * m + j], fma(E[r * m + i], Us[j + r * m], acc));
+    const double g = Gr[e] - acc;
     G[e] = g;
     G[(int64_t)j * m + i] = g;
   }
@@ -2472,13 +2489,18 @@ void resid_gram_proj(const void* x, Elem t, const ModeView& v, const double* U, 
   gram_m64(static_cast<const float*>(x), v, reg_mode(t, v, R), part, G, s);
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_project_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (64 * 128 + 64 * 64) * (int)sizeof(double));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_project_kernel<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kProjLdsDoubles * (int)sizeof(double));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_project_kernel<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kProjLdsDoubles * (int)sizeof(double));
     attr = true;
   }
   ProfScope prof(KKind::Layout, s, 0.0, 0.0);
-  const size_t lds = ((size_t)R * v.m + (size_t)R * R) * sizeof(double);
-  gram_project_kernel<<<1, 256, lds, s>>>(G, (int)v.m, U, R);
+  const int m = (int)v.m;
+  if (proj_lds_doubles(m, R, true) <= kProjLdsDoubles)
+    gram_project_kernel<true><<<1, kProjThreads, proj_lds_doubles(m, R, true) * sizeof(double), s>>>(G, m, U, R);
+  else
+    gram_project_kernel<false><<<1, kProjThreads, proj_lds_doubles(m, R, false) * sizeof(double), s>>>(G, m, U, R);
 }
 
 void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hipStream_t s) {
