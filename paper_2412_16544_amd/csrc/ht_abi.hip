@@ -794,7 +794,7 @@ void node_gram(ht_state* h, int node, const Level& cur, const ModeView& v, int r
   if (r_old == 0) {
     ht::gram(cur.ptr, cur.t, v, h->gpart, h->gram[node], s);
   } else if (gm) {
-    ht::resid_gram_proj(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], s);
+    ht::resid_gram_proj(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], h->bufZ, s);
   } else if (v.m <= ht::kResidGramMaxM) {
     // formed in registers or tile by tile in LDS, never written out
     if (f32)
@@ -823,7 +823,8 @@ void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initia
     if (alpha - r_old <= 0) continue;  // the basis already spans the whole mode
     // at the rank cap the decision still runs (rmax = 0) to detect a needed growth
     const int room = std::max(0, std::min(alpha, h->rank_cap) - r_old);
-    const bool gm = mixed && proj && r_old > 0 && ht::resid_gram_proj_applies(cur.t, v, r_old);
+    const bool gm = mixed && proj && r_old > 0 && ht::resid_gram_proj_applies(cur.t, v, r_old) &&
+                    ht::resid_gram_proj_work_doubles(v.m, r_old) <= h->resid_elems;
     const bool f32 = !gm && mixed && r_old > 0 && v.m <= ht::kResidGramMaxM && !(fp64 && (*fp64)[node]);
     node_gram(h, node, cur, v, r_old, f32, s, gm);
     L.f32.push_back(f32 ? 1 : 0);

@@ -200,10 +200,13 @@ __device__ __forceinline__ void tile_of(int t, bool diag, int tI, int tJ, int& t
 // S, each row segment contiguous), loaded by this helper into registers one tile
 // ahead; when S < GBK it is floor(GBK/S) whole slices p, one contiguous block of
 // memory, scattered straight into LDS by the kernel.
+// The values stay in the data type until they are stored to LDS: a conversion right
+// after the load would make the wave wait for it there, and the tile ahead would no
+// longer overlap the products of the current one.
 template <typename T>
 __device__ __forceinline__ void gram_load_tile(const T* __restrict__ X, int64_t m, int64_t S, int64_t K, int64_t kt,
                                                int tw, int64_t rowI0, int rowsI, int64_t rowJ0, int rowsJ, bool diag,
-                                               double (&ri)[GBK * GB / 256], double (&rj)[GBK * GB / 256]) {
+                                               T (&ri)[GBK * GB / 256], T (&rj)[GBK * GB / 256]) {
   constexpr int PER = GBK * GB / 256;
   // thread owns column kk = tid % GBK of the tile and rows tid / GBK + 8 q
   const int kk = threadIdx.x % GBK;
@@ -213,8 +216,8 @@ __device__ __forceinline__ void gram_load_tile(const T* __restrict__ X, int64_t 
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int row = threadIdx.x / GBK + q * (256 / GBK);
-    ri[q] = (cv && row < rowsI) ? ld(X, base + (rowI0 + row) * S) : 0.0;
-    rj[q] = (!diag && cv && row < rowsJ) ? ld(X, base + (rowJ0 + row) * S) : 0.0;
+    ri[q] = (cv && row < rowsI) ? X[base + (rowI0 + row) * S] : T(0);
+    rj[q] = (!diag && cv && row < rowsJ) ? X[base + (rowJ0 + row) * S] : T(0);
   }
 }
 
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
   const bool slab = S < GBK;
   const int ms = (int)(m * S);
 
-  double ri[PER], rj[PER];
+  T ri[PER], rj[PER];
   if (kt0 < kt1 && !slab)
     gram_load_tile(X, m, S, K, kt0, tw, rowI0, rowsI, rowJ0, rowsJ, diag, ri, rj);
   for (int64_t kt = kt0; kt < kt1; ++kt) {
@@ -292,8 +295,8 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
       for (int q = 0; q < PER; ++q) {
         const int kk = threadIdx.x % GBK;
         const int row = threadIdx.x / GBK + q * (256 / GBK);
-        sI[kk * GLD + row] = ri[q];
-        if (!diag) sJ[kk * GLD + row] = rj[q];
+        sI[kk * GLD + row] = static_cast<double>(ri[q]);
+        if (!diag) sJ[kk * GLD + row] = static_cast<double>(rj[q]);
       }
       // prefetch the next tile while this one is multiplied
       if (kt + 1 < kt1) gram_load_tile(X, m, S, K, kt + 1, tw, rowI0, rowsI, rowJ0, rowsJ, diag, ri, rj);
@@ -713,6 +716,63 @@ __global__ __launch_bounds__(kProjThreads) void gram_project_kernel(double* __re
     G[e] = g;
     G[(int64_t)j * m + i] = g;
   }
+}
+
+// The same projection for modes of more than 128 rows, in four launches over global
+// memory (G in L2): B = U^T G, V = B U, E = B - V U^T / 2, then the upper triangle
+// of G - U E - E^T U^T, mirrored.  Reads of G, U and E are coalesced along the
+// thread index or broadcast over a wave.
+__global__ __launch_bounds__(256) void gram_proj_b_kernel(const double* __restrict__ G, int m,
+                                                          const double* __restrict__ U, int R, double* __restrict__ B) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)R * m) return;
+  const int r = (int)(e / m), j = (int)(e - (int64_t)r * m);
+  const double* u = U + (int64_t)r * m;
+  double a0 = 0.0, a1 = 0.0;
+  int i = 0;
+  for (; i + 1 < m; i += 2) {
+    a0 = fma(u[i], G[(int64_t)i * m + j], a0);
+    a1 = fma(u[i + 1], G[(int64_t)(i + 1) * m + j], a1);
+  }
+  if (i < m) a0 = fma(u[i], G[(int64_t)i * m + j], a0);
+  B[e] = a0 + a1;
+}
+
+__global__ __launch_bounds__(256) void gram_proj_v_kernel(const double* __restrict__ B, int m,
+                                                          const double* __restrict__ U, int R, double* __restrict__ V) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= R * R) return;
+  const int r = e / R, q = e - r * R;
+  const double* b = B + (int64_t)r * m;
+  const double* u = U + (int64_t)q * m;
+  double acc = 0.0;
+  for (int j = 0; j < m; ++j) acc = fma(b[j], u[j], acc);
+  V[e] = acc;
+}
+
+__global__ __launch_bounds__(256) void gram_proj_e_kernel(const double* __restrict__ B, int m,
+                                                          const double* __restrict__ U, int R,
+                                                          const double* __restrict__ V, double* __restrict__ E) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)R * m) return;
+  const int r = (int)(e / m), j = (int)(e - (int64_t)r * m);
+  double acc = 0.0;
+  for (int q = 0; q < R; ++q) acc = fma(V[r * R + q], U[j + (int64_t)q * m], acc);
+  E[e] = B[e] - 0.5 * acc;
+}
+
+__global__ __launch_bounds__(256) void gram_proj_g_kernel(double* __restrict__ G, int m, const double* __restrict__ U,
+                                                          int R, const double* __restrict__ E) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)m * m) return;
+  const int i = (int)(e / m), j = (int)(e - (int64_t)i * m);
+  if (i > j) return;
+  double acc = 0.0;
+  for (int r = 0; r < R; ++r)
+    acc = fma(U[i + (int64_t)r * m], E[(int64_t)r * m + j], fma(E[(int64_t)r * m + i], U[j + (int64_t)r * m], acc));
+  const double g = G[e] - acc;
+  G[e] = g;
+  G[(int64_t)j * m + i] = g;
 }
 
 struct GramPlan {
@@ -1707,21 +1767,21 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
     __syncthreads();
     const int nst = ac4 >> 2;
     const T* xp = X + base + a0 * S;
-    double b[8];
+    T b[8];  // in the data type until used: a conversion at the load would wait for it
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int a = 4 * (wave + 4 * q) + kr;
-      b[q] = (cv && a < ac) ? static_cast<double>(xp[(int64_t)a * S]) : 0.0;
+      b[q] = (cv && a < ac) ? xp[(int64_t)a * S] : T(0);
     }
     for (int j = 0; wave + 4 * j < nst; j += 8) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int st = wave + 4 * (j + q);
         if (st < nst) {
-          const double bv = b[q];
+          const double bv = static_cast<double>(b[q]);
           if (SQ) xsq = fma(bv, bv, xsq);
           const int an = 4 * (st + 32) + kr;
-          b[q] = (cv && an < ac) ? static_cast<double>(xp[(int64_t)an * S]) : 0.0;
+          b[q] = (cv && an < ac) ? xp[(int64_t)an * S] : T(0);
           const double* ua = sU + (4 * st + kr) * ULD + (lane & 15);
 #pragma unroll
           for (int t = 0; t < 4; ++t)
@@ -1813,13 +1873,12 @@ __global__ __launch_bounds__(256) void ttm_direct_cols_kernel(const T* __restric
       __syncthreads();
       const int nst = ac4 >> 2;
       for (int st = 0; st < nst; st += 4) {  // four row steps of both blocks: eight loads in flight
-        double b[2][4];
+        T b[2][4];  // converted at use: all eight loads go out first
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int a = 4 * (st + q) + kr;
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
-            b[j][q] = (cv[j] && a < ac) ? static_cast<double>(X[base[j] + (a0 + a) * S]) : 0.0;
+          for (int j = 0; j < 2; ++j) b[j][q] = (cv[j] && a < ac) ? X[base[j] + (a0 + a) * S] : T(0);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -1827,10 +1886,11 @@ __global__ __launch_bounds__(256) void ttm_direct_cols_kernel(const T* __restric
             const double* ua = sU + (4 * (st + q) + kr) * ULD + (lane & 15);
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-              if (SQ) xsq = fma(b[j][q], b[j][q], xsq);
+              const double bv = static_cast<double>(b[j][q]);
+              if (SQ) xsq = fma(bv, bv, xsq);
 #pragma unroll
               for (int t = 0; t < 4; ++t)
-                if (t < rt) acc[j][t] = mfma16(ua[t * 16], b[j][q], acc[j][t]);
+                if (t < rt) acc[j][t] = mfma16(ua[t * 16], bv, acc[j][t]);
             }
           }
         }
@@ -2481,11 +2541,31 @@ void gram_m64(const float* x, const ModeView& v, int mode, double* part, double*
 bool gram_reg_shape(Elem t, const ModeView& v, int R) { return reg_mode(t, v, R) >= 0; }
 
 bool resid_gram_proj_applies(Elem t, const ModeView& v, int R) {
-  return reg_mode(t, v, R) >= 0 && (double)v.P * v.m * v.S >= kGramProjMinElems;
+  if ((double)v.P * v.m * v.S < kGramProjMinElems) return false;
+  if (v.m <= kResidGramMaxM) return reg_mode(t, v, R) >= 0;
+  return R >= 1 && R <= 64 && v.m <= kGramProjMaxM;
+}
+
+size_t resid_gram_proj_work_doubles(int64_t m, int R) {
+  return m <= kResidGramMaxM ? 0 : (size_t)2 * R * m + (size_t)R * R;
 }
 
 void resid_gram_proj(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,
-                     hipStream_t s) {
+                     double* work, hipStream_t s) {
+  if (v.m > kResidGramMaxM) {
+    gram(x, t, v, part, G, s);
+    ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+    const int m = (int)v.m;
+    double* B = work;
+    double* E = work + (size_t)R * m;
+    double* V = E + (size_t)R * m;
+    const unsigned nrm = (unsigned)(((int64_t)R * m + 255) / 256);
+    gram_proj_b_kernel<<<nrm, 256, 0, s>>>(G, m, U, R, B);
+    gram_proj_v_kernel<<<(unsigned)((R * R + 255) / 256), 256, 0, s>>>(B, m, U, R, V);
+    gram_proj_e_kernel<<<nrm, 256, 0, s>>>(B, m, U, R, V, E);
+    gram_proj_g_kernel<<<(unsigned)(((int64_t)m * m + 255) / 256), 256, 0, s>>>(G, m, U, R, E);
+    return;
+  }
   gram_m64(static_cast<const float*>(x), v, reg_mode(t, v, R), part, G, s);
   static bool attr = false;
   if (!attr) {

@@ -21,7 +21,7 @@ ht_status ht_test_sumsq(const void* x, int32_t dtype, int64_t n, double* out, do
 
 size_t ht_test_gram_scratch_doubles(int64_t P, int64_t m, int64_t S) {
   if (P < 1 || m < 1 || S < 1) return 0;
-  return ht::gram_partial_doubles(ht::ModeView{P, m, S});
+  return ht::gram_partial_doubles(ht::ModeView{P, m, S}) + ht::resid_gram_proj_work_doubles(m, 64);
 }
 
 ht_status ht_test_gram(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, double* G, double* scratch,
@@ -58,10 +58,12 @@ ht_status ht_test_resid_gram_f32(const void* x, int32_t dtype, int64_t P, int64_
 
 ht_status ht_test_resid_gram_proj(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
                                   int32_t R, double* G, double* scratch, void* s) {
+  const ht::ModeView v{P, m, S};
   if (!x || !U || !G || !scratch || P < 1 || m < 1 || S < 1 || R < 1 || R > 64 || !ok_dtype(dtype) ||
-      !ht::gram_reg_shape(elem(dtype), ht::ModeView{P, m, S}, R))
+      m > ht::kGramProjMaxM || (m <= ht::kResidGramMaxM && !ht::gram_reg_shape(elem(dtype), v, R)))
     return HT_EINVAL;
-  ht::resid_gram_proj(x, elem(dtype), ht::ModeView{P, m, S}, U, R, scratch, G, st(s));
+  // the projection's work follows the partials in the scratch
+  ht::resid_gram_proj(x, elem(dtype), v, U, R, scratch, G, scratch + ht::gram_partial_doubles(v), st(s));
   return hipGetLastError() == hipSuccess ? HT_OK : HT_EDEVICE;
 }
 

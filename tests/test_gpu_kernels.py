@@ -99,6 +99,25 @@ def test_resid_gram_proj(P, m, S, R):
     assert err <= 16.0 and terr <= 16.0, (err, terr)
 
 
+# modes of more than 128 rows (transfer nodes): the Gram of M by the large-mode Gram
+# kernel, FP32 or FP64 data, and the projection in four launches
+@pytest.mark.parametrize("P,m,S,R", [(2, 200, 1000, 30), (16, 400, 256, 24), (3, 576, 100, 64), (1, 129, 4000, 1)])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_resid_gram_proj_large_modes(P, m, S, R, dtype):
+    x, U = proj_inputs(P, m, S, R, 13 * P + m + S + R)
+    x = x.astype(dtype)
+    G = H.ht_test_resid_gram_proj(torch.from_numpy(x).cuda(), P, m, S, torch.from_numpy(U).cuda()).cpu().numpy()
+    M = unfold_np(x.astype(np.float64), P, m, S)
+    Rr = M - U @ (U.T @ M)
+    ref = Rr @ Rr.T
+    unit = 2.0 ** -53 * float(np.sum(M * M))
+    assert np.array_equal(G, G.T)
+    err = np.max(np.abs(G - ref)) / unit
+    lg, lr = np.linalg.eigvalsh(G)[::-1], np.linalg.eigvalsh(ref)[::-1]
+    terr = np.max(np.abs(np.cumsum(lg[::-1])[::-1] - np.cumsum(lr[::-1])[::-1])) / unit
+    assert err <= 16.0 and terr <= 16.0, (err, terr)
+
+
 def test_resid_gram_proj_rejects_other_shapes():
     x = torch.zeros(3 * 50 * 33, dtype=torch.float32).cuda()
     U = torch.zeros((50, 4), dtype=torch.float64).cuda()
