@@ -26,6 +26,7 @@ sample of the headline stream.
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--form both|mixed|fp64]
                     [--workload field48|field96] [--only] [--no-many] [--cpu-sample B]
     python bench.py --copy-probe      # a plain 2 GiB device copy (counter calibration)
+    python bench.py --bw-probe        # achievable HBM rates: a read-only sum and a copy
     python bench.py --ingest-counters FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB
 """
 
@@ -164,6 +165,31 @@ def copy_probe():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}), flush=True)
+
+
+def bw_probe():
+    """Achievable HBM rates on this device with library-free kernels: a read-only
+    reduction (torch.sum) and a copy (half reads, half writes), each over 1.36 GB of
+    FP32 (the size of one 48^4 x 4 x 16 batch), the median of 10 launches."""
+    import torch
+    n = 16 * 48 ** 4 * 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    res = {}
+    for name, fn, nbytes in (("read_sum", lambda: x.sum(), 4 * n), ("copy", lambda: y.copy_(x), 8 * n)):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(10):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        ms = sorted(ts)[len(ts) // 2]
+        res[name] = {"bytes": nbytes, "ms": round(ms, 4), "GB_per_s": round(nbytes / ms / 1e6, 1)}
+    print(json.dumps({"bw_probe": res}), flush=True)
 
 
 def run_form(form, spec, ys, golden, steps, warmup, rank_cap):
@@ -549,6 +575,7 @@ def main():
     ap.add_argument("--only", action="store_true", help="measure the headline stream only")
     ap.add_argument("--cpu-sample", type=int, default=2, help="batches of the oracle baseline (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--bw-probe", action="store_true")
     ap.add_argument("--no-many", action="store_true", help="skip the many-streams measurement")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
                     help="write profiles/traffic.json from rocprofv3 --pmc databases (host only)")
@@ -557,6 +584,9 @@ def main():
         print("bench.py measures one GPU: the library runs a stream on a single device and this build "
               "has no multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.bw_probe:
+        bw_probe()
+        return
     if args.copy_probe:
         copy_probe()
         return
