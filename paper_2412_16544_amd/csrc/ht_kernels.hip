@@ -722,32 +722,37 @@ __global__ __launch_bounds__(kProjThreads) void gram_project_kernel(double* __re
 // memory (G in L2): B = U^T G, V = B U, E = B - V U^T / 2, then the upper triangle
 // of G - U E - E^T U^T, mirrored.  Reads of G, U and E are coalesced along the
 // thread index or broadcast over a wave.
+// B = U^T G: a workgroup per (r, 32 columns j); eight threads per column split the
+// rows i (i = ic mod 8) and add their sums in a fixed order.
 __global__ __launch_bounds__(256) void gram_proj_b_kernel(const double* __restrict__ G, int m,
                                                           const double* __restrict__ U, int R, double* __restrict__ B) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)R * m) return;
-  const int r = (int)(e / m), j = (int)(e - (int64_t)r * m);
+  __shared__ double red[8][33];
+  const int nj = (m + 31) / 32;
+  const int r = blockIdx.x / nj, j = (blockIdx.x - r * nj) * 32 + (threadIdx.x & 31);
+  const int ic = threadIdx.x >> 5;
   const double* u = U + (int64_t)r * m;
-  double a0 = 0.0, a1 = 0.0;
-  int i = 0;
-  for (; i + 1 < m; i += 2) {
-    a0 = fma(u[i], G[(int64_t)i * m + j], a0);
-    a1 = fma(u[i + 1], G[(int64_t)(i + 1) * m + j], a1);
+  double acc = 0.0;
+  if (j < m)
+    for (int i = ic; i < m; i += 8) acc = fma(u[i], G[(int64_t)i * m + j], acc);
+  red[ic][threadIdx.x & 31] = acc;
+  __syncthreads();
+  if (ic == 0 && j < m) {
+    const int l = threadIdx.x & 31;
+    B[(int64_t)r * m + j] = ((red[0][l] + red[1][l]) + (red[2][l] + red[3][l])) +
+                            ((red[4][l] + red[5][l]) + (red[6][l] + red[7][l]));
   }
-  if (i < m) a0 = fma(u[i], G[(int64_t)i * m + j], a0);
-  B[e] = a0 + a1;
 }
 
-__global__ __launch_bounds__(256) void gram_proj_v_kernel(const double* __restrict__ B, int m,
-                                                          const double* __restrict__ U, int R, double* __restrict__ V) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= R * R) return;
-  const int r = e / R, q = e - r * R;
+// V = B U: one wave per entry, lanes over j, the wave's sum in a fixed order.
+__global__ __launch_bounds__(64) void gram_proj_v_kernel(const double* __restrict__ B, int m,
+                                                         const double* __restrict__ U, int R, double* __restrict__ V) {
+  const int r = blockIdx.x / R, q = blockIdx.x - r * R;
   const double* b = B + (int64_t)r * m;
   const double* u = U + (int64_t)q * m;
   double acc = 0.0;
-  for (int j = 0; j < m; ++j) acc = fma(b[j], u[j], acc);
-  V[e] = acc;
+  for (int j = threadIdx.x; j < m; j += 64) acc = fma(b[j], u[j], acc);
+  acc = wave_sum(acc);
+  if (threadIdx.x == 0) V[blockIdx.x] = acc;
 }
 
 __global__ __launch_bounds__(256) void gram_proj_e_kernel(const double* __restrict__ B, int m,
@@ -2560,8 +2565,8 @@ void resid_gram_proj(const void* x, Elem t, const ModeView& v, const double* U, 
     double* E = work + (size_t)R * m;
     double* V = E + (size_t)R * m;
     const unsigned nrm = (unsigned)(((int64_t)R * m + 255) / 256);
-    gram_proj_b_kernel<<<nrm, 256, 0, s>>>(G, m, U, R, B);
-    gram_proj_v_kernel<<<(unsigned)((R * R + 255) / 256), 256, 0, s>>>(B, m, U, R, V);
+    gram_proj_b_kernel<<<(unsigned)(R * ((m + 31) / 32)), 256, 0, s>>>(G, m, U, R, B);
+    gram_proj_v_kernel<<<(unsigned)(R * R), 64, 0, s>>>(B, m, U, R, V);
     gram_proj_e_kernel<<<nrm, 256, 0, s>>>(B, m, U, R, V, E);
     gram_proj_g_kernel<<<(unsigned)(((int64_t)m * m + 255) / 256), 256, 0, s>>>(G, m, U, R, E);
     return;
