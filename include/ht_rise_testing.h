@@ -45,9 +45,8 @@ ht_status ht_test_resid_gram_f32(const void* x, int32_t dtype, int64_t P, int64_
 
 /* Mixed form: the residual Gram above as (I - U U^T) G (I - U U^T) from the FP64 Gram
  * G = X_(k) X_(k)^T, no residual formed (the identity R R^T = (I - U U^T) G (I - U U^T)
- * of Eq. compute_residual).  Up to 128 rows FP32 x in register-direct blocks only:
- * m % 4 == 0 and S % 32 == 0 (or S <= 4 with 32 < m <= 96 and R <= 32); 129 to 4096
- * rows any x; else HT_EINVAL.  Same arguments and scratch as ht_test_resid_gram. */
+ * of Eq. compute_residual).  m <= 4096, 1 <= R <= 64 (else HT_EINVAL); FP32 or FP64
+ * x.  Same arguments and scratch as ht_test_resid_gram. */
 ht_status ht_test_resid_gram_proj(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
                                   int32_t R, double* G, double* scratch, void* hip_stream);
 

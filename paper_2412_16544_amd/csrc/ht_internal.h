@@ -107,15 +107,15 @@ struct TtmJob {
 bool ttm_groupable(const ModeView& v, int R);
 void ttm_group(const std::vector<TtmJob>& jobs, hipStream_t s);
 // The residual Gram (I - U U^T) G (I - U U^T) from the FP64 Gram G = M M^T of an
-// unfolding of at least kGramProjMinElems elements (FP32 register-direct shapes up to
-// 128 rows; any level tensor of 129 to kGramProjMaxM rows), no residual formed: FP64
-// products, G's rounding relative to ||M||^2.  Modes of more than 128 rows need work
-// of resid_gram_proj_work_doubles(m, R) doubles.
+// unfolding of at least kGramProjMinElems elements and at most kGramProjMaxM rows
+// (register-direct blocks for FP32 data in their shapes, else the LDS-panel or
+// large-mode Gram), no residual formed: FP64 products, G's rounding relative to
+// ||M||^2.  Modes of more than 128 rows need work of resid_gram_proj_work_doubles(m, R)
+// doubles.
 constexpr double kGramProjMinElems = 4194304.0;
 constexpr int64_t kGramProjMaxM = 4096;
 bool resid_gram_proj_applies(Elem t, const ModeView& v, int R);
 size_t resid_gram_proj_work_doubles(int64_t m, int R);
-bool gram_reg_shape(Elem t, const ModeView& v, int R);  // register-direct blocks apply (any size)
 void resid_gram_proj(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,
                      double* work, hipStream_t s);
 // Gram of the explicit residual with the products on FP32 matrix cores and the

@@ -2548,11 +2548,8 @@ void gram_m64(const float* x, const ModeView& v, int mode, double* part, double*
   gram_finish(g, v, part, G, s);
 }
 
-bool gram_reg_shape(Elem t, const ModeView& v, int R) { return reg_mode(t, v, R) >= 0; }
-
 bool resid_gram_proj_applies(Elem t, const ModeView& v, int R) {
   if ((double)v.P * v.m * v.S < kGramProjMinElems) return false;
-  if (v.m <= kResidGramMaxM) return reg_mode(t, v, R) >= 0;
   return R >= 1 && R <= 64 && v.m <= kGramProjMaxM;
 }
 
@@ -2576,7 +2573,11 @@ void resid_gram_proj(const void* x, Elem t, const ModeView& v, const double* U, 
     gram_proj_g_kernel<<<(unsigned)(((int64_t)m * m + 255) / 256), 256, 0, s>>>(G, m, U, R, E);
     return;
   }
-  gram_m64(static_cast<const float*>(x), v, reg_mode(t, v, R), part, G, s);
+  const int mode = reg_mode(t, v, R);
+  if (mode >= 0)
+    gram_m64(static_cast<const float*>(x), v, mode, part, G, s);
+  else
+    gram(x, t, v, part, G, s);  // LDS-panel FP64 Gram of the data (other shapes)
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_project_kernel<true>),

@@ -60,7 +60,7 @@ ht_status ht_test_resid_gram_proj(const void* x, int32_t dtype, int64_t P, int64
                                   int32_t R, double* G, double* scratch, void* s) {
   const ht::ModeView v{P, m, S};
   if (!x || !U || !G || !scratch || P < 1 || m < 1 || S < 1 || R < 1 || R > 64 || !ok_dtype(dtype) ||
-      m > ht::kGramProjMaxM || (m <= ht::kResidGramMaxM && !ht::gram_reg_shape(elem(dtype), v, R)))
+      m > ht::kGramProjMaxM)
     return HT_EINVAL;
   // the projection's work follows the partials in the scratch
   ht::resid_gram_proj(x, elem(dtype), v, U, R, scratch, G, scratch + ht::gram_partial_doubles(v), st(s));

@@ -118,9 +118,28 @@ def test_resid_gram_proj_large_modes(P, m, S, R, dtype):
     assert err <= 16.0 and terr <= 16.0, (err, terr)
 
 
-def test_resid_gram_proj_rejects_other_shapes():
+# ... and the shapes outside the register-direct blocks (rows not in steps of four,
+# runs not in blocks of 32): the LDS-panel FP64 Gram of the data
+@pytest.mark.parametrize("P,m,S,R", [(3, 50, 33, 4), (7, 47, 100, 12), (40, 17, 5, 6), (2, 126, 70, 64)])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_resid_gram_proj_panel_shapes(P, m, S, R, dtype):
+    x, U = proj_inputs(P, m, S, R, 17 * P + m + S + R)
+    x = x.astype(dtype)
+    G = H.ht_test_resid_gram_proj(torch.from_numpy(x).cuda(), P, m, S, torch.from_numpy(U).cuda()).cpu().numpy()
+    M = unfold_np(x.astype(np.float64), P, m, S)
+    Rr = M - U @ (U.T @ M)
+    ref = Rr @ Rr.T
+    unit = 2.0 ** -53 * float(np.sum(M * M))
+    assert np.array_equal(G, G.T)
+    err = np.max(np.abs(G - ref)) / unit
+    lg, lr = np.linalg.eigvalsh(G)[::-1], np.linalg.eigvalsh(ref)[::-1]
+    terr = np.max(np.abs(np.cumsum(lg[::-1])[::-1] - np.cumsum(lr[::-1])[::-1])) / unit
+    assert err <= 16.0 and terr <= 16.0, (err, terr)
+
+
+def test_resid_gram_proj_rejects_bad_arguments():
     x = torch.zeros(3 * 50 * 33, dtype=torch.float32).cuda()
-    U = torch.zeros((50, 4), dtype=torch.float64).cuda()
+    U = torch.zeros((50, 65), dtype=torch.float64).cuda()
     with pytest.raises(H.HTError):
         H.ht_test_resid_gram_proj(x, 3, 50, 33, U)
 
