@@ -789,12 +789,13 @@ struct LayerJobs {
 // residual R = M - U_old U_old^T M (Eq. compute_residual): formed explicitly, with FP32
 // products when f32 (modes of at most 128 rows), or with gm as
 // (I - U_old U_old^T) M M^T (I - U_old U_old^T) from the FP64 Gram of M.
+// pj: queue for the projections of gm Grams of at most 128 rows (launched by the caller).
 void node_gram(ht_state* h, int node, const Level& cur, const ModeView& v, int r_old, bool f32, hipStream_t s,
-               bool gm = false) {
+               bool gm = false, std::vector<ht::ProjJob>* pj = nullptr) {
   if (r_old == 0) {
     ht::gram(cur.ptr, cur.t, v, h->gpart, h->gram[node], s);
   } else if (gm) {
-    ht::resid_gram_proj(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], h->bufZ, s);
+    ht::resid_gram_proj(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], h->bufZ, s, pj);
   } else if (v.m <= ht::kResidGramMaxM) {
     // formed in registers or tile by tile in LDS, never written out
     if (f32)
@@ -811,7 +812,8 @@ void node_gram(ht_state* h, int node, const Level& cur, const ModeView& v, int r
 
 // proj: the handle's error budget admits residual Grams from the Gram of M (gram_proj_ok).
 void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initial, bool mixed, hipStream_t s,
-                 LayerJobs& L, int only_k = -1, const std::vector<char>* fp64 = nullptr, bool proj = false) {
+                 LayerJobs& L, int only_k = -1, const std::vector<char>* fp64 = nullptr, bool proj = false,
+                 std::vector<ht::ProjJob>* pj = nullptr) {
   const std::vector<int> f = h->tree.frontier(ell);
   for (size_t k = 0; k < f.size(); ++k) {
     const int node = f[k];
@@ -826,7 +828,7 @@ void layer_grams(ht_state* h, int ell, const Level& cur, double thr, bool initia
     const bool gm = mixed && proj && r_old > 0 && ht::resid_gram_proj_applies(cur.t, v, r_old) &&
                     ht::resid_gram_proj_work_doubles(v.m, r_old) <= h->resid_elems;
     const bool f32 = !gm && mixed && r_old > 0 && v.m <= ht::kResidGramMaxM && !(fp64 && (*fp64)[node]);
-    node_gram(h, node, cur, v, r_old, f32, s, gm);
+    node_gram(h, node, cur, v, r_old, f32, s, gm, pj);
     L.f32.push_back(f32 ? 1 : 0);
     L.gm.push_back(gm ? 1 : 0);
     L.view.push_back(v);
@@ -1339,6 +1341,7 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
       };
       std::vector<ht::EigJob> all;
       std::vector<ht::AuxJob> aux;
+      std::vector<ht::ProjJob> pj;  // projections of the layer's gm Grams, one launch
       for (size_t a = 0; a < act.size(); ++a) {
         Upd& u = *act[a];
         u.L = LayerJobs();
@@ -1347,12 +1350,13 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
         std::vector<char> f64;
         fp64_nodes(u, layer_of(u), f64);
         layer_grams(u.h, layer_of(u), u.cur, u.thr, false, u.mixed, s, u.L, only ? (*only)[0] : -1, &f64,
-                    u.mixed && gram_proj_ok(u.ny, u.thr));
+                    u.mixed && gram_proj_ok(u.ny, u.thr), &pj);
         for (size_t q = 0; q < u.L.node.size(); ++q)
           if (u.mixed && !u.L.f32[q] && !u.L.gm[q] && f64[u.L.node[q]]) u.recomputed += 1;
         all.insert(all.end(), u.L.jobs.begin(), u.L.jobs.end());
         if (u.mixed) aux_jobs(u, nullptr, aux);
       }
+      if (!pj.empty()) ht::gram_project_batch(pj.data(), (int)pj.size(), s);
       launch_eig(all, s);
       if (!aux.empty()) ht::decision_aux(aux.data(), (int)aux.size(), s);
       HT_HIP(hipGetLastError());

@@ -116,8 +116,18 @@ constexpr double kGramProjMinElems = 4194304.0;
 constexpr int64_t kGramProjMaxM = 4096;
 bool resid_gram_proj_applies(Elem t, const ModeView& v, int R);
 size_t resid_gram_proj_work_doubles(int64_t m, int R);
+// The projection of an m <= 128 Gram, in place; with defer, resid_gram_proj queues it
+// there instead of launching it, and gram_project_batch launches a layer's (of every
+// handle) together, one workgroup each.
+struct ProjJob {
+  double* G;
+  const double* U;
+  int m, R;
+};
+constexpr int kMaxProjJobs = 32;
 void resid_gram_proj(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,
-                     double* work, hipStream_t s);
+                     double* work, hipStream_t s, std::vector<ProjJob>* defer = nullptr);
+void gram_project_batch(const ProjJob* jobs, int count, hipStream_t s);
 // Gram of the explicit residual with the products on FP32 matrix cores and the
 // workgroup partials summed in FP64.
 void resid_gram_f32(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,

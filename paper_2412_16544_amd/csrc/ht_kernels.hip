@@ -663,9 +663,17 @@ __host__ __device__ constexpr int proj_lds_doubles(int m, int R, bool stage) {
   return R * m + R * R + (stage ? m * m + R * m : 0);
 }
 
-template <bool STAGE>
-__global__ __launch_bounds__(kProjThreads) void gram_project_kernel(double* __restrict__ G, int m,
-                                                                    const double* __restrict__ U, int R) {
+struct ProjBatch {
+  ProjJob j[kMaxProjJobs];
+};
+
+// one workgroup per job; a job stages G and U when its layout fits lds_cap doubles
+__global__ __launch_bounds__(kProjThreads) void gram_project_kernel(ProjBatch b, int lds_cap) {
+  const ProjJob J = b.j[blockIdx.x];
+  double* __restrict__ G = J.G;
+  const double* __restrict__ U = J.U;
+  const int m = J.m, R = J.R;
+  const bool STAGE = proj_lds_doubles(m, R, true) <= lds_cap;
   extern __shared__ double gpL[];
   double* E = gpL;               // R x m: B, then E
   double* V = E + R * m;         // R x R
@@ -2557,8 +2565,29 @@ size_t resid_gram_proj_work_doubles(int64_t m, int R) {
   return m <= kResidGramMaxM ? 0 : (size_t)2 * R * m + (size_t)R * R;
 }
 
+void gram_project_batch(const ProjJob* jobs, int count, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_project_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kProjLdsDoubles * (int)sizeof(double));
+    attr = true;
+  }
+  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
+  for (int b0 = 0; b0 < count; b0 += kMaxProjJobs) {
+    const int n = std::min(kMaxProjJobs, count - b0);
+    ProjBatch b;
+    int cap = 0;
+    for (int i = 0; i < n; ++i) {
+      b.j[i] = jobs[b0 + i];
+      const int st = proj_lds_doubles(b.j[i].m, b.j[i].R, true);
+      cap = std::max(cap, st <= kProjLdsDoubles ? st : proj_lds_doubles(b.j[i].m, b.j[i].R, false));
+    }
+    gram_project_kernel<<<n, kProjThreads, (size_t)cap * sizeof(double), s>>>(b, cap);
+  }
+}
+
 void resid_gram_proj(const void* x, Elem t, const ModeView& v, const double* U, int R, double* part, double* G,
-                     double* work, hipStream_t s) {
+                     double* work, hipStream_t s, std::vector<ProjJob>* defer) {
   if (v.m > kResidGramMaxM) {
     gram(x, t, v, part, G, s);
     ProfScope prof(KKind::Layout, s, 0.0, 0.0);
@@ -2578,20 +2607,11 @@ void resid_gram_proj(const void* x, Elem t, const ModeView& v, const double* U, 
     gram_m64(static_cast<const float*>(x), v, mode, part, G, s);
   else
     gram(x, t, v, part, G, s);  // LDS-panel FP64 Gram of the data (other shapes)
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_project_kernel<true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kProjLdsDoubles * (int)sizeof(double));
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_project_kernel<false>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kProjLdsDoubles * (int)sizeof(double));
-    attr = true;
-  }
-  ProfScope prof(KKind::Layout, s, 0.0, 0.0);
-  const int m = (int)v.m;
-  if (proj_lds_doubles(m, R, true) <= kProjLdsDoubles)
-    gram_project_kernel<true><<<1, kProjThreads, proj_lds_doubles(m, R, true) * sizeof(double), s>>>(G, m, U, R);
+  const ProjJob job{G, U, (int)v.m, R};
+  if (defer)
+    defer->push_back(job);
   else
-    gram_project_kernel<false><<<1, kProjThreads, proj_lds_doubles(m, R, false) * sizeof(double), s>>>(G, m, U, R);
+    gram_project_batch(&job, 1, s);
 }
 
 void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hipStream_t s) {
