@@ -38,6 +38,15 @@ ht_status ht_test_resid_gram(const void* x, int32_t dtype, int64_t P, int64_t m,
 ht_status ht_test_ttm_contract(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
                                int32_t R, double* Z, void* hip_stream);
 
+/* The contraction above for modes of more than 128 rows (Z FP64), with the energies
+ * sq[0] = ||X||^2 and sq[1] = ||Z||^2, and with scratch_doubles of device scratch lent
+ * to it: a contraction of fewer than 256 column blocks of 16 is then split into row
+ * chunks whose partial products are summed in chunk order.  sq holds 2 + 2048
+ * doubles (the sums, then the workgroup partials).  HT_EINVAL for m <= 128. */
+ht_status ht_test_ttm_contract_split(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
+                                     int32_t R, double* Z, double* scratch, size_t scratch_doubles, double* sq,
+                                     void* hip_stream);
+
 /* Mixed form (HT_FP32): the residual Gram above with every product on FP32 matrix
  * cores and the workgroup partials summed in FP64.  Same arguments and scratch. */
 ht_status ht_test_resid_gram_f32(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,

@@ -584,6 +584,8 @@ Level merge_level(const ht_state* h, int ell, const Level& cur);
 void contract_one(const ht_state* h, Level& cur, int k, int node, double* dst, hipStream_t s, double* norm_out,
                   bool mixed, double* energy, std::vector<char>* expl, std::vector<ht::TtmJob>* group = nullptr) {
   const ModeView v = view_of(cur, k);
+  // the residual buffer is free during contractions: row chunks of few-column ones
+  const ht::SplitScratch split(h->resid, h->resid_elems);
   const bool grouped = group != nullptr && ht::ttm_groupable(v, h->rank[node]) &&
                        (mixed ? v.m <= ht::kResidGramMaxM : energy == nullptr);
   if (mixed && v.m <= ht::kResidGramMaxM) {

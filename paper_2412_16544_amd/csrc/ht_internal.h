@@ -116,6 +116,16 @@ constexpr double kGramProjMinElems = 4194304.0;
 constexpr int64_t kGramProjMaxM = 4096;
 bool resid_gram_proj_applies(Elem t, const ModeView& v, int R);
 size_t resid_gram_proj_work_doubles(int64_t m, int R);
+// Device scratch (doubles) that the direct contractions of modes above 128 rows may
+// use while the scope lives (one host thread), to split a contraction of few column
+// blocks into row chunks; without it they run unsplit.
+struct SplitScratch {
+  SplitScratch(double* p, size_t n);
+  ~SplitScratch();
+  SplitScratch(const SplitScratch&) = delete;
+  SplitScratch& operator=(const SplitScratch&) = delete;
+};
+
 // The projection of an m <= 128 Gram, in place; with defer, resid_gram_proj queues it
 // there instead of launching it, and gram_project_batch launches a layer's (of every
 // handle) together, one workgroup each.

@@ -1760,11 +1760,15 @@ constexpr int kDirectLdsDoubles = 19968;  // U chunk: chunk x (RP + 1) doubles o
 constexpr unsigned kDirectColsMinBlocks = 1024;  // column blocks from which whole blocks go to waves
 
 // SQ: also the workgroup partials of ||X||^2 (in_part) and ||Z||^2 (out_part)
+// With gridDim.y > 1 workgroup (x, y) takes rows [y rows, (y + 1) rows) only and writes
+// its partial product to Zp + y P R S (summed by split_sum_kernel), and ||X||^2 of its
+// rows to in_part[y gridDim.x + x].
 template <typename T, bool SQ>
 __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
                                                          const double* __restrict__ U, int R, int chunk,
                                                          double* __restrict__ Z, double* __restrict__ in_part,
-                                                         double* __restrict__ out_part) {
+                                                         double* __restrict__ out_part, int64_t rows,
+                                                         double* __restrict__ Zp) {
   extern __shared__ double sU[];  // sU[a][r] (chunk rows of ULD), then the wave partials
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int RP = (R + 15) & ~15, ULD = RP + 1, rt = RP >> 4;
@@ -1777,8 +1781,10 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
   double xsq = 0.0;
-  for (int64_t a0 = 0; a0 < m; a0 += chunk) {
-    const int ac = (int)min<int64_t>(chunk, m - a0);
+  const bool split = gridDim.y > 1;
+  const int64_t lo = (int64_t)blockIdx.y * rows, hi = min(m, lo + rows);
+  for (int64_t a0 = lo; a0 < hi; a0 += chunk) {
+    const int ac = (int)min<int64_t>(chunk, hi - a0);
     const int ac4 = (ac + 3) & ~3;
     __syncthreads();
     stage_ut(U, m, R, a0, ac4, RP, ac, sU, ULD);
@@ -1832,8 +1838,12 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
           for (int w = 0; w < 3; ++w) z += sU[((w * 4 + t) * 4 + v) * 64 + lane];
           const int r = t * 16 + MA<double>::row(lane, v);
           if (r < R) {
-            Z[(p * R + r) * S + sidx] = z;
-            if (SQ) zsq = fma(z, z, zsq);
+            if (split) {
+              Zp[(int64_t)blockIdx.y * P * R * S + (p * R + r) * S + sidx] = z;
+            } else {
+              Z[(p * R + r) * S + sidx] = z;
+              if (SQ) zsq = fma(z, z, zsq);
+            }
           }
         }
       }
@@ -1846,9 +1856,30 @@ __global__ __launch_bounds__(256) void ttm_direct_kernel(const T* __restrict__ X
     if (lane == 0) red[wave] = xsq;
     __syncthreads();
     if (threadIdx.x == 0) {
-      in_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-      out_part[blockIdx.x] = zsq;
+      in_part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+      if (!split) out_part[blockIdx.x] = zsq;
     }
+  }
+}
+
+// Z = the sum of the nsplit partial products (in split order); with SQ the
+// workgroup partials of ||Z||^2
+template <bool SQ>
+__global__ __launch_bounds__(256) void split_sum_kernel(const double* __restrict__ Zp, int nsplit, int64_t n,
+                                                        double* __restrict__ Z, double* __restrict__ out_part) {
+  double zsq = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    double z = Zp[e];
+    for (int k = 1; k < nsplit; ++k) z += Zp[(int64_t)k * n + e];
+    Z[e] = z;
+    if (SQ) zsq = fma(z, z, zsq);
+  }
+  if (SQ) {
+    __shared__ double red[4];
+    zsq = wave_sum(zsq);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = zsq;
+    __syncthreads();
+    if (threadIdx.x == 0) out_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
   }
 }
 
@@ -2688,6 +2719,36 @@ void ttm_contract(const void* x, Elem t, const ModeView& v, const double* U, int
   ttm_contract_norm(x, t, v, U, R, Z, nullptr, nullptr, s);
 }
 
+// ---- row splits of the direct contraction ------------------------------------
+// A contraction of few column blocks runs on few workgroups, each over all m rows;
+// with device scratch lent by SplitScratch it is split into row chunks (one
+// workgroup per block and chunk) whose partial products a second launch sums in
+// chunk order.
+thread_local double* t_split_ws = nullptr;
+thread_local size_t t_split_elems = 0;
+SplitScratch::SplitScratch(double* p, size_t n) {
+  t_split_ws = p;
+  t_split_elems = n;
+}
+SplitScratch::~SplitScratch() {
+  t_split_ws = nullptr;
+  t_split_elems = 0;
+}
+
+int split_sum_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 255) / 256)); }
+
+// row chunks of a per-block direct contraction: about 512 workgroups in all, chunks of
+// at least 64 rows, at most 8, and the partial products within the lent scratch
+int direct_split(const ModeView& v, int R, int64_t blocks) {
+  if (t_split_ws == nullptr || blocks >= 256 || v.m < 128) return 1;
+  int n = (int)std::min<int64_t>({8, (512 + blocks - 1) / blocks, v.m / 64});
+  while (n > 1 && (size_t)n * v.P * R * v.S > t_split_elems) --n;
+  if (n < 2) return 1;
+  // whole chunks of rows in steps of four
+  const int64_t rows = ((v.m + n - 1) / n + 3) & ~int64_t(3);
+  return (int)((v.m + rows - 1) / rows);
+}
+
 // one launch of the direct contraction (modes of more than 128 rows); with SQ also
 // ||X||^2 and ||Z||^2 from the workgroup partials
 template <bool SQ>
@@ -2738,26 +2799,34 @@ void launch_ttm_direct(const void* x, Elem t, const ModeView& v, const double* U
     }
     return;
   }
-  // few column blocks (transfer nodes): all of U in one chunk; many: at most 64 KiB,
-  // two workgroups per compute unit
+  // few column blocks (transfer nodes): all of U (or of the rows of a split) in one
+  // chunk; many: at most 64 KiB, two workgroups per compute unit
+  const int nsplit = direct_split(v, R, blocks);
+  const int64_t rows = nsplit > 1 ? ((v.m + nsplit - 1) / nsplit + 3) & ~int64_t(3) : v.m;
   const int cap = blocks >= 512 ? 8192 : kDirectLdsDoubles;
-  const int chunk = (int)std::min<int64_t>(((cap / (RP + 1)) / 4) * 4, (v.m + 3) & ~3);
+  const int chunk = (int)std::min<int64_t>(((cap / (RP + 1)) / 4) * 4, (rows + 3) & ~3);
   // the wave partials (3 x 4 x 4 x 64 doubles) reuse the same space at the end
   const size_t lds = (size_t)std::max<int64_t>((int64_t)chunk * (RP + 1), 3 * 4 * 4 * 64) * sizeof(double);
+  const dim3 grid(blocks, (unsigned)nsplit);
+  double* Zp = nsplit > 1 ? t_split_ws : nullptr;
   {
     ProfScope prof(KKind::TtmContract, s, 2.0 * R * v.m * (double)K,
                    (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8);
     if (t == Elem::F32)
-      ttm_direct_kernel<float, SQ><<<blocks, 256, lds, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R, chunk, Z,
-                                                            in_part, out_part);
+      ttm_direct_kernel<float, SQ><<<grid, 256, lds, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R, chunk, Z,
+                                                          in_part, out_part, rows, Zp);
     else
-      ttm_direct_kernel<double, SQ><<<blocks, 256, lds, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U, R, chunk,
-                                                             Z, in_part, out_part);
+      ttm_direct_kernel<double, SQ><<<grid, 256, lds, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U, R, chunk,
+                                                           Z, in_part, out_part, rows, Zp);
+    if (nsplit > 1) {
+      const int64_t n = v.P * R * v.S;
+      split_sum_kernel<SQ><<<split_sum_blocks(n), 256, 0, s>>>(Zp, nsplit, n, Z, out_part);
+    }
   }
   if (SQ) {
     ProfScope prof(KKind::Layout, s, 0.0, 0.0);
-    finish_sum(in_part, (int)blocks, in_out, s);
-    finish_sum(out_part, (int)blocks, out_out, s);
+    finish_sum(in_part, (int)blocks * nsplit, in_out, s);
+    finish_sum(out_part, nsplit > 1 ? split_sum_blocks(v.P * R * v.S) : (int)blocks, out_out, s);
   }
 }
 
@@ -2985,8 +3054,10 @@ bool ttm_contract_sq(const void* x, Elem t, const ModeView& v, const double* U, 
                      double* in_out, double* out_part, double* out_out, int max_parts, hipStream_t s) {
   const int64_t K = v.P * v.S;
   const int64_t blocks = (K + 15) / 16;
-  // workgroup partials: one per column block, or at most 512 with whole blocks per wave
-  const int64_t parts = blocks >= kDirectColsMinBlocks ? std::min<int64_t>(512, (blocks + 7) / 8) : blocks;
+  // workgroup partials: one per column block (and row chunk), or at most 512 with
+  // whole blocks per wave
+  const int64_t parts = blocks >= kDirectColsMinBlocks ? std::min<int64_t>(512, (blocks + 7) / 8)
+                                                       : blocks * direct_split(v, R, blocks);
   if (v.m <= GB || parts > max_parts) return false;
   launch_ttm_direct<true>(x, t, v, U, R, Z, in_part, in_out, out_part, out_out, s);
   return true;

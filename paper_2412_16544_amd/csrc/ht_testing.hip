@@ -47,6 +47,19 @@ ht_status ht_test_ttm_contract(const void* x, int32_t dtype, int64_t P, int64_t 
   return hipGetLastError() == hipSuccess ? HT_OK : HT_EDEVICE;
 }
 
+ht_status ht_test_ttm_contract_split(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
+                                     int32_t R, double* Z, double* scratch, size_t scratch_doubles, double* sq,
+                                     void* s) {
+  if (!x || !U || !Z || !scratch || !sq || P < 1 || m < 1 || S < 1 || R < 1 || R > 64 || !ok_dtype(dtype))
+    return HT_EINVAL;
+  // partials of ||X||^2 and ||Z||^2 (sq[0], sq[1]) follow the two sums in sq
+  const ht::SplitScratch split(scratch, scratch_doubles);
+  if (!ht::ttm_contract_sq(x, elem(dtype), ht::ModeView{P, m, S}, U, R, Z, sq + 2, sq, sq + 2 + 1024, sq + 1, 1024,
+                           st(s)))
+    return HT_EINVAL;
+  return hipGetLastError() == hipSuccess ? HT_OK : HT_EDEVICE;
+}
+
 ht_status ht_test_resid_gram_f32(const void* x, int32_t dtype, int64_t P, int64_t m, int64_t S, const double* U,
                                  int32_t R, double* G, double* scratch, void* s) {
   if (!x || !U || !G || !scratch || P < 1 || m < 1 || m > ht::kResidGramMaxM || S < 1 || R < 1 || R > 64 ||

@@ -327,6 +327,7 @@ def _tlib():
         L.ht_test_resid_gram.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, vp]
         L.ht_test_resid_gram_f32.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, vp]
         L.ht_test_resid_gram_proj.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, vp]
+        L.ht_test_ttm_contract_split.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, sz, vp, vp]
         L.ht_test_ttm_partials_doubles.argtypes = []
         L.ht_test_ttm_partials_doubles.restype = sz
         L.ht_test_ttm_contract_f32.argtypes = [vp, i32, i64, i64, i64, vp, i32, vp, vp, vp, vp, vp]
@@ -339,7 +340,7 @@ def _tlib():
         L.ht_test_decision_certified.argtypes = [i32, i32, i32, dbl, dbl, dbl, dbl, dbl]
         L.ht_test_decision_certified.restype = i32
         for name in ("ht_test_sumsq", "ht_test_gram", "ht_test_resid_gram", "ht_test_resid_gram_f32",
-                     "ht_test_resid_gram_proj",
+                     "ht_test_resid_gram_proj", "ht_test_ttm_contract_split",
                      "ht_test_ttm_contract", "ht_test_ttm_contract_f32", "ht_test_ttm_expand", "ht_test_eig",
                      "ht_test_eig_method", "ht_test_orth_expand"):
             getattr(L, name).restype = ctypes.c_int
@@ -415,6 +416,21 @@ def ht_test_ttm_contract_f32(x, P: int, m: int, S: int, U, stream=None):
                                       _ptr(sc), _stream(stream)), "ht_test_ttm_contract_f32")
     torch.cuda.synchronize()
     return Z, float(out[0].item()), float(out[1].item())
+
+
+def ht_test_ttm_contract_split(x, P: int, m: int, S: int, U, scratch_doubles: int, stream=None):
+    """Returns (Z float64 [P][R][S], ||X||^2, ||Z||^2) of the direct contraction with
+    scratch_doubles of lent scratch (row chunks when it has few column blocks)."""
+    import torch
+    R = U.shape[1]
+    Ucm = U.t().contiguous()
+    Z = torch.empty((P, R, S), dtype=torch.float64, device=x.device)
+    sc = torch.empty(max(1, scratch_doubles), dtype=torch.float64, device=x.device)
+    sq = torch.zeros(2 + 2048, dtype=torch.float64, device=x.device)
+    _check(_tlib().ht_test_ttm_contract_split(_ptr(x), _dt(x), P, m, S, _ptr(Ucm), R, _ptr(Z), _ptr(sc),
+                                              scratch_doubles, _ptr(sq), _stream(stream)), "ht_test_ttm_contract_split")
+    torch.cuda.synchronize()
+    return Z, float(sq[0].item()), float(sq[1].item())
 
 
 def ht_test_ttm_contract(x, P: int, m: int, S: int, U, stream=None):

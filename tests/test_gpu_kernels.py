@@ -64,6 +64,26 @@ def test_resid_gram(P, m, S, R, dtype):
     assert np.max(np.abs(G - ref)) <= 1e-12 * max(1.0, np.max(np.abs(M @ M.T)))
 
 
+# Direct contraction of modes above 128 rows with lent scratch: few column blocks are
+# split into row chunks (partial products summed in chunk order); with the energies
+# ||X||^2 and ||Z||^2.  No scratch, or too little, runs it unsplit; the results agree.
+@pytest.mark.parametrize("P,m,S,R", [(16, 600, 68, 32), (4, 480, 100, 24), (2, 129, 50, 5), (3, 1000, 7, 64),
+                                     (1, 131, 1, 1)])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_ttm_contract_split(P, m, S, R, dtype):
+    g = rng(P + m + S + R + 5)
+    x = g.standard_normal(P * m * S).astype(dtype)
+    U = g.standard_normal((m, R))
+    xt, Ut = torch.from_numpy(x).cuda(), torch.from_numpy(U).cuda()
+    ref = np.einsum("ar,pas->prs", U, x.astype(np.float64).reshape(P, m, S))
+    for ws in (8 * P * R * S, 0):
+        Z, nx, nz = H.ht_test_ttm_contract_split(xt, P, m, S, Ut, ws)
+        Z = Z.cpu().numpy()
+        assert np.max(np.abs(Z - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+        assert nx == pytest.approx(float(np.sum(x.astype(np.float64) ** 2)), rel=1e-12)
+        assert nz == pytest.approx(float(np.sum(ref ** 2)), rel=1e-12)
+
+
 # The residual Gram as (I - U U^T) M M^T (I - U U^T) from the FP64 Gram of M
 # (register-direct shapes; 128 rows with 64 basis columns; runs of 1-4 columns;
 # eight row tiles).  M near the span of U, as in HT-RISE, so the residual is small next
