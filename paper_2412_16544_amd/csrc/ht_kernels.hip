@@ -1892,7 +1892,8 @@ __global__ __launch_bounds__(256) void ttm_direct_cols_kernel(const T* __restric
                                                               int64_t S, const double* __restrict__ U, int R,
                                                               int chunk, double* __restrict__ Z,
                                                               double* __restrict__ in_part,
-                                                              double* __restrict__ out_part) {
+                                                              double* __restrict__ out_part, int64_t rows,
+                                                              double* __restrict__ Zp) {
   extern __shared__ double sU[];  // sU[a][r], chunk rows of ULD
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int RP = (R + 15) & ~15, ULD = RP + 1, rt = RP >> 4;
@@ -1900,6 +1901,8 @@ __global__ __launch_bounds__(256) void ttm_direct_cols_kernel(const T* __restric
   const int64_t ncb = (K + 15) / 16;
   const int kr = lane >> 4;
   double xsq = 0.0, zsq = 0.0;
+  const bool split = gridDim.y > 1;  // rows [y rows, (y + 1) rows) into Zp + y P R S
+  const int64_t lo = (int64_t)blockIdx.y * rows, hi = min(m, lo + rows);
   for (int64_t cb0 = (int64_t)blockIdx.x * 8; cb0 < ncb; cb0 += (int64_t)gridDim.x * 8) {  // uniform
     int64_t c[2], base[2];
     bool cv[2];
@@ -1914,8 +1917,8 @@ __global__ __launch_bounds__(256) void ttm_direct_cols_kernel(const T* __restric
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int t = 0; t < 4; ++t) acc[j][t] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t a0 = 0; a0 < m; a0 += chunk) {
-      const int ac = (int)min<int64_t>(chunk, m - a0);
+    for (int64_t a0 = lo; a0 < hi; a0 += chunk) {
+      const int ac = (int)min<int64_t>(chunk, hi - a0);
       const int ac4 = (ac + 3) & ~3;
       __syncthreads();
       stage_ut(U, m, R, a0, ac4, RP, ac, sU, ULD);
@@ -1957,8 +1960,12 @@ __global__ __launch_bounds__(256) void ttm_direct_cols_kernel(const T* __restric
             const int r = t * 16 + MA<double>::row(lane, v);
             if (r < R) {
               const double z = acc[j][t][v];
-              Z[(p * R + r) * S + sidx] = z;
-              if (SQ) zsq = fma(z, z, zsq);
+              if (split) {
+                Zp[(int64_t)blockIdx.y * P * R * S + (p * R + r) * S + sidx] = z;
+              } else {
+                Z[(p * R + r) * S + sidx] = z;
+                if (SQ) zsq = fma(z, z, zsq);
+              }
             }
           }
         }
@@ -1975,8 +1982,8 @@ __global__ __launch_bounds__(256) void ttm_direct_cols_kernel(const T* __restric
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      in_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-      out_part[blockIdx.x] = (red[4] + red[5]) + (red[6] + red[7]);
+      in_part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+      if (!split) out_part[blockIdx.x] = (red[4] + red[5]) + (red[6] + red[7]);
     }
   }
 }
@@ -2780,22 +2787,30 @@ void launch_ttm_direct(const void* x, Elem t, const ModeView& v, const double* U
     const int64_t tiles = ((int64_t)blocks + 7) / 8;
     const int64_t per = (tiles + 511) / 512;
     const unsigned grid = (unsigned)((tiles + per - 1) / per);
-    const int chunk = (int)std::min<int64_t>(((8192 / (RP + 1)) / 4) * 4, (v.m + 3) & ~3);
+    const int nsplit = direct_split(v, R, grid);
+    const int64_t rows = nsplit > 1 ? ((v.m + nsplit - 1) / nsplit + 3) & ~int64_t(3) : v.m;
+    const int chunk = (int)std::min<int64_t>(((8192 / (RP + 1)) / 4) * 4, (rows + 3) & ~3);
     const size_t lds = (size_t)chunk * (RP + 1) * sizeof(double);
+    const dim3 g2(grid, (unsigned)nsplit);
+    double* Zp = nsplit > 1 ? t_split_ws : nullptr;
     {
       ProfScope prof(KKind::TtmContract, s, 2.0 * R * v.m * (double)K,
                      (double)v.m * K * (t == Elem::F32 ? 4 : 8) + (double)R * K * 8 + (double)v.m * R * 8);
       if (t == Elem::F32)
-        ttm_direct_cols_kernel<float, SQ><<<grid, 256, lds, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R,
-                                                                 chunk, Z, in_part, out_part);
+        ttm_direct_cols_kernel<float, SQ><<<g2, 256, lds, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, U, R,
+                                                               chunk, Z, in_part, out_part, rows, Zp);
       else
-        ttm_direct_cols_kernel<double, SQ><<<grid, 256, lds, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U,
-                                                                  R, chunk, Z, in_part, out_part);
+        ttm_direct_cols_kernel<double, SQ><<<g2, 256, lds, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, U,
+                                                                R, chunk, Z, in_part, out_part, rows, Zp);
+      if (nsplit > 1) {
+        const int64_t n = v.P * R * v.S;
+        split_sum_kernel<SQ><<<split_sum_blocks(n), 256, 0, s>>>(Zp, nsplit, n, Z, out_part);
+      }
     }
     if (SQ) {
       ProfScope prof(KKind::Layout, s, 0.0, 0.0);
-      finish_sum(in_part, (int)grid, in_out, s);
-      finish_sum(out_part, (int)grid, out_out, s);
+      finish_sum(in_part, (int)grid * nsplit, in_out, s);
+      finish_sum(out_part, nsplit > 1 ? split_sum_blocks(v.P * R * v.S) : (int)grid, out_out, s);
     }
     return;
   }
@@ -3056,7 +3071,8 @@ bool ttm_contract_sq(const void* x, Elem t, const ModeView& v, const double* U, 
   const int64_t blocks = (K + 15) / 16;
   // workgroup partials: one per column block (and row chunk), or at most 512 with
   // whole blocks per wave
-  const int64_t parts = blocks >= kDirectColsMinBlocks ? std::min<int64_t>(512, (blocks + 7) / 8)
+  const int64_t tiles = (blocks + 7) / 8, grid = (tiles + (tiles + 511) / 512 - 1) / ((tiles + 511) / 512);
+  const int64_t parts = blocks >= kDirectColsMinBlocks ? grid * direct_split(v, R, grid)
                                                        : blocks * direct_split(v, R, blocks);
   if (v.m <= GB || parts > max_parts) return false;
   launch_ttm_direct<true>(x, t, v, U, R, Z, in_part, in_out, out_part, out_out, s);

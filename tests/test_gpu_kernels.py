@@ -68,7 +68,10 @@ def test_resid_gram(P, m, S, R, dtype):
 # split into row chunks (partial products summed in chunk order); with the energies
 # ||X||^2 and ||Z||^2.  No scratch, or too little, runs it unsplit; the results agree.
 @pytest.mark.parametrize("P,m,S,R", [(16, 600, 68, 32), (4, 480, 100, 24), (2, 129, 50, 5), (3, 1000, 7, 64),
-                                     (1, 131, 1, 1)])
+                                     (1, 131, 1, 1),
+                                     # column-tiled kernel (1024 blocks or more) on fewer than 256
+                                     # workgroups; a ragged last block
+                                     (16, 480, 1088, 24), (3, 300, 5999, 20)])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_ttm_contract_split(P, m, S, R, dtype):
     g = rng(P + m + S + R + 5)
