@@ -806,7 +806,11 @@ void node_gram(ht_state* h, int node, const Level& cur, const ModeView& v, int r
       ht::resid_gram(cur.ptr, cur.t, v, h->core[node], r_old, h->gpart, h->gram[node], s);
   } else {
     double* z = h->bufZ;  // U_old^T M: as large as the level tensor when alpha == r_old
-    ht::ttm_contract(cur.ptr, cur.t, v, h->core[node], r_old, z, s);
+    {
+      // (row chunks through the residual buffer, which the expansion overwrites after)
+      const ht::SplitScratch split(h->resid, h->resid_elems);
+      ht::ttm_contract(cur.ptr, cur.t, v, h->core[node], r_old, z, s);
+    }
     ht::ttm_expand(z, v.P, r_old, v.S, h->core[node], v.m, cur.ptr, cur.t, h->resid, Elem::F64, s);
     ht::gram(h->resid, Elem::F64, v, h->gpart, h->gram[node], s);
   }
