@@ -239,18 +239,30 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
   const int rowsI = (int)min<int64_t>(GB, m - (int64_t)bi * GB);
   const int rowsJ = (int)min<int64_t>(GB, m - (int64_t)bj * GB);
   const int tI = (rowsI + 15) >> 4, tJ = (rowsJ + 15) >> 4;
-  const int ntiles = diag ? tI * (tI + 1) / 2 : tI * tJ;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-  int myti[GMAXT], mytj[GMAXT];
-#pragma unroll
-  for (int q = 0; q < GMAXT; ++q) {
-    const int t = wave + 4 * q;
-    int a = 0, b = 0;
-    if (t < ntiles) tile_of(t, diag, tI, tJ, a, b);
-    myti[q] = a;
-    mytj[q] = b;
+  // A wave owns two tile rows and every tile of them in the pair's block: off the
+  // diagonal rows 2w and 2w + 1 (16 tiles); on it rows w and tI - 1 - w, whose upper
+  // tiles add up to tI + 1 (9 of the 36).  A k step then reads 2 A and 8 B operands
+  // from LDS for up to 16 products; the bit 8 i + j of `act` (uniform) says whether
+  // the tile of row slot i, tile column j is the wave's.
+  int rowA, rowB;
+  if (diag) {
+    rowA = wave < (tI + 1) / 2 ? wave : tI;
+    rowB = tI - 1 - wave > rowA ? tI - 1 - wave : tI;
+  } else {
+    rowA = 2 * wave;
+    rowB = 2 * wave + 1;
   }
+  unsigned act = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (rowA < tI && j < tJ && (!diag || j >= rowA)) act |= 1u << j;
+    if (rowB < tI && j < tJ && (!diag || j >= rowB)) act |= 1u << (8 + j);
+  }
+  const int offA = (rowA < tI ? rowA : 0) * 16 + (lane & 15);
+  const int offB = (rowB < tI ? rowB : 0) * 16 + (lane & 15);
   d4 acc[GMAXT];
 #pragma unroll
   for (int q = 0; q < GMAXT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
@@ -305,13 +317,15 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
 #pragma unroll
     for (int ks = 0; ks < GBK; ks += 4) {
       const int kr = ks + (lane >> 4);
+      // every operand of the step first (all in the staged panels), then the products
+      const double a0 = sI[kr * GLD + offA], a1 = sI[kr * GLD + offB];
+      double b[8];
 #pragma unroll
-      for (int q = 0; q < GMAXT; ++q) {
-        if (wave + 4 * q < ntiles) {
-          const double a = sI[kr * GLD + myti[q] * 16 + (lane & 15)];
-          const double b = sB[kr * GLD + mytj[q] * 16 + (lane & 15)];
-          acc[q] = mfma16(a, b, acc[q]);
-        }
+      for (int j = 0; j < 8; ++j) b[j] = sB[kr * GLD + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (act & (1u << j)) acc[j] = mfma16(a0, b[j], acc[j]);
+        if (act & (1u << (8 + j))) acc[8 + j] = mfma16(a1, b[j], acc[8 + j]);
       }
     }
     __syncthreads();
@@ -320,11 +334,12 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
   const int ld_out = (int)min<int64_t>(GB, m);
 #pragma unroll
   for (int q = 0; q < GMAXT; ++q) {
-    if (wave + 4 * q < ntiles) {
+    if (act & (1u << q)) {
+      const int ti = q < 8 ? rowA : rowB, tj = q & 7;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = myti[q] * 16 + (lane >> 4) + 4 * v;
-        const int j = mytj[q] * 16 + (lane & 15);
+        const int i = ti * 16 + (lane >> 4) + 4 * v;
+        const int j = tj * 16 + (lane & 15);
         if (i < rowsI && j < rowsJ) out[i * ld_out + j] = acc[q][v];
       }
     }

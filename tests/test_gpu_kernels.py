@@ -30,7 +30,11 @@ GRAM_SHAPES = [(1, 1, 1), (3, 8, 1), (2, 9, 31), (6, 33, 32), (3, 96, 1000), (5,
                (4, 256, 3), (9, 40, 64), (1, 300, 2),
                # register-direct blocks (FP32 input): runs in blocks of 32, and runs of 1-4 columns
                (3, 96, 1024), (2, 128, 64), (5, 40, 96), (64, 12, 16384), (100, 96, 3), (37, 64, 1), (50, 48, 2),
-               (19, 96, 4), (3, 120, 32), (4, 108, 64)]
+               (19, 96, 4), (3, 120, 32), (4, 108, 64),
+               # above 128 rows (waves owning two tile rows of a block pair): three block rows
+               # with a ragged last one and many column ranges, four block rows, slices of fewer
+               # than 32 columns, eight block rows with an odd tile count in the last one
+               (1, 306, 4608), (2, 500, 333), (40, 200, 7), (1, 1000, 97)]
 
 
 @pytest.mark.parametrize("P,m,S", GRAM_SHAPES)
