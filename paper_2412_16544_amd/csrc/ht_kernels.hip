@@ -154,6 +154,10 @@ constexpr int GB = 128;
 constexpr int GBK = 32;
 constexpr int GLD = GB + 1;  // odd stride in doubles: conflict-free column writes
 constexpr int GMAXT = 16;
+// Column tile of the Gram of modes above 128 rows for FP32 data: 64 columns, so that
+// a wave's load of one row is 256 contiguous bytes and each barrier pair covers 16
+// k steps (FP64 data keeps 32: its prefetched tile would not fit the registers).
+constexpr int GPK = 64;
 
 // A basis U (column-major, m rows, R columns, FP64) staged transposed into LDS:
 // dst[a * ld + r] = U[a0 + a, r] for a < na, r < nr, zero where a >= na_valid or
@@ -196,37 +200,37 @@ __device__ __forceinline__ void tile_of(int t, bool diag, int tI, int tJ, int& t
   tj = row + rem;
 }
 
-// Column tiles: when S >= GBK a tile is GBK consecutive columns (rows strided by
+// Column tiles: when S >= BK a tile is BK consecutive columns (rows strided by
 // S, each row segment contiguous), loaded by this helper into registers one tile
-// ahead; when S < GBK it is floor(GBK/S) whole slices p, one contiguous block of
+// ahead; when S < BK it is floor(BK/S) whole slices p, one contiguous block of
 // memory, scattered straight into LDS by the kernel.
 // The values stay in the data type until they are stored to LDS: a conversion right
 // after the load would make the wave wait for it there, and the tile ahead would no
 // longer overlap the products of the current one.
-template <typename T>
+template <typename T, int BK>
 __device__ __forceinline__ void gram_load_tile(const T* __restrict__ X, int64_t m, int64_t S, int64_t K, int64_t kt,
                                                int tw, int64_t rowI0, int rowsI, int64_t rowJ0, int rowsJ, bool diag,
-                                               T (&ri)[GBK * GB / 256], T (&rj)[GBK * GB / 256]) {
-  constexpr int PER = GBK * GB / 256;
-  // thread owns column kk = tid % GBK of the tile and rows tid / GBK + 8 q
-  const int kk = threadIdx.x % GBK;
+                                               T (&ri)[BK * GB / 256], T (&rj)[BK * GB / 256]) {
+  constexpr int PER = BK * GB / 256;
+  // thread owns column kk = tid % BK of the tile and rows tid / BK + (256 / BK) q
+  const int kk = threadIdx.x % BK;
   const int64_t c = kt * tw + kk;
   const bool cv = c < K;
   const int64_t base = cv ? col_base(c, m, S) : 0;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int row = threadIdx.x / GBK + q * (256 / GBK);
+    const int row = threadIdx.x / BK + q * (256 / BK);
     ri[q] = (cv && row < rowsI) ? X[base + (rowI0 + row) * S] : T(0);
     rj[q] = (!diag && cv && row < rowsJ) ? X[base + (rowJ0 + row) * S] : T(0);
   }
 }
 
-template <typename T>
+template <typename T, int BK>
 __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__ X, int64_t P, int64_t m, int64_t S,
                                                            int nb, int npairs, int64_t ktiles, int64_t kt_per_split,
                                                            int64_t blk, int tw, double* __restrict__ part) {
-  __shared__ double sI[GBK * GLD];
-  __shared__ double sJ[GBK * GLD];
+  __shared__ double sI[BK * GLD];
+  __shared__ double sJ[BK * GLD];
   const int pair = blockIdx.x;
   const int split = blockIdx.y;
   int bi = 0, rem = pair;
@@ -272,19 +276,19 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
   const int64_t kt1 = min(ktiles, kt0 + kt_per_split);
   const int64_t rowI0 = (int64_t)bi * GB, rowJ0 = (int64_t)bj * GB;
   const double* sB = diag ? sI : sJ;
-  constexpr int PER = GBK * GB / 256;
-  const bool slab = S < GBK;
+  constexpr int PER = BK * GB / 256;
+  const bool slab = S < BK;
   const int ms = (int)(m * S);
 
   T ri[PER], rj[PER];
   if (kt0 < kt1 && !slab)
-    gram_load_tile(X, m, S, K, kt0, tw, rowI0, rowsI, rowJ0, rowsJ, diag, ri, rj);
+    gram_load_tile<T, BK>(X, m, S, K, kt0, tw, rowI0, rowsI, rowJ0, rowsJ, diag, ri, rj);
   for (int64_t kt = kt0; kt < kt1; ++kt) {
     if (slab) {
       // contiguous region of whole slices, scattered to (column, row) in LDS
-      for (int e = threadIdx.x; e < GBK * GB; e += 256) {
-        sI[(e % GBK) * GLD + e / GBK] = 0.0;
-        if (!diag) sJ[(e % GBK) * GLD + e / GBK] = 0.0;
+      for (int e = threadIdx.x; e < BK * GB; e += 256) {
+        sI[(e % BK) * GLD + e / BK] = 0.0;
+        if (!diag) sJ[(e % BK) * GLD + e / BK] = 0.0;
       }
       __syncthreads();
       const int64_t p0 = kt * tw / S;
@@ -305,17 +309,17 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
     } else {
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
-        const int kk = threadIdx.x % GBK;
-        const int row = threadIdx.x / GBK + q * (256 / GBK);
+        const int kk = threadIdx.x % BK;
+        const int row = threadIdx.x / BK + q * (256 / BK);
         sI[kk * GLD + row] = static_cast<double>(ri[q]);
         if (!diag) sJ[kk * GLD + row] = static_cast<double>(rj[q]);
       }
       // prefetch the next tile while this one is multiplied
-      if (kt + 1 < kt1) gram_load_tile(X, m, S, K, kt + 1, tw, rowI0, rowsI, rowJ0, rowsJ, diag, ri, rj);
+      if (kt + 1 < kt1) gram_load_tile<T, BK>(X, m, S, K, kt + 1, tw, rowI0, rowsI, rowJ0, rowsJ, diag, ri, rj);
     }
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < GBK; ks += 4) {
+    for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4);
       // every operand of the step first (all in the staged panels), then the products
       const double a0 = sI[kr * GLD + offA], a1 = sI[kr * GLD + offB];
@@ -808,12 +812,12 @@ struct GramPlan {
   int64_t ktiles, kt_per_split, blk;
 };
 
-GramPlan gram_plan(const ModeView& v) {
+GramPlan gram_plan(const ModeView& v, int bk = GBK) {
   GramPlan g;
   g.nb = (int)((v.m + GB - 1) / GB);
   g.npairs = g.nb * (g.nb + 1) / 2;
   const int64_t K = v.P * v.S;
-  g.tw = v.S >= GBK ? GBK : (int)(v.S * (GBK / v.S));
+  g.tw = v.S >= bk ? bk : (int)(v.S * (bk / v.S));
   g.ktiles = (K + g.tw - 1) / g.tw;
   int64_t want = std::max<int64_t>(1, 512 / g.npairs);
   want = std::min<int64_t>(want, std::max<int64_t>(1, g.ktiles));
@@ -2441,10 +2445,10 @@ size_t gram_partial_bound(int64_t m) {
 
 size_t gram_partial_doubles(const ModeView& v) {
   if (v.m <= kSmallM) return (size_t)kSmallBlocks * (kSmallM * (kSmallM + 1) / 2);
-  const GramPlan g = gram_plan(v);
+  const GramPlan g = gram_plan(v), w = gram_plan(v, GPK);  // (the latter for modes above 128 rows)
   // (the register-direct Grams write up to 512 partials of m x m)
   const size_t reg = v.m <= kResidGramMaxM ? (size_t)512 * v.m * v.m : 0;
-  return std::max<size_t>((size_t)g.nsplit * g.npairs * g.blk, reg);
+  return std::max<size_t>(std::max<size_t>((size_t)g.nsplit * g.npairs, (size_t)w.nsplit * w.npairs) * g.blk, reg);
 }
 
 // Register-direct block mode of an FP32 mode view: 0 for column runs in blocks of
@@ -2687,7 +2691,7 @@ void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hip
     gram_m64(static_cast<const float*>(x), v, mode, part, G, s);
     return;
   }
-  const GramPlan g = gram_plan(v);
+  const GramPlan g = v.m <= GB || t != Elem::F32 ? gram_plan(v) : gram_plan(v, GPK);
   if (v.m <= GB) {
     ProfScope prof(KKind::Gram, s, md * md * K, md * K * (t == Elem::F32 ? 4 : 8));
     launch_panel<double, false>(x, t, v, g, nullptr, 0, part, s);
@@ -2695,10 +2699,10 @@ void gram(const void* x, Elem t, const ModeView& v, double* part, double* G, hip
     dim3 grid(g.npairs, g.nsplit);
     ProfScope prof(KKind::Gram, s, md * md * K, md * K * (t == Elem::F32 ? 4 : 8));
     if (t == Elem::F32)
-      gram_partial_kernel<float><<<grid, 256, 0, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, g.nb, g.npairs,
+      gram_partial_kernel<float, GPK><<<grid, 256, 0, s>>>(static_cast<const float*>(x), v.P, v.m, v.S, g.nb, g.npairs,
                                                       g.ktiles, g.kt_per_split, g.blk, g.tw, part);
     else
-      gram_partial_kernel<double><<<grid, 256, 0, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, g.nb,
+      gram_partial_kernel<double, GBK><<<grid, 256, 0, s>>>(static_cast<const double*>(x), v.P, v.m, v.S, g.nb,
                                                        g.npairs, g.ktiles, g.kt_per_split, g.blk, g.tw, part);
   }
   gram_finish(g, v, part, G, s);
