@@ -146,9 +146,9 @@ void finish_sum(const double* part, int n, double* out, hipStream_t s) {
 // --------------------------------------------------------------------------
 // Gram of a mode unfolding: G = X_(k) X_(k)^T, FP64 MFMA.
 // Grid (pair, split): pair enumerates 128x128 blocks (bi <= bj) of G, split a
-// contiguous range of 32-column tiles of the unfolding.  Each workgroup stages
-// the two 128-row panels of its columns in LDS and accumulates its block's
-// 16x16 tiles (upper ones only on the diagonal) round-robin over 4 waves.
+// contiguous range of column tiles of the unfolding (BK columns each).  Each
+// workgroup stages the two 128-row panels of its columns in LDS and accumulates its
+// block's 16x16 tiles (upper ones only on the diagonal), each wave two tile rows.
 // --------------------------------------------------------------------------
 constexpr int GB = 128;
 constexpr int GBK = 32;
