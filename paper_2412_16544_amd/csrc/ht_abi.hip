@@ -440,9 +440,11 @@ Layout make_layout(const ht_config* c, const Tree& tree, std::vector<int64_t>& a
   L.ssnode = take(L, (size_t)nn * 2 * ht::kSumsqBlocks * sizeof(double));
   L.orthsc = take(L, ht::orth_scratch_doubles(64) * sizeof(double));
   L.padtmp = take(L, max_core * sizeof(double));
-  L.tails = take(L, (size_t)nn * sizeof(double));
-  L.aux = take(L, 2 * (size_t)nn * sizeof(double));
-  L.ranks_dev = take(L, (size_t)nn * sizeof(int));
+  // the layer read-back block, laid out as its host staging: the nodes' discarded
+  // energies, their ranks (in nn doubles of room), two certificate values per node
+  L.tails = take(L, 4 * (size_t)nn * sizeof(double));
+  L.ranks_dev = L.tails + (size_t)nn * sizeof(double);
+  L.aux = L.tails + 2 * (size_t)nn * sizeof(double);
   return L;
 }
 
@@ -863,11 +865,11 @@ void launch_eig(const std::vector<ht::EigJob>& jobs, hipStream_t s) {
 
 // Ranks and discarded energies of the layer (device -> host staging, not yet
 // synchronised), and after the wait their copies.
+// The device block (tails, ranks, aux) and its host staging share one layout, so
+// one copy brings back all three.
 ht_status layer_readback(ht_state* h, hipStream_t s, bool with_aux = false) {
   const int nn = (int)h->tree.nodes.size();
-  HT_HIP(hipMemcpyAsync(h->h_ranks, h->ranks_dev, nn * sizeof(int), hipMemcpyDeviceToHost, s));
-  HT_HIP(hipMemcpyAsync(h->h_tails, h->tails, nn * sizeof(double), hipMemcpyDeviceToHost, s));
-  if (with_aux) HT_HIP(hipMemcpyAsync(h->h_aux, h->aux, 2 * nn * sizeof(double), hipMemcpyDeviceToHost, s));
+  HT_HIP(hipMemcpyAsync(h->h_tails, h->tails, (with_aux ? 4 : 2) * nn * sizeof(double), hipMemcpyDeviceToHost, s));
   return HT_OK;
 }
 
