@@ -1263,8 +1263,14 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
     }
     ht::reduce_batch(sums, s);
   }
+  // The root slices of the batch as a skip leaves them are written before the skip
+  // test is read back: a skipped batch then needs no launch after its decision, and an
+  // updated one appends its own slices over the same slots (n_acc only advances when
+  // the call succeeds).
   for (Upd* up : act) {
     ht_state* h = up->h;
+    const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
+    ht::root_append(up->c1.ptr, up->c1.t, up->N, r11, r12, h->root, h->n_acc, h->rank_cap, s);
     const size_t ns = up->mixed ? kScalars((int)h->tree.nodes.size()) : 2;
     HT_HIP(hipMemcpyAsync(h->h_scal, h->scal, ns * sizeof(double), hipMemcpyDeviceToHost, s));
   }
@@ -1301,10 +1307,7 @@ ht_status rise_pass(std::vector<Upd*>& act, hipStream_t s) {
       continue;
     }
     u.skip = u.eps_proj <= u.eps_des;
-    if (u.skip) {
-      const int r11 = h->rank[h->tree.nodes[0].child[0]], r12 = h->rank[h->tree.nodes[0].child[1]];
-      ht::root_append(u.c1.ptr, u.c1.t, u.N, r11, r12, h->root, h->n_acc, h->rank_cap, s);
-    } else {
+    if (!u.skip) {
       u.busy = true;
       u.began = true;
       u.saved = h->rank;
