@@ -1776,7 +1776,7 @@ constexpr int TUS = 65;  // LDS row stride (doubles) of the staged U chunk of th
 // added in wave order through LDS.
 // --------------------------------------------------------------------------
 constexpr int kDirectLdsDoubles = 19968;  // U chunk: chunk x (RP + 1) doubles of dynamic LDS
-constexpr unsigned kDirectColsMinBlocks = 1024;  // column blocks from which whole blocks go to waves
+constexpr unsigned kDirectColsMinBlocks = 512;  // column blocks from which whole blocks go to waves
 
 // SQ: also the workgroup partials of ||X||^2 (in_part) and ||Z||^2 (out_part)
 // With gridDim.y > 1 workgroup (x, y) takes rows [y rows, (y + 1) rows) only and writes
